@@ -1,0 +1,434 @@
+/*
+ * Slow, plain CPU oracle for scalar spherical harmonic synthesis on the
+ * HEALPix grid and its adjoint, after the Wavemoth paper
+ * (D. S. Seljebotn, arXiv:1110.4874).
+ *
+ * TEST INFRASTRUCTURE.  Only the tests, the smoke check and the CPU
+ * baseline leg of the benchmark load this library.  It shares no code,
+ * header, table or helper with the HIP library under
+ * paper_1110_4874_amd/csrc; the only thing both sides consume is the
+ * seeded input from paper_1110_4874_amd/synthetic.py.
+ *
+ * Layouts (all plain C arrays):
+ *   alm  [nalm][B] complex (re,im doubles), m-major, l ascending inside
+ *        each m, offset(m) = m(2L+3-m)/2  (Sec. A.3: m-major input with
+ *        maps interleaved).
+ *   map  [B][Npix] doubles, HEALPix RING order.
+ *   q    [L+1][nrings][B] complex: the Legendre phase q_m(z_k).
+ *
+ * Precision: IEEE double, except the *_ld entry points, which run the
+ * same algorithm in long double (x87 80-bit) and round the result once.
+ *
+ * Parity pins for every function are in tests/test_oracle_pins.py; see
+ * the per-function comments for which property pins which part.
+ */
+#include <math.h>
+#include <tgmath.h>
+#include <stdlib.h>
+#include <string.h>
+#include <omp.h>
+
+/* ---- instantiate the core for double ------------------------------- */
+#define REAL double
+#define SFX(name) name##_d
+#include "oracle_core.inc"
+#undef REAL
+#undef SFX
+#undef R_PI
+
+/* ---- instantiate the core for long double -------------------------- */
+#define REAL long double
+#define SFX(name) name##_ld
+#include "oracle_core.inc"
+#undef REAL
+#undef SFX
+#undef R_PI
+
+static long long nalm_of(int L) { return (long long)(L + 1) * (L + 2) / 2; }
+
+/* ================================================================== */
+/* Geometry                                                            */
+/* ================================================================== */
+
+/* Ring i (1..4N-1): z, sin(theta), J (pixels), s (phi_0 = pi s / J),
+   offset of the first pixel.  Gorski et al. (2005), RING scheme. */
+void oracle_ring_info(long nside, long ring, double *z, double *sth, long *J,
+                      long *s, long long *off)
+{
+    ring_geom_d(nside, ring, z, sth, J, s, off);
+}
+
+/* Pixel index -> (ring, j), by integer search over the ring offsets. */
+void oracle_pixel_ring(long nside, long long p, long *ring, long *j)
+{
+    long long N = nside, ncap = 2 * N * (N - 1), npix = 12 * N * N;
+    if (p < ncap) {
+        long i = 1;
+        while (2LL * (i + 1) * i <= p) i++;
+        *ring = i;
+        *j = (long)(p - 2LL * i * (i - 1));
+    } else if (p < npix - ncap) {
+        long long q = p - ncap;
+        *ring = (long)(N + q / (4 * N));
+        *j = (long)(q % (4 * N));
+    } else {
+        long long pp = npix - 1 - p; /* mirrored index from the end */
+        long i = 1;
+        while (2LL * (i + 1) * i <= pp) i++;
+        *ring = (long)(4 * N - i);
+        long long off = npix - 2LL * i * (i + 1);
+        *j = (long)(p - off);
+    }
+}
+
+/* ================================================================== */
+/* Legendre functions                                                  */
+/* ================================================================== */
+
+/* P~_l^m(z) for l = m..L at an arbitrary z = cos(theta) (sth = sin(theta)).
+   out has L-m+1 entries. */
+void oracle_plm_z(int L, int m, double z, double sth, double *out)
+{
+    plm_column_d(L, m, z, sth, out);
+}
+
+/* P~_l^m at the z of HEALPix ring `ring`. */
+void oracle_plm_ring(int L, int m, long nside, long ring, double *out)
+{
+    double z, sth;
+    long J, s;
+    long long off;
+    ring_geom_d(nside, ring, &z, &sth, &J, &s, &off);
+    plm_column_d(L, m, z, sth, out);
+}
+
+/* Long-double P~ at a ring, rounded once to double. */
+void oracle_plm_ring_ld(int L, int m, long nside, long ring, double *out)
+{
+    long double z, sth;
+    long J, s;
+    long long off;
+    ring_geom_ld(nside, ring, &z, &sth, &J, &s, &off);
+    long double *col = malloc(sizeof(long double) * (L + 1));
+    plm_column_ld(L, m, z, sth, col);
+    for (int l = m; l <= L; l++) out[l - m] = (double)col[l - m];
+    free(col);
+}
+
+/* ================================================================== */
+/* Legendre phase q_m(z_k) (Sec. 2.4 Eq. 12), every ring evaluated at  */
+/* its own z (south rings included: no even/odd fold is used here).    */
+/* ================================================================== */
+
+/* Selected rings: q_out [nr][L+1][B] complex. */
+void oracle_legendre_phase_rings(int L, long nside, int B, const double *alm,
+                                 int nr, const long *rings, double *q_out)
+{
+#pragma omp parallel
+    {
+        double *col = malloc(sizeof(double) * (L + 1));
+        double *q = malloc(sizeof(double) * 2 * (L + 1) * B);
+#pragma omp for schedule(dynamic, 1)
+        for (int r = 0; r < nr; r++) {
+            double z, sth;
+            long J, s;
+            long long off;
+            ring_geom_d(nside, rings[r], &z, &sth, &J, &s, &off);
+            ring_phase_d(L, z, sth, B, alm, q, col);
+            memcpy(q_out + (size_t)r * 2 * (L + 1) * B, q,
+                   sizeof(double) * 2 * (L + 1) * B);
+        }
+        free(col);
+        free(q);
+    }
+}
+
+/* Long-double version of the same, rounded once to double. */
+void oracle_legendre_phase_rings_ld(int L, long nside, int B, const double *alm,
+                                    int nr, const long *rings, double *q_out)
+{
+#pragma omp parallel
+    {
+        long double *col = malloc(sizeof(long double) * (L + 1));
+        long double *q = malloc(sizeof(long double) * 2 * (L + 1) * B);
+#pragma omp for schedule(dynamic, 1)
+        for (int r = 0; r < nr; r++) {
+            long double z, sth;
+            long J, s;
+            long long off;
+            ring_geom_ld(nside, rings[r], &z, &sth, &J, &s, &off);
+            ring_phase_ld(L, z, sth, B, alm, q, col);
+            for (long k = 0; k < 2L * (L + 1) * B; k++)
+                q_out[(size_t)r * 2 * (L + 1) * B + k] = (double)q[k];
+        }
+        free(col);
+        free(q);
+    }
+}
+
+/* ================================================================== */
+/* Synthesis (Sec. 1 Eq. 1 via Sec. 2.3 Eq. 8): Legendre phase then a  */
+/* direct per-ring DFT.                                                */
+/* ================================================================== */
+
+/* Selected rings.  out: packed [B][sum_r J_r], rings in the given order. */
+void oracle_synthesis_rings(int L, long nside, int B, const double *alm, int nr,
+                            const long *rings, double *out)
+{
+    long long *base = malloc(sizeof(long long) * (nr + 1));
+    base[0] = 0;
+    for (int r = 0; r < nr; r++) {
+        double z, sth;
+        long J, s;
+        long long off;
+        ring_geom_d(nside, rings[r], &z, &sth, &J, &s, &off);
+        base[r + 1] = base[r] + J;
+    }
+    long long tot = base[nr];
+#pragma omp parallel
+    {
+        double *col = malloc(sizeof(double) * (L + 1));
+        double *q = malloc(sizeof(double) * 2 * (L + 1) * B);
+        double *cs = malloc(sizeof(double) * 8 * nside);
+        double *sn = malloc(sizeof(double) * 8 * nside);
+        double *f = malloc(sizeof(double) * 4 * nside * B);
+#pragma omp for schedule(dynamic, 1)
+        for (int r = 0; r < nr; r++) {
+            double z, sth;
+            long J, s;
+            long long off;
+            ring_geom_d(nside, rings[r], &z, &sth, &J, &s, &off);
+            ring_phase_d(L, z, sth, B, alm, q, col);
+            ring_dft_d(L, J, s, B, q, f, cs, sn);
+            for (int b = 0; b < B; b++)
+                memcpy(out + b * tot + base[r], f + b * J, sizeof(double) * J);
+        }
+        free(col); free(q); free(cs); free(sn); free(f);
+    }
+    free(base);
+}
+
+/* Same in long double (spot-check mode), rounded once to double. */
+void oracle_synthesis_rings_ld(int L, long nside, int B, const double *alm, int nr,
+                               const long *rings, double *out)
+{
+    long long *base = malloc(sizeof(long long) * (nr + 1));
+    base[0] = 0;
+    for (int r = 0; r < nr; r++) {
+        double z, sth;
+        long J, s;
+        long long off;
+        ring_geom_d(nside, rings[r], &z, &sth, &J, &s, &off);
+        base[r + 1] = base[r] + J;
+    }
+    long long tot = base[nr];
+#pragma omp parallel
+    {
+        long double *col = malloc(sizeof(long double) * (L + 1));
+        long double *q = malloc(sizeof(long double) * 2 * (L + 1) * B);
+        long double *cs = malloc(sizeof(long double) * 8 * nside);
+        long double *sn = malloc(sizeof(long double) * 8 * nside);
+        long double *f = malloc(sizeof(long double) * 4 * nside * B);
+#pragma omp for schedule(dynamic, 1)
+        for (int r = 0; r < nr; r++) {
+            long double z, sth;
+            long J, s;
+            long long off;
+            ring_geom_ld(nside, rings[r], &z, &sth, &J, &s, &off);
+            ring_phase_ld(L, z, sth, B, alm, q, col);
+            ring_dft_ld(L, J, s, B, q, f, cs, sn);
+            for (int b = 0; b < B; b++)
+                for (long j = 0; j < J; j++)
+                    out[b * tot + base[r] + j] = (double)f[b * J + j];
+        }
+        free(col); free(q); free(cs); free(sn); free(f);
+    }
+    free(base);
+}
+
+/* Full map: map [B][Npix]. */
+void oracle_synthesis(int L, long nside, int B, const double *alm, double *map)
+{
+    long long npix = 12LL * nside * nside;
+#pragma omp parallel
+    {
+        double *col = malloc(sizeof(double) * (L + 1));
+        double *q = malloc(sizeof(double) * 2 * (L + 1) * B);
+        double *cs = malloc(sizeof(double) * 8 * nside);
+        double *sn = malloc(sizeof(double) * 8 * nside);
+        double *f = malloc(sizeof(double) * 4 * nside * B);
+#pragma omp for schedule(dynamic, 1)
+        for (long ring = 1; ring <= 4 * nside - 1; ring++) {
+            double z, sth;
+            long J, s;
+            long long off;
+            ring_geom_d(nside, ring, &z, &sth, &J, &s, &off);
+            ring_phase_d(L, z, sth, B, alm, q, col);
+            ring_dft_d(L, J, s, B, q, f, cs, sn);
+            for (int b = 0; b < B; b++)
+                memcpy(map + b * npix + off, f + b * J, sizeof(double) * J);
+        }
+        free(col); free(q); free(cs); free(sn); free(f);
+    }
+}
+
+/* ================================================================== */
+/* Direct O(L^2)-per-pixel evaluation of Sec. 1 Eq. 1 for a real field */
+/* (tiny L only): f(n_p) = sum_l [a_l0 Y_l0 + 2 sum_{m>=1} Re(a_lm Y_lm)]*/
+/* with phi = pi(2j+s)/J formed in floating point and cos(m phi),      */
+/* sin(m phi) called directly -- independent of the ring DFT's integer */
+/* phase reduction.  out: [B][npsel].                                  */
+/* ================================================================== */
+void oracle_synthesis_direct(int L, long nside, int B, const double *alm,
+                             long npsel, const long long *pix, double *out)
+{
+#pragma omp parallel
+    {
+        double *col = malloc(sizeof(double) * (L + 1));
+#pragma omp for schedule(dynamic, 16)
+        for (long k = 0; k < npsel; k++) {
+            long ring, j, J, s;
+            double z, sth;
+            long long off;
+            oracle_pixel_ring(nside, pix[k], &ring, &j);
+            ring_geom_d(nside, ring, &z, &sth, &J, &s, &off);
+            double phi = M_PI * (2.0 * j + s) / (double)J;
+            for (int b = 0; b < B; b++) out[b * npsel + k] = 0.0;
+            for (int m = 0; m <= L; m++) {
+                plm_column_d(L, m, z, sth, col);
+                double c = cos(m * phi), sn = sin(m * phi);
+                long long o = (long long)m * (2 * L + 3 - m) / 2;
+                for (int l = m; l <= L; l++) {
+                    for (int b = 0; b < B; b++) {
+                        const double *a = alm + 2 * ((o + l - m) * B + b);
+                        double y_re = col[l - m] * c, y_im = col[l - m] * sn;
+                        if (m == 0)
+                            out[b * npsel + k] += a[0] * y_re;
+                        else
+                            out[b * npsel + k] += 2.0 * (a[0] * y_re - a[1] * y_im);
+                    }
+                }
+            }
+        }
+        free(col);
+    }
+}
+
+/* ================================================================== */
+/* Adjoint.  With the real inner product <a,g> = sum_{l,m>=0} (Re a Re g */
+/* + Im a Im g) on the coefficients, the transpose of synthesis is      */
+/*   g_lm = w_m sum_k P~_l^m(z_k) sum_j y_kj e^{-i m phi_kj},            */
+/* w_0 = 1 (real part only, Im g_l0 = 0), w_m = 2 for m >= 1            */
+/* (convention 0).  Convention 1 is the complex adjoint Y^dagger of     */
+/* Sec. 2.2 Eq. 7 restricted to m >= 0: w_m = 1 for all m.              */
+/* ================================================================== */
+
+static double weight_of(int m, int conv) { return (m == 0 || conv == 1) ? 1.0 : 2.0; }
+
+/* Full adjoint.  map [B][Npix] -> g [nalm][B] complex. */
+void oracle_adjoint(int L, long nside, int B, const double *map, int conv, double *g)
+{
+    long nrings = 4 * nside - 1;
+    long long npix = 12LL * nside * nside;
+    double *ybar = malloc(sizeof(double) * 2 * (size_t)nrings * (L + 1) * B);
+    double *zs = malloc(sizeof(double) * nrings), *ss = malloc(sizeof(double) * nrings);
+#pragma omp parallel
+    {
+        double *cs = malloc(sizeof(double) * 8 * nside);
+        double *sn = malloc(sizeof(double) * 8 * nside);
+        double *y = malloc(sizeof(double) * 4 * nside * B);
+#pragma omp for schedule(dynamic, 1)
+        for (long ring = 1; ring <= nrings; ring++) {
+            double z, sth;
+            long J, s;
+            long long off;
+            ring_geom_d(nside, ring, &z, &sth, &J, &s, &off);
+            zs[ring - 1] = z;
+            ss[ring - 1] = sth;
+            for (int b = 0; b < B; b++)
+                memcpy(y + b * J, map + b * npix + off, sizeof(double) * J);
+            ring_dft_adjoint_d(L, J, s, B, y,
+                               ybar + (size_t)(ring - 1) * 2 * (L + 1) * B, cs, sn);
+        }
+        free(cs); free(sn); free(y);
+    }
+    memset(g, 0, sizeof(double) * 2 * nalm_of(L) * B);
+#pragma omp parallel
+    {
+        double *col = malloc(sizeof(double) * (L + 1));
+#pragma omp for schedule(dynamic, 1)
+        for (int m = 0; m <= L; m++) {
+            long long o = (long long)m * (2 * L + 3 - m) / 2;
+            double w = weight_of(m, conv);
+            for (long ring = 0; ring < nrings; ring++) {
+                plm_column_d(L, m, zs[ring], ss[ring], col);
+                const double *yb = ybar + (size_t)ring * 2 * (L + 1) * B + 2 * (size_t)m * B;
+                for (int l = m; l <= L; l++)
+                    for (int b = 0; b < B; b++) {
+                        g[2 * ((o + l - m) * B + b)] += w * col[l - m] * yb[2 * b];
+                        if (m > 0)
+                            g[2 * ((o + l - m) * B + b) + 1] += w * col[l - m] * yb[2 * b + 1];
+                    }
+            }
+        }
+        free(col);
+    }
+    free(ybar); free(zs); free(ss);
+}
+
+/* Adjoint for selected m only (sampled parity at large L).
+   g_out [nm][L+1][B] complex, entry l-m holds g_lm (entries past L-m
+   are zero). */
+void oracle_adjoint_msel(int L, long nside, int B, const double *map, int conv,
+                         int nm, const int *ms, double *g_out)
+{
+    long nrings = 4 * nside - 1;
+    long long npix = 12LL * nside * nside;
+    double *yb = malloc(sizeof(double) * 2 * (size_t)nrings * B);
+    double *col = malloc(sizeof(double) * (L + 1));
+    memset(g_out, 0, sizeof(double) * 2 * (size_t)nm * (L + 1) * B);
+    for (int k = 0; k < nm; k++) {
+        int m = ms[k];
+        double w = weight_of(m, conv);
+        double *gk = g_out + (size_t)k * 2 * (L + 1) * B;
+        /* ring DFT for this m, one ring per iteration */
+#pragma omp parallel for schedule(dynamic, 4)
+        for (long ring = 1; ring <= nrings; ring++) {
+            double z, sth;
+            long J, s;
+            long long off;
+            ring_geom_d(nside, ring, &z, &sth, &J, &s, &off);
+            for (int b = 0; b < B; b++) {
+                double re = 0, im = 0;
+                for (long j = 0; j < J; j++) {
+                    long r = (long)(((long long)m * (2 * j + s)) % (2 * J));
+                    double y = map[b * npix + off + j];
+                    re += y * cos(M_PI * (double)r / (double)J);
+                    im -= y * sin(M_PI * (double)r / (double)J);
+                }
+                yb[2 * ((ring - 1) * B + b)] = re;
+                yb[2 * ((ring - 1) * B + b) + 1] = im;
+            }
+        }
+        /* Legendre sum over rings, serial so the summation order is fixed */
+        for (long ring = 1; ring <= nrings; ring++) {
+            double z, sth;
+            long J, s;
+            long long off;
+            ring_geom_d(nside, ring, &z, &sth, &J, &s, &off);
+            plm_column_d(L, m, z, sth, col);
+            for (int l = m; l <= L; l++)
+                for (int b = 0; b < B; b++) {
+                    gk[2 * ((l - m) * B + b)] += w * col[l - m] * yb[2 * ((ring - 1) * B + b)];
+                    if (m > 0)
+                        gk[2 * ((l - m) * B + b) + 1] +=
+                            w * col[l - m] * yb[2 * ((ring - 1) * B + b) + 1];
+                }
+        }
+    }
+    free(yb);
+    free(col);
+}
+
+/* Threads the OpenMP runtime will use (reported by the CPU baseline). */
+int oracle_num_threads(void) { return omp_get_max_threads(); }

@@ -1,0 +1,414 @@
+"""Pins of the CPU oracle against what the paper and mathematics fix.
+
+Each test ties one part of the oracle to something other than the oracle
+itself, chosen so that a plausible mistake (a dropped term, a wrong sign or
+index, a transposed operand, a wrong phase origin) fails at least one:
+
+  geometry          -> HEALPix base-pixel centres (golden) + an independent
+                       rational re-derivation of every ring
+  P~ normalisation  -> addition theorem, Gauss-Legendre orthogonality
+  CS phase, phi_0   -> textbook closed forms for l <= 3 (golden), scipy's
+                       sph_harm_y (a library routine)
+  Legendre x DFT    -> point-source identity with P_l from the Bonnet
+                       recurrence in long double
+  DFT phase/wrap    -> O(L^2)-per-pixel direct sum, rotation by pi/2
+  even/odd symmetry -> reflection a_lm -> (-1)^(l+m) a_lm
+  adjoint           -> dot-product test against synthesis
+"""
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1110_4874_amd.synthetic import alm_gaussian, lm_index, nalm
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# --------------------------------------------------------------------------
+# Independent geometry (Gorski et al. 2005, RING scheme), exact rationals.
+# --------------------------------------------------------------------------
+def ring_exact(N, i):
+    """(z as Fraction, J, phi_0/pi as Fraction, first pixel) for ring i."""
+    if i <= 2 * N:
+        ii, sgn = i, 1
+    else:
+        ii, sgn = 4 * N - i, -1
+    if ii < N:
+        z = 1 - Fraction(ii * ii, 3 * N * N)
+        J = 4 * ii
+        phi0 = Fraction(1, 2 * J) * 2  # pi/(2*ii) * 1/2 = pi/(4 ii) -> phi0/pi = 1/(4 ii)
+        phi0 = Fraction(1, 4 * ii)
+    else:
+        z = Fraction(4, 3) - Fraction(2 * ii, 3 * N)
+        J = 4 * N
+        shifted = (ii - N) % 2 == 0
+        phi0 = Fraction(1, 4 * N) if shifted else Fraction(0)
+    ncap = 2 * N * (N - 1)
+    if i < N:
+        off = 2 * i * (i - 1)
+    elif i <= 3 * N:
+        off = ncap + (i - N) * 4 * N
+    else:
+        ip = 4 * N - i
+        off = 12 * N * N - 2 * ip * (ip + 1)
+    return sgn * z, J, phi0, off
+
+
+def pixel_angles(N):
+    """(cos theta, sin theta, phi) of every pixel, from the exact ring table."""
+    cz, sz, ph = [], [], []
+    for i in range(1, 4 * N):
+        z, J, phi0, off = ring_exact(N, i)
+        st = math.sqrt(float((1 - z) * (1 + z)))
+        for j in range(J):
+            cz.append(float(z))
+            sz.append(st)
+            ph.append(math.pi * float(phi0 + Fraction(2 * j, J)))
+    return np.array(cz), np.array(sz), np.array(ph)
+
+
+def test_geometry_base_pixels_golden():
+    rows = np.loadtxt(os.path.join(GOLDEN, "healpix_nside1_centres.txt"))
+    for p, z, phi_over_pi in rows:
+        ring, j = oracle.pixel_ring(1, int(p))
+        zz, st, J, s, off = oracle.ring_info(1, ring)
+        assert off + j == int(p)
+        assert zz == pytest.approx(z, abs=1e-16)
+        assert math.pi * (2 * j + s) / J == pytest.approx(math.pi * phi_over_pi, abs=1e-15)
+        assert st == pytest.approx(math.sqrt(1 - z * z), abs=1e-16)
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 8, 13, 64, 2048])
+def test_geometry_matches_exact_rationals(N):
+    rings = range(1, 4 * N) if N <= 64 else list(range(1, 40)) + list(range(N - 3, N + 4)) \
+        + list(range(2 * N - 3, 2 * N + 4)) + list(range(4 * N - 40, 4 * N))
+    total = 0
+    for i in rings:
+        z, J, phi0, off = ring_exact(N, i)
+        zz, st, JJ, s, oo = oracle.ring_info(N, i)
+        assert JJ == J and oo == off
+        assert Fraction(s, J) == phi0
+        assert zz == float(z)  # correctly rounded from the exact rational
+        # sin(theta) from the exact (1-z)(1+z), relative error <= 1 ulp
+        exact = math.sqrt(float((1 - z) * (1 + z))) if abs(z) < 1 else 0.0
+        assert st == pytest.approx(exact, rel=3e-16)
+        total += J
+    if N <= 64:
+        assert total == 12 * N * N
+
+
+@pytest.mark.parametrize("N", [1, 2, 5, 16])
+def test_pixel_ring_roundtrip(N):
+    for p in range(12 * N * N):
+        ring, j = oracle.pixel_ring(N, p)
+        _, _, J, _, off = oracle.ring_info(N, ring)
+        assert 0 <= j < J and off + j == p
+
+
+# --------------------------------------------------------------------------
+# Normalisation and phase of P~ (Sec. 2.1 Eq. 2)
+# --------------------------------------------------------------------------
+def test_y00_constant_map():
+    # a_00 = 1 gives f = Y_00 = 1/sqrt(4 pi) everywhere
+    for N, L in [(1, 0), (4, 0), (4, 7), (16, 31)]:
+        alm = np.zeros((nalm(L), 1), complex)
+        alm[0, 0] = 1.0
+        f = oracle.synthesis(L, N, alm)
+        assert np.max(np.abs(f - 0.28209479177387814)) <= 1e-16
+
+
+def _golden_harmonics():
+    out = []
+    with open(os.path.join(GOLDEN, "low_l_harmonics.txt")) as fh:
+        for line in fh:
+            if line.startswith("#") or not line.strip():
+                continue
+            l, m, pre, poly = line.split()
+            out.append((int(l), int(m), pre, poly))
+    return out
+
+
+@pytest.mark.parametrize("l,m,pre,poly", _golden_harmonics())
+def test_low_l_closed_forms(l, m, pre, poly):
+    N, L = 8, 3
+    c, s, ph = pixel_angles(N)
+    env = {"sqrt": math.sqrt, "pi": math.pi, "c": c, "s": s}
+    Y = eval(pre, env) * eval(poly, env) * np.exp(1j * m * ph)
+    a = 0.7 - 0.4j if m > 0 else 1.3
+    alm = np.zeros((nalm(L), 1), complex)
+    ls, ms = lm_index(L)
+    alm[np.flatnonzero((ls == l) & (ms == m))[0], 0] = a
+    expect = (a * Y).real if m == 0 else 2 * (a * Y).real
+    f = oracle.synthesis(L, N, alm)[0]
+    # test-side exp(i m phi) carries ~m*2pi*1e-16 of rounding of its own
+    assert np.max(np.abs(f - expect)) <= 1e-14 * np.max(np.abs(expect))
+
+
+@pytest.mark.parametrize("N,L,step,ld", [(16, 31, 1, False), (64, 127, 1, False),
+                                         (2048, 4095, 1023, False), (2048, 4095, 2047, True)])
+def test_addition_theorem(N, L, step, ld):
+    # P~_l^0(z)^2 + 2 sum_{m>=1} P~_l^m(z)^2 = (2l+1)/(4 pi), every l <= L.
+    # A three-term recurrence in z near a pole is ill-conditioned in theta
+    # (rounding acts like a perturbation of z, amplified ~ l/sin(theta)), so
+    # the FP64 residual grows like l^2 eps at the first rings; the long-double
+    # mode is ~2000x tighter.  Any normalisation or sign error is O(1).
+    rings = sorted(set(list(range(1, 4 * N, step)) + [1, 2, N, 2 * N]))
+    ell = np.arange(L + 1)
+    tol = (3e-16 if not ld else 2e-19) * (ell + 10.0) ** 2 + (0 if not ld else 1e-15)
+    for ring in rings:
+        acc = np.zeros(L + 1)
+        for m in range(L + 1):
+            col = oracle.plm_ring(L, m, N, ring, ld=ld)
+            acc[m:] += (1.0 if m == 0 else 2.0) * col ** 2
+        expect = (2 * ell + 1) / (4 * np.pi)
+        assert np.all(np.abs(acc / expect - 1) <= tol), ring
+
+
+@pytest.mark.parametrize("L", [6, 17, 32])
+def test_gauss_legendre_orthogonality(L):
+    # int_{-1}^{1} P~_l^m P~_l'^m dz = delta_ll' / (2 pi) with the 1/(4 pi)
+    # normalisation of Eq. 2 (the paper's orthogonality line omits 1/(2 pi)).
+    x, w = np.polynomial.legendre.leggauss(L + 2)
+    for m in range(L + 1):
+        P = np.array([oracle.plm_z(L, m, xi, math.sqrt(1 - xi * xi)) for xi in x])
+        G = (P * w[:, None]).T @ P
+        assert np.max(np.abs(G - np.eye(L - m + 1) / (2 * np.pi))) <= 2e-14
+
+
+def test_scipy_sph_harm_pixels():
+    from scipy.special import sph_harm_y
+    N, L = 8, 12
+    alm = alm_gaussian(L, [11, 12], spectrum="white")
+    c, s, ph = pixel_angles(N)
+    th = np.arctan2(s, c)
+    ls, ms = lm_index(L)
+    expect = np.zeros((2, len(th)))
+    for k, (l, m) in enumerate(zip(ls, ms)):
+        Y = sph_harm_y(int(l), int(m), th, ph)
+        for b in range(2):
+            t = alm[k, b] * Y
+            expect[b] += t.real if m == 0 else 2 * t.real
+    f_ring = oracle.synthesis(L, N, alm)
+    f_direct = oracle.synthesis_direct(L, N, alm, np.arange(12 * N * N))
+    scale = np.max(np.abs(expect))
+    assert np.max(np.abs(f_ring - expect)) <= 1e-13 * scale
+    assert np.max(np.abs(f_direct - expect)) <= 1e-13 * scale
+
+
+# --------------------------------------------------------------------------
+# Point source: a_lm = conj(Y_lm(n0)) synthesises sum_l (2l+1)/(4 pi) P_l(cos g)
+# --------------------------------------------------------------------------
+def _source_dir(th0):
+    """(cos, sin) of the source colatitude as a pair of doubles that lies on
+    the unit circle to ~1e-20: f near the source is sensitive to cos(gamma) at
+    the L^2/4 level, so the pair must satisfy z0^2 + s0^2 = 1 far below eps.
+    Searched among the doubles next to cos(th0), exactly, with Fractions."""
+    best = None
+    z = math.cos(th0)
+    for _ in range(4000):
+        s = float(np.sqrt((1 - np.longdouble(z)) * (1 + np.longdouble(z))))
+        res = abs(Fraction(z) ** 2 + Fraction(s) ** 2 - 1)
+        if best is None or res < best[0]:
+            best = (res, z, s)
+        z = math.nextafter(z, 1.0)
+    return best[1], best[2]
+
+
+def _point_source_alm(L, th0, ph0):
+    ls, ms = lm_index(L)
+    alm = np.zeros((nalm(L), 1), complex)
+    z0, s0 = _source_dir(th0)
+    o = 0
+    for m in range(L + 1):
+        col = oracle.plm_z(L, m, z0, s0)
+        alm[o:o + L + 1 - m, 0] = col * np.exp(-1j * m * ph0)
+        o += L + 1 - m
+    return alm
+
+
+def _legendre_sum_ld(L, cosg):
+    """sum_{l<=L} (2l+1)/(4 pi) P_l(x) by the Bonnet recurrence, long double."""
+    x = np.asarray(cosg, dtype=np.longdouble)
+    p0 = np.ones_like(x)
+    p1 = x.copy()
+    tot = p0 * 1 + (3 * p1 if L >= 1 else 0)
+    for l in range(1, L):
+        p2 = ((2 * l + 1) * x * p1 - l * p0) / (l + 1)
+        p0, p1 = p1, p2
+        tot = tot + (2 * (l + 1) + 1) * p1
+    return tot / (4 * np.pi)
+
+
+def _cos_gamma_ld(N, ring, th0, ph0):
+    """cos(gamma) to the pixels of a ring, from the exact rational ring z."""
+    z, J, phi0, off = ring_exact(N, ring)
+    zl = np.longdouble(z.numerator) / np.longdouble(z.denominator)
+    w = (1 - z) * (1 + z)
+    sl = np.sqrt(np.longdouble(w.numerator) / np.longdouble(w.denominator))
+    j = np.arange(J, dtype=np.longdouble)
+    pi = np.longdouble(np.pi) + np.longdouble(1.2246467991473532e-16)
+    phi = pi * (np.longdouble(phi0.numerator) / phi0.denominator + 2 * j / J)
+    z0, s0 = (np.longdouble(v) for v in _source_dir(th0))
+    return zl * z0 + sl * s0 * np.cos(phi - np.longdouble(ph0))
+
+
+@pytest.mark.parametrize("N,L,rings,ld", [(32, 63, None, True), (32, 63, None, False),
+                                          (256, 511, [1, 7, 200, 256, 300, 304, 511, 700, 1022], True),
+                                          (2048, 4095, [1, 1000, 2432, 2700, 4096], True)])
+def test_point_source(N, L, rings, ld):
+    # Near the source f is sensitive to cos(gamma) at the L^2/4 level, so the
+    # FP64 oracle (evaluated at the correctly rounded FP64 ring z) can differ
+    # from the exact-geometry reference by ~L^2 eps/4 of max f; the long-double
+    # mode evaluates at the exact ring z.
+    th0, ph0 = 1.0, 0.7
+    alm = _point_source_alm(L, th0, ph0)
+    if rings is None:
+        rings = list(range(1, 4 * N))
+    vals = oracle.synthesis_rings(L, N, alm, rings, ld=ld)
+    fmax = (L + 1) ** 2 / (4 * np.pi)
+    tol = 2e-14 if ld else 2e-14 + (L + 1) ** 2 * 1.2e-16 / 4
+    for ring, f in zip(rings, vals):
+        expect = _legendre_sum_ld(L, _cos_gamma_ld(N, ring, th0, ph0))
+        err = np.max(np.abs(f[0] - expect.astype(np.float64)))
+        assert err <= tol * fmax, (ring, err / fmax)
+
+
+# --------------------------------------------------------------------------
+# Symmetries: reflection (even/odd fold) and rotation by pi/2 (phases, phi_0)
+# --------------------------------------------------------------------------
+def test_reflection_symmetry():
+    N, L = 16, 31
+    alm = alm_gaussian(L, [3])
+    ls, ms = lm_index(L)
+    refl = alm * ((-1.0) ** (ls + ms))[:, None]
+    f = oracle.synthesis(L, N, alm)[0]
+    g = oracle.synthesis(L, N, refl)[0]
+    scale = np.max(np.abs(f))
+    for i in range(1, 4 * N):
+        _, _, J, _, off = oracle.ring_info(N, i)
+        _, _, J2, _, off2 = oracle.ring_info(N, 4 * N - i)
+        assert J == J2
+        assert np.max(np.abs(f[off:off + J] - g[off2:off2 + J])) <= 1e-15 * scale * 8
+
+
+def test_rotation_quarter_turn():
+    N, L = 16, 40  # L > 2N-1 also exercises the wrap of polar rings
+    alm = alm_gaussian(L, [4])
+    ls, ms = lm_index(L)
+    rot = alm * ((-1j) ** ms)[:, None]
+    f = oracle.synthesis(L, N, alm)[0]
+    g = oracle.synthesis(L, N, rot)[0]
+    scale = np.max(np.abs(f))
+    for i in range(1, 4 * N):
+        _, _, J, _, off = oracle.ring_info(N, i)
+        assert np.max(np.abs(g[off:off + J] - np.roll(f[off:off + J], J // 4))) <= 1e-14 * scale
+
+
+def test_direct_sum_matches_ring_dft():
+    N, L = 8, 15
+    alm = alm_gaussian(L, [5, 6, 7])
+    f = oracle.synthesis(L, N, alm)
+    d = oracle.synthesis_direct(L, N, alm, np.arange(12 * N * N))
+    assert np.max(np.abs(f - d)) <= 1e-14 * np.max(np.abs(f))
+
+
+def test_direct_sum_wrapping_regime():
+    # L well above 2N: every polar ring aliases many m into its J bins
+    N, L = 4, 29
+    alm = alm_gaussian(L, [8], spectrum="white")
+    f = oracle.synthesis(L, N, alm)
+    d = oracle.synthesis_direct(L, N, alm, np.arange(12 * N * N))
+    assert np.max(np.abs(f - d)) <= 1e-13 * np.max(np.abs(f))
+
+
+def test_im_al0_ignored():
+    N, L = 4, 7
+    alm = alm_gaussian(L, [9])
+    alm2 = alm.copy()
+    alm2[: L + 1] += 5j  # imaginary parts of the m = 0 coefficients
+    assert np.array_equal(oracle.synthesis(L, N, alm), oracle.synthesis(L, N, alm2))
+
+
+# --------------------------------------------------------------------------
+# Adjoint: exact transpose under the real inner product
+# --------------------------------------------------------------------------
+def _real_dot(a, g):
+    return float(np.sum(a.real * g.real + a.imag * g.imag))
+
+
+@pytest.mark.parametrize("N,L", [(8, 15), (16, 40)])
+def test_adjoint_dot_product(N, L):
+    a = alm_gaussian(L, [21, 22], spectrum="white")
+    a[: L + 1] = a[: L + 1].real  # real-field coefficients: a_l0 real
+    y = np.random.default_rng(23).standard_normal((2, 12 * N * N))
+    f = oracle.synthesis(L, N, a)
+    g = oracle.adjoint(L, N, y, conv=0)
+    lhs = float(np.sum(f * y))
+    rhs = _real_dot(a, g)
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+    assert np.all(g[: L + 1].imag == 0)
+    # convention 1 (complex adjoint) differs by w_m only
+    g1 = oracle.adjoint(L, N, y, conv=1)
+    _, ms = lm_index(L)
+    w = np.where(ms == 0, 1.0, 2.0)[:, None]
+    assert np.max(np.abs(g1 * w - g)) <= 1e-13 * np.max(np.abs(g))
+    # per-m sampled adjoint agrees with the full one
+    sel = [0, 3, L]
+    gs = oracle.adjoint_msel(L, N, y, sel, conv=0)
+    o = [m * (2 * L + 3 - m) // 2 for m in sel]
+    for k, m in enumerate(sel):
+        assert np.max(np.abs(gs[k, : L + 1 - m] - g[o[k]:o[k] + L + 1 - m])) <= 1e-12 * np.max(np.abs(g))
+
+
+def test_gradient_of_quadratic_loss_is_exact_fd():
+    # loss(a) = ||Y a - d||^2 is quadratic: central differences are exact up to
+    # rounding, and the gradient is 2 A^T (Y a - d)
+    N, L = 4, 9
+    a = alm_gaussian(L, [31], spectrum="white")
+    a[: L + 1] = a[: L + 1].real
+    d = np.random.default_rng(32).standard_normal((1, 12 * N * N))
+    r = oracle.synthesis(L, N, a) - d
+    grad = 2 * oracle.adjoint(L, N, r)
+    rng = np.random.default_rng(33)
+    v = rng.standard_normal(a.shape) + 1j * rng.standard_normal(a.shape)
+    v[: L + 1] = v[: L + 1].real
+    h = 1e-3
+    lp = np.sum((oracle.synthesis(L, N, a + h * v) - d) ** 2)
+    lm = np.sum((oracle.synthesis(L, N, a - h * v) - d) ** 2)
+    fd = (lp - lm) / (2 * h)
+    assert fd == pytest.approx(_real_dot(v, grad), rel=1e-11)
+
+
+# --------------------------------------------------------------------------
+# Long-double spot mode agrees with the FP64 oracle to FP64 rounding
+# --------------------------------------------------------------------------
+def test_long_double_spot_mode():
+    N, L = 256, 511
+    alm = alm_gaussian(L, [2])
+    rings = [1, 2, 100, 255, 256, 511, 512, 800, 1022]
+    d = oracle.synthesis_rings(L, N, alm, rings)
+    ld = oracle.synthesis_rings(L, N, alm, rings, ld=True)
+    scale = max(np.max(np.abs(x)) for x in ld)
+    for ring, x, y in zip(rings, d, ld):
+        # FP64 recurrence error near a pole grows like L eps / sin(theta)
+        sth = oracle.ring_info(N, ring)[1]
+        tol = 2e-14 + 0.1 * L * 1.1e-16 / sth
+        assert np.max(np.abs(x - y)) <= tol * scale, ring
+    q = oracle.legendre_phase_rings(L, N, alm, rings)
+    qld = oracle.legendre_phase_rings(L, N, alm, rings, ld=True)
+    for k, ring in enumerate(rings):
+        sth = oracle.ring_info(N, ring)[1]
+        tol = 2e-14 + 0.1 * L * 1.1e-16 / sth
+        assert np.max(np.abs(q[k] - qld[k])) <= tol * np.max(np.abs(qld)), ring
+
+
+def test_synthetic_inputs():
+    a = alm_gaussian(63, [1, 2])
+    b = alm_gaussian(63, [1, 2])
+    assert np.array_equal(a, b) and a.shape == (nalm(63), 2)
+    assert np.all(a[:64].imag == 0)
+    assert not np.array_equal(a[:, 0], a[:, 1])
