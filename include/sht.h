@@ -1,0 +1,149 @@
+/*
+ * sht.h -- C ABI of the MI355X (gfx950) scalar spherical harmonic synthesis
+ * library, after D. S. Seljebotn, "Wavemoth -- Fast spherical harmonic
+ * transforms by butterfly matrix compression" (arXiv:1110.4874).
+ *
+ * Problem (Sec. 1 Eq. 1, Sec. 2.1 Eq. 2): given coefficients a_lm of a real
+ * field (a_{l,-m} = (-1)^m conj(a_lm), so only m >= 0 is stored), band limit
+ * L, evaluate f = sum_{l<=L} sum_{|m|<=l} a_lm Y_lm at the pixel centres of a
+ * HEALPix grid with resolution nside (12 nside^2 pixels on 4 nside - 1
+ * iso-latitude rings, RING order).  The transform is computed as in Sec. 2.3
+ * and 2.4: per-m Legendre phases q_m(z_k) on the rings (Eq. 12, using the
+ * even/odd ring symmetry of Eqs. 13-14), then one real backward FFT per ring
+ * after phase shift and wrap (Eqs. 8-11).
+ *
+ * Conventions shared by every entry point
+ *   - All functions are extern "C", never throw and never abort.  They
+ *     return an sht_status (0 on success); sht_last_error() gives a
+ *     thread-local message for the last failure on the calling thread.
+ *   - Array arguments named alm, map, q, workspace are DEVICE pointers
+ *     (memory of the GPU the plan was built on).  Host pointers are rejected
+ *     with SHT_EINVAL before anything is launched.  The caller owns them.
+ *   - alm layout: complex128 (re, im) pairs, m-major with l ascending inside
+ *     each m and the nmaps maps interleaved (Sec. A.3):
+ *         alm[2*((off(m) + l - m)*nmaps + b) + {0,1}],  off(m) = m(2L+3-m)/2.
+ *     Im a_l0 is ignored by synthesis (real field).
+ *   - map layout: float64, stacked maps, RING order: map[b*Npix + p].
+ *     (The paper interleaves output maps; stacked maps are kept here so that
+ *     each ring is one contiguous, coalesced run per map.)
+ *   - q layout (Legendre phase): complex128, m-major then ring then map:
+ *         q[2*((m*nrings + k)*nmaps + b) + {0,1}],  ring k = 0..4nside-2
+ *     (k = 0 is the northernmost ring).
+ *   - Work is enqueued on the stream given in sht_exec_opts (NULL = the
+ *     default stream) and is asynchronous with respect to the host.  Errors
+ *     raised by the device are reported by a later call.
+ */
+#ifndef SHT_H
+#define SHT_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sht_plan_s sht_plan_t;
+
+typedef enum {
+    SHT_OK = 0,
+    SHT_EINVAL = -1,       /* bad argument (range, null, host pointer, layout) */
+    SHT_ENOMEM = -2,       /* host or device allocation failed, or workspace too small */
+    SHT_EDEVICE = -3,      /* HIP runtime error, or a host-only plan used for compute */
+    SHT_ECORRUPT = -4,     /* reserved: unreadable serialised plan */
+    SHT_EUNSUPPORTED = -5  /* valid request outside what this build supports */
+} sht_status;
+
+enum { SHT_PATH_AUTO = 0, SHT_PATH_BRUTE = 1 };
+
+/* Options for building a plan.  Fill with sht_plan_opts_default() first. */
+typedef struct sht_plan_opts {
+    double cutoff;     /* Legendre values below this magnitude at the start of
+                          each l-chain are skipped (App. A.2: 1e-30). */
+    double dd_sin;     /* rings with sin(theta) below this threshold run the
+                          recurrence in compensated double-double arithmetic;
+                          < 0 selects the default 0.1 * L / 4095.  FP64
+                          recurrences lose ~L eps / sin(theta) near the poles. */
+    int nthreads;      /* host threads for plan construction; 0 = all cores */
+    int host_only;     /* 1: build host tables only (no device memory); such a
+                          plan can be inspected but not executed */
+} sht_plan_opts;
+
+/* Options for one execution.  Fill with sht_exec_opts_default() first. */
+typedef struct sht_exec_opts {
+    int nmaps;                /* number of maps B >= 1 transformed together */
+    int path;                 /* SHT_PATH_* */
+    void *stream;             /* hipStream_t, NULL = default stream */
+    void *workspace;          /* device scratch of >= sht_workspace_bytes(), or
+                                 NULL to let the call allocate (stream ordered) */
+    size_t workspace_bytes;
+} sht_exec_opts;
+
+/* Statistics of a plan. */
+typedef struct sht_plan_info {
+    int L, nside, nrings, n_dd_rings;
+    double eps;
+    long long n_step;         /* (l, ring) recurrence steps per map-independent
+                                 pass over the north rings, both parities,
+                                 after the cutoff skip: the brute-force
+                                 Legendre work unit */
+    long long n_step_dd;      /* of which in compensated-arithmetic ring blocks */
+    size_t device_bytes;      /* device memory held by the plan */
+    double build_seconds;     /* wall time of sht_plan */
+} sht_plan_info_t;
+
+void sht_plan_opts_default(sht_plan_opts *o);
+void sht_exec_opts_default(sht_exec_opts *o);
+
+/* Build a plan for band limit L >= 0 on a HEALPix grid of resolution
+ * 1 <= nside <= 2048, on the current HIP device.  eps = 0 selects the
+ * brute-force Legendre transform (the only path of this build; eps > 0 is
+ * rejected with SHT_EUNSUPPORTED).  The plan holds the ring geometry, the
+ * two-step recurrence coefficients of App. A.2 Eq. A2 and, per (m, parity,
+ * ring), the first Legendre values above the cutoff (App. A.2).
+ * Returns NULL on failure (see sht_last_error).  The plan is immutable and
+ * may be shared by threads; free it with sht_plan_free. */
+sht_plan_t *sht_plan(int L, int nside, double eps);
+sht_plan_t *sht_plan_ex(int L, int nside, double eps, const sht_plan_opts *opts);
+void sht_plan_free(sht_plan_t *plan);
+int sht_plan_info(const sht_plan_t *plan, sht_plan_info_t *out);
+
+/* Device scratch needed by one execution with these options (the Legendre
+ * phase buffer, nmaps * (L+1) * nrings complex values). */
+size_t sht_workspace_bytes(const sht_plan_t *plan, const sht_exec_opts *x);
+
+/* Synthesis f = Y a for one map (sht_synthesis) or x->nmaps maps. */
+int sht_synthesis(const sht_plan_t *plan, const double *alm, double *map);
+int sht_synthesis_ex(const sht_plan_t *plan, const sht_exec_opts *x,
+                     const double *alm, double *map);
+
+const char *sht_last_error(void);
+
+/* ---- private test API (the paper's unit-test entry points, Sec. 4.1) ---- */
+
+/* Legendre phase only: q_m(z_k) for every m and ring (Sec. 2.4 Eq. 12),
+ * written to q in the layout above. */
+int sht_debug_legendre_phase(const sht_plan_t *plan, const sht_exec_opts *x,
+                             const double *alm, double *q);
+
+/* Ring stage only: phase shift, wrap and real backward FFT per ring
+ * (Sec. 2.3 Eqs. 8-11) from a given q to the map. */
+int sht_debug_ring_synthesis(const sht_plan_t *plan, const sht_exec_opts *x,
+                             const double *q, double *map);
+
+/* Host-side tables (valid also for host_only plans), copied to host memory:
+ *   coef: for order m, (L - m + 1) entries of (beta_l, alpha_l*beta_l,
+ *         gamma_l) of the two-step recurrence
+ *         P_{l+2} = (z^2 + alpha_l) beta_l P_l + gamma_l P_{l-2}
+ *         (App. A.2 Eq. A2), l = m..L, rounded to double.
+ *   start: for order m, parity t and north ring k (0 <= k < 2 nside):
+ *         *idx = first chain index i (l = m + t + 2i) held in the table,
+ *         rounded down to the kernel's chunk (or >= chain length if the
+ *         whole chain stays below the cutoff), vals[0..1] = P at i, i+1. */
+int sht_debug_coef(const sht_plan_t *plan, int m, double *coef_out);
+int sht_debug_start(const sht_plan_t *plan, int m, int t, int k, int *idx,
+                    double *vals);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SHT_H */

@@ -1,0 +1,291 @@
+// C ABI entry points (include/sht.h): argument checking, workspace
+// management and the launch sequence of each transform.
+#include <chrono>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+
+namespace sht {
+const char *last_error();
+}
+
+using namespace sht;
+
+namespace {
+
+struct DeviceGuard {  // make the plan's device current for the call
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+// The pointer must be device memory of `dev` with at least `bytes` bytes
+// left in its allocation; checked before any kernel may touch it.
+int check_dev_ptr(const void *ptr, size_t bytes, int dev, const char *name) {
+    if (!ptr) return fail(SHT_EINVAL, std::string(name) + " is NULL");
+    hipPointerAttribute_t at;
+    std::memset(&at, 0, sizeof(at));
+    if (hipPointerGetAttributes(&at, ptr) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SHT_EINVAL, std::string(name) + " is not a device pointer");
+    }
+    if (at.type != hipMemoryTypeDevice)
+        return fail(SHT_EINVAL, std::string(name) + " is not device memory");
+    if (at.device != dev)
+        return fail(SHT_EINVAL, std::string(name) + " lives on another device than the plan");
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    if (hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)ptr) == hipSuccess && base) {
+        size_t used = (size_t)((const char *)ptr - (const char *)base);
+        if (used > size || size - used < bytes)
+            return fail(SHT_EINVAL, std::string(name) + " is smaller than the transform needs");
+    } else {
+        (void)hipGetLastError();
+    }
+    if (((uintptr_t)ptr & 15) != 0) return fail(SHT_EINVAL, std::string(name) + " is not 16-byte aligned");
+    return SHT_OK;
+}
+
+int check_plan(const sht_plan_t *p) {
+    if (!p) return fail(SHT_EINVAL, "plan is NULL");
+    if (p->device < 0) return fail(SHT_EDEVICE, "host-only plan cannot execute transforms");
+    return SHT_OK;
+}
+
+size_t nalm_of(int L) { return (size_t)(L + 1) * (L + 2) / 2; }
+size_t npix_of(int N) { return 12ull * N * N; }
+size_t q_bytes(const sht_plan_t *p, int B) { return (size_t)(p->L + 1) * p->nrings * B * 16; }
+
+int check_exec(const sht_plan_t *p, const sht_exec_opts *x) {
+    if (!x) return fail(SHT_EINVAL, "exec opts is NULL");
+    if (x->nmaps < 1) return fail(SHT_EINVAL, "nmaps must be >= 1");
+    if (x->path != SHT_PATH_AUTO && x->path != SHT_PATH_BRUTE)
+        return fail(SHT_EUNSUPPORTED, "only the brute-force path is available");
+    (void)p;
+    return SHT_OK;
+}
+
+// Stream-ordered scratch: the caller's workspace or a temporary allocation.
+struct Scratch {
+    void *ptr = nullptr;
+    bool owned = false;
+    hipStream_t st = nullptr;
+    int get(const sht_exec_opts *x, size_t bytes, int dev) {
+        st = (hipStream_t)x->stream;
+        if (x->workspace) {
+            if (x->workspace_bytes < bytes)
+                return fail(SHT_ENOMEM, "workspace smaller than sht_workspace_bytes()");
+            int rc = check_dev_ptr(x->workspace, bytes, dev, "workspace");
+            if (rc) return rc;
+            ptr = x->workspace;
+            return SHT_OK;
+        }
+        hipError_t e = hipMallocAsync(&ptr, bytes, st);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            ptr = nullptr;
+            return fail(SHT_ENOMEM, std::string("workspace allocation: ") + hipGetErrorString(e));
+        }
+        owned = true;
+        return SHT_OK;
+    }
+    ~Scratch() {
+        if (owned && ptr) (void)hipFreeAsync(ptr, st);
+    }
+};
+
+int hip_status(hipError_t e, const char *what) {
+    if (e == hipSuccess) return SHT_OK;
+    return fail(SHT_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+}  // namespace
+
+extern "C" {
+
+void sht_plan_opts_default(sht_plan_opts *o) {
+    if (!o) return;
+    o->cutoff = 1e-30;
+    o->dd_sin = -1.0;
+    o->nthreads = 0;
+    o->host_only = 0;
+}
+
+void sht_exec_opts_default(sht_exec_opts *o) {
+    if (!o) return;
+    o->nmaps = 1;
+    o->path = SHT_PATH_AUTO;
+    o->stream = nullptr;
+    o->workspace = nullptr;
+    o->workspace_bytes = 0;
+}
+
+const char *sht_last_error(void) { return sht::last_error(); }
+
+sht_plan_t *sht_plan(int L, int nside, double eps) { return sht_plan_ex(L, nside, eps, nullptr); }
+
+sht_plan_t *sht_plan_ex(int L, int nside, double eps, const sht_plan_opts *opts) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (L < 0 || L > 16383) {
+        fail(SHT_EINVAL, "L must be in [0, 16383]");
+        return nullptr;
+    }
+    if (nside < 1 || nside > 2048) {
+        fail(nside < 1 ? SHT_EINVAL : SHT_EUNSUPPORTED, "nside must be in [1, 2048]");
+        return nullptr;
+    }
+    if (!(eps >= 0.0)) {
+        fail(SHT_EINVAL, "eps must be >= 0");
+        return nullptr;
+    }
+    if (eps > 0.0) {
+        fail(SHT_EUNSUPPORTED, "butterfly compression (eps > 0) is not available in this build");
+        return nullptr;
+    }
+    sht_plan_opts o;
+    sht_plan_opts_default(&o);
+    if (opts) o = *opts;
+    if (!(o.cutoff > 0.0) || o.cutoff > 1e-10) {
+        fail(SHT_EINVAL, "cutoff must be in (0, 1e-10]");
+        return nullptr;
+    }
+    sht_plan_s *p = new (std::nothrow) sht_plan_s();
+    if (!p) {
+        fail(SHT_ENOMEM, "out of host memory");
+        return nullptr;
+    }
+    p->L = L;
+    p->nside = nside;
+    p->eps = eps;
+    p->opts = o;
+    int rc;
+    try {
+        rc = build_host_tables(p);
+    } catch (const std::bad_alloc &) {
+        rc = fail(SHT_ENOMEM, "out of host memory while building the plan");
+    }
+    if (rc != SHT_OK) {
+        delete p;
+        return nullptr;
+    }
+    if (!o.host_only) {
+        int dev = -1;
+        if (hipGetDevice(&dev) != hipSuccess || dev < 0) {
+            (void)hipGetLastError();
+            fail(SHT_EDEVICE, "no HIP device available");
+            delete p;
+            return nullptr;
+        }
+        p->device = dev;
+        if (upload_tables(p) != SHT_OK) {
+            delete p;
+            return nullptr;
+        }
+    }
+    p->build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return p;
+}
+
+void sht_plan_free(sht_plan_t *p) {
+    if (!p) return;
+    if (p->device >= 0) {
+        DeviceGuard g(p->device);
+        free_device_tables(p);
+    }
+    delete p;
+}
+
+int sht_plan_info(const sht_plan_t *p, sht_plan_info_t *out) {
+    if (!p || !out) return fail(SHT_EINVAL, "NULL argument");
+    std::memset(out, 0, sizeof(*out));
+    out->L = p->L;
+    out->nside = p->nside;
+    out->nrings = p->nrings;
+    out->n_dd_rings = p->n_dd_rings;
+    out->eps = p->eps;
+    out->n_step = p->n_step;
+    out->n_step_dd = p->n_step_dd;
+    out->device_bytes = p->device_bytes;
+    out->build_seconds = p->build_seconds;
+    return SHT_OK;
+}
+
+size_t sht_workspace_bytes(const sht_plan_t *p, const sht_exec_opts *x) {
+    if (!p || !x || x->nmaps < 1) return 0;
+    return q_bytes(p, x->nmaps);
+}
+
+int sht_synthesis(const sht_plan_t *p, const double *alm, double *map) {
+    sht_exec_opts x;
+    sht_exec_opts_default(&x);
+    return sht_synthesis_ex(p, &x, alm, map);
+}
+
+int sht_synthesis_ex(const sht_plan_t *p, const sht_exec_opts *x, const double *alm, double *map) {
+    int rc = check_plan(p);
+    if (!rc) rc = check_exec(p, x);
+    if (rc) return rc;
+    DeviceGuard g(p->device);
+    if (!g.ok) return fail(SHT_EDEVICE, "cannot select the plan's device");
+    const int B = x->nmaps;
+    if ((rc = check_dev_ptr(alm, nalm_of(p->L) * B * 16, p->device, "alm"))) return rc;
+    if ((rc = check_dev_ptr(map, npix_of(p->nside) * B * 8, p->device, "map"))) return rc;
+    Scratch ws;
+    if ((rc = ws.get(x, q_bytes(p, B), p->device))) return rc;
+    hipStream_t st = (hipStream_t)x->stream;
+    double *q = (double *)ws.ptr;
+    if ((rc = hip_status(launch_legendre(p, B, alm, q, st), "Legendre kernel launch"))) return rc;
+    return hip_status(launch_ring_synthesis(p, B, q, map, st), "ring kernel launch");
+}
+
+int sht_debug_legendre_phase(const sht_plan_t *p, const sht_exec_opts *x, const double *alm, double *q) {
+    int rc = check_plan(p);
+    if (!rc) rc = check_exec(p, x);
+    if (rc) return rc;
+    DeviceGuard g(p->device);
+    const int B = x->nmaps;
+    if ((rc = check_dev_ptr(alm, nalm_of(p->L) * B * 16, p->device, "alm"))) return rc;
+    if ((rc = check_dev_ptr(q, q_bytes(p, B), p->device, "q"))) return rc;
+    return hip_status(launch_legendre(p, B, alm, q, (hipStream_t)x->stream), "Legendre kernel launch");
+}
+
+int sht_debug_ring_synthesis(const sht_plan_t *p, const sht_exec_opts *x, const double *q, double *map) {
+    int rc = check_plan(p);
+    if (!rc) rc = check_exec(p, x);
+    if (rc) return rc;
+    DeviceGuard g(p->device);
+    const int B = x->nmaps;
+    if ((rc = check_dev_ptr(q, q_bytes(p, B), p->device, "q"))) return rc;
+    if ((rc = check_dev_ptr(map, npix_of(p->nside) * B * 8, p->device, "map"))) return rc;
+    return hip_status(launch_ring_synthesis(p, B, q, map, (hipStream_t)x->stream), "ring kernel launch");
+}
+
+int sht_debug_coef(const sht_plan_t *p, int m, double *out) {
+    if (!p || !out) return fail(SHT_EINVAL, "NULL argument");
+    if (m < 0 || m > p->L) return fail(SHT_EINVAL, "m out of range");
+    long long base = p->coef_off[m];
+    for (int e = 0; e <= p->L - m; e++)
+        for (int j = 0; j < 3; j++) out[3 * e + j] = p->coef_hi[4 * (base + e) + j];
+    return SHT_OK;
+}
+
+int sht_debug_start(const sht_plan_t *p, int m, int t, int k, int *idx, double *vals) {
+    if (!p || !idx || !vals) return fail(SHT_EINVAL, "NULL argument");
+    if (m < 0 || m > p->L || t < 0 || t > 1 || k < 0 || k >= p->n_north)
+        return fail(SHT_EINVAL, "index out of range");
+    size_t row = (size_t)(2 * m + t);
+    *idx = p->start_idx[row * p->n_north_pad + k];
+    vals[0] = p->start_val[(row * 2 + 0) * p->n_north_pad + k];
+    vals[1] = p->start_val[(row * 2 + 1) * p->n_north_pad + k];
+    return SHT_OK;
+}
+
+}  // extern "C"

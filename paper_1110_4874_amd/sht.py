@@ -1,0 +1,208 @@
+"""ctypes binding of libsht.so (the C ABI in include/sht.h).
+
+Argument marshalling only: every step of the transform runs in the HIP
+kernels of the library.  Torch provides device memory and streams.  If the
+library has not been built this module raises instead of falling back to
+anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # imported first so that the library shares torch's HIP runtime
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsht.so")
+
+SHT_OK, SHT_EINVAL, SHT_ENOMEM, SHT_EDEVICE, SHT_ECORRUPT, SHT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+PATH_AUTO, PATH_BRUTE = 0, 1
+
+_c = ctypes
+_lib = None
+
+
+class PlanOpts(_c.Structure):
+    _fields_ = [("cutoff", _c.c_double), ("dd_sin", _c.c_double), ("nthreads", _c.c_int),
+                ("host_only", _c.c_int)]
+
+
+class ExecOpts(_c.Structure):
+    _fields_ = [("nmaps", _c.c_int), ("path", _c.c_int), ("stream", _c.c_void_p),
+                ("workspace", _c.c_void_p), ("workspace_bytes", _c.c_size_t)]
+
+
+class PlanInfo(_c.Structure):
+    _fields_ = [("L", _c.c_int), ("nside", _c.c_int), ("nrings", _c.c_int), ("n_dd_rings", _c.c_int),
+                ("eps", _c.c_double), ("n_step", _c.c_longlong), ("n_step_dd", _c.c_longlong),
+                ("device_bytes", _c.c_size_t), ("build_seconds", _c.c_double)]
+
+
+EXPORTS = {
+    "sht_plan_opts_default": (None, [_c.POINTER(PlanOpts)]),
+    "sht_exec_opts_default": (None, [_c.POINTER(ExecOpts)]),
+    "sht_plan": (_c.c_void_p, [_c.c_int, _c.c_int, _c.c_double]),
+    "sht_plan_ex": (_c.c_void_p, [_c.c_int, _c.c_int, _c.c_double, _c.POINTER(PlanOpts)]),
+    "sht_plan_free": (None, [_c.c_void_p]),
+    "sht_plan_info": (_c.c_int, [_c.c_void_p, _c.POINTER(PlanInfo)]),
+    "sht_workspace_bytes": (_c.c_size_t, [_c.c_void_p, _c.POINTER(ExecOpts)]),
+    "sht_synthesis": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p]),
+    "sht_synthesis_ex": (_c.c_int, [_c.c_void_p, _c.POINTER(ExecOpts), _c.c_void_p, _c.c_void_p]),
+    "sht_last_error": (_c.c_char_p, []),
+    "sht_debug_legendre_phase": (_c.c_int, [_c.c_void_p, _c.POINTER(ExecOpts), _c.c_void_p, _c.c_void_p]),
+    "sht_debug_ring_synthesis": (_c.c_int, [_c.c_void_p, _c.POINTER(ExecOpts), _c.c_void_p, _c.c_void_p]),
+    "sht_debug_coef": (_c.c_int, [_c.c_void_p, _c.c_int, _c.POINTER(_c.c_double)]),
+    "sht_debug_start": (_c.c_int, [_c.c_void_p, _c.c_int, _c.c_int, _c.c_int, _c.POINTER(_c.c_int),
+                                   _c.POINTER(_c.c_double)]),
+}
+
+
+class ShtError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"sht error {code}: {msg}")
+        self.code = code
+
+
+def load():
+    """Load libsht.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1110_4874_amd.build`")
+        lib = _c.CDLL(LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(rc):
+    if rc != SHT_OK:
+        raise ShtError(rc, load().sht_last_error().decode())
+
+
+def nalm(L):
+    return (L + 1) * (L + 2) // 2
+
+
+def _stream_handle(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return _c.c_void_p(s.cuda_stream)
+
+
+class Plan:
+    """A transform plan for band limit L on a HEALPix grid of resolution nside."""
+
+    def __init__(self, L, nside, eps=0.0, *, cutoff=None, dd_sin=None, nthreads=0, host_only=False):
+        lib = load()
+        o = PlanOpts()
+        lib.sht_plan_opts_default(_c.byref(o))
+        if cutoff is not None:
+            o.cutoff = cutoff
+        if dd_sin is not None:
+            o.dd_sin = dd_sin
+        o.nthreads = nthreads
+        o.host_only = 1 if host_only else 0
+        if not host_only:
+            torch.cuda.init()
+        h = lib.sht_plan_ex(int(L), int(nside), float(eps), _c.byref(o))
+        if not h:
+            raise ShtError(-1, lib.sht_last_error().decode())
+        self._h = _c.c_void_p(h)
+        self.L, self.nside, self.eps = int(L), int(nside), float(eps)
+        self.nrings = 4 * self.nside - 1
+        self.npix = 12 * self.nside * self.nside
+        self.nalm = nalm(self.L)
+        self.host_only = host_only
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().sht_plan_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        inf = PlanInfo()
+        _check(load().sht_plan_info(self._h, _c.byref(inf)))
+        return {f: getattr(inf, f) for f, _ in PlanInfo._fields_}
+
+    # ---- execution ----------------------------------------------------
+    def _exec(self, nmaps, path=PATH_AUTO, stream=None, workspace=None):
+        x = ExecOpts()
+        load().sht_exec_opts_default(_c.byref(x))
+        x.nmaps = int(nmaps)
+        x.path = int(path)
+        x.stream = _stream_handle(stream)
+        if workspace is not None:
+            x.workspace = _c.c_void_p(workspace.data_ptr())
+            x.workspace_bytes = workspace.numel() * workspace.element_size()
+        return x
+
+    def workspace_bytes(self, nmaps=1):
+        x = self._exec(nmaps)
+        return int(load().sht_workspace_bytes(self._h, _c.byref(x)))
+
+    def workspace(self, nmaps=1, device="cuda"):
+        return torch.empty(self.workspace_bytes(nmaps), dtype=torch.uint8, device=device)
+
+    def _alm_arg(self, alm):
+        if alm.dtype != torch.complex128 or not alm.is_cuda:
+            raise TypeError("alm must be a complex128 CUDA tensor")
+        a = alm if alm.dim() == 2 else alm.reshape(-1, 1)
+        if a.shape[0] != self.nalm:
+            raise ValueError(f"alm has {a.shape[0]} rows, expected nalm = {self.nalm}")
+        return a.contiguous()
+
+    def synthesis(self, alm, out=None, *, path=PATH_AUTO, stream=None, workspace=None):
+        """maps (B, Npix) float64 from alm (nalm, B) or (nalm,) complex128."""
+        a = self._alm_arg(alm)
+        B = a.shape[1]
+        if out is None:
+            out = torch.empty((B, self.npix), dtype=torch.float64, device=a.device)
+        if workspace is None:
+            workspace = self.workspace(B, a.device)
+        x = self._exec(B, path, stream, workspace)
+        _check(load().sht_synthesis_ex(self._h, _c.byref(x), _c.c_void_p(a.data_ptr()),
+                                       _c.c_void_p(out.data_ptr())))
+        return out
+
+    def legendre_phase(self, alm, *, stream=None):
+        """q (L+1, nrings, B) complex128 (private test entry point)."""
+        a = self._alm_arg(alm)
+        B = a.shape[1]
+        q = torch.empty((self.L + 1, self.nrings, B), dtype=torch.complex128, device=a.device)
+        x = self._exec(B, stream=stream)
+        _check(load().sht_debug_legendre_phase(self._h, _c.byref(x), _c.c_void_p(a.data_ptr()),
+                                               _c.c_void_p(q.data_ptr())))
+        return q
+
+    def ring_synthesis(self, q, out=None, *, stream=None):
+        """maps (B, Npix) from q (L+1, nrings, B) complex128 (private test entry point)."""
+        q = q.contiguous()
+        B = q.shape[2]
+        if out is None:
+            out = torch.empty((B, self.npix), dtype=torch.float64, device=q.device)
+        x = self._exec(B, stream=stream)
+        _check(load().sht_debug_ring_synthesis(self._h, _c.byref(x), _c.c_void_p(q.data_ptr()),
+                                               _c.c_void_p(out.data_ptr())))
+        return out
+
+    # ---- host tables ----------------------------------------------------
+    def coef(self, m):
+        buf = (_c.c_double * (3 * (self.L - m + 1)))()
+        _check(load().sht_debug_coef(self._h, int(m), buf))
+        import numpy as np
+        return np.frombuffer(buf, dtype=np.float64).reshape(-1, 3).copy()
+
+    def start(self, m, t, k):
+        idx = _c.c_int()
+        vals = (_c.c_double * 2)()
+        _check(load().sht_debug_start(self._h, int(m), int(t), int(k), _c.byref(idx), vals))
+        return idx.value, (vals[0], vals[1])
