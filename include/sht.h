@@ -55,6 +55,9 @@ typedef enum {
 
 enum { SHT_PATH_AUTO = 0, SHT_PATH_BRUTE = 1 };
 
+/* Stages of a transform, for sht_exec_opts.stage_events. */
+enum { SHT_STAGE_LEGENDRE = 0, SHT_STAGE_RING = 1, SHT_NSTAGES = 2 };
+
 /* Options for building a plan.  Fill with sht_plan_opts_default() first. */
 typedef struct sht_plan_opts {
     double cutoff;     /* Legendre values below this magnitude at the start of
@@ -64,6 +67,10 @@ typedef struct sht_plan_opts {
                           < 0 selects the default 0.1 * L / 4095.  FP64
                           recurrences lose ~L eps / sin(theta) near the poles. */
     int nthreads;      /* host threads for plan construction; 0 = all cores */
+    int rings_per_lane;/* rings each lane of the FP64 Legendre kernel owns:
+                          1, 2 or 4 (0 = default 2); a tuning knob */
+    int ring_threads;  /* workgroup size of the ring FFT kernel: 256, 512 or
+                          1024 (0 = default 1024); a tuning knob */
     int host_only;     /* 1: build host tables only (no device memory); such a
                           plan can be inspected but not executed */
 } sht_plan_opts;
@@ -76,17 +83,25 @@ typedef struct sht_exec_opts {
     void *workspace;          /* device scratch of >= sht_workspace_bytes(), or
                                  NULL to let the call allocate (stream ordered) */
     size_t workspace_bytes;
+    void **stage_events;      /* NULL, or 2*SHT_NSTAGES hipEvent_t handles
+                                 (entries may be NULL): events[2s] is recorded
+                                 on the stream before stage s runs and
+                                 events[2s+1] after it */
 } sht_exec_opts;
 
 /* Statistics of a plan. */
 typedef struct sht_plan_info {
     int L, nside, nrings, n_dd_rings;
     double eps;
-    long long n_step;         /* (l, ring) recurrence steps per map-independent
-                                 pass over the north rings, both parities,
-                                 after the cutoff skip: the brute-force
-                                 Legendre work unit */
-    long long n_step_dd;      /* of which in compensated-arithmetic ring blocks */
+    long long n_step;         /* (l, ring) pairs of the north rings, both
+                                 parities, whose Legendre value is at or above
+                                 the cutoff: the brute-force work unit (each
+                                 costs 5 flops of recurrence + 4 per map) */
+    long long n_step_exec;    /* recurrence steps the kernel executes (chain
+                                 starts rounded down to a chunk boundary) */
+    long long n_step_dd;      /* executed steps in compensated ring blocks */
+    long long n_step_lanes;   /* lane-steps the Legendre kernel issues (idle
+                                 lanes of partially active waves included) */
     size_t device_bytes;      /* device memory held by the plan */
     double build_seconds;     /* wall time of sht_plan */
 } sht_plan_info_t;

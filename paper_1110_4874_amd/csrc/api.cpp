@@ -102,6 +102,13 @@ struct Scratch {
     }
 };
 
+// Record the caller's stage event (before: which = 0, after: which = 1).
+void stage_event(const sht_exec_opts *x, int stage, int which) {
+    if (!x->stage_events) return;
+    void *ev = x->stage_events[2 * stage + which];
+    if (ev) (void)hipEventRecord((hipEvent_t)ev, (hipStream_t)x->stream);
+}
+
 int hip_status(hipError_t e, const char *what) {
     if (e == hipSuccess) return SHT_OK;
     return fail(SHT_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
@@ -116,6 +123,8 @@ void sht_plan_opts_default(sht_plan_opts *o) {
     o->cutoff = 1e-30;
     o->dd_sin = -1.0;
     o->nthreads = 0;
+    o->rings_per_lane = 0;
+    o->ring_threads = 0;
     o->host_only = 0;
 }
 
@@ -126,6 +135,7 @@ void sht_exec_opts_default(sht_exec_opts *o) {
     o->stream = nullptr;
     o->workspace = nullptr;
     o->workspace_bytes = 0;
+    o->stage_events = nullptr;
 }
 
 const char *sht_last_error(void) { return sht::last_error(); }
@@ -212,7 +222,9 @@ int sht_plan_info(const sht_plan_t *p, sht_plan_info_t *out) {
     out->n_dd_rings = p->n_dd_rings;
     out->eps = p->eps;
     out->n_step = p->n_step;
+    out->n_step_exec = p->n_step_exec;
     out->n_step_dd = p->n_step_dd;
+    out->n_step_lanes = p->n_step_lanes;
     out->device_bytes = p->device_bytes;
     out->build_seconds = p->build_seconds;
     return SHT_OK;
@@ -242,8 +254,13 @@ int sht_synthesis_ex(const sht_plan_t *p, const sht_exec_opts *x, const double *
     if ((rc = ws.get(x, q_bytes(p, B), p->device))) return rc;
     hipStream_t st = (hipStream_t)x->stream;
     double *q = (double *)ws.ptr;
+    stage_event(x, SHT_STAGE_LEGENDRE, 0);
     if ((rc = hip_status(launch_legendre(p, B, alm, q, st), "Legendre kernel launch"))) return rc;
-    return hip_status(launch_ring_synthesis(p, B, q, map, st), "ring kernel launch");
+    stage_event(x, SHT_STAGE_LEGENDRE, 1);
+    stage_event(x, SHT_STAGE_RING, 0);
+    rc = hip_status(launch_ring_synthesis(p, B, q, map, st), "ring kernel launch");
+    stage_event(x, SHT_STAGE_RING, 1);
+    return rc;
 }
 
 int sht_debug_legendre_phase(const sht_plan_t *p, const sht_exec_opts *x, const double *alm, double *q) {

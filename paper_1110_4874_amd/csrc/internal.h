@@ -6,6 +6,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -13,19 +14,15 @@
 
 namespace sht {
 
-// Legendre kernel geometry.  A wave (64 lanes) owns kRingsPerLane rings per
-// lane; start indices of every l-chain are rounded down to a multiple of
-// kChunk chain steps so that new lanes only join at chunk boundaries.
+// Legendre kernel geometry.  North rings form groups of 64 (one per lane of
+// a wave); a wave owns R groups (R rings per lane).  Start indices of every
+// l-chain are rounded down to a multiple of kChunk chain steps so that new
+// lanes only join at chunk boundaries.
 constexpr int kLanes = 64;
-constexpr int kRingsPerLane = 2;
-constexpr int kBlockRings = kLanes * kRingsPerLane;
 constexpr int kChunk = 8;
 constexpr int kCoefPad = 2 * kChunk + 8;   // coefficient entries kept past l = L
 constexpr int kDead = 0x3fffffff;          // start index of a chain that never
                                            // reaches the cutoff
-
-// Ring-synthesis kernel: threads per workgroup and LDS classes.
-constexpr int kRingThreads = 256;
 
 void set_error(const std::string &msg);
 int fail(int code, const std::string &msg);
@@ -34,7 +31,8 @@ int fail(int code, const std::string &msg);
 void parallel_for(long n, int nthreads, void (*fn)(long, void *), void *ctx);
 
 struct RingClass {
-    int lds_entries;              // complex entries of the FFT buffer
+    int lds_entries;              // complex entries of the FFT buffer (before padding)
+    bool wrap = false;            // some ring has J/2 <= L (q staged through LDS)
     std::vector<int> rings;       // ring indices (host)
     int *d_rings = nullptr;       // device copy
 };
@@ -58,8 +56,10 @@ struct sht_plan_s {
     std::vector<double> start_val;             // [(L+1)*2][2][n_north_pad]
     std::vector<double> start_lo;              // [(L+1)*2][2][n_dd_pad]
     std::vector<int> grp_lo, grp_hi;           // [(L+1)][n_north_pad/64]
-    int n_dd_rings = 0, n_dd_blocks = 0;
-    long long n_step = 0, n_step_dd = 0;
+    int n_dd_rings = 0, n_dd_groups = 0;
+    int rings_per_lane = 2;                    // R of the FP64 Legendre waves
+    int ring_threads = 1024;                   // workgroup size of the ring kernel
+    long long n_step = 0, n_step_exec = 0, n_step_dd = 0, n_step_lanes = 0;
 
     // ring FFT tables
     int tw_log = 0;                            // twiddle table covers 2^tw_log
@@ -79,6 +79,7 @@ struct sht_plan_s {
     int *d_grp_lo = nullptr, *d_grp_hi = nullptr;
     double *d_tw = nullptr, *d_bs_table = nullptr;
     size_t device_bytes = 0;
+
 };
 
 namespace sht {

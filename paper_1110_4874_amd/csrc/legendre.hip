@@ -4,9 +4,9 @@
 //   q_m(+-z_k) = q^even_m(z_k) +- q^odd_m(z_k),
 //   q^t_m(z)   = sum_i P~_{m+t+2i}^m(z) a_{m+t+2i, m}
 //
-// One wavefront handles one order m and a block of 64 x kRingsPerLane
-// north rings; every lane owns kRingsPerLane rings and runs both parity
-// chains of the two-step recurrence for them.  The recurrence coefficients
+// One wavefront handles one order m and a block of 64 x R north rings;
+// every lane owns R rings (R = 1, 2 or 4, a plan parameter) and runs both
+// parity chains of the two-step recurrence for them.  The recurrence coefficients
 // and the a_lm of the current l are the same for every lane, so they are
 // read as wave-uniform (scalar) loads and used straight from SGPRs; P~ never
 // leaves VGPRs (the GPU form of the paper's register-resident SSE kernel).
@@ -37,7 +37,8 @@ struct LegArgs {
     double *__restrict__ q;
     int L, nrings, n_north, np, n_dd_pad, ng;
     int nmaps, map0;  // map stride of alm/q and first map of this pass
-    int rb0, nrb;     // ring blocks covered by this launch
+    int dd_groups;    // 64-ring groups run in double-double (from the pole)
+    int fp_blocks;    // FP64 ring blocks of R groups after them
 };
 
 // ---- double-double helpers (error-free transformations) --------------
@@ -71,31 +72,32 @@ __device__ __forceinline__ dd dd_add(dd a, dd b) {
 }
 #pragma clang fp contract(on)
 
-template <int NB, bool DD>
-__global__ __launch_bounds__(64) void k_legendre(LegArgs a) {
-    constexpr int R = kRingsPerLane;
-    const int blk = blockIdx.x;
-    const int m = blk / a.nrb;
-    const int rb = a.rb0 + blk % a.nrb;
+// One wave: order m, rings of the 64-ring groups g0 .. g0+R-1 (R per lane).
+// Groups at or past a.ng do not exist (partial last block) and are skipped.
+template <int NB, int R, bool DD>
+__device__ __forceinline__ void legendre_wave(const LegArgs &a, const int m, const int g0) {
     const int lane = threadIdx.x;
     const int L = a.L;
 
     int k[R];
+    bool gv[R];
 #pragma unroll
-    for (int r = 0; r < R; r++) k[r] = rb * kBlockRings + r * kLanes + lane;
+    for (int r = 0; r < R; r++) {
+        gv[r] = g0 + r < a.ng;
+        k[r] = (g0 + r) * kLanes + lane;
+    }
 
     // wave-uniform chain range of this block
     int lo = kDead, hi = -1;
 #pragma unroll
     for (int r = 0; r < R; r++) {
-        int g = rb * R + r;
-        lo = min(lo, a.grp_lo[(size_t)m * a.ng + g]);
-        hi = max(hi, a.grp_hi[(size_t)m * a.ng + g]);
+        if (!gv[r]) continue;
+        lo = min(lo, a.grp_lo[(size_t)m * a.ng + g0 + r]);
+        hi = max(hi, a.grp_hi[(size_t)m * a.ng + g0 + r]);
     }
     const int n0 = (L - m) / 2 + 1;                    // even chain length
     const int n1 = (L - m >= 1) ? (L - m - 1) / 2 + 1 : 0;  // odd chain length
 
-    double ae_r[NB], ae_i[NB], ao_r[NB], ao_i[NB];
     double accE_r[R][NB], accE_i[R][NB], accO_r[R][NB], accO_i[R][NB];
 #pragma unroll
     for (int r = 0; r < R; r++)
@@ -108,16 +110,17 @@ __global__ __launch_bounds__(64) void k_legendre(LegArgs a) {
         dd st0[R][2], st1[R][2], p0[R][2], p1[R][2];
 #pragma unroll
         for (int r = 0; r < R; r++) {
-            z2h[r] = a.z2_hi[k[r]];
-            z2l[r] = DD ? a.z2_lo[k[r]] : 0.0;
+            const int kk = gv[r] ? k[r] : 0;
+            z2h[r] = a.z2_hi[kk];
+            z2l[r] = DD ? a.z2_lo[kk] : 0.0;
 #pragma unroll
             for (int t = 0; t < 2; t++) {
                 size_t row = (size_t)(2 * m + t);
-                sid[r][t] = a.start_idx[row * a.np + k[r]];
-                st0[r][t].h = a.start_val[(row * 2 + 0) * a.np + k[r]];
-                st1[r][t].h = a.start_val[(row * 2 + 1) * a.np + k[r]];
-                st0[r][t].l = DD ? a.start_lo[(row * 2 + 0) * a.n_dd_pad + k[r]] : 0.0;
-                st1[r][t].l = DD ? a.start_lo[(row * 2 + 1) * a.n_dd_pad + k[r]] : 0.0;
+                sid[r][t] = gv[r] ? a.start_idx[row * a.np + kk] : kDead;
+                st0[r][t].h = a.start_val[(row * 2 + 0) * a.np + kk];
+                st1[r][t].h = a.start_val[(row * 2 + 1) * a.np + kk];
+                st0[r][t].l = DD ? a.start_lo[(row * 2 + 0) * a.n_dd_pad + kk] : 0.0;
+                st1[r][t].l = DD ? a.start_lo[(row * 2 + 1) * a.n_dd_pad + kk] : 0.0;
                 p0[r][t] = {0.0, 0.0};
                 p1[r][t] = {0.0, 0.0};
             }
@@ -140,34 +143,51 @@ __global__ __launch_bounds__(64) void k_legendre(LegArgs a) {
                     }
         };
 
-        // one chain step i for both parities: accumulate P(i) a_l, advance
-        auto step = [&](int i, bool odd_ok) {
-            const double *ce = ch + 4 * (2 * i + 2);  // l = m + 2i + 2 (even), next entry odd
-            const double be = ce[0], abe = ce[1], ge = ce[2];
-            const double bo = ce[4], abo = ce[5], go = ce[6];
+        // operands of chain step i (the same for every lane: scalar loads)
+        struct Ops {
+            double be, abe, ge, bo, abo, go;
+            double er[NB], ei[NB], orr[NB], oi[NB];
+        };
+        auto load_ops = [&](int i, bool odd_ok) {
+            Ops o;
+            // entries l = m + 2i + 2 (even chain) and the next one (odd chain)
+            const double4 *ce = reinterpret_cast<const double4 *>(ch) + (2 * i + 2);
+            const double4 e4 = ce[0], o4 = ce[1];
+            o.be = e4.x;
+            o.abe = e4.y;
+            o.ge = e4.z;
+            o.bo = o4.x;
+            o.abo = o4.y;
+            o.go = o4.z;
             const double *ape = al + (size_t)(2 * i) * astride;
 #pragma unroll
             for (int b = 0; b < NB; b++) {
-                ae_r[b] = ape[2 * b];
-                ae_i[b] = ape[2 * b + 1];
-                ao_r[b] = odd_ok ? ape[astride + 2 * b] : 0.0;
-                ao_i[b] = odd_ok ? ape[astride + 2 * b + 1] : 0.0;
+                o.er[b] = ape[2 * b];
+                o.ei[b] = ape[2 * b + 1];
+                o.orr[b] = odd_ok ? ape[astride + 2 * b] : 0.0;
+                o.oi[b] = odd_ok ? ape[astride + 2 * b + 1] : 0.0;
             }
+            return o;
+        };
+
+        // one chain step i for both parities: accumulate P(i) a_l, advance
+        auto compute = [&](const Ops &o, int i) {
             if constexpr (!DD) {
+                (void)i;
 #pragma unroll
                 for (int r = 0; r < R; r++) {
                     const double pe = p0[r][0].h, po = p0[r][1].h;
 #pragma unroll
                     for (int b = 0; b < NB; b++) {
-                        accE_r[r][b] = __builtin_fma(pe, ae_r[b], accE_r[r][b]);
-                        accE_i[r][b] = __builtin_fma(pe, ae_i[b], accE_i[r][b]);
-                        accO_r[r][b] = __builtin_fma(po, ao_r[b], accO_r[r][b]);
-                        accO_i[r][b] = __builtin_fma(po, ao_i[b], accO_i[r][b]);
+                        accE_r[r][b] = __builtin_fma(pe, o.er[b], accE_r[r][b]);
+                        accE_i[r][b] = __builtin_fma(pe, o.ei[b], accE_i[r][b]);
+                        accO_r[r][b] = __builtin_fma(po, o.orr[b], accO_r[r][b]);
+                        accO_i[r][b] = __builtin_fma(po, o.oi[b], accO_i[r][b]);
                     }
-                    const double Ae = __builtin_fma(z2h[r], be, abe);
-                    const double Ao = __builtin_fma(z2h[r], bo, abo);
-                    const double ne = __builtin_fma(Ae, p1[r][0].h, ge * pe);
-                    const double no = __builtin_fma(Ao, p1[r][1].h, go * po);
+                    const double Ae = __builtin_fma(z2h[r], o.be, o.abe);
+                    const double Ao = __builtin_fma(z2h[r], o.bo, o.abo);
+                    const double ne = __builtin_fma(Ae, p1[r][0].h, o.ge * pe);
+                    const double no = __builtin_fma(Ao, p1[r][1].h, o.go * po);
                     p0[r][0].h = p1[r][0].h;
                     p1[r][0].h = ne;
                     p0[r][1].h = p1[r][1].h;
@@ -175,17 +195,17 @@ __global__ __launch_bounds__(64) void k_legendre(LegArgs a) {
                 }
             } else {
                 const double *cle = cl + 4 * (2 * i + 2);
-                const dd Be = {be, cle[0]}, ABe = {abe, cle[1]}, Ge = {ge, cle[2]};
-                const dd Bo = {bo, cle[4]}, ABo = {abo, cle[5]}, Go = {go, cle[6]};
+                const dd Be = {o.be, cle[0]}, ABe = {o.abe, cle[1]}, Ge = {o.ge, cle[2]};
+                const dd Bo = {o.bo, cle[4]}, ABo = {o.abo, cle[5]}, Go = {o.go, cle[6]};
 #pragma unroll
                 for (int r = 0; r < R; r++) {
                     const double pe = p0[r][0].h, po = p0[r][1].h;
 #pragma unroll
                     for (int b = 0; b < NB; b++) {
-                        accE_r[r][b] = __builtin_fma(pe, ae_r[b], accE_r[r][b]);
-                        accE_i[r][b] = __builtin_fma(pe, ae_i[b], accE_i[r][b]);
-                        accO_r[r][b] = __builtin_fma(po, ao_r[b], accO_r[r][b]);
-                        accO_i[r][b] = __builtin_fma(po, ao_i[b], accO_i[r][b]);
+                        accE_r[r][b] = __builtin_fma(pe, o.er[b], accE_r[r][b]);
+                        accE_i[r][b] = __builtin_fma(pe, o.ei[b], accE_i[r][b]);
+                        accO_r[r][b] = __builtin_fma(po, o.orr[b], accO_r[r][b]);
+                        accO_i[r][b] = __builtin_fma(po, o.oi[b], accO_i[r][b]);
                     }
                     const dd z2 = {z2h[r], z2l[r]};
                     const dd Ae = dd_add(dd_mul(z2, Be), ABe);
@@ -206,7 +226,7 @@ __global__ __launch_bounds__(64) void k_legendre(LegArgs a) {
         for (; c < c_full; c += kChunk) {
             if (c <= hi) inject(c);
 #pragma unroll
-            for (int u = 0; u < kChunk; u++) step(c + u, true);
+            for (int u = 0; u < kChunk; u++) compute(load_ops(c + u, true), c + u);
         }
         // tail: the odd chain may end first
         for (; c < n0; c += kChunk) {
@@ -214,7 +234,7 @@ __global__ __launch_bounds__(64) void k_legendre(LegArgs a) {
             for (int u = 0; u < kChunk; u++) {
                 int i = c + u;
                 if (i >= n0) break;
-                step(i, i < n1);
+                compute(load_ops(i, i < n1), i);
             }
         }
     }
@@ -222,7 +242,7 @@ __global__ __launch_bounds__(64) void k_legendre(LegArgs a) {
     // fused even/odd fold and store (Eqs. 13-14)
 #pragma unroll
     for (int r = 0; r < R; r++) {
-        if (k[r] >= a.n_north) continue;
+        if (!gv[r] || k[r] >= a.n_north) continue;
         const int kn = k[r], ks = a.nrings - 1 - k[r];
         double *qn = a.q + 2 * (((size_t)m * a.nrings + kn) * a.nmaps + a.map0);
         double *qs = a.q + 2 * (((size_t)m * a.nrings + ks) * a.nmaps + a.map0);
@@ -237,23 +257,51 @@ __global__ __launch_bounds__(64) void k_legendre(LegArgs a) {
     }
 }
 
+// One launch covers every (m, ring block).  Workgroups are dispatched
+// round-robin over the 8 XCDs: block b runs on XCD b % 8, and the ring
+// blocks of one order m take consecutive slots of one XCD so that its L2
+// serves the m's coefficient and a_lm stream to all of them.  Orders are
+// visited from m = 0 (the longest chains) upward.  Within an order the
+// compensated (double-double) waves nearest the poles come first, one 64-ring
+// group each, so their long chains start early; they take the maps two at a
+// time to stay inside the FP64 waves' register budget.  The FP64 waves
+// follow with R groups each.
+template <int NB, int R>
+__global__ __launch_bounds__(64, (R == 4 ? 2 : 4)) void k_legendre(LegArgs a) {
+    const int nrb = a.dd_groups + a.fp_blocks;
+    const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+    const int m = 8 * (slot / nrb) + xcd;
+    const int rb = slot % nrb;
+    if (m > a.L) return;
+    if (rb < a.dd_groups) {
+        constexpr int NBD = NB < 2 ? NB : 2;
+        for (int b0 = 0; b0 < NB; b0 += NBD) {
+            LegArgs ab = a;
+            ab.map0 = a.map0 + b0;
+            legendre_wave<NBD, 1, true>(ab, m, rb);
+        }
+    } else {
+        legendre_wave<NB, R, false>(a, m, a.dd_groups + (rb - a.dd_groups) * R);
+    }
+}
+
+template <int NB, int R>
+static hipError_t launch_nbr(const sht_plan_s *p, LegArgs a, hipStream_t st) {
+    const int morders = (p->L + 1 + 7) / 8 * 8;  // orders rounded up to the XCD count
+    a.dd_groups = p->n_dd_groups;
+    a.fp_blocks = (a.ng - p->n_dd_groups + R - 1) / R;
+    const long long grid = (long long)morders * (a.dd_groups + a.fp_blocks);
+    hipLaunchKernelGGL((k_legendre<NB, R>), dim3((unsigned)grid), dim3(kLanes), 0, st, a);
+    return hipGetLastError();
+}
+
 template <int NB>
 static hipError_t launch_nb(const sht_plan_s *p, LegArgs a, hipStream_t st) {
-    const int nblocks = p->n_north_pad / kBlockRings;
-    // compensated blocks first (they sit nearest the poles), then the rest
-    if (p->n_dd_blocks > 0) {
-        a.rb0 = 0;
-        a.nrb = p->n_dd_blocks;
-        hipLaunchKernelGGL((k_legendre<NB, true>), dim3((unsigned)((p->L + 1) * a.nrb)), dim3(kLanes), 0,
-                           st, a);
+    switch (p->rings_per_lane) {
+        case 1: return launch_nbr<NB, 1>(p, a, st);
+        case 4: return launch_nbr<NB, 4>(p, a, st);
+        default: return launch_nbr<NB, 2>(p, a, st);
     }
-    if (nblocks > p->n_dd_blocks) {
-        a.rb0 = p->n_dd_blocks;
-        a.nrb = nblocks - p->n_dd_blocks;
-        hipLaunchKernelGGL((k_legendre<NB, false>), dim3((unsigned)((p->L + 1) * a.nrb)), dim3(kLanes), 0,
-                           st, a);
-    }
-    return hipGetLastError();
 }
 
 hipError_t launch_legendre(const sht_plan_s *p, int nmaps, const double *alm, double *q,
@@ -276,6 +324,7 @@ hipError_t launch_legendre(const sht_plan_s *p, int nmaps, const double *alm, do
     a.n_north = p->n_north;
     a.np = p->n_north_pad;
     a.n_dd_pad = std::max(p->n_dd_pad, 1);
+    a.dd_groups = a.fp_blocks = 0;
     a.ng = p->n_north_pad / kLanes;
     a.nmaps = nmaps;
     hipError_t e = hipSuccess;

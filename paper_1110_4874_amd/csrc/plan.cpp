@@ -102,7 +102,9 @@ struct BuildCtx {
     std::vector<ld> coefl;         // [entries][3] long double beta, alpha*beta, gamma
     std::vector<ld> zl, sinl;      // [n_north]
     std::atomic<int> bad{0};
-    std::vector<long long> steps;  // per ring
+    std::vector<long long> steps;  // per ring: executed steps
+    std::vector<long long> alive;  // per ring: steps at or above the cutoff
+    std::vector<long long> lane_steps;  // per m: lane-steps executed by the kernel
 };
 
 static void coef_worker(long m, void *vctx) {
@@ -140,7 +142,7 @@ static void start_worker(long k, void *vctx) {
     const bool dd = k < p->n_dd_pad;
     ld v = 1.0L;
     long E = 0;
-    long long steps = 0;
+    long long steps = 0, alive = 0;
     for (int m = 0; m <= L; m++) {
         if (m > 0) {
             int ex;
@@ -169,6 +171,7 @@ static void start_worker(long k, void *vctx) {
                     }
                     if (PE > -16000 && fabsl(ldexpl(P0, (int)PE)) >= cutoff) {
                         found = i - i % kChunk;
+                        alive += nt - i;
                         break;
                     }
                     int e = t + 2 * i + 2;  // coefficients at l = m + t + 2(i+1)
@@ -200,12 +203,14 @@ static void start_worker(long k, void *vctx) {
         }
     }
     c->steps[k] = steps;
+    c->alive[k] = alive;
 }
 
 static void group_worker(long m, void *vctx) {
     BuildCtx *c = (BuildCtx *)vctx;
     sht_plan_s *p = c->p;
     const int np = p->n_north_pad, ng = np / kLanes;
+    const int n0 = (p->L - (int)m) / 2 + 1;
     for (int g = 0; g < ng; g++) {
         int lo = kDead, hi = -1;
         for (int t = 0; t < 2; t++)
@@ -219,6 +224,17 @@ static void group_worker(long m, void *vctx) {
         p->grp_lo[(size_t)m * ng + g] = lo;
         p->grp_hi[(size_t)m * ng + g] = hi;
     }
+    // lane-steps the kernel executes for this m (every lane of a wave runs
+    // both parities from the wave's first chunk to the end of the chain)
+    long long lanes = 0;
+    const int R = p->rings_per_lane, gdd = p->n_dd_groups;
+    for (int g0 = 0; g0 < ng; g0 += (g0 < gdd ? 1 : R)) {
+        const int w = g0 < gdd ? 1 : std::min(R, ng - g0);
+        int lo = kDead;
+        for (int r = 0; r < w; r++) lo = std::min(lo, p->grp_lo[(size_t)m * ng + g0 + r]);
+        if (lo < n0) lanes += 2LL * kLanes * w * (n0 - lo);
+    }
+    c->lane_steps[m] = lanes;
 }
 
 // ---------------------------------------------------------------------
@@ -299,9 +315,11 @@ static void bs_worker(long idx, void *vctx) {
 int build_host_tables(sht_plan_s *p) {
     const int L = p->L, N = p->nside;
     const int nth = p->opts.nthreads;
+    p->rings_per_lane = (p->opts.rings_per_lane == 1 || p->opts.rings_per_lane == 4) ? p->opts.rings_per_lane : 2;
+    p->ring_threads = (p->opts.ring_threads == 256 || p->opts.ring_threads == 512) ? p->opts.ring_threads : 1024;
     p->nrings = 4 * N - 1;
     p->n_north = 2 * N;
-    p->n_north_pad = (p->n_north + kBlockRings - 1) / kBlockRings * kBlockRings;
+    p->n_north_pad = (p->n_north + kLanes - 1) / kLanes * kLanes;
     const int np = p->n_north_pad;
 
     BuildCtx ctx;
@@ -335,13 +353,18 @@ int build_host_tables(sht_plan_s *p) {
     int ndd = 0;
     while (ndd < p->n_north && (double)ctx.sinl[ndd] < dd_sin) ndd++;
     p->n_dd_rings = ndd;
-    p->n_dd_blocks = (ndd + kBlockRings - 1) / kBlockRings;
-    p->n_dd_pad = p->n_dd_blocks * kBlockRings;
+    p->n_dd_groups = (ndd + kLanes - 1) / kLanes;
+    p->n_dd_pad = p->n_dd_groups * kLanes;
 
     // recurrence coefficients
     p->coef_off.resize(L + 2);
     p->coef_off[0] = 0;
-    for (int m = 0; m <= L; m++) p->coef_off[m + 1] = p->coef_off[m] + (L - m + 1) + kCoefPad;
+    // runs start at even entries so that each (even, odd) entry pair the
+    // kernel reads is one aligned 64-byte load
+    for (int m = 0; m <= L; m++) {
+        long long cnt = (L - m + 1) + kCoefPad;
+        p->coef_off[m + 1] = p->coef_off[m] + cnt + (cnt & 1);
+    }
     long long ne = p->coef_off[L + 1];
     ctx.coefl.assign(3 * (size_t)ne, 0.0L);
     p->coef_hi.assign(4 * (size_t)ne, 0.0);
@@ -353,20 +376,24 @@ int build_host_tables(sht_plan_s *p) {
     p->start_val.assign((size_t)(L + 1) * 2 * 2 * np, 0.0);
     p->start_lo.assign((size_t)(L + 1) * 2 * 2 * std::max(p->n_dd_pad, 1), 0.0);
     ctx.steps.assign(np, 0);
+    ctx.alive.assign(np, 0);
     parallel_for(p->n_north, nth, start_worker, &ctx);
     if (ctx.bad.load())
         return fail(SHT_EUNSUPPORTED,
                     "a Legendre chain start value underflows double precision");
-    p->n_step = 0;
-    p->n_step_dd = 0;
+    p->n_step = p->n_step_exec = p->n_step_dd = 0;
     for (int k = 0; k < np; k++) {
-        p->n_step += ctx.steps[k];
+        p->n_step += ctx.alive[k];
+        p->n_step_exec += ctx.steps[k];
         if (k < p->n_dd_pad) p->n_step_dd += ctx.steps[k];
     }
     int ng = np / kLanes;
     p->grp_lo.assign((size_t)(L + 1) * ng, kDead);
     p->grp_hi.assign((size_t)(L + 1) * ng, -1);
+    ctx.lane_steps.assign(L + 1, 0);
     parallel_for(L + 1, nth, group_worker, &ctx);
+    p->n_step_lanes = 0;
+    for (int m = 0; m <= L; m++) p->n_step_lanes += ctx.lane_steps[m];
 
     // ring FFT tables: twiddles, Bluestein sizes, LDS classes
     int maxS = 2;
@@ -408,14 +435,18 @@ int build_host_tables(sht_plan_s *p) {
     const int class_size[4] = {1024, 2048, 4096, 8192};
     p->classes.clear();
     for (int ci = 0; ci < 4; ci++) {
-        RingClass rc;
-        rc.lds_entries = class_size[ci];
-        for (int r = 0; r < p->nrings; r++) {
-            int S = p->ring_M[r] ? p->ring_M[r] : p->ring_J[r] / 2;
-            int lo = ci == 0 ? 0 : class_size[ci - 1];
-            if (S > lo && S <= class_size[ci]) rc.rings.push_back(r);
+        for (int wrap = 0; wrap < 2; wrap++) {
+            RingClass rc;
+            rc.lds_entries = class_size[ci];
+            rc.wrap = wrap != 0;
+            for (int r = 0; r < p->nrings; r++) {
+                int S = p->ring_M[r] ? p->ring_M[r] : p->ring_J[r] / 2;
+                int lo = ci == 0 ? 0 : class_size[ci - 1];
+                bool w = p->ring_J[r] / 2 <= L;
+                if (S > lo && S <= class_size[ci] && w == rc.wrap) rc.rings.push_back(r);
+            }
+            if (!rc.rings.empty()) p->classes.push_back(rc);
         }
-        if (!rc.rings.empty()) p->classes.push_back(rc);
     }
     return SHT_OK;
 }
@@ -476,6 +507,7 @@ void free_device_tables(sht_plan_s *p) {
         if (q) (void)hipFree(q);
     for (auto &rc : p->classes)
         if (rc.d_rings) (void)hipFree(rc.d_rings), rc.d_rings = nullptr;
+
     p->d_z2_hi = p->d_z2_lo = nullptr;
     p->d_ring_J = p->d_ring_s = p->d_ring_M = nullptr;
     p->d_ring_off = p->d_ring_bs_off = p->d_coef_off = nullptr;

@@ -8,16 +8,20 @@
 // complex DFT of half length n = J/2 (even and odd pixels in the real and
 // imaginary parts) after the usual pre-twiddle.
 //
-// One workgroup handles one (ring, map).  Bin b gathers the m in its two
+// One workgroup handles one (ring, map).  Bin b collects the m of its two
 // residue classes m = b + jJ and m = jJ - b; all of them share the phase
 // e^{i pi b s/J} up to the sign (-1)^{js}, so each bin needs one sincospi.
-// Small rings split the m range over thread groups and reduce in a fixed
-// order (deterministic, no atomics).  The half-length DFT runs in LDS:
-// radix-2 in place when n is a power of two (input written bit-reversed),
-// otherwise Bluestein's chirp convolution with a power-of-two M >= 2n-1
-// whose chirp spectrum is a plan table.  Workgroups are ordered so that the
-// 8 (ring, map) pairs whose q entries share a 128-byte line run back to back
-// on the same XCD (dispatch is round-robin over the 8 XCDs).
+// Rings with J/2 > L (no wrap) load their q values straight into registers,
+// all loads in flight at once; wrapped rings stage q through LDS in chunks
+// and reduce bin sums in a fixed order (deterministic, no atomics).  The
+// half-length DFT runs in LDS with in-place radix-8 passes (radix-4/2 for the
+// remainder): decimation in time on bit-reversed input when n is a power of
+// two, otherwise Bluestein's chirp convolution with a power-of-two M >= 2n-1
+// (forward decimation in frequency, pointwise product with the plan's chirp
+// spectrum, backward decimation in time).  LDS indices are padded by one
+// entry per 16 to spread strided accesses over the banks.  Workgroups are
+// ordered so the 8 (ring, map) items whose q entries share a 128-byte line
+// run back to back on the same XCD (dispatch is round-robin over 8 XCDs).
 #include "internal.h"
 
 namespace sht {
@@ -37,7 +41,12 @@ struct RingArgs {
     double *__restrict__ map;
     int L, nrings, nmaps;
     long long npix;
+    int fft_entries;  // padded FFT buffer entries of this launch's class
+    int stage;        // q entries staged per chunk for wrapped rings (multiple of the block size)
 };
+
+constexpr int kMaxStage = 2048;     // staged q entries per chunk (at most)
+constexpr int kMaxPairs = 2049;     // Hermitian bin pairs of the largest ring (n = 4096)
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -52,76 +61,165 @@ __device__ __forceinline__ double2 expipi(double x) {  // e^{i pi x}
 }
 __device__ __forceinline__ int ilog2_dev(int n) { return 31 - __clz(n); }
 __device__ __forceinline__ int bitrev(int k, int lg) { return lg == 0 ? 0 : (int)(__brev((unsigned)k) >> (32 - lg)); }
+__device__ __forceinline__ int pidx(int i) { return i + (i >> 4); }
 
 // Workgroup -> work item, grouping 8 consecutive items on one XCD.
 __device__ __forceinline__ int xcd_item(int wg) { return (wg & ~63) + ((wg & 7) << 3) + ((wg >> 3) & 7); }
 
-// In-place radix-2 decimation-in-time DFT of size 2^lg, bit-reversed input,
-// natural output, sign +1 (backward): a_p <- sum_k a_k e^{+2 pi i k p / n}.
+// x * e^{2 pi i j / 8} for j = 0..7 (exact constants)
+__device__ __forceinline__ double2 rot8(double2 x, int j) {
+    const double r = 0.70710678118654752440;
+    switch (j & 7) {
+        case 0: return x;
+        case 1: return make_double2(r * (x.x - x.y), r * (x.x + x.y));
+        case 2: return make_double2(-x.y, x.x);
+        case 3: return make_double2(-r * (x.x + x.y), r * (x.x - x.y));
+        case 4: return make_double2(-x.x, -x.y);
+        case 5: return make_double2(r * (x.y - x.x), -r * (x.x + x.y));
+        case 6: return make_double2(x.y, -x.x);
+        default: return make_double2(r * (x.x + x.y), r * (x.y - x.x));
+    }
+}
+
+// One in-place pass of 2^r radix-2 stages s .. s+r-1 (h = 2^(s-1)).
+// Decimation in time, sign +1 (backward): within each group of R = 2^r
+// elements base + k h, sub-stage u combines k and k + 2^u with the twiddle
+// e^{+2 pi i (pos + j h) / (2^(u+1) h)}, j = k mod 2^u.
+template <int r>
+__device__ __forceinline__ void dit_pass(double2 *a, int lg, int s, const double2 *__restrict__ tw,
+                                         int tw_log) {
+    constexpr int R = 1 << r;
+    const int n = 1 << lg, h = 1 << (s - 1);
+    for (int gi = threadIdx.x; gi < n / R; gi += blockDim.x) {
+        const int pos = gi & (h - 1);
+        const int base = (gi >> (s - 1)) * (R * h) + pos;
+        double2 x[R];
+#pragma unroll
+        for (int k = 0; k < R; k++) x[k] = a[pidx(base + k * h)];
+        double2 wp[r];                             // wp[u] = e^{2 pi i pos / (2^(u+1) h)}
+        wp[r - 1] = tw[pos << (tw_log - (s - 1) - r)];
+#pragma unroll
+        for (int u = r - 2; u >= 0; u--) wp[u] = cmul(wp[u + 1], wp[u + 1]);
+#pragma unroll
+        for (int u = 0; u < r; u++) {
+            const int span = 1 << u;
+#pragma unroll
+            for (int k = 0; k < R; k++) {
+                if (k & span) continue;
+                const int j = k & (span - 1);
+                const double2 w = rot8(wp[u], j * (4 >> u));  // e^{2 pi i j / 2^(u+1)}
+                const double2 t = cmul(x[k + span], w);
+                x[k + span] = csub(x[k], t);
+                x[k] = cadd(x[k], t);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < R; k++) a[pidx(base + k * h)] = x[k];
+    }
+    __syncthreads();
+}
+
+// Decimation in frequency, sign -1 (forward): the same groups with the
+// sub-stages in reverse order and conjugate twiddles applied after the
+// difference.
+template <int r>
+__device__ __forceinline__ void dif_pass(double2 *a, int lg, int s, const double2 *__restrict__ tw,
+                                         int tw_log) {
+    constexpr int R = 1 << r;
+    const int n = 1 << lg, h = 1 << (s - 1);
+    for (int gi = threadIdx.x; gi < n / R; gi += blockDim.x) {
+        const int pos = gi & (h - 1);
+        const int base = (gi >> (s - 1)) * (R * h) + pos;
+        double2 x[R];
+#pragma unroll
+        for (int k = 0; k < R; k++) x[k] = a[pidx(base + k * h)];
+        double2 wp[r];
+        wp[r - 1] = tw[pos << (tw_log - (s - 1) - r)];
+#pragma unroll
+        for (int u = r - 2; u >= 0; u--) wp[u] = cmul(wp[u + 1], wp[u + 1]);
+#pragma unroll
+        for (int u = r - 1; u >= 0; u--) {
+            const int span = 1 << u;
+#pragma unroll
+            for (int k = 0; k < R; k++) {
+                if (k & span) continue;
+                const int j = k & (span - 1);
+                const double2 w = cconj(rot8(wp[u], j * (4 >> u)));
+                const double2 x0 = x[k], x1 = x[k + span];
+                x[k] = cadd(x0, x1);
+                x[k + span] = cmul(csub(x0, x1), w);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < R; k++) a[pidx(base + k * h)] = x[k];
+    }
+    __syncthreads();
+}
+
+// Backward DFT of size 2^lg, bit-reversed input, natural output.
 __device__ void fft_dit_inv(double2 *a, int lg, const double2 *__restrict__ tw, int tw_log) {
-    const int n = 1 << lg;
-    for (int s = 1; s <= lg; s++) {
-        const int half = 1 << (s - 1);
-        const int tsh = tw_log - s;
-        for (int j = threadIdx.x; j < n / 2; j += blockDim.x) {
-            const int pos = j & (half - 1);
-            const int i0 = ((j >> (s - 1)) << s) + pos;
-            const int i1 = i0 + half;
-            const double2 w = tw[pos << tsh];
-            const double2 t = cmul(a[i1], w);
-            const double2 x0 = a[i0];
-            a[i0] = cadd(x0, t);
-            a[i1] = csub(x0, t);
-        }
-        __syncthreads();
+    int s = 1;
+    while (lg - s + 1 >= 3) {
+        dit_pass<3>(a, lg, s, tw, tw_log);
+        s += 3;
     }
+    if (lg - s + 1 == 2) dit_pass<2>(a, lg, s, tw, tw_log);
+    else if (lg - s + 1 == 1) dit_pass<1>(a, lg, s, tw, tw_log);
 }
 
-// In-place radix-2 decimation-in-frequency DFT, natural input, bit-reversed
-// output, sign -1 (forward).
+// Forward DFT of size 2^lg, natural input, bit-reversed output.
 __device__ void fft_dif_fwd(double2 *a, int lg, const double2 *__restrict__ tw, int tw_log) {
-    const int n = 1 << lg;
-    for (int s = lg; s >= 1; s--) {
-        const int half = 1 << (s - 1);
-        const int tsh = tw_log - s;
-        for (int j = threadIdx.x; j < n / 2; j += blockDim.x) {
-            const int pos = j & (half - 1);
-            const int i0 = ((j >> (s - 1)) << s) + pos;
-            const int i1 = i0 + half;
-            const double2 w = cconj(tw[pos << tsh]);
-            const double2 x0 = a[i0], x1 = a[i1];
-            a[i0] = cadd(x0, x1);
-            a[i1] = cmul(csub(x0, x1), w);
-        }
-        __syncthreads();
+    const int rem = lg % 3;
+    int s = lg - 2;
+    while (s >= 1 + rem) {
+        dif_pass<3>(a, lg, s, tw, tw_log);
+        s -= 3;
     }
+    if (rem == 2) dif_pass<2>(a, lg, 1, tw, tw_log);
+    else if (rem == 1) dif_pass<1>(a, lg, 1, tw, tw_log);
 }
 
-// Raw wrap sum for bin b (without the common phase e^{i pi b s/J}) over the
-// residue-class terms j = g, g+G, ... of both classes.
-__device__ __forceinline__ double2 gather_bin(const double2 *__restrict__ qr, size_t qstride, int L,
-                                              int J, int s, int b, int g, int G) {
+// First j >= jlo with j = g (mod G).
+__device__ __forceinline__ long long first_in_class(long long jlo, int g, int G) {
+    long long d = ((long long)g - jlo) % G;
+    if (d < 0) d += G;
+    return jlo + d;
+}
+
+// Raw wrap sum of bin b (before the common phase) over the q values staged
+// for m in [m0, m0 + cnt), restricted to terms j = g (mod G).
+__device__ __forceinline__ double2 bin_chunk(const double2 *st, int m0, int cnt, int J, int s, int b, int g,
+                                             int G) {
     double2 acc = make_double2(0.0, 0.0);
-    if (b == 0 && g == 0) acc.x = qr[0].x;  // m = 0: real part only
-    for (int j = g;; j += G) {               // m = b + jJ
-        long long m = (long long)b + (long long)j * J;
-        if (m > L) break;
-        if (m == 0) continue;
-        double2 v = qr[(size_t)m * qstride];
+    const long long m1 = (long long)m0 + cnt;  // exclusive
+    // class 1: m = b + jJ, j >= 0
+    long long jlo = (m0 - b + (long long)J - 1) / J;
+    if ((long long)m0 - b <= 0) jlo = 0;
+    for (long long j = first_in_class(jlo, g, G);; j += G) {
+        long long m = b + j * J;
+        if (m >= m1) break;
+        double2 v = st[m - m0];
+        if (m == 0) v = make_double2(v.x, 0.0);  // real part of q_0 only
         if (s & j & 1) v = make_double2(-v.x, -v.y);
         acc = cadd(acc, v);
     }
-    for (int j = (g == 0 ? G : g);; j += G) {  // m = jJ - b, j >= 1
-        long long m = (long long)j * J - b;
-        if (m > L) break;
-        double2 v = cconj(qr[(size_t)m * qstride]);
+    // class 2: m = jJ - b, j >= 1
+    long long jlo2 = ((long long)m0 + b + J - 1) / J;
+    if (jlo2 < 1) jlo2 = 1;
+    for (long long j = first_in_class(jlo2, g, G);; j += G) {
+        long long m = j * J - b;
+        if (m >= m1) break;
+        double2 v = cconj(st[m - m0]);
         if (s & j & 1) v = make_double2(-v.x, -v.y);
         acc = cadd(acc, v);
     }
     return acc;
 }
 
-__global__ __launch_bounds__(kRingThreads) void k_ring_synth(RingArgs a) {
+template <int T>
+__global__ __launch_bounds__(T) void k_ring_synth(RingArgs a) {
+    constexpr int kPairsPerThread = (kMaxPairs + T - 1) / T;
+    constexpr int kMaxStagePerThread = kMaxStage / T;
     extern __shared__ double2 sm[];
     const int item = xcd_item(blockIdx.x);
     if (item >= a.count * a.nmaps) return;
@@ -132,23 +230,95 @@ __global__ __launch_bounds__(kRingThreads) void k_ring_synth(RingArgs a) {
     const bool bs = M > 0;
     const int S = bs ? M : n, lgS = ilog2_dev(S);
     double2 *buf = sm;
-    double2 *part = sm + S;  // kRingThreads * 2 entries
+    double2 *stage = sm + a.fft_entries;  // a.stage entries (wrapped rings only)
     const double2 *qr = a.q + (size_t)rho * a.nmaps + b;
     const size_t qstride = (size_t)a.nrings * a.nmaps;
-    const int T = blockDim.x, tid = threadIdx.x;
+    const int tid = threadIdx.x;
+    const int L = a.L;
+    const int npair = n / 2 + 1;
 
     if (bs)
-        for (int i = n + tid; i < M; i += T) buf[i] = make_double2(0.0, 0.0);
+        for (int i = n + tid; i < M; i += T) buf[pidx(i)] = make_double2(0.0, 0.0);
 
-    // Z_k for the pair (k, n-k) from the Hermitian bins X_k, X_{n-k}
-    auto emit = [&](int k, double2 rk, double2 rnk) {
-        double2 Xk = rk, Xnk = rnk;
+    // raw bin sums for the pairs (k, n-k) owned by this thread
+    double2 xa[kPairsPerThread], xb[kPairsPerThread];
+#pragma unroll
+    for (int j = 0; j < kPairsPerThread; j++) xa[j] = xb[j] = make_double2(0.0, 0.0);
+
+    const bool wrap = n <= L;
+    int G = 1;
+    if (!wrap) {
+        // every bin b <= L holds exactly q_b; issue all loads first
+#pragma unroll
+        for (int j = 0; j < kPairsPerThread; j++) {
+            const int k = tid + j * T;
+            if (k < npair) {
+                if (k <= L) xa[j] = qr[(size_t)k * qstride];
+                if (k == 0) xa[j].y = 0.0;
+                if (k != 0 && n - k <= L) xb[j] = qr[(size_t)(n - k) * qstride];
+            }
+        }
+    } else {
+        G = npair >= T ? 1 : T / npair;
+        for (int m0 = 0; m0 <= L; m0 += a.stage) {
+            const int cnt = min(a.stage, L + 1 - m0);
+            double2 v[kMaxStagePerThread];
+#pragma unroll
+            for (int i = 0; i < kMaxStagePerThread; i++) {
+                const int mm = tid + i * T;
+                if (mm < cnt) v[i] = qr[(size_t)(m0 + mm) * qstride];
+            }
+#pragma unroll
+            for (int i = 0; i < kMaxStagePerThread; i++) {
+                const int mm = tid + i * T;
+                if (mm < cnt) stage[mm] = v[i];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < kPairsPerThread; j++) {
+                const int u = tid + j * T;
+                const int g = u / npair, k = u % npair;
+                if (g < G) {
+                    xa[j] = cadd(xa[j], bin_chunk(stage, m0, cnt, J, s, k, g, G));
+                    if (k != 0 && 2 * k != n)
+                        xb[j] = cadd(xb[j], bin_chunk(stage, m0, cnt, J, s, n - k, g, G));
+                    else if (k == 0)
+                        xb[j] = cadd(xb[j], bin_chunk(stage, m0, cnt, J, s, n, g, G));
+                }
+            }
+            __syncthreads();
+        }
+        if (G > 1) {
+            // reduce the group partials in a fixed order (stage region reused)
+            if (tid < G * npair) {
+                stage[2 * tid] = xa[0];
+                stage[2 * tid + 1] = xb[0];
+            }
+            __syncthreads();
+            if (tid < npair) {
+                double2 s0 = make_double2(0.0, 0.0), s1 = make_double2(0.0, 0.0);
+                for (int g = 0; g < G; g++) {
+                    s0 = cadd(s0, stage[2 * (g * npair + tid)]);
+                    s1 = cadd(s1, stage[2 * (g * npair + tid) + 1]);
+                }
+                xa[0] = s0;
+                xb[0] = s1;
+            }
+        }
+    }
+
+    // phase shift, Hermitian pre-twiddle, store into the DFT input
+#pragma unroll
+    for (int j = 0; j < kPairsPerThread; j++) {
+        const int k = tid + j * T;
+        if (k >= npair || (G > 1 && j > 0)) continue;
+        double2 Xk = xa[j], Xnk = xb[j];
         if (s) {
             Xk = cmul(Xk, expipi((double)k / J));
             Xnk = cmul(Xnk, expipi((double)(n - k) / J));
         }
-        double2 Zk, Znk;
-        bool two = (k != 0) && (2 * k != n);
+        double2 Zk, Znk = make_double2(0.0, 0.0);
+        const bool two = (k != 0) && (2 * k != n);
         if (k == 0) {
             double2 e = cadd(Xk, cconj(Xnk)), o = csub(Xk, cconj(Xnk));
             Zk = make_double2(e.x - o.y, e.y + o.x);
@@ -161,38 +331,15 @@ __global__ __launch_bounds__(kRingThreads) void k_ring_synth(RingArgs a) {
             Znk = make_double2(e.x + o.y, -e.y + o.x);  // conj(e) + i conj(o)
         }
         if (!bs) {
-            buf[bitrev(k, lgn)] = Zk;
-            if (two) buf[bitrev(n - k, lgn)] = Znk;
+            buf[pidx(bitrev(k, lgn))] = Zk;
+            if (two) buf[pidx(bitrev(n - k, lgn))] = Znk;
         } else {
-            long long r = ((long long)k * k) % (2LL * n);
-            buf[k] = cmul(Zk, expipi((double)r / n));
+            long long r1 = ((long long)k * k) % (2LL * n);
+            buf[pidx(k)] = cmul(Zk, expipi((double)r1 / n));
             if (two) {
                 long long r2 = ((long long)(n - k) * (n - k)) % (2LL * n);
-                buf[n - k] = cmul(Znk, expipi((double)r2 / n));
+                buf[pidx(n - k)] = cmul(Znk, expipi((double)r2 / n));
             }
-        }
-    };
-
-    const int npair = n / 2 + 1;
-    if (npair * 2 >= T) {
-        for (int k = tid; k < npair; k += T)
-            emit(k, gather_bin(qr, qstride, a.L, J, s, k, 0, 1),
-                 gather_bin(qr, qstride, a.L, J, s, n - k, 0, 1));
-    } else {
-        const int G = T / npair;
-        const int g = tid / npair, k = tid % npair;
-        if (g < G) {
-            part[2 * (g * npair + k)] = gather_bin(qr, qstride, a.L, J, s, k, g, G);
-            part[2 * (g * npair + k) + 1] = gather_bin(qr, qstride, a.L, J, s, n - k, g, G);
-        }
-        __syncthreads();
-        if (tid < npair) {
-            double2 x0 = make_double2(0.0, 0.0), x1 = make_double2(0.0, 0.0);
-            for (int gg = 0; gg < G; gg++) {
-                x0 = cadd(x0, part[2 * (gg * npair + tid)]);
-                x1 = cadd(x1, part[2 * (gg * npair + tid) + 1]);
-            }
-            emit(tid, x0, x1);
         }
     }
     __syncthreads();
@@ -202,18 +349,43 @@ __global__ __launch_bounds__(kRingThreads) void k_ring_synth(RingArgs a) {
     } else {
         fft_dif_fwd(buf, lgS, a.tw, a.tw_log);
         const double2 *V = a.bs_table + a.ring_bs_off[rho];
-        for (int i = tid; i < M; i += T) buf[i] = cmul(buf[i], V[i]);
+        for (int i = tid; i < M; i += T) buf[pidx(i)] = cmul(buf[pidx(i)], V[i]);
         __syncthreads();
         fft_dit_inv(buf, lgS, a.tw, a.tw_log);
         for (int p = tid; p < n; p += T) {
             long long r = ((long long)p * p) % (2LL * n);
-            buf[p] = cmul(buf[p], expipi((double)r / n));
+            buf[pidx(p)] = cmul(buf[pidx(p)], expipi((double)r / n));
         }
         __syncthreads();
     }
     // pixel 2p = Re z_p, pixel 2p+1 = Im z_p
     double2 *out = reinterpret_cast<double2 *>(a.map + (size_t)b * a.npix + a.ring_off[rho]);
-    for (int p = tid; p < n; p += T) out[p] = buf[p];
+    for (int p = tid; p < n; p += T) out[p] = buf[pidx(p)];
+}
+
+template <int T>
+static hipError_t launch_classes(const sht_plan_s *p, RingArgs a, int nmaps, hipStream_t stream) {
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute((const void *)k_ring_synth<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  160 * 1024);
+        attr_set = true;
+    }
+    for (const auto &rc : p->classes) {
+        a.rings = rc.d_rings;
+        a.count = (int)rc.rings.size();
+        a.fft_entries = rc.lds_entries + rc.lds_entries / 16;
+        // staging chunk: as much of the 160 KiB LDS as the FFT buffer leaves
+        const int room = (int)(160 * 1024 / sizeof(double2)) - a.fft_entries;
+        a.stage = std::min(kMaxStage, room / T * T);
+        long long items = (long long)a.count * nmaps;
+        long long grid = (items + 63) / 64 * 64;
+        size_t lds = (size_t)(a.fft_entries + (rc.wrap ? a.stage : 0)) * sizeof(double2);
+        hipLaunchKernelGGL(k_ring_synth<T>, dim3((unsigned)grid), dim3(T), lds, stream, a);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_ring_synthesis(const sht_plan_s *p, int nmaps, const double *q, double *map,
@@ -233,21 +405,10 @@ hipError_t launch_ring_synthesis(const sht_plan_s *p, int nmaps, const double *q
     a.nrings = p->nrings;
     a.nmaps = nmaps;
     a.npix = 12LL * p->nside * p->nside;
-    static bool attr_set = false;
-    if (!attr_set) {
-        (void)hipFuncSetAttribute((const void *)k_ring_synth, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  160 * 1024);
-        attr_set = true;
-    }
-    for (const auto &rc : p->classes) {
-        a.rings = rc.d_rings;
-        a.count = (int)rc.rings.size();
-        long long items = (long long)a.count * nmaps;
-        long long grid = (items + 63) / 64 * 64;
-        size_t lds = (size_t)(rc.lds_entries + 2 * kRingThreads) * sizeof(double2);
-        hipLaunchKernelGGL(k_ring_synth, dim3((unsigned)grid), dim3(kRingThreads), lds, stream, a);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+    switch (p->ring_threads) {
+        case 256: return launch_classes<256>(p, a, nmaps, stream);
+        case 512: return launch_classes<512>(p, a, nmaps, stream);
+        default: return launch_classes<1024>(p, a, nmaps, stream);
     }
     return hipSuccess;
 }

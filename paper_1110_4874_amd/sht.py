@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libsht.so")
 
 SHT_OK, SHT_EINVAL, SHT_ENOMEM, SHT_EDEVICE, SHT_ECORRUPT, SHT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 PATH_AUTO, PATH_BRUTE = 0, 1
+STAGE_LEGENDRE, STAGE_RING, NSTAGES = 0, 1, 2
 
 _c = ctypes
 _lib = None
@@ -24,17 +25,19 @@ _lib = None
 
 class PlanOpts(_c.Structure):
     _fields_ = [("cutoff", _c.c_double), ("dd_sin", _c.c_double), ("nthreads", _c.c_int),
-                ("host_only", _c.c_int)]
+                ("rings_per_lane", _c.c_int), ("ring_threads", _c.c_int), ("host_only", _c.c_int)]
 
 
 class ExecOpts(_c.Structure):
     _fields_ = [("nmaps", _c.c_int), ("path", _c.c_int), ("stream", _c.c_void_p),
-                ("workspace", _c.c_void_p), ("workspace_bytes", _c.c_size_t)]
+                ("workspace", _c.c_void_p), ("workspace_bytes", _c.c_size_t),
+                ("stage_events", _c.POINTER(_c.c_void_p))]
 
 
 class PlanInfo(_c.Structure):
     _fields_ = [("L", _c.c_int), ("nside", _c.c_int), ("nrings", _c.c_int), ("n_dd_rings", _c.c_int),
-                ("eps", _c.c_double), ("n_step", _c.c_longlong), ("n_step_dd", _c.c_longlong),
+                ("eps", _c.c_double), ("n_step", _c.c_longlong), ("n_step_exec", _c.c_longlong),
+                ("n_step_dd", _c.c_longlong), ("n_step_lanes", _c.c_longlong),
                 ("device_bytes", _c.c_size_t), ("build_seconds", _c.c_double)]
 
 
@@ -95,7 +98,8 @@ def _stream_handle(stream):
 class Plan:
     """A transform plan for band limit L on a HEALPix grid of resolution nside."""
 
-    def __init__(self, L, nside, eps=0.0, *, cutoff=None, dd_sin=None, nthreads=0, host_only=False):
+    def __init__(self, L, nside, eps=0.0, *, cutoff=None, dd_sin=None, nthreads=0, rings_per_lane=0,
+                 ring_threads=0, host_only=False):
         lib = load()
         o = PlanOpts()
         lib.sht_plan_opts_default(_c.byref(o))
@@ -104,6 +108,8 @@ class Plan:
         if dd_sin is not None:
             o.dd_sin = dd_sin
         o.nthreads = nthreads
+        o.rings_per_lane = rings_per_lane
+        o.ring_threads = ring_threads
         o.host_only = 1 if host_only else 0
         if not host_only:
             torch.cuda.init()
@@ -134,7 +140,7 @@ class Plan:
         return {f: getattr(inf, f) for f, _ in PlanInfo._fields_}
 
     # ---- execution ----------------------------------------------------
-    def _exec(self, nmaps, path=PATH_AUTO, stream=None, workspace=None):
+    def _exec(self, nmaps, path=PATH_AUTO, stream=None, workspace=None, events=None):
         x = ExecOpts()
         load().sht_exec_opts_default(_c.byref(x))
         x.nmaps = int(nmaps)
@@ -143,6 +149,13 @@ class Plan:
         if workspace is not None:
             x.workspace = _c.c_void_p(workspace.data_ptr())
             x.workspace_bytes = workspace.numel() * workspace.element_size()
+        if events is not None:
+            # events: list of 2*NSTAGES torch.cuda.Event (already recorded once) or None
+            arr = (_c.c_void_p * (2 * NSTAGES))()
+            for i, ev in enumerate(events):
+                arr[i] = _c.c_void_p(ev.cuda_event) if ev is not None else None
+            x.stage_events = arr
+            self._keep = arr
         return x
 
     def workspace_bytes(self, nmaps=1):
@@ -160,7 +173,7 @@ class Plan:
             raise ValueError(f"alm has {a.shape[0]} rows, expected nalm = {self.nalm}")
         return a.contiguous()
 
-    def synthesis(self, alm, out=None, *, path=PATH_AUTO, stream=None, workspace=None):
+    def synthesis(self, alm, out=None, *, path=PATH_AUTO, stream=None, workspace=None, events=None):
         """maps (B, Npix) float64 from alm (nalm, B) or (nalm,) complex128."""
         a = self._alm_arg(alm)
         B = a.shape[1]
@@ -168,7 +181,7 @@ class Plan:
             out = torch.empty((B, self.npix), dtype=torch.float64, device=a.device)
         if workspace is None:
             workspace = self.workspace(B, a.device)
-        x = self._exec(B, path, stream, workspace)
+        x = self._exec(B, path, stream, workspace, events)
         _check(load().sht_synthesis_ex(self._h, _c.byref(x), _c.c_void_p(a.data_ptr()),
                                        _c.c_void_p(out.data_ptr())))
         return out

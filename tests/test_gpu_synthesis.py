@@ -100,6 +100,25 @@ def test_l4095_sampled_rings_vs_long_double(gpu):
     assert worst <= TOL
 
 
+@pytest.mark.parametrize("threads", [256, 512, 1024])
+def test_every_pixel_written_and_deterministic(gpu, threads):
+    # outputs pre-filled with NaN: any pixel the ring kernel leaves unwritten,
+    # or any bin it leaves uncomputed, shows up as non-finite or as a mismatch
+    L, N = 300, 128  # wrapped polar rings, Bluestein and radix-2 rings, no-wrap belt
+    alm = _dev(alm_gaussian(L, [1, 2, 3, 4]))
+    p = gpu.Plan(L, N, ring_threads=threads)
+    q = p.legendre_phase(alm)
+    outs = []
+    for _ in range(2):
+        out = torch.full((4, p.npix), float("nan"), dtype=torch.float64, device="cuda")
+        p.ring_synthesis(q, out=out)
+        outs.append(out)
+    assert bool(torch.isfinite(outs[0]).all())
+    assert torch.equal(outs[0], outs[1])
+    ref = oracle.synthesis(L, N, alm.cpu().numpy())
+    assert maxrel(outs[0].cpu().numpy(), ref) <= TOL
+
+
 def test_deterministic(gpu):
     L, N = 127, 64
     alm = _dev(alm_gaussian(L, [1, 2]))
