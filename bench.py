@@ -63,8 +63,9 @@ def main():
     ap.add_argument("--L", type=int, default=4095)
     ap.add_argument("--nside", type=int, default=2048)
     ap.add_argument("--maps", type=int, default=4)
-    ap.add_argument("--cpu-rings", type=int, default=96, help="rings in the CPU-baseline sample")
+    ap.add_argument("--cpu-rings", type=int, default=900, help="rings in the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip timing the adjoint")
     ap.add_argument("--rings-per-lane", type=int, default=0, help="Legendre kernel tile (1, 2, 4; 0 = plan default)")
     ap.add_argument("--ring-threads", type=int, default=0, help="ring kernel workgroup size (256, 512, 1024; 0 = default)")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -129,6 +130,28 @@ def main():
     achieved = flops / (leg_ms * 1e-3) / 1e12
     log(f"[bench] {ms_per_step:.3f} ms/step, legendre {leg_ms:.3f} ms, ring {ring_ms:.3f} ms")
 
+    # the hand-written adjoint on the same workload (reported beside the metric)
+    adj = None
+    if not args.no_adjoint:
+        y = out.clone()
+        g = torch.empty((plan.nalm, B), dtype=torch.complex128, device=dev)
+        for i in range(args.warmup):
+            plan.adjoint(y, g, workspace=ws)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        for k in range(args.steps):
+            plan.adjoint(y, g, workspace=ws, events=ev_sets[k])
+        torch.cuda.synchronize()
+        adj_elapsed = time.perf_counter() - ta
+        ra_ms = float(np.mean([e[4].elapsed_time(e[5]) for e in ev_sets]))
+        la_ms = float(np.mean([e[6].elapsed_time(e[7]) for e in ev_sets]))
+        adj = {"maps_per_s": round(B * args.steps / adj_elapsed, 3),
+               "ms_per_step": round(1e3 * adj_elapsed / args.steps, 4),
+               "stages_ms": {"ring_analysis": round(ra_ms, 4), "legendre_adjoint": round(la_ms, 4)},
+               "legendre_adjoint_tflops": round(flops / (la_ms * 1e-3) / 1e12, 3)}
+        log(f"[bench] adjoint {adj['ms_per_step']:.3f} ms/step, ring analysis {ra_ms:.3f} ms, "
+            f"legendre adjoint {la_ms:.3f} ms")
+
     if args.copy_calibration:
         nbytes = args.copy_calibration << 20
         src = torch.empty(nbytes // 8, dtype=torch.float64, device=dev).normal_()
@@ -169,6 +192,8 @@ def main():
             "flops_per_launch": flops,
         },
     }
+    if adj is not None:
+        line["adjoint"] = adj
 
     if not args.no_cpu_baseline:
         import oracle

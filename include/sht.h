@@ -56,7 +56,22 @@ typedef enum {
 enum { SHT_PATH_AUTO = 0, SHT_PATH_BRUTE = 1 };
 
 /* Stages of a transform, for sht_exec_opts.stage_events. */
-enum { SHT_STAGE_LEGENDRE = 0, SHT_STAGE_RING = 1, SHT_NSTAGES = 2 };
+enum {
+    SHT_STAGE_LEGENDRE = 0,      /* synthesis: Legendre phase q_m(z_k) */
+    SHT_STAGE_RING = 1,          /* synthesis: phase shift, wrap, ring FFT */
+    SHT_STAGE_RING_ADJ = 2,      /* adjoint: ring FFT, unwrap, weights */
+    SHT_STAGE_LEGENDRE_ADJ = 3,  /* adjoint: transposed Legendre transform */
+    SHT_NSTAGES = 4
+};
+
+/* Adjoint conventions (sht_exec_opts.adjoint_convention). */
+enum {
+    SHT_ADJ_TRANSPOSE = 0,  /* exact transpose of synthesis under the real inner
+                               product sum_{l, m>=0} Re a Re g + Im a Im g:
+                               weight 2 for m >= 1 (the gradient convention) */
+    SHT_ADJ_DAGGER = 1      /* Y^dagger of Sec. 2.2 Eq. 7 restricted to m >= 0:
+                               weight 1 for every m */
+};
 
 /* Options for building a plan.  Fill with sht_plan_opts_default() first. */
 typedef struct sht_plan_opts {
@@ -83,6 +98,7 @@ typedef struct sht_exec_opts {
     void *workspace;          /* device scratch of >= sht_workspace_bytes(), or
                                  NULL to let the call allocate (stream ordered) */
     size_t workspace_bytes;
+    int adjoint_convention;   /* SHT_ADJ_*, used by the adjoint only */
     void **stage_events;      /* NULL, or 2*SHT_NSTAGES hipEvent_t handles
                                  (entries may be NULL): events[2s] is recorded
                                  on the stream before stage s runs and
@@ -131,6 +147,18 @@ int sht_synthesis(const sht_plan_t *plan, const double *alm, double *map);
 int sht_synthesis_ex(const sht_plan_t *plan, const sht_exec_opts *x,
                      const double *alm, double *map);
 
+/* Adjoint g = A^T y of synthesis (Sec. 2.2: the operator the Wiener filter of
+ * Eq. 7 needs; the paper builds synthesis only).  With the default
+ * convention SHT_ADJ_TRANSPOSE,
+ *     g_lm = w_m sum_k P~_l^m(z_k) sum_j y_kj e^{-i m phi_kj},
+ * w_0 = 1 (Im g_l0 = 0), w_m = 2 for m >= 1, so that
+ * <synthesis(a), y> = sum Re a Re g + Im a Im g for real-field a.
+ * map: x->nmaps stacked maps (input); alm: output in the alm layout.
+ * The Legendre functions are recomputed (nothing is kept from synthesis). */
+int sht_adjoint(const sht_plan_t *plan, const double *map, double *alm);
+int sht_adjoint_ex(const sht_plan_t *plan, const sht_exec_opts *x, const double *map,
+                   double *alm);
+
 const char *sht_last_error(void);
 
 /* ---- private test API (the paper's unit-test entry points, Sec. 4.1) ---- */
@@ -154,6 +182,16 @@ int sht_debug_ring_synthesis(const sht_plan_t *plan, const sht_exec_opts *x,
  *         *idx = first chain index i (l = m + t + 2i) held in the table,
  *         rounded down to the kernel's chunk (or >= chain length if the
  *         whole chain stays below the cutoff), vals[0..1] = P at i, i+1. */
+/* Adjoint ring stage only: ybar_m(z_k) = w_m sum_j y_kj e^{-i m phi_kj} for
+ * every m and ring, written in the q layout. */
+int sht_debug_ring_analysis(const sht_plan_t *plan, const sht_exec_opts *x,
+                            const double *map, double *ybar);
+
+/* Adjoint Legendre stage only: g_lm = sum_k P~_l^m(z_k) ybar_m(z_k) from ybar
+ * in the q layout to alm layout. */
+int sht_debug_legendre_adjoint(const sht_plan_t *plan, const sht_exec_opts *x,
+                               const double *ybar, double *alm);
+
 int sht_debug_coef(const sht_plan_t *plan, int m, double *coef_out);
 int sht_debug_start(const sht_plan_t *plan, int m, int t, int k, int *idx,
                     double *vals);

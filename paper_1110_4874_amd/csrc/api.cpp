@@ -135,6 +135,7 @@ void sht_exec_opts_default(sht_exec_opts *o) {
     o->stream = nullptr;
     o->workspace = nullptr;
     o->workspace_bytes = 0;
+    o->adjoint_convention = SHT_ADJ_TRANSPOSE;
     o->stage_events = nullptr;
 }
 
@@ -261,6 +262,68 @@ int sht_synthesis_ex(const sht_plan_t *p, const sht_exec_opts *x, const double *
     rc = hip_status(launch_ring_synthesis(p, B, q, map, st), "ring kernel launch");
     stage_event(x, SHT_STAGE_RING, 1);
     return rc;
+}
+
+int sht_adjoint(const sht_plan_t *p, const double *map, double *alm) {
+    sht_exec_opts x;
+    sht_exec_opts_default(&x);
+    return sht_adjoint_ex(p, &x, map, alm);
+}
+
+static int check_conv(const sht_exec_opts *x) {
+    if (x->adjoint_convention != SHT_ADJ_TRANSPOSE && x->adjoint_convention != SHT_ADJ_DAGGER)
+        return fail(SHT_EINVAL, "unknown adjoint convention");
+    return SHT_OK;
+}
+
+int sht_adjoint_ex(const sht_plan_t *p, const sht_exec_opts *x, const double *map, double *alm) {
+    int rc = check_plan(p);
+    if (!rc) rc = check_exec(p, x);
+    if (!rc) rc = check_conv(x);
+    if (rc) return rc;
+    DeviceGuard g(p->device);
+    if (!g.ok) return fail(SHT_EDEVICE, "cannot select the plan's device");
+    const int B = x->nmaps;
+    if ((rc = check_dev_ptr(map, npix_of(p->nside) * B * 8, p->device, "map"))) return rc;
+    if ((rc = check_dev_ptr(alm, nalm_of(p->L) * B * 16, p->device, "alm"))) return rc;
+    Scratch ws;
+    if ((rc = ws.get(x, q_bytes(p, B), p->device))) return rc;
+    hipStream_t st = (hipStream_t)x->stream;
+    double *ybar = (double *)ws.ptr;
+    const double wpos = x->adjoint_convention == SHT_ADJ_DAGGER ? 1.0 : 2.0;
+    stage_event(x, SHT_STAGE_RING_ADJ, 0);
+    if ((rc = hip_status(launch_ring_analysis(p, B, map, ybar, wpos, st), "ring analysis launch"))) return rc;
+    stage_event(x, SHT_STAGE_RING_ADJ, 1);
+    stage_event(x, SHT_STAGE_LEGENDRE_ADJ, 0);
+    rc = hip_status(launch_legendre_adjoint(p, B, ybar, alm, st), "adjoint Legendre launch");
+    stage_event(x, SHT_STAGE_LEGENDRE_ADJ, 1);
+    return rc;
+}
+
+int sht_debug_ring_analysis(const sht_plan_t *p, const sht_exec_opts *x, const double *map, double *ybar) {
+    int rc = check_plan(p);
+    if (!rc) rc = check_exec(p, x);
+    if (!rc) rc = check_conv(x);
+    if (rc) return rc;
+    DeviceGuard g(p->device);
+    const int B = x->nmaps;
+    if ((rc = check_dev_ptr(map, npix_of(p->nside) * B * 8, p->device, "map"))) return rc;
+    if ((rc = check_dev_ptr(ybar, q_bytes(p, B), p->device, "ybar"))) return rc;
+    const double wpos = x->adjoint_convention == SHT_ADJ_DAGGER ? 1.0 : 2.0;
+    return hip_status(launch_ring_analysis(p, B, map, ybar, wpos, (hipStream_t)x->stream),
+                      "ring analysis launch");
+}
+
+int sht_debug_legendre_adjoint(const sht_plan_t *p, const sht_exec_opts *x, const double *ybar, double *alm) {
+    int rc = check_plan(p);
+    if (!rc) rc = check_exec(p, x);
+    if (rc) return rc;
+    DeviceGuard g(p->device);
+    const int B = x->nmaps;
+    if ((rc = check_dev_ptr(ybar, q_bytes(p, B), p->device, "ybar"))) return rc;
+    if ((rc = check_dev_ptr(alm, nalm_of(p->L) * B * 16, p->device, "alm"))) return rc;
+    return hip_status(launch_legendre_adjoint(p, B, ybar, alm, (hipStream_t)x->stream),
+                      "adjoint Legendre launch");
 }
 
 int sht_debug_legendre_phase(const sht_plan_t *p, const sht_exec_opts *x, const double *alm, double *q) {

@@ -94,5 +94,9 @@ hipError_t launch_legendre(const sht_plan_s *p, int nmaps, const double *alm, do
                            hipStream_t stream);
 hipError_t launch_ring_synthesis(const sht_plan_s *p, int nmaps, const double *q, double *map,
                                  hipStream_t stream);
+hipError_t launch_ring_analysis(const sht_plan_s *p, int nmaps, const double *map, double *ybar,
+                                double wpos, hipStream_t stream);
+hipError_t launch_legendre_adjoint(const sht_plan_s *p, int nmaps, const double *ybar, double *g,
+                                   hipStream_t stream);
 
 }  // namespace sht

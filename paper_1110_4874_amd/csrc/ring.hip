@@ -43,6 +43,10 @@ struct RingArgs {
     long long npix;
     int fft_entries;  // padded FFT buffer entries of this launch's class
     int stage;        // q entries staged per chunk for wrapped rings (multiple of the block size)
+    // adjoint direction: pixel values in, weighted phases ybar out
+    const double *__restrict__ map_in;
+    double2 *__restrict__ ybar;
+    double wpos;      // weight of m >= 1 (2: transpose of synthesis, 1: Y^dagger)
 };
 
 constexpr int kMaxStage = 2048;     // staged q entries per chunk (at most)
@@ -177,6 +181,30 @@ __device__ void fft_dif_fwd(double2 *a, int lg, const double2 *__restrict__ tw, 
     }
     if (rem == 2) dif_pass<2>(a, lg, 1, tw, tw_log);
     else if (rem == 1) dif_pass<1>(a, lg, 1, tw, tw_log);
+}
+
+// Unnormalised backward DFT of size n in LDS: z_p = sum_k Z_k e^{+2 pi i k p/n}.
+// On entry the buffer holds Z_k at pidx(bitrev(k)) (n a power of two, M = 0)
+// or the chirp-weighted u_k = Z_k e^{i pi k^2/n} at pidx(k) with zeros up to
+// M (Bluestein); on exit z_p is at pidx(p), p < n.
+template <int T>
+__device__ __forceinline__ void backward_dft(double2 *buf, int n, int M, const double2 *__restrict__ V,
+                                             const double2 *__restrict__ tw, int tw_log) {
+    const int tid = threadIdx.x;
+    if (M == 0) {
+        fft_dit_inv(buf, ilog2_dev(n), tw, tw_log);
+        return;
+    }
+    const int lgM = ilog2_dev(M);
+    fft_dif_fwd(buf, lgM, tw, tw_log);
+    for (int i = tid; i < M; i += T) buf[pidx(i)] = cmul(buf[pidx(i)], V[i]);
+    __syncthreads();
+    fft_dit_inv(buf, lgM, tw, tw_log);
+    for (int p = tid; p < n; p += T) {
+        long long r = ((long long)p * p) % (2LL * n);
+        buf[pidx(p)] = cmul(buf[pidx(p)], expipi((double)r / n));
+    }
+    __syncthreads();
 }
 
 // First j >= jlo with j = g (mod G).
@@ -344,20 +372,7 @@ __global__ __launch_bounds__(T) void k_ring_synth(RingArgs a) {
     }
     __syncthreads();
 
-    if (!bs) {
-        fft_dit_inv(buf, lgn, a.tw, a.tw_log);
-    } else {
-        fft_dif_fwd(buf, lgS, a.tw, a.tw_log);
-        const double2 *V = a.bs_table + a.ring_bs_off[rho];
-        for (int i = tid; i < M; i += T) buf[pidx(i)] = cmul(buf[pidx(i)], V[i]);
-        __syncthreads();
-        fft_dit_inv(buf, lgS, a.tw, a.tw_log);
-        for (int p = tid; p < n; p += T) {
-            long long r = ((long long)p * p) % (2LL * n);
-            buf[pidx(p)] = cmul(buf[pidx(p)], expipi((double)r / n));
-        }
-        __syncthreads();
-    }
+    backward_dft<T>(buf, n, M, a.bs_table + (bs ? a.ring_bs_off[rho] : 0), a.tw, a.tw_log);
     // pixel 2p = Re z_p, pixel 2p+1 = Im z_p
     double2 *out = reinterpret_cast<double2 *>(a.map + (size_t)b * a.npix + a.ring_off[rho]);
     for (int p = tid; p < n; p += T) out[p] = buf[pidx(p)];
@@ -401,6 +416,9 @@ hipError_t launch_ring_synthesis(const sht_plan_s *p, int nmaps, const double *q
     a.bs_table = reinterpret_cast<const double2 *>(p->d_bs_table);
     a.q = reinterpret_cast<const double2 *>(q);
     a.map = map;
+    a.map_in = nullptr;
+    a.ybar = nullptr;
+    a.wpos = 0.0;
     a.L = p->L;
     a.nrings = p->nrings;
     a.nmaps = nmaps;
@@ -411,6 +429,130 @@ hipError_t launch_ring_synthesis(const sht_plan_s *p, int nmaps, const double *q
         default: return launch_classes<1024>(p, a, nmaps, stream);
     }
     return hipSuccess;
+}
+
+// Ring stage of the adjoint (the transpose of the above).  For ring k:
+//   ybar_m = w_m sum_j y_j e^{-i m phi_j} = w_m e^{-i pi m s/J} F_{m mod J},
+//   F_b = sum_j y_j e^{-2 pi i b j/J}  (F_{J-b} = conj F_b),
+// with w_0 = 1 and w_m = wpos for m >= 1.  F_0..F_{J/2} come from one complex
+// DFT of half length on z_p = y_{2p} + i y_{2p+1} (forward DFT taken as the
+// conjugate of the backward one, so the synthesis FFT code is reused), and
+// every m of bin b's two residue classes is written from G_b =
+// e^{-i pi b s/J} F_b:  ybar_{b+jJ} = w (-1)^{js} G_b,
+// ybar_{jJ-b} = w (-1)^{js} conj(G_b).
+template <int T>
+__global__ __launch_bounds__(T) void k_ring_analysis(RingArgs a) {
+    extern __shared__ double2 sm[];
+    const int item = xcd_item(blockIdx.x);
+    if (item >= a.count * a.nmaps) return;
+    const int pos = item / a.nmaps, b = item % a.nmaps;
+    const int rho = a.rings[pos];
+    const int J = a.ring_J[rho], s = a.ring_s[rho], M = a.ring_M[rho];
+    const int n = J / 2, lgn = ilog2_dev(n);
+    const bool bs = M > 0;
+    double2 *buf = sm;
+    const int tid = threadIdx.x;
+    const int L = a.L;
+    const size_t qstride = (size_t)a.nrings * a.nmaps;
+    double2 *yr = a.ybar + (size_t)rho * a.nmaps + b;
+
+    if (bs)
+        for (int i = n + tid; i < M; i += T) buf[pidx(i)] = make_double2(0.0, 0.0);
+    const double2 *pix = reinterpret_cast<const double2 *>(a.map_in + (size_t)b * a.npix + a.ring_off[rho]);
+    for (int p = tid; p < n; p += T) {
+        const double2 zc = cconj(pix[p]);
+        if (!bs) {
+            buf[pidx(bitrev(p, lgn))] = zc;
+        } else {
+            long long r1 = ((long long)p * p) % (2LL * n);
+            buf[pidx(p)] = cmul(zc, expipi((double)r1 / n));
+        }
+    }
+    __syncthreads();
+    backward_dft<T>(buf, n, M, a.bs_table + (bs ? a.ring_bs_off[rho] : 0), a.tw, a.tw_log);
+
+    // bins b = 0..n, split over G groups of the residue classes for small rings
+    const int nb = n + 1;
+    const int G = nb >= T ? 1 : T / nb;
+    for (int u = tid; u < G * nb; u += T) {
+        const int g = u / nb, bin = u % nb;
+        const double2 Zb = cconj(buf[pidx(bin == n ? 0 : bin)]);
+        const double2 Znb = cconj(buf[pidx(bin == 0 ? 0 : n - bin)]);
+        // F_b = (Z_b + conj Z_{n-b})/2 - (i/2) e^{-2 pi i b/J} (Z_b - conj Z_{n-b})
+        const double2 e = cadd(Zb, cconj(Znb));
+        const double2 d = cmul(csub(Zb, cconj(Znb)), expipi(-(double)bin / n));
+        double2 F = make_double2(0.5 * (e.x + d.y), 0.5 * (e.y - d.x));
+        double2 Gb = s ? cmul(F, expipi(-(double)bin / J)) : F;
+        // class 1: m = bin + jJ (j >= 0)
+        for (long long j = g;; j += G) {
+            const long long m = bin + j * J;
+            if (m > L) break;
+            double2 v = (s & j & 1) ? make_double2(-Gb.x, -Gb.y) : Gb;
+            if (m == 0) v = make_double2(v.x, 0.0);
+            else v = make_double2(a.wpos * v.x, a.wpos * v.y);
+            yr[(size_t)m * qstride] = v;
+        }
+        // class 2: m = jJ - bin (j >= 1); bins 0 and n are covered by class 1
+        if (bin != 0 && bin != n) {
+            for (long long j = (g == 0 ? G : g);; j += G) {
+                const long long m = j * J - bin;
+                if (m > L) break;
+                double2 v = cconj(Gb);
+                if (s & j & 1) v = make_double2(-v.x, -v.y);
+                yr[(size_t)m * qstride] = make_double2(a.wpos * v.x, a.wpos * v.y);
+            }
+        }
+    }
+}
+
+template <int T>
+static hipError_t launch_analysis_classes(const sht_plan_s *p, RingArgs a, int nmaps, hipStream_t stream) {
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute((const void *)k_ring_analysis<T>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        attr_set = true;
+    }
+    for (const auto &rc : p->classes) {
+        a.rings = rc.d_rings;
+        a.count = (int)rc.rings.size();
+        a.fft_entries = rc.lds_entries + rc.lds_entries / 16;
+        long long items = (long long)a.count * nmaps;
+        long long grid = (items + 63) / 64 * 64;
+        size_t lds = (size_t)a.fft_entries * sizeof(double2);
+        hipLaunchKernelGGL(k_ring_analysis<T>, dim3((unsigned)grid), dim3(T), lds, stream, a);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_ring_analysis(const sht_plan_s *p, int nmaps, const double *map, double *ybar,
+                                double wpos, hipStream_t stream) {
+    RingArgs a;
+    a.ring_J = p->d_ring_J;
+    a.ring_s = p->d_ring_s;
+    a.ring_M = p->d_ring_M;
+    a.ring_off = p->d_ring_off;
+    a.ring_bs_off = p->d_ring_bs_off;
+    a.tw = reinterpret_cast<const double2 *>(p->d_tw);
+    a.tw_log = p->tw_log;
+    a.bs_table = reinterpret_cast<const double2 *>(p->d_bs_table);
+    a.q = nullptr;
+    a.map = nullptr;
+    a.map_in = map;
+    a.ybar = reinterpret_cast<double2 *>(ybar);
+    a.wpos = wpos;
+    a.L = p->L;
+    a.nrings = p->nrings;
+    a.nmaps = nmaps;
+    a.npix = 12LL * p->nside * p->nside;
+    a.stage = 0;
+    switch (p->ring_threads) {
+        case 256: return launch_analysis_classes<256>(p, a, nmaps, stream);
+        case 512: return launch_analysis_classes<512>(p, a, nmaps, stream);
+        default: return launch_analysis_classes<1024>(p, a, nmaps, stream);
+    }
 }
 
 }  // namespace sht

@@ -17,7 +17,8 @@ LIB_PATH = os.path.join(HERE, "libsht.so")
 
 SHT_OK, SHT_EINVAL, SHT_ENOMEM, SHT_EDEVICE, SHT_ECORRUPT, SHT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 PATH_AUTO, PATH_BRUTE = 0, 1
-STAGE_LEGENDRE, STAGE_RING, NSTAGES = 0, 1, 2
+STAGE_LEGENDRE, STAGE_RING, STAGE_RING_ADJ, STAGE_LEGENDRE_ADJ, NSTAGES = 0, 1, 2, 3, 4
+ADJ_TRANSPOSE, ADJ_DAGGER = 0, 1
 
 _c = ctypes
 _lib = None
@@ -31,7 +32,7 @@ class PlanOpts(_c.Structure):
 class ExecOpts(_c.Structure):
     _fields_ = [("nmaps", _c.c_int), ("path", _c.c_int), ("stream", _c.c_void_p),
                 ("workspace", _c.c_void_p), ("workspace_bytes", _c.c_size_t),
-                ("stage_events", _c.POINTER(_c.c_void_p))]
+                ("adjoint_convention", _c.c_int), ("stage_events", _c.POINTER(_c.c_void_p))]
 
 
 class PlanInfo(_c.Structure):
@@ -51,6 +52,10 @@ EXPORTS = {
     "sht_workspace_bytes": (_c.c_size_t, [_c.c_void_p, _c.POINTER(ExecOpts)]),
     "sht_synthesis": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p]),
     "sht_synthesis_ex": (_c.c_int, [_c.c_void_p, _c.POINTER(ExecOpts), _c.c_void_p, _c.c_void_p]),
+    "sht_adjoint": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p]),
+    "sht_adjoint_ex": (_c.c_int, [_c.c_void_p, _c.POINTER(ExecOpts), _c.c_void_p, _c.c_void_p]),
+    "sht_debug_ring_analysis": (_c.c_int, [_c.c_void_p, _c.POINTER(ExecOpts), _c.c_void_p, _c.c_void_p]),
+    "sht_debug_legendre_adjoint": (_c.c_int, [_c.c_void_p, _c.POINTER(ExecOpts), _c.c_void_p, _c.c_void_p]),
     "sht_last_error": (_c.c_char_p, []),
     "sht_debug_legendre_phase": (_c.c_int, [_c.c_void_p, _c.POINTER(ExecOpts), _c.c_void_p, _c.c_void_p]),
     "sht_debug_ring_synthesis": (_c.c_int, [_c.c_void_p, _c.POINTER(ExecOpts), _c.c_void_p, _c.c_void_p]),
@@ -140,11 +145,12 @@ class Plan:
         return {f: getattr(inf, f) for f, _ in PlanInfo._fields_}
 
     # ---- execution ----------------------------------------------------
-    def _exec(self, nmaps, path=PATH_AUTO, stream=None, workspace=None, events=None):
+    def _exec(self, nmaps, path=PATH_AUTO, stream=None, workspace=None, events=None, convention=ADJ_TRANSPOSE):
         x = ExecOpts()
         load().sht_exec_opts_default(_c.byref(x))
         x.nmaps = int(nmaps)
         x.path = int(path)
+        x.adjoint_convention = int(convention)
         x.stream = _stream_handle(stream)
         if workspace is not None:
             x.workspace = _c.c_void_p(workspace.data_ptr())
@@ -186,6 +192,48 @@ class Plan:
                                        _c.c_void_p(out.data_ptr())))
         return out
 
+    def _map_arg(self, maps):
+        if maps.dtype != torch.float64 or not maps.is_cuda:
+            raise TypeError("maps must be a float64 CUDA tensor")
+        m = maps if maps.dim() == 2 else maps.reshape(1, -1)
+        if m.shape[1] != self.npix:
+            raise ValueError(f"maps have {m.shape[1]} pixels, expected {self.npix}")
+        return m.contiguous()
+
+    def adjoint(self, maps, out=None, *, path=PATH_AUTO, stream=None, workspace=None, events=None,
+                convention=ADJ_TRANSPOSE):
+        """alm (nalm, B) complex128 = A^T maps, maps (B, Npix) or (Npix,) float64."""
+        m = self._map_arg(maps)
+        B = m.shape[0]
+        if out is None:
+            out = torch.empty((self.nalm, B), dtype=torch.complex128, device=m.device)
+        if workspace is None:
+            workspace = self.workspace(B, m.device)
+        x = self._exec(B, path, stream, workspace, events, convention)
+        _check(load().sht_adjoint_ex(self._h, _c.byref(x), _c.c_void_p(m.data_ptr()),
+                                     _c.c_void_p(out.data_ptr())))
+        return out
+
+    def ring_analysis(self, maps, *, stream=None, convention=ADJ_TRANSPOSE):
+        """ybar (L+1, nrings, B) complex128 (private test entry point)."""
+        m = self._map_arg(maps)
+        B = m.shape[0]
+        yb = torch.empty((self.L + 1, self.nrings, B), dtype=torch.complex128, device=m.device)
+        x = self._exec(B, stream=stream, convention=convention)
+        _check(load().sht_debug_ring_analysis(self._h, _c.byref(x), _c.c_void_p(m.data_ptr()),
+                                              _c.c_void_p(yb.data_ptr())))
+        return yb
+
+    def legendre_adjoint(self, ybar, *, stream=None):
+        """alm (nalm, B) from ybar (L+1, nrings, B) (private test entry point)."""
+        yb = ybar.contiguous()
+        B = yb.shape[2]
+        out = torch.empty((self.nalm, B), dtype=torch.complex128, device=yb.device)
+        x = self._exec(B, stream=stream)
+        _check(load().sht_debug_legendre_adjoint(self._h, _c.byref(x), _c.c_void_p(yb.data_ptr()),
+                                                 _c.c_void_p(out.data_ptr())))
+        return out
+
     def legendre_phase(self, alm, *, stream=None):
         """q (L+1, nrings, B) complex128 (private test entry point)."""
         a = self._alm_arg(alm)
@@ -219,3 +267,28 @@ class Plan:
         vals = (_c.c_double * 2)()
         _check(load().sht_debug_start(self._h, int(m), int(t), int(k), _c.byref(idx), vals))
         return idx.value, (vals[0], vals[1])
+
+
+class _Synthesis(torch.autograd.Function):
+    """maps = synthesis(alm) with the hand-written transpose as its backward.
+
+    For a real loss, torch's gradient of a complex leaf is dL/dRe + i dL/dIm,
+    which is the adjoint under the real inner product (convention
+    ADJ_TRANSPOSE); Im a_l0 does not enter synthesis and gets zero gradient.
+    """
+
+    @staticmethod
+    def forward(ctx, plan, alm):
+        ctx.plan = plan
+        ctx.shape = alm.shape
+        return plan.synthesis(alm.detach())
+
+    @staticmethod
+    def backward(ctx, grad_maps):
+        g = ctx.plan.adjoint(grad_maps.contiguous(), convention=ADJ_TRANSPOSE)
+        return None, g.reshape(ctx.shape)
+
+
+def synthesis_fn(plan, alm):
+    """Differentiable synthesis: alm (nalm, B) or (nalm,) complex128 -> maps."""
+    return _Synthesis.apply(plan, alm)

@@ -22,3 +22,9 @@ def gpu():
     from paper_1110_4874_amd import sht
     sht.load()
     return sht
+
+
+@pytest.fixture(scope="session")
+def plan4095(gpu):
+    """The benchmark workload's plan (L = 4095, nside = 2048), built once."""
+    return gpu.Plan(4095, 2048)

@@ -81,11 +81,11 @@ def test_white_spectrum_l511(gpu):
     assert maxrel(f, ref) <= TOL
 
 
-def test_l4095_sampled_rings_vs_long_double(gpu):
+def test_l4095_sampled_rings_vs_long_double(gpu, plan4095):
     # the benchmark's configuration: L = 4095, nside = 2048, 4 maps
     L, N, B = 4095, 2048, 4
     alm = alm_gaussian(L, [400, 401, 402, 403])
-    p = gpu.Plan(L, N)
+    p = plan4095
     f = p.synthesis(_dev(alm)).cpu().numpy()
     rings = [1, 2, 3, 17, 100, 255, 256, 700, 2047, 2048, 2049, 3000, 4095, 4096, 4097, 6000,
              8000, 8190, 8191]
