@@ -53,7 +53,19 @@ typedef enum {
     SHT_EUNSUPPORTED = -5  /* valid request outside what this build supports */
 } sht_status;
 
-enum { SHT_PATH_AUTO = 0, SHT_PATH_BRUTE = 1 };
+enum {
+    SHT_PATH_AUTO = 0,      /* butterfly when the plan has it (eps > 0), else brute force */
+    SHT_PATH_BRUTE = 1,     /* recurrence over every (l, ring) above the cutoff (App. A.2) */
+    SHT_PATH_BUTTERFLY = 2  /* compressed operator of Sec. 4.2; needs an eps > 0 plan */
+};
+
+/* Arithmetic of the butterfly level products (sht_exec_opts.precision).
+ * The residual recurrence, the fold and the ring FFT stay FP64. */
+enum {
+    SHT_PREC_FP64 = 0,
+    SHT_PREC_FP32 = 1       /* FP32 interpolation matrices and vectors with FP32
+                               accumulation (plan built with store_fp32) */
+};
 
 /* Stages of a transform, for sht_exec_opts.stage_events. */
 enum {
@@ -88,6 +100,19 @@ typedef struct sht_plan_opts {
                           1024 (0 = default 1024); a tuning knob */
     int host_only;     /* 1: build host tables only (no device memory); such a
                           plan can be inspected but not executed */
+    /* Butterfly compression (eps > 0 plans only; Sec. 4.2 and 4.4): */
+    double rho;        /* cost of one stored interpolation entry relative to one
+                          residual recurrence element when choosing the depth per
+                          (m, parity); <= 0 selects the default 2.5 (MI355X: HBM
+                          bytes of an FP64 entry vs the FP64 flops of an element
+                          at 4 maps) */
+    int max_levels;    /* -1: depth from the rho cost model; 0: no compression;
+                          > 0: exactly this many levels where the rows allow */
+    int chunk;         /* column block width at level 1 (0 = default 64) */
+    double id_safety;  /* IDs are taken at tolerance eps / id_safety (>= 1;
+                          0 = default 1) */
+    int store_fp32;    /* 1: also keep an FP32 copy of the interpolation
+                          matrices for SHT_PREC_FP32 */
 } sht_plan_opts;
 
 /* Options for one execution.  Fill with sht_exec_opts_default() first. */
@@ -99,6 +124,7 @@ typedef struct sht_exec_opts {
                                  NULL to let the call allocate (stream ordered) */
     size_t workspace_bytes;
     int adjoint_convention;   /* SHT_ADJ_*, used by the adjoint only */
+    int precision;            /* SHT_PREC_*, butterfly path only */
     void **stage_events;      /* NULL, or 2*SHT_NSTAGES hipEvent_t handles
                                  (entries may be NULL): events[2s] is recorded
                                  on the stream before stage s runs and
@@ -120,17 +146,29 @@ typedef struct sht_plan_info {
                                  lanes of partially active waves included) */
     size_t device_bytes;      /* device memory held by the plan */
     double build_seconds;     /* wall time of sht_plan */
+    /* butterfly (zero unless eps > 0) */
+    int bf_built;
+    long long bf_T_entries;   /* stored dense interpolation entries (FP64: 8 B each) */
+    long long bf_res_elems;   /* residual recurrence elements (l, skeleton ring) */
+    long long bf_nodes;       /* pair nodes over all (m, parity, level) */
+    long long bf_units;       /* level output columns over all nodes */
+    long long bf_res_lanes;   /* residual (leaf, skeleton ring) lanes */
+    long long bf_depth_hist[11]; /* (m, parity) items per kept depth 0..10 */
+    double bf_build_seconds;
 } sht_plan_info_t;
 
 void sht_plan_opts_default(sht_plan_opts *o);
 void sht_exec_opts_default(sht_exec_opts *o);
 
 /* Build a plan for band limit L >= 0 on a HEALPix grid of resolution
- * 1 <= nside <= 2048, on the current HIP device.  eps = 0 selects the
- * brute-force Legendre transform (the only path of this build; eps > 0 is
- * rejected with SHT_EUNSUPPORTED).  The plan holds the ring geometry, the
- * two-step recurrence coefficients of App. A.2 Eq. A2 and, per (m, parity,
- * ring), the first Legendre values above the cutoff (App. A.2).
+ * 1 <= nside <= 2048, on the current HIP device.  The plan holds the ring
+ * geometry, the two-step recurrence coefficients of App. A.2 Eq. A2 and, per
+ * (m, parity, ring), the first Legendre values above the cutoff (App. A.2):
+ * everything the brute-force path needs.  eps > 0 additionally runs the FP64
+ * butterfly precompute of Sec. 4.2 (interpolative decompositions at
+ * tolerance eps, Eq. 17, depth per (m, parity) from the cost model of
+ * Sec. 4.4) on the host's cores and uploads the compressed operator; this
+ * takes minutes at L = 4095 and tens of GB of device memory.
  * Returns NULL on failure (see sht_last_error).  The plan is immutable and
  * may be shared by threads; free it with sht_plan_free. */
 sht_plan_t *sht_plan(int L, int nside, double eps);
@@ -138,8 +176,9 @@ sht_plan_t *sht_plan_ex(int L, int nside, double eps, const sht_plan_opts *opts)
 void sht_plan_free(sht_plan_t *plan);
 int sht_plan_info(const sht_plan_t *plan, sht_plan_info_t *out);
 
-/* Device scratch needed by one execution with these options (the Legendre
- * phase buffer, nmaps * (L+1) * nrings complex values). */
+/* Device scratch needed by one execution with these options: the Legendre
+ * phase buffer, nmaps * (L+1) * nrings complex values, plus on the butterfly
+ * path one vector slot per resident workgroup. */
 size_t sht_workspace_bytes(const sht_plan_t *plan, const sht_exec_opts *x);
 
 /* Synthesis f = Y a for one map (sht_synthesis) or x->nmaps maps. */
@@ -193,6 +232,23 @@ int sht_debug_legendre_adjoint(const sht_plan_t *plan, const sht_exec_opts *x,
                                const double *ybar, double *alm);
 
 int sht_debug_coef(const sht_plan_t *plan, int m, double *coef_out);
+
+/* Interpolative decomposition of Sec. 4.1 on the host, as the butterfly
+ * precompute takes it: A is r x c column-major (not modified), tol the
+ * relative tolerance.  Writes the rank to *k, the column order to piv[c]
+ * (piv[0..k) are the skeleton columns) and T (k x (c-k), row-major) with
+ * A[:, piv[k+j]] ~= sum_s A[:, piv[s]] T[s][j]; T must hold c*c doubles. */
+int sht_debug_interp_decomp(const double *A, int r, int c, double tol, int *k, int *piv, double *T);
+
+/* Host evaluation of q^t_m(z_k) = sum_i Lambda[i][k] x_i over the north
+ * rings from the plan's compressed records (residual recurrence + levels),
+ * for x of length n_t = (L - m - t)/2 + 1 (real).  y: n_north doubles.
+ * Needs an eps > 0 plan whose interpolation data is still on the host
+ * (plans under 256 MiB of it). */
+int sht_debug_butterfly_apply(const sht_plan_t *plan, int m, int t, const double *x, double *y);
+
+/* Depth kept for (m, t) of an eps > 0 plan, or -1. */
+int sht_debug_butterfly_depth(const sht_plan_t *plan, int m, int t);
 int sht_debug_start(const sht_plan_t *plan, int m, int t, int k, int *idx,
                     double *vals);
 

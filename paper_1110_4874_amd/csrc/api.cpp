@@ -64,12 +64,27 @@ size_t nalm_of(int L) { return (size_t)(L + 1) * (L + 2) / 2; }
 size_t npix_of(int N) { return 12ull * N * N; }
 size_t q_bytes(const sht_plan_t *p, int B) { return (size_t)(p->L + 1) * p->nrings * B * 16; }
 
+bool use_butterfly(const sht_plan_t *p, const sht_exec_opts *x) {
+    return p->bf.built && (x->path == SHT_PATH_BUTTERFLY || (x->path == SHT_PATH_AUTO));
+}
+
+size_t synth_ws_bytes(const sht_plan_t *p, const sht_exec_opts *x) {
+    size_t b = q_bytes(p, x->nmaps);
+    if (use_butterfly(p, x)) b += bf_scratch_bytes(p, x->nmaps, x->precision == SHT_PREC_FP32);
+    return b;
+}
+
 int check_exec(const sht_plan_t *p, const sht_exec_opts *x) {
     if (!x) return fail(SHT_EINVAL, "exec opts is NULL");
     if (x->nmaps < 1) return fail(SHT_EINVAL, "nmaps must be >= 1");
-    if (x->path != SHT_PATH_AUTO && x->path != SHT_PATH_BRUTE)
-        return fail(SHT_EUNSUPPORTED, "only the brute-force path is available");
-    (void)p;
+    if (x->path != SHT_PATH_AUTO && x->path != SHT_PATH_BRUTE && x->path != SHT_PATH_BUTTERFLY)
+        return fail(SHT_EINVAL, "unknown path");
+    if (x->path == SHT_PATH_BUTTERFLY && !p->bf.built)
+        return fail(SHT_EUNSUPPORTED, "the butterfly path needs a plan built with eps > 0");
+    if (x->precision != SHT_PREC_FP64 && x->precision != SHT_PREC_FP32)
+        return fail(SHT_EINVAL, "unknown precision");
+    if (x->precision == SHT_PREC_FP32 && !p->d_bf_T32)
+        return fail(SHT_EUNSUPPORTED, "FP32 butterfly products need a plan built with store_fp32 = 1");
     return SHT_OK;
 }
 
@@ -126,6 +141,11 @@ void sht_plan_opts_default(sht_plan_opts *o) {
     o->rings_per_lane = 0;
     o->ring_threads = 0;
     o->host_only = 0;
+    o->rho = 0.0;
+    o->max_levels = -1;
+    o->chunk = 0;
+    o->id_safety = 0.0;
+    o->store_fp32 = 0;
 }
 
 void sht_exec_opts_default(sht_exec_opts *o) {
@@ -136,6 +156,7 @@ void sht_exec_opts_default(sht_exec_opts *o) {
     o->workspace = nullptr;
     o->workspace_bytes = 0;
     o->adjoint_convention = SHT_ADJ_TRANSPOSE;
+    o->precision = SHT_PREC_FP64;
     o->stage_events = nullptr;
 }
 
@@ -157,13 +178,17 @@ sht_plan_t *sht_plan_ex(int L, int nside, double eps, const sht_plan_opts *opts)
         fail(SHT_EINVAL, "eps must be >= 0");
         return nullptr;
     }
-    if (eps > 0.0) {
-        fail(SHT_EUNSUPPORTED, "butterfly compression (eps > 0) is not available in this build");
+    if (eps >= 1e-2) {
+        fail(SHT_EINVAL, "eps must be below 1e-2");
         return nullptr;
     }
     sht_plan_opts o;
     sht_plan_opts_default(&o);
     if (opts) o = *opts;
+    if (o.max_levels < -1 || o.max_levels > kBfMaxLv || o.chunk < 0 || o.chunk > 4096) {
+        fail(SHT_EINVAL, "max_levels must be in [-1, 10] and chunk in [0, 4096]");
+        return nullptr;
+    }
     if (!(o.cutoff > 0.0) || o.cutoff > 1e-10) {
         fail(SHT_EINVAL, "cutoff must be in (0, 1e-10]");
         return nullptr;
@@ -228,12 +253,23 @@ int sht_plan_info(const sht_plan_t *p, sht_plan_info_t *out) {
     out->n_step_lanes = p->n_step_lanes;
     out->device_bytes = p->device_bytes;
     out->build_seconds = p->build_seconds;
+    const BflyPlan &b = p->bf;
+    out->bf_built = b.built;
+    if (b.built) {
+        out->bf_T_entries = b.T_entries;
+        out->bf_res_elems = b.res_elems;
+        out->bf_nodes = b.n_nodes;
+        out->bf_units = (long long)b.unit_node.size();
+        out->bf_res_lanes = (long long)b.res_rec.size() / 4;
+        for (int i = 0; i <= kBfMaxLv; i++) out->bf_depth_hist[i] = b.depth_hist[i];
+        out->bf_build_seconds = b.build_seconds;
+    }
     return SHT_OK;
 }
 
 size_t sht_workspace_bytes(const sht_plan_t *p, const sht_exec_opts *x) {
     if (!p || !x || x->nmaps < 1) return 0;
-    return q_bytes(p, x->nmaps);
+    return synth_ws_bytes(p, x);
 }
 
 int sht_synthesis(const sht_plan_t *p, const double *alm, double *map) {
@@ -252,11 +288,18 @@ int sht_synthesis_ex(const sht_plan_t *p, const sht_exec_opts *x, const double *
     if ((rc = check_dev_ptr(alm, nalm_of(p->L) * B * 16, p->device, "alm"))) return rc;
     if ((rc = check_dev_ptr(map, npix_of(p->nside) * B * 8, p->device, "map"))) return rc;
     Scratch ws;
-    if ((rc = ws.get(x, q_bytes(p, B), p->device))) return rc;
+    if ((rc = ws.get(x, synth_ws_bytes(p, x), p->device))) return rc;
     hipStream_t st = (hipStream_t)x->stream;
     double *q = (double *)ws.ptr;
     stage_event(x, SHT_STAGE_LEGENDRE, 0);
-    if ((rc = hip_status(launch_legendre(p, B, alm, q, st), "Legendre kernel launch"))) return rc;
+    if (use_butterfly(p, x)) {
+        void *scr = (char *)ws.ptr + q_bytes(p, B);
+        if ((rc = hip_status(launch_butterfly(p, B, alm, q, scr, x->precision == SHT_PREC_FP32, st),
+                             "butterfly kernel launch")))
+            return rc;
+    } else if ((rc = hip_status(launch_legendre(p, B, alm, q, st), "Legendre kernel launch"))) {
+        return rc;
+    }
     stage_event(x, SHT_STAGE_LEGENDRE, 1);
     stage_event(x, SHT_STAGE_RING, 0);
     rc = hip_status(launch_ring_synthesis(p, B, q, map, st), "ring kernel launch");
@@ -324,6 +367,28 @@ int sht_debug_legendre_adjoint(const sht_plan_t *p, const sht_exec_opts *x, cons
     if ((rc = check_dev_ptr(alm, nalm_of(p->L) * B * 16, p->device, "alm"))) return rc;
     return hip_status(launch_legendre_adjoint(p, B, ybar, alm, (hipStream_t)x->stream),
                       "adjoint Legendre launch");
+}
+
+int sht_debug_interp_decomp(const double *A, int r, int c, double tol, int *k, int *piv, double *T) {
+    if (!A || !k || !piv || !T || r < 1 || c < 1 || !(tol > 0)) return fail(SHT_EINVAL, "bad argument");
+    std::vector<double> w(A, A + (size_t)r * c), Tv;
+    std::vector<int> pv;
+    *k = interp_decomp(w.data(), r, c, tol, 0.0, pv, Tv);
+    std::memcpy(piv, pv.data(), sizeof(int) * c);
+    std::memcpy(T, Tv.data(), sizeof(double) * Tv.size());
+    return SHT_OK;
+}
+
+int sht_debug_butterfly_apply(const sht_plan_t *p, int m, int t, const double *x, double *y) {
+    if (!p || !x || !y || m < 0 || m > p->L || t < 0 || t > 1) return fail(SHT_EINVAL, "bad argument");
+    if (!p->bf.built) return fail(SHT_EUNSUPPORTED, "plan has no butterfly (eps = 0)");
+    if (!p->bf.host_T_kept) return fail(SHT_EUNSUPPORTED, "interpolation data is on the device only");
+    return butterfly_apply_host(p, m, t, x, y);
+}
+
+int sht_debug_butterfly_depth(const sht_plan_t *p, int m, int t) {
+    if (!p || !p->bf.built || m < 0 || m > p->L || t < 0 || t > 1) return -1;
+    return p->bf.depth[(size_t)2 * m + t];
 }
 
 int sht_debug_legendre_phase(const sht_plan_t *p, const sht_exec_opts *x, const double *alm, double *q) {

@@ -30,6 +30,42 @@ int fail(int code, const std::string &msg);
 // Run fn(i) for i in [0, n) on up to nthreads host threads (dynamic schedule).
 void parallel_for(long n, int nthreads, void (*fn)(long, void *), void *ctx);
 
+// Butterfly records (butterfly_plan.cpp builds them, butterfly.hip walks them).
+constexpr int kBfMaxLv = 10;     // deepest level a plan may keep
+constexpr int kBfNodeInts = 8;   // vin0, vin1, k0, k1, nd0, nd1, out, ubase
+
+// Long-double inputs of the butterfly precompute (from the plan build).
+struct BflyInput {
+    const long double *coefl;     // [entries][3] beta, alpha*beta, gamma
+    const long double *start_ld;  // [(L+1)*2][2][n_north_pad] chain start values
+    const long double *z2l;       // [n_north] z^2
+};
+
+struct BflyPlan {
+    int built = 0;
+    int K = 0;                        // columns: north rings
+    long long vmax = 0;               // entries of one parity's level vector region
+    long long slot_entries = 0;       // 2K + 4 vmax entries of 2B doubles per work slot
+    std::vector<int> depth;           // [(L+1)*2] levels kept per (m, t)
+    std::vector<int> order;           // [L+1] m by decreasing work
+    std::vector<long long> res_off;   // [L+2] residual lanes of m
+    std::vector<int> res_rec;         // [lanes][4] ring, i0, i1, 2*out + t
+    std::vector<double> res_val;      // [lanes][2] Legendre values at i0, i0+1
+    std::vector<long long> unit_off;  // [L+1][kBfMaxLv+1] unit ranges, deepest level first
+    std::vector<int> unit_node;       // [units] pair node of the unit
+    std::vector<int> code;            // [units] (code0 & 0xffff) | code1 << 16
+    std::vector<int> node_i;          // [nodes][kBfNodeInts]
+    std::vector<long long> node_T;    // [nodes][2] offsets of the dense blocks in T
+    std::vector<double> T;            // interpolation matrices, dense part, [s][d]
+    long long T_entries = 0, res_elems = 0, n_nodes = 0;
+    long long depth_hist[kBfMaxLv + 1] = {};
+    double build_seconds = 0.0;
+    bool host_T_kept = true;
+};
+
+int interp_decomp(double *A, int r, int c, double tol, double abs_floor, std::vector<int> &piv,
+                  std::vector<double> &T);
+
 struct RingClass {
     int lds_entries;              // complex entries of the FFT buffer (before padding)
     bool wrap = false;            // some ring has J/2 <= L (q staged through LDS)
@@ -80,12 +116,22 @@ struct sht_plan_s {
     double *d_tw = nullptr, *d_bs_table = nullptr;
     size_t device_bytes = 0;
 
+    // ---- butterfly (eps > 0) ------------------------------------------
+    sht::BflyPlan bf;
+    int *d_bf_order = nullptr, *d_bf_depth = nullptr, *d_bf_res_rec = nullptr;
+    long long *d_bf_res_off = nullptr, *d_bf_unit_off = nullptr, *d_bf_node_T = nullptr;
+    double *d_bf_res_val = nullptr, *d_bf_T = nullptr;
+    float *d_bf_T32 = nullptr;
+    int *d_bf_unit_node = nullptr, *d_bf_code = nullptr, *d_bf_node_i = nullptr;
+
 };
 
 namespace sht {
 
-// Host plan construction (plan.cpp).
+// Host plan construction (plan.cpp, butterfly_plan.cpp).
 int build_host_tables(sht_plan_s *p);
+int build_butterfly(sht_plan_s *p, const BflyInput &in);
+int butterfly_apply_host(const sht_plan_s *p, int m, int t, const double *x, double *y);
 int upload_tables(sht_plan_s *p);
 void free_device_tables(sht_plan_s *p);
 
@@ -98,5 +144,12 @@ hipError_t launch_ring_analysis(const sht_plan_s *p, int nmaps, const double *ma
                                 double wpos, hipStream_t stream);
 hipError_t launch_legendre_adjoint(const sht_plan_s *p, int nmaps, const double *ybar, double *g,
                                    hipStream_t stream);
+// Butterfly Legendre phase (eps > 0 plans): alm -> folded q, like
+// launch_legendre; scratch holds bf_slots() slots of slot_entries * 2 * nmaps
+// doubles (FP64) or floats (FP32).
+int bf_slots(const sht_plan_s *p);
+size_t bf_scratch_bytes(const sht_plan_s *p, int nmaps, int fp32);
+hipError_t launch_butterfly(const sht_plan_s *p, int nmaps, const double *alm, double *q, void *scratch,
+                            int fp32, hipStream_t stream);
 
 }  // namespace sht

@@ -105,6 +105,8 @@ struct BuildCtx {
     std::vector<long long> steps;  // per ring: executed steps
     std::vector<long long> alive;  // per ring: steps at or above the cutoff
     std::vector<long long> lane_steps;  // per m: lane-steps executed by the kernel
+    bool keep_ld = false;               // butterfly: keep long-double starts
+    std::vector<ld> start_ld;           // [(L+1)*2][2][n_north_pad]
 };
 
 static void coef_worker(long m, void *vctx) {
@@ -191,6 +193,10 @@ static void start_worker(long k, void *vctx) {
                 // one of the pair may sit on a root of P~; the pair as a whole must
                 // be far from the double underflow range
                 if (fmax(fabs(ah), fabs(bh)) < 1e-290) c->bad.store(1);
+                if (c->keep_ld) {
+                    c->start_ld[(row * 2 + 0) * np + k] = a;
+                    c->start_ld[(row * 2 + 1) * np + k] = b;
+                }
                 p->start_idx[row * np + k] = found;
                 p->start_val[(row * 2 + 0) * np + k] = ah;
                 p->start_val[(row * 2 + 1) * np + k] = bh;
@@ -377,6 +383,8 @@ int build_host_tables(sht_plan_s *p) {
     p->start_lo.assign((size_t)(L + 1) * 2 * 2 * std::max(p->n_dd_pad, 1), 0.0);
     ctx.steps.assign(np, 0);
     ctx.alive.assign(np, 0);
+    ctx.keep_ld = p->eps > 0.0;
+    if (ctx.keep_ld) ctx.start_ld.assign((size_t)(L + 1) * 2 * 2 * np, 0.0L);
     parallel_for(p->n_north, nth, start_worker, &ctx);
     if (ctx.bad.load())
         return fail(SHT_EUNSUPPORTED,
@@ -431,6 +439,14 @@ int build_host_tables(sht_plan_s *p) {
         ld ang = 2.0L * kPi * (ld)k / (ld)(1 << p->tw_log);
         p->tw[2 * k] = (double)cosl(ang);
         p->tw[2 * k + 1] = (double)sinl(ang);
+    }
+    if (ctx.keep_ld) {
+        std::vector<ld> z2l(p->n_north);
+        for (int k = 0; k < p->n_north; k++) z2l[k] = ctx.zl[k] * ctx.zl[k];
+        BflyInput in{ctx.coefl.data(), ctx.start_ld.data(), z2l.data()};
+        int rc = build_butterfly(p, in);
+        if (rc != SHT_OK) return rc;
+        std::vector<ld>().swap(ctx.start_ld);
     }
     const int class_size[4] = {1024, 2048, 4096, 8192};
     p->classes.clear();
@@ -489,6 +505,41 @@ int upload_tables(sht_plan_s *p) {
 #undef UP
     for (auto &rc : p->classes)
         if (e == hipSuccess) e = up(&rc.d_rings, rc.rings, &b);
+    if (p->bf.built) {
+        BflyPlan &f = p->bf;
+#define UPB(d, h) \
+    if (e == hipSuccess) e = up(&p->d, f.h, &b)
+        UPB(d_bf_order, order);
+        UPB(d_bf_depth, depth);
+        UPB(d_bf_res_off, res_off);
+        UPB(d_bf_res_rec, res_rec);
+        UPB(d_bf_res_val, res_val);
+        UPB(d_bf_unit_off, unit_off);
+        UPB(d_bf_unit_node, unit_node);
+        UPB(d_bf_code, code);
+        UPB(d_bf_node_i, node_i);
+        UPB(d_bf_node_T, node_T);
+        UPB(d_bf_T, T);
+#undef UPB
+        if (e == hipSuccess && p->opts.store_fp32) {
+            const size_t n = std::max<size_t>(f.T.size(), 1);
+            e = hipMalloc((void **)&p->d_bf_T32, n * sizeof(float));
+            b += n * sizeof(float);
+            std::vector<float> buf;
+            const size_t chunk = (size_t)1 << 24;
+            for (size_t o = 0; e == hipSuccess && o < f.T.size(); o += chunk) {
+                const size_t cnt = std::min(chunk, f.T.size() - o);
+                buf.resize(cnt);
+                for (size_t i = 0; i < cnt; i++) buf[i] = (float)f.T[o + i];
+                e = hipMemcpy(p->d_bf_T32 + o, buf.data(), cnt * sizeof(float), hipMemcpyHostToDevice);
+            }
+        }
+        // large interpolation data lives on the device only
+        if (e == hipSuccess && f.T.size() * sizeof(double) > ((size_t)256 << 20)) {
+            std::vector<double>().swap(f.T);
+            f.host_T_kept = false;
+        }
+    }
     p->device_bytes = b;
     if (e != hipSuccess) {
         free_device_tables(p);
@@ -502,7 +553,10 @@ void free_device_tables(sht_plan_s *p) {
     void *ptrs[] = {p->d_z2_hi,     p->d_z2_lo,     p->d_ring_J,     p->d_ring_s,   p->d_ring_M,
                     p->d_ring_off,  p->d_ring_bs_off, p->d_coef_off, p->d_coef_hi,  p->d_coef_lo,
                     p->d_start_idx, p->d_start_val, p->d_start_lo,   p->d_grp_lo,   p->d_grp_hi,
-                    p->d_tw,        p->d_bs_table};
+                    p->d_tw,        p->d_bs_table,
+                    p->d_bf_order,  p->d_bf_depth,  p->d_bf_res_rec, p->d_bf_res_off, p->d_bf_unit_off,
+                    p->d_bf_node_T, p->d_bf_res_val, p->d_bf_T,      p->d_bf_T32,   p->d_bf_unit_node,
+                    p->d_bf_code,   p->d_bf_node_i};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     for (auto &rc : p->classes)
@@ -516,6 +570,11 @@ void free_device_tables(sht_plan_s *p) {
     p->d_start_val = p->d_start_lo = nullptr;
     p->d_grp_lo = p->d_grp_hi = nullptr;
     p->d_tw = p->d_bs_table = nullptr;
+    p->d_bf_order = p->d_bf_depth = p->d_bf_res_rec = nullptr;
+    p->d_bf_res_off = p->d_bf_unit_off = p->d_bf_node_T = nullptr;
+    p->d_bf_res_val = p->d_bf_T = nullptr;
+    p->d_bf_T32 = nullptr;
+    p->d_bf_unit_node = p->d_bf_code = p->d_bf_node_i = nullptr;
     p->device_bytes = 0;
 }
 

@@ -16,7 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsht.so")
 
 SHT_OK, SHT_EINVAL, SHT_ENOMEM, SHT_EDEVICE, SHT_ECORRUPT, SHT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-PATH_AUTO, PATH_BRUTE = 0, 1
+PATH_AUTO, PATH_BRUTE, PATH_BUTTERFLY = 0, 1, 2
+PREC_FP64, PREC_FP32 = 0, 1
 STAGE_LEGENDRE, STAGE_RING, STAGE_RING_ADJ, STAGE_LEGENDRE_ADJ, NSTAGES = 0, 1, 2, 3, 4
 ADJ_TRANSPOSE, ADJ_DAGGER = 0, 1
 
@@ -26,20 +27,26 @@ _lib = None
 
 class PlanOpts(_c.Structure):
     _fields_ = [("cutoff", _c.c_double), ("dd_sin", _c.c_double), ("nthreads", _c.c_int),
-                ("rings_per_lane", _c.c_int), ("ring_threads", _c.c_int), ("host_only", _c.c_int)]
+                ("rings_per_lane", _c.c_int), ("ring_threads", _c.c_int), ("host_only", _c.c_int),
+                ("rho", _c.c_double), ("max_levels", _c.c_int), ("chunk", _c.c_int),
+                ("id_safety", _c.c_double), ("store_fp32", _c.c_int)]
 
 
 class ExecOpts(_c.Structure):
     _fields_ = [("nmaps", _c.c_int), ("path", _c.c_int), ("stream", _c.c_void_p),
                 ("workspace", _c.c_void_p), ("workspace_bytes", _c.c_size_t),
-                ("adjoint_convention", _c.c_int), ("stage_events", _c.POINTER(_c.c_void_p))]
+                ("adjoint_convention", _c.c_int), ("precision", _c.c_int),
+                ("stage_events", _c.POINTER(_c.c_void_p))]
 
 
 class PlanInfo(_c.Structure):
     _fields_ = [("L", _c.c_int), ("nside", _c.c_int), ("nrings", _c.c_int), ("n_dd_rings", _c.c_int),
                 ("eps", _c.c_double), ("n_step", _c.c_longlong), ("n_step_exec", _c.c_longlong),
                 ("n_step_dd", _c.c_longlong), ("n_step_lanes", _c.c_longlong),
-                ("device_bytes", _c.c_size_t), ("build_seconds", _c.c_double)]
+                ("device_bytes", _c.c_size_t), ("build_seconds", _c.c_double),
+                ("bf_built", _c.c_int), ("bf_T_entries", _c.c_longlong), ("bf_res_elems", _c.c_longlong),
+                ("bf_nodes", _c.c_longlong), ("bf_units", _c.c_longlong), ("bf_res_lanes", _c.c_longlong),
+                ("bf_depth_hist", _c.c_longlong * 11), ("bf_build_seconds", _c.c_double)]
 
 
 EXPORTS = {
@@ -60,6 +67,10 @@ EXPORTS = {
     "sht_debug_legendre_phase": (_c.c_int, [_c.c_void_p, _c.POINTER(ExecOpts), _c.c_void_p, _c.c_void_p]),
     "sht_debug_ring_synthesis": (_c.c_int, [_c.c_void_p, _c.POINTER(ExecOpts), _c.c_void_p, _c.c_void_p]),
     "sht_debug_coef": (_c.c_int, [_c.c_void_p, _c.c_int, _c.POINTER(_c.c_double)]),
+    "sht_debug_interp_decomp": (_c.c_int, [_c.c_void_p, _c.c_int, _c.c_int, _c.c_double,
+                                           _c.POINTER(_c.c_int), _c.c_void_p, _c.c_void_p]),
+    "sht_debug_butterfly_apply": (_c.c_int, [_c.c_void_p, _c.c_int, _c.c_int, _c.c_void_p, _c.c_void_p]),
+    "sht_debug_butterfly_depth": (_c.c_int, [_c.c_void_p, _c.c_int, _c.c_int]),
     "sht_debug_start": (_c.c_int, [_c.c_void_p, _c.c_int, _c.c_int, _c.c_int, _c.POINTER(_c.c_int),
                                    _c.POINTER(_c.c_double)]),
 }
@@ -91,6 +102,22 @@ def _check(rc):
         raise ShtError(rc, load().sht_last_error().decode())
 
 
+def interp_decomp(A, tol):
+    """Host interpolative decomposition as the butterfly precompute takes it
+    (private test entry point).  A: (r, c) float64.  Returns (k, piv, T)."""
+    import numpy as np
+    A = np.asarray(A, dtype=np.float64)
+    r, c = A.shape
+    Af = np.asfortranarray(A)
+    k = _c.c_int(0)
+    piv = np.zeros(c, dtype=np.int32)
+    T = np.zeros(c * c, dtype=np.float64)
+    _check(load().sht_debug_interp_decomp(Af.ctypes.data_as(_c.c_void_p), r, c, float(tol), _c.byref(k),
+                                          piv.ctypes.data_as(_c.c_void_p), T.ctypes.data_as(_c.c_void_p)))
+    kk = k.value
+    return kk, piv, T[:kk * (c - kk)].reshape(kk, c - kk)
+
+
 def nalm(L):
     return (L + 1) * (L + 2) // 2
 
@@ -104,10 +131,16 @@ class Plan:
     """A transform plan for band limit L on a HEALPix grid of resolution nside."""
 
     def __init__(self, L, nside, eps=0.0, *, cutoff=None, dd_sin=None, nthreads=0, rings_per_lane=0,
-                 ring_threads=0, host_only=False):
+                 ring_threads=0, host_only=False, rho=0.0, max_levels=-1, chunk=0, id_safety=0.0,
+                 store_fp32=False):
         lib = load()
         o = PlanOpts()
         lib.sht_plan_opts_default(_c.byref(o))
+        o.rho = float(rho)
+        o.max_levels = int(max_levels)
+        o.chunk = int(chunk)
+        o.id_safety = float(id_safety)
+        o.store_fp32 = 1 if store_fp32 else 0
         if cutoff is not None:
             o.cutoff = cutoff
         if dd_sin is not None:
@@ -142,14 +175,31 @@ class Plan:
     def info(self):
         inf = PlanInfo()
         _check(load().sht_plan_info(self._h, _c.byref(inf)))
-        return {f: getattr(inf, f) for f, _ in PlanInfo._fields_}
+        d = {f: getattr(inf, f) for f, _ in PlanInfo._fields_}
+        d["bf_depth_hist"] = list(inf.bf_depth_hist)
+        return d
+
+    def butterfly_apply_host(self, m, t, x):
+        """Host evaluation of Lambda^T x for (m, parity t) from the compressed
+        records (private test entry point); x: numpy float64 of length n_t."""
+        import numpy as np
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        y = np.zeros(2 * self.nside, dtype=np.float64)
+        _check(load().sht_debug_butterfly_apply(self._h, int(m), int(t), x.ctypes.data_as(_c.c_void_p),
+                                                y.ctypes.data_as(_c.c_void_p)))
+        return y
+
+    def butterfly_depth(self, m, t):
+        return int(load().sht_debug_butterfly_depth(self._h, int(m), int(t)))
 
     # ---- execution ----------------------------------------------------
-    def _exec(self, nmaps, path=PATH_AUTO, stream=None, workspace=None, events=None, convention=ADJ_TRANSPOSE):
+    def _exec(self, nmaps, path=PATH_AUTO, stream=None, workspace=None, events=None, convention=ADJ_TRANSPOSE,
+              precision=PREC_FP64):
         x = ExecOpts()
         load().sht_exec_opts_default(_c.byref(x))
         x.nmaps = int(nmaps)
         x.path = int(path)
+        x.precision = int(precision)
         x.adjoint_convention = int(convention)
         x.stream = _stream_handle(stream)
         if workspace is not None:
@@ -164,12 +214,12 @@ class Plan:
             self._keep = arr
         return x
 
-    def workspace_bytes(self, nmaps=1):
-        x = self._exec(nmaps)
+    def workspace_bytes(self, nmaps=1, path=PATH_AUTO, precision=PREC_FP64):
+        x = self._exec(nmaps, path=path, precision=precision)
         return int(load().sht_workspace_bytes(self._h, _c.byref(x)))
 
-    def workspace(self, nmaps=1, device="cuda"):
-        return torch.empty(self.workspace_bytes(nmaps), dtype=torch.uint8, device=device)
+    def workspace(self, nmaps=1, device="cuda", path=PATH_AUTO, precision=PREC_FP64):
+        return torch.empty(self.workspace_bytes(nmaps, path, precision), dtype=torch.uint8, device=device)
 
     def _alm_arg(self, alm):
         if alm.dtype != torch.complex128 or not alm.is_cuda:
@@ -179,15 +229,16 @@ class Plan:
             raise ValueError(f"alm has {a.shape[0]} rows, expected nalm = {self.nalm}")
         return a.contiguous()
 
-    def synthesis(self, alm, out=None, *, path=PATH_AUTO, stream=None, workspace=None, events=None):
+    def synthesis(self, alm, out=None, *, path=PATH_AUTO, stream=None, workspace=None, events=None,
+                  precision=PREC_FP64):
         """maps (B, Npix) float64 from alm (nalm, B) or (nalm,) complex128."""
         a = self._alm_arg(alm)
         B = a.shape[1]
         if out is None:
             out = torch.empty((B, self.npix), dtype=torch.float64, device=a.device)
         if workspace is None:
-            workspace = self.workspace(B, a.device)
-        x = self._exec(B, path, stream, workspace, events)
+            workspace = self.workspace(B, a.device, path, precision)
+        x = self._exec(B, path, stream, workspace, events, precision=precision)
         _check(load().sht_synthesis_ex(self._h, _c.byref(x), _c.c_void_p(a.data_ptr()),
                                        _c.c_void_p(out.data_ptr())))
         return out

@@ -44,8 +44,13 @@ def test_invalid_arguments(sht):
     assert not lib.sht_plan(10, 0, 0.0)
     assert not lib.sht_plan(10, 4096, 0.0)
     assert not lib.sht_plan(10, 4, -1.0)
-    assert not lib.sht_plan(10, 4, 1e-12)
-    assert "not available" in lib.sht_last_error().decode()
+    assert not lib.sht_plan(10, 4, 0.5)
+    assert "eps must be below" in lib.sht_last_error().decode()
+    o = sht.PlanOpts()
+    lib.sht_plan_opts_default(o)
+    o.max_levels = 11
+    assert not lib.sht_plan_ex(10, 4, 1e-12, o)
+    assert "max_levels" in lib.sht_last_error().decode()
 
 
 def test_host_only_plan_cannot_execute(sht):
