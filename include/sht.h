@@ -153,6 +153,7 @@ typedef struct sht_plan_info {
     long long bf_nodes;       /* pair nodes over all (m, parity, level) */
     long long bf_units;       /* level output columns over all nodes */
     long long bf_res_lanes;   /* residual (leaf, skeleton ring) lanes */
+    long long bf_res_exec;    /* lane-steps the residual kernel executes (>= bf_res_elems) */
     long long bf_depth_hist[11]; /* (m, parity) items per kept depth 0..10 */
     double bf_build_seconds;
 } sht_plan_info_t;

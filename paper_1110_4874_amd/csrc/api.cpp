@@ -259,8 +259,9 @@ int sht_plan_info(const sht_plan_t *p, sht_plan_info_t *out) {
         out->bf_T_entries = b.T_entries;
         out->bf_res_elems = b.res_elems;
         out->bf_nodes = b.n_nodes;
-        out->bf_units = (long long)b.unit_node.size();
-        out->bf_res_lanes = (long long)b.res_rec.size() / 4;
+        out->bf_units = b.n_units;
+        out->bf_res_lanes = b.n_res_lanes;
+        out->bf_res_exec = b.res_exec;
         for (int i = 0; i <= kBfMaxLv; i++) out->bf_depth_hist[i] = b.depth_hist[i];
         out->bf_build_seconds = b.build_seconds;
     }

@@ -3,202 +3,327 @@
 //   a^T Lambda = (a^T R) S_d P_{d-1} ... P_1 S_1,
 // followed by the even/odd fold of Sec. 2.4 (Eqs. 13-14).
 //
-// One workgroup owns one order m (both parities) at a time, taking orders
-// in the plan's decreasing-work order with a grid stride, and runs:
-//  1. the residual R: one thread per (leaf, skeleton ring) lane regenerates
-//     Legendre values with the two-step recurrence (App. A.2, Eq. A2) over
-//     the leaf's rows from two stored values and accumulates
-//     v = sum_l a_lm P~_l^m(z) for every map;
-//  2. the levels, deepest first: one thread per output column c of a pair
-//     node (two sibling row blocks sharing the column set C) computes
-//     u_c = sum_{child} (identity: v[s] | dense: sum_s T[s][d] v[s]), which
-//     is the input vector of the next level (level 1 yields q^t per ring);
-//     the dense interpolation blocks T are streamed from HBM once per call;
-//  3. the fold into q rows k and 4 nside - k (the equator once).
-// Vectors live in a per-workgroup slot of device scratch (L2/MALL resident),
-// with __syncthreads() between phases.
+// The paper walks each order's tree depth first to stay in a CPU's caches.
+// Here every level is one launch over all orders at once (breadth first),
+// which gives the GPU tens of thousands of independent waves to stream the
+// interpolation matrices with; vectors between levels live in a device
+// workspace (read and written once per level):
+//  1. k_bf_residual: one wave per residual task (up to 128 skeleton rings of
+//     one row block, two per lane) regenerates the Legendre values with the
+//     two-step recurrence (App. A.2, Eq. A2) over the block's rows from two
+//     stored values per ring and accumulates v = sum_l a_lm P~_l^m(z) for
+//     every map; a_lm and the coefficients are wave-uniform scalar loads;
+//  2. k_bf_level, deepest level first: one wave per pair node (two sibling
+//     row blocks sharing the column set C) computes
+//     u = A~_0^T v_0 + A~_1^T v_1: identity rows copy v, the dense part
+//     T^T V runs on the matrix cores; level 1 yields q^t per north ring;
+//  3. k_bf_fold: q rows k and 4 nside - k from q^even +- q^odd.
 #include "internal.h"
 
 namespace sht {
 
 template <typename S>
 struct BfArgs {
-    const int *__restrict__ order;
-    const long long *__restrict__ res_off;
-    const int4 *__restrict__ res_rec;
+    const int4 *__restrict__ res_task;
+    const int2 *__restrict__ res_lane;
     const double2 *__restrict__ res_val;
-    const long long *__restrict__ unit_off;
-    const int *__restrict__ unit_node;
-    const int *__restrict__ code;
+    const int16_t *__restrict__ perm;
     const int *__restrict__ node_i;
-    const long long *__restrict__ node_T;
     const S *__restrict__ T;
     const double *__restrict__ z2;
     const long long *__restrict__ coef_off;
     const double *__restrict__ coef;
     const double2 *__restrict__ alm;
     double2 *__restrict__ q;
-    S *__restrict__ scratch;
-    int L, K, nrings, nmaps, map0, nitems;
-    long long slot_entries;
+    S *__restrict__ ws;  // vector workspace, entries of 2 NB values
+    long long rsize[4];  // region sizes (entries): distance to a region's second copy
+    int L, K, nrings, nmaps, map0;
+    long long ntasks;
 };
 
 constexpr int kBfThreads = 256;
 
-__device__ __forceinline__ double fma_s(double a, double b, double c) { return __builtin_fma(a, b, c); }
-__device__ __forceinline__ float fma_s(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+// Read-only operands that every lane of a wave needs at the same address
+// (a_lm rows, recurrence coefficients) are read through the constant
+// address space so that they arrive by scalar loads into SGPRs.
+typedef const __attribute__((address_space(4))) double c_double;
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+template <typename S>
+struct Acc;
+template <>
+struct Acc<double> {
+    typedef d4_t type;
+};
+template <>
+struct Acc<float> {
+    typedef f4_t type;
+};
+
+// D(16x16) += A(16x4) B(4x16) on the matrix cores.  Lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16].  Element r of the accumulator of
+// lane l is D[acc_row(l / 16, r)][l % 16]: row 4 (l / 16) + r for FP32, row
+// l / 16 + 4 r for FP64 (measured on gfx950).
+__device__ __forceinline__ d4_t mfma_16x16x4(double a, double b, d4_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4_t mfma_16x16x4(float a, float b, f4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+template <typename S>
+__device__ __forceinline__ int acc_row(int k4, int r) {
+    return sizeof(S) == 8 ? k4 + 4 * r : 4 * k4 + r;
+}
+
+// One ID block (child ch of a pair node) on one wave:
+//   u_ch = A~_ch^T v_ch  over the columns C the two sibling row blocks share.
+// The identity rows copy v; the dense part T^T V (nd x k times k x NC) runs
+// on the matrix cores, 64 dense rows (four 16-row tiles sharing each V
+// operand) by kBfKSteps * 4 rows of T per batch of loads.  The two children of a node
+// write separate copies of u, which the reader adds, so no wave waits on
+// another's stores.  Input vectors from a previous level are likewise the
+// sum of two copies (leaf vectors from the residual are single).
+constexpr int kBfKSteps = 2;  // K-steps (4 rows of T each) per batch of loads
 
 template <int NB, typename S>
-__global__ __launch_bounds__(kBfThreads) void k_butterfly(BfArgs<S> a) {
-    constexpr int NC = 2 * NB;  // components per vector entry
-    const int tid = threadIdx.x;
-    S *__restrict__ slot = a.scratch + (size_t)blockIdx.x * a.slot_entries * NC;
-    for (int item = blockIdx.x; item < a.nitems; item += gridDim.x) {
-        const int m = a.order[item];
-        const size_t aoff = (size_t)m * (2 * a.L + 3 - m) / 2;
-        const double4 *__restrict__ cf = reinterpret_cast<const double4 *>(a.coef) + a.coef_off[m];
-
-        // 1. residual lanes
-        const long long r0 = a.res_off[m], r1 = a.res_off[m + 1];
-        for (long long r = r0 + tid; r < r1; r += kBfThreads) {
-            const int4 rec = a.res_rec[r];
-            const double2 sv = a.res_val[r];
-            const int t = rec.w & 1;
-            const long long out = rec.w >> 1;
-            const double z2 = a.z2[rec.x];
-            double P0 = sv.x, P1 = sv.y;
-            double acc[NC];
+__device__ __forceinline__ void id_block(const BfArgs<S> &a, int node, int ch, int lane) {
+    constexpr int NC = 2 * NB;
+    typedef typename Acc<S>::type acc_t;
+    const int *ni = a.node_i + (size_t)node * kBfNodeInts;
+    const int n = ni[2] + ni[4];
+    const int kk = ni[2 + ch], nd = ni[4 + ch], fl = ni[8];
+    const long long pin = a.rsize[fl & 3], pout = a.rsize[(fl >> 2) & 3];
+    const S *__restrict__ v0 = a.ws + (size_t)ni[ch] * NC;
+    const S *__restrict__ v1 = v0 + (size_t)pin * NC;  // read only when pin > 0
+    S *__restrict__ u = a.ws + ((size_t)ni[6] + (size_t)ch * pout) * NC;
+    const int16_t *__restrict__ pm = a.perm + ni[7] + (size_t)ch * n;
+    const long long toff = (long long)(unsigned)ni[12 + 2 * ch] | ((long long)ni[13 + 2 * ch] << 32);
+    const S *__restrict__ Tb = a.T + toff;
+    // 32-bit element offsets from wave-uniform bases (saddr addressing)
+    auto vin = [&](unsigned e) -> S { return pin ? v0[e] + v1[e] : v0[e]; };
+    // identity rows
+    for (int e = lane; e < kk * NC; e += 64) {
+        const int s = e / NC, q = e - s * NC;
+        u[(unsigned)pm[s] * NC + q] = vin((unsigned)e);
+    }
+    // dense rows
+    const int i16 = lane & 15, k4 = lane >> 4;
+    for (int g0 = 0; g0 < nd; g0 += 64) {
+        const int ntile = min(4, (nd - g0 + 15) >> 4);
+        acc_t acc[4];
 #pragma unroll
-            for (int c = 0; c < NC; c++) acc[c] = 0.0;
-            const double2 *ap = a.alm + (aoff + t) * a.nmaps + a.map0;
-            for (int i = rec.y; i < rec.z; i++) {
-                const double2 *ai = ap + (size_t)2 * i * a.nmaps;
+        for (int tt = 0; tt < 4; tt++) acc[tt] = acc_t{0, 0, 0, 0};
+        for (int s0 = 0; s0 < kk; s0 += 4 * kBfKSteps) {
+            S av[kBfKSteps][4], bv[kBfKSteps];
 #pragma unroll
-                for (int b = 0; b < NB; b++) {
-                    const double2 v = ai[b];
-                    acc[2 * b] = __builtin_fma(P0, v.x, acc[2 * b]);
-                    acc[2 * b + 1] = __builtin_fma(P0, v.y, acc[2 * b + 1]);
+            for (int j = 0; j < kBfKSteps; j++) {
+                const int s = s0 + 4 * j + k4;
+                const bool sv = s < kk;
+                bv[j] = (sv && i16 < NC) ? vin((unsigned)(s * NC + i16)) : (S)0;
+#pragma unroll
+                for (int tt = 0; tt < 4; tt++) {
+                    const int d = g0 + 16 * tt + i16;
+                    av[j][tt] = (sv && d < nd) ? Tb[(unsigned)(s * nd + d)] : (S)0;
                 }
-                const double4 e = cf[t + 2 * i + 2];
-                const double P2 = __builtin_fma(__builtin_fma(z2, e.x, e.y), P1, e.z * P0);
-                P0 = P1;
-                P1 = P2;
             }
-            S *dst = slot + out * NC;
+            const int nj = min(kBfKSteps, (kk - s0 + 3) >> 2);
 #pragma unroll
-            for (int c = 0; c < NC; c++) dst[c] = (S)acc[c];
-        }
-        __syncthreads();
-
-        // 2. levels, deepest first
-        const long long *uo = a.unit_off + (size_t)m * (kBfMaxLv + 1);
-        for (int lq = 0; lq < kBfMaxLv; lq++) {
-            const long long u0 = uo[lq], u1 = uo[lq + 1];
-            if (u0 == u1) continue;
-            for (long long u = u0 + tid; u < u1; u += kBfThreads) {
-                const int node = a.unit_node[u];
-                const int *ni = a.node_i + (size_t)node * kBfNodeInts;
-                const int code = a.code[u];
-                const int c = (int)(u - ni[7]);
-                S acc[NC];
+            for (int j = 0; j < kBfKSteps; j++) {
+                if (j >= nj) break;
 #pragma unroll
-                for (int q = 0; q < NC; q++) acc[q] = (S)0;
-#pragma unroll
-                for (int ch = 0; ch < 2; ch++) {
-                    const int cd = (int)(short)(ch == 0 ? (code & 0xffff) : ((unsigned)code >> 16));
-                    const S *v = slot + (size_t)ni[ch] * NC;
-                    if (cd >= 0) {
-#pragma unroll
-                        for (int q = 0; q < NC; q++) acc[q] += v[(size_t)cd * NC + q];
-                    } else {
-                        const int d = -1 - cd, kk = ni[2 + ch], nd = ni[4 + ch];
-                        const S *__restrict__ Tp = a.T + a.node_T[2 * node + ch] + d;
-                        for (int s = 0; s < kk; s++) {
-                            const S w = Tp[(size_t)s * nd];
-#pragma unroll
-                            for (int q = 0; q < NC; q++) acc[q] = fma_s(w, v[(size_t)s * NC + q], acc[q]);
-                        }
-                    }
-                }
-                S *dst = slot + ((size_t)ni[6] + c) * NC;
-#pragma unroll
-                for (int q = 0; q < NC; q++) dst[q] = acc[q];
+                for (int tt = 0; tt < 4; tt++)
+                    if (tt < ntile) acc[tt] = mfma_16x16x4(av[j][tt], bv[j], acc[tt]);
             }
-            __syncthreads();
         }
-
-        // 3. fold q^even, q^odd into the north ring and its mirror
-        const int K = a.K;
-        for (int e = tid; e < K * NB; e += kBfThreads) {
-            const int k = e / NB, b = e % NB;
-            const S *qe = slot + (size_t)k * NC + 2 * b;
-            const S *qo = slot + (size_t)(K + k) * NC + 2 * b;
-            double er = (double)qe[0], ei = (double)qe[1], orr = (double)qo[0], oi = (double)qo[1];
-            if (m == 0) ei = oi = 0.0;
-            a.q[((size_t)m * a.nrings + k) * a.nmaps + a.map0 + b] = make_double2(er + orr, ei + oi);
-            const int ks = a.nrings - 1 - k;
-            if (ks != k) a.q[((size_t)m * a.nrings + ks) * a.nmaps + a.map0 + b] = make_double2(er - orr, ei - oi);
+#pragma unroll
+        for (int tt = 0; tt < 4; tt++) {
+            if (tt >= ntile) break;
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int dd = g0 + 16 * tt + acc_row<S>(k4, r);
+                if (dd < nd && i16 < NC) u[(unsigned)pm[kk + dd] * NC + i16] = acc[tt][r];
+            }
         }
-        __syncthreads();
     }
 }
 
-int bf_slots(const sht_plan_s *p) { return std::min(p->L + 1, 1024); }
+// One residual task on one wave: R rings per lane (lane j: rings j, j + 64),
+// rows [imin, iend) of one parity, outputs at entries outb + ring.
+template <int NB, int R, typename S>
+__device__ __forceinline__ void residual_task(const BfArgs<S> &a, S *__restrict__ slot, long long tk, int lane,
+                                              int t, int imin, int iend, int nl, int outb, int clear2,
+                                              c_double *ap, c_double *cfs, int astride) {
+    constexpr int NC = 2 * NB;
+    int i0[R];
+    double z2[R], v0[R], v1[R], P0[R], P1[R], acc[R][NC];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const size_t li = (size_t)tk * kBfTaskRings + r * 64 + lane;
+        const int2 ln = a.res_lane[li];
+        const double2 sv = a.res_val[li];
+        i0[r] = ln.y;
+        z2[r] = a.z2[ln.x];
+        v0[r] = sv.x;
+        v1[r] = sv.y;
+        P0[r] = P1[r] = 0.0;
+#pragma unroll
+        for (int c = 0; c < NC; c++) acc[r][c] = 0.0;
+    }
+    auto step = [&](int i) {
+        c_double *ai = ap + (size_t)i * astride;
+        c_double *e = cfs + 4 * (t + 2 * i + 2);
+        const double eb = e[0], eab = e[1], eg = e[2];
+        double av[NC];
+#pragma unroll
+        for (int c = 0; c < NC; c++) av[c] = ai[c];
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+#pragma unroll
+            for (int c = 0; c < NC; c++) acc[r][c] = __builtin_fma(P0[r], av[c], acc[r][c]);
+            const double P2 = __builtin_fma(__builtin_fma(z2[r], eb, eab), P1[r], eg * P0[r]);
+            P0[r] = P1[r];
+            P1[r] = P2;
+        }
+    };
+    for (int c = imin; c < iend;) {
+#pragma unroll
+        for (int r = 0; r < R; r++)
+            if (i0[r] == c) {
+                P0[r] = v0[r];
+                P1[r] = v1[r];
+            }
+        const int ce = min(iend, (c & ~(kChunk - 1)) + kChunk);
+        if (ce - c == kChunk) {
+#pragma unroll
+            for (int u = 0; u < kChunk; u++) step(c + u);
+        } else {
+            for (int i = c; i < ce; i++) step(i);
+        }
+        c = ce;
+    }
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int j = r * 64 + lane;
+        if (j < nl) {
+            S *dst = slot + ((size_t)outb + j) * NC;
+#pragma unroll
+            for (int c = 0; c < NC; c++) dst[c] = (S)acc[r][c];
+            if (clear2) {  // depth 0: the second copy of q^t stays zero
+                S *dst2 = dst + (size_t)clear2 * NC;
+#pragma unroll
+                for (int c = 0; c < NC; c++) dst2[c] = (S)0;
+            }
+        }
+    }
+}
+
+template <int NB, typename S>
+__global__ __launch_bounds__(kBfThreads) void k_bf_residual(BfArgs<S> a) {
+    const int lane = threadIdx.x & 63;
+    const long long tk = (long long)blockIdx.x * (kBfThreads / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (tk >= a.ntasks) return;
+    const int4 h = a.res_task[2 * tk], h2 = a.res_task[2 * tk + 1];
+    const int t = __builtin_amdgcn_readfirstlane(h.x), imin = __builtin_amdgcn_readfirstlane(h.y);
+    const int iend = __builtin_amdgcn_readfirstlane(h.z), nl = __builtin_amdgcn_readfirstlane(h.w);
+    const int outb = __builtin_amdgcn_readfirstlane(h2.x), m = __builtin_amdgcn_readfirstlane(h2.y);
+    const int clear2 = __builtin_amdgcn_readfirstlane(h2.z);
+    const size_t aoff = (size_t)m * (2 * a.L + 3 - m) / 2;
+    c_double *ap = (c_double *)(a.alm + (aoff + t) * a.nmaps + a.map0);
+    c_double *cfs = (c_double *)(a.coef + 4 * a.coef_off[m]);
+    const int astride = 4 * a.nmaps;  // doubles between rows i and i+1
+    if (nl > 64)
+        residual_task<NB, 2>(a, a.ws, tk, lane, t, imin, iend, nl, outb, clear2, ap, cfs, astride);
+    else
+        residual_task<NB, 1>(a, a.ws, tk, lane, t, imin, iend, nl, outb, clear2, ap, cfs, astride);
+}
+
+template <int NB, typename S>
+__global__ __launch_bounds__(kBfThreads) void k_bf_level(BfArgs<S> a, long long n0, long long n1) {
+    const long long w = (long long)blockIdx.x * (kBfThreads / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const long long node = n0 + (w >> 1);
+    if (node >= n1) return;
+    id_block<NB, S>(a, (int)node, (int)(w & 1), threadIdx.x & 63);
+}
+
+template <int NB, typename S>
+__global__ __launch_bounds__(kBfThreads) void k_bf_fold(BfArgs<S> a) {
+    constexpr int NC = 2 * NB;
+    const int K = a.K;
+    const long long e = (long long)blockIdx.x * kBfThreads + threadIdx.x;
+    if (e >= (long long)(a.L + 1) * K * NB) return;
+    const int b = (int)(e % NB);
+    const long long mk = e / NB;
+    const int k = (int)(mk % K), m = (int)(mk / K);
+    const S *qe = a.ws + ((size_t)(2 * m) * K + k) * NC + 2 * b;
+    const S *qo = a.ws + ((size_t)(2 * m + 1) * K + k) * NC + 2 * b;
+    const size_t p2 = (size_t)a.rsize[0] * NC;  // second copy of q^t
+    double er = (double)qe[0] + (double)qe[p2], ei = (double)qe[1] + (double)qe[p2 + 1];
+    double orr = (double)qo[0] + (double)qo[p2], oi = (double)qo[1] + (double)qo[p2 + 1];
+    if (m == 0) ei = oi = 0.0;  // real field: Im a_l0 is ignored
+    a.q[((size_t)m * a.nrings + k) * a.nmaps + a.map0 + b] = make_double2(er + orr, ei + oi);
+    const int ks = a.nrings - 1 - k;
+    if (ks != k) a.q[((size_t)m * a.nrings + ks) * a.nmaps + a.map0 + b] = make_double2(er - orr, ei - oi);
+}
+
+static int bf_nb(int nmaps) { return nmaps >= 8 ? 8 : nmaps >= 4 ? 4 : nmaps >= 2 ? 2 : 1; }
 
 size_t bf_scratch_bytes(const sht_plan_s *p, int nmaps, int fp32) {
-    const int nb = nmaps >= 8 ? 8 : nmaps >= 4 ? 4 : nmaps >= 2 ? 2 : 1;
-    return (size_t)bf_slots(p) * (size_t)p->bf.slot_entries * 2 * nb * (fp32 ? sizeof(float) : sizeof(double));
+    return (size_t)p->bf.ws_entries * 2 * bf_nb(nmaps) * (fp32 ? sizeof(float) : sizeof(double));
 }
 
 template <int NB, typename S>
 static hipError_t launch_bf_nb(const sht_plan_s *p, BfArgs<S> a, hipStream_t st) {
-    hipLaunchKernelGGL((k_butterfly<NB, S>), dim3((unsigned)bf_slots(p)), dim3(kBfThreads), 0, st, a);
+    constexpr int WPB = kBfThreads / 64;
+    const BflyPlan &b = p->bf;
+    if (b.n_tasks > 0)
+        hipLaunchKernelGGL((k_bf_residual<NB, S>), dim3((unsigned)((b.n_tasks + WPB - 1) / WPB)), dim3(kBfThreads), 0,
+                           st, a);
+    for (int lvl = kBfMaxLv; lvl >= 1; lvl--) {
+        const long long n0 = b.lv_off[lvl], n1 = lvl > 1 ? b.lv_off[lvl - 1] : b.lv_off[0];
+        if (n1 <= n0) continue;
+        hipLaunchKernelGGL((k_bf_level<NB, S>), dim3((unsigned)((2 * (n1 - n0) + WPB - 1) / WPB)), dim3(kBfThreads),
+                           0, st, a, n0, n1);
+    }
+    const long long nf = (long long)(p->L + 1) * b.K * NB;
+    hipLaunchKernelGGL((k_bf_fold<NB, S>), dim3((unsigned)((nf + kBfThreads - 1) / kBfThreads)), dim3(kBfThreads), 0,
+                       st, a);
     return hipGetLastError();
 }
 
 template <typename S>
-static hipError_t launch_bf(const sht_plan_s *p, int nmaps, const double *alm, double *q, S *scratch,
-                            const S *T, hipStream_t st) {
+static hipError_t launch_bf(const sht_plan_s *p, int nmaps, const double *alm, double *q, S *ws, const S *T,
+                            hipStream_t st) {
     BfArgs<S> a;
-    a.order = p->d_bf_order;
-    a.res_off = p->d_bf_res_off;
-    a.res_rec = reinterpret_cast<const int4 *>(p->d_bf_res_rec);
+    a.res_task = reinterpret_cast<const int4 *>(p->d_bf_res_task);
+    a.res_lane = reinterpret_cast<const int2 *>(p->d_bf_res_lane);
     a.res_val = reinterpret_cast<const double2 *>(p->d_bf_res_val);
-    a.unit_off = p->d_bf_unit_off;
-    a.unit_node = p->d_bf_unit_node;
-    a.code = p->d_bf_code;
+    a.perm = p->d_bf_perm;
     a.node_i = p->d_bf_node_i;
-    a.node_T = p->d_bf_node_T;
     a.T = T;
     a.z2 = p->d_z2_hi;
     a.coef_off = p->d_coef_off;
     a.coef = p->d_coef_hi;
     a.alm = reinterpret_cast<const double2 *>(alm);
     a.q = reinterpret_cast<double2 *>(q);
-    a.scratch = scratch;
+    a.ws = ws;
     a.L = p->L;
     a.K = p->bf.K;
     a.nrings = p->nrings;
     a.nmaps = nmaps;
-    a.nitems = p->L + 1;
-    a.slot_entries = p->bf.slot_entries;
+    a.ntasks = p->bf.n_tasks;
+    for (int r = 0; r < 4; r++) a.rsize[r] = p->bf.region_size[r];
     hipError_t e = hipSuccess;
     for (int b = 0; b < nmaps && e == hipSuccess;) {
-        const int rem = nmaps - b;
+        const int nb = bf_nb(nmaps - b);
         a.map0 = b;
-        if (rem >= 8) {
-            e = launch_bf_nb<8, S>(p, a, st);
-            b += 8;
-        } else if (rem >= 4) {
-            e = launch_bf_nb<4, S>(p, a, st);
-            b += 4;
-        } else if (rem >= 2) {
-            e = launch_bf_nb<2, S>(p, a, st);
-            b += 2;
-        } else {
-            e = launch_bf_nb<1, S>(p, a, st);
-            b += 1;
+        switch (nb) {
+            case 8: e = launch_bf_nb<8, S>(p, a, st); break;
+            case 4: e = launch_bf_nb<4, S>(p, a, st); break;
+            case 2: e = launch_bf_nb<2, S>(p, a, st); break;
+            default: e = launch_bf_nb<1, S>(p, a, st); break;
         }
+        b += nb;
     }
     return e;
 }

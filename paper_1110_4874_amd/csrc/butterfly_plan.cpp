@@ -155,6 +155,7 @@ struct Item {
     // Legendre values at the first two chain indices
     std::vector<int> lane;                 // [nl][4]
     std::vector<double> lval;              // [nl][2]
+    std::vector<int> seg;                  // [nseg][4] lane range and rows of each row block
     long long T_entries = 0, res_elems = 0;
 };
 
@@ -217,6 +218,7 @@ void item_worker(long idx, void *vctx) {
     if (c->max_levels >= 0) maxd = std::min(maxd, c->max_levels);
     if (maxd == 0 || n == 0) {
         // brute force: one lane per ring from its chain start
+        it.seg.insert(it.seg.end(), {0, K, 0, n});
         for (int k = 0; k < K; k++) {
             const int i0 = it.st[k];
             it.lane.insert(it.lane.end(), {k, i0, n, k});
@@ -340,6 +342,7 @@ void item_worker(long idx, void *vctx) {
         it.lval.push_back(i0 + 1 < n ? col[i0 + 1] : 0.0);
     };
     if (it.depth == 0) {
+        it.seg.insert(it.seg.end(), {0, K, 0, n});
         for (int k = 0; k < K; k++) lane(k, 0, n, k);
     } else {
         const int d = it.depth, G = groups_at(it, d);
@@ -347,11 +350,13 @@ void item_worker(long idx, void *vctx) {
         for (int rho = 0; rho < (1 << d); rho++) {
             int r0, r1;
             row_bounds(n, d, rho, &r0, &r1);
+            const int l0 = (int)it.lane.size() / 4;
             for (int g = 0; g < G; g++) {
                 const Node &nd = it.lv[d - 1][(size_t)rho * G + g];
                 for (int s = 0; s < nd.k; s++) lane(nd.skel[s], r0, r1, off + s);
                 off += nd.k;
             }
+            it.seg.insert(it.seg.end(), {l0, (int)it.lane.size() / 4, r0, r1});
         }
     }
 }
@@ -379,121 +384,165 @@ int build_butterfly(sht_plan_s *p, const BflyInput &in) {
     b = BflyPlan();
     b.K = K;
     {
-        size_t nT = 0, nl = 0;
+        size_t nT = 0, ntask = 0;
         for (auto &it : c.items) {
             nT += (size_t)it.T_entries;
-            nl += it.lane.size() / 4;
+            for (size_t q = 0; q + 3 < it.seg.size(); q += 4)
+                ntask += (size_t)(it.seg[q + 1] - it.seg[q] + kBfTaskRings - 1) / kBfTaskRings;
         }
         b.T.reserve(nT);
-        b.res_rec.reserve(4 * nl);
-        b.res_val.reserve(2 * nl);
+        b.res_task.reserve(8 * ntask);
+        b.res_lane.reserve(2 * kBfTaskRings * ntask);
+        b.res_val.reserve(2 * kBfTaskRings * ntask);
     }
     b.depth.assign((size_t)(L + 1) * 2, 0);
-    b.res_off.assign(L + 2, 0);
-    b.unit_off.assign((size_t)(L + 1) * (kBfMaxLv + 1), 0);
-    // per-parity vector region size: the largest level vector of any item
-    long long vmax = 1;
-    for (auto &it : c.items)
-        for (auto &lvn : it.lv) {
-            long long s = 0;
-            for (auto &nd : lvn) s += nd.k;
-            vmax = std::max(vmax, s);
-        }
-    b.vmax = vmax;
-    b.slot_entries = 2LL * K + 4 * vmax;
-    auto region = [&](int t, int i) -> long long { return 2LL * K + (2LL * t + (i & 1)) * vmax; };
-
-    std::vector<double> work(L + 1, 0.0);
+    // Vector regions of the workspace (entries of 2B values): Q holds the
+    // level-1 output q^t of every (m, t) (or the residual output at depth 0),
+    // LEAF the residual output at the deepest level kept, and R0 / R1 the
+    // vectors that level launches produce for even / odd levels.  Offsets
+    // are region-relative while building and made absolute at the end.
+    enum { RQ = 0, RLEAF = 1, RR0 = 2, RR1 = 3 };
+    long long leaf_cnt = 0, lvl_cnt[kBfMaxLv + 1] = {};
+    std::vector<std::vector<int>> lvnodes(kBfMaxLv + 1);  // per level: node records
+    std::vector<int> task_region;                          // per task: region of its output
     for (int m = 0; m <= L; m++) {
-        b.res_off[m] = (long long)b.res_rec.size() / 4;
-        int dm = 0;
         for (int t = 0; t < 2; t++) {
             Item &it = c.items[(size_t)2 * m + t];
-            b.depth[(size_t)2 * m + t] = it.depth;
+            const int d = it.depth;
+            b.depth[(size_t)2 * m + t] = d;
             b.T_entries += it.T_entries;
             b.res_elems += it.res_elems;
-            b.depth_hist[std::min(it.depth, kBfMaxLv)]++;
-            work[m] += c.rho * (double)it.T_entries + (double)it.res_elems;
-            dm = std::max(dm, it.depth);
-        }
-        // residual lanes: leaves of the deepest level kept (or every ring)
-        for (int t = 0; t < 2; t++) {
-            Item &it = c.items[(size_t)2 * m + t];
-            const long long base = it.depth == 0 ? (long long)t * K : region(t, it.depth);
-            const size_t nl = it.lane.size() / 4;
-            for (size_t q = 0; q < nl; q++) {
-                const int *ln = &it.lane[4 * q];
-                b.res_rec.insert(b.res_rec.end(), {ln[0], ln[1], ln[2], (int)((base + ln[3]) * 2 + t)});
-                b.res_val.push_back(it.lval[2 * q]);
-                b.res_val.push_back(it.lval[2 * q + 1]);
+            b.depth_hist[std::min(d, kBfMaxLv)]++;
+            const long long qbase = (long long)(2 * m + t) * K;
+            // offsets of this item's vectors at every level it has
+            std::vector<std::vector<long long>> voff(d + 1);  // voff[i][node index] (level i vectors)
+            std::vector<int> vreg(d + 1, RQ);
+            for (int i = 1; i <= d; i++) {
+                const auto &lvn = it.lv[i - 1];
+                voff[i].resize(lvn.size());
+                long long *cnt = (i == d) ? &leaf_cnt : &lvl_cnt[i];
+                vreg[i] = (i == d) ? RLEAF : ((i & 1) ? RR1 : RR0);
+                for (size_t q = 0; q < lvn.size(); q++) {
+                    voff[i][q] = *cnt;
+                    *cnt += lvn[q].k;
+                }
             }
-            std::vector<int>().swap(it.lane);
-            std::vector<double>().swap(it.lval);
-        }
-        // level records, deepest first; level i of parity t reads region (t, i)
-        // and writes region (t, i-1) (level 1 writes the q^t rows)
-        for (int lvl = kBfMaxLv; lvl >= 1; lvl--) {
-            b.unit_off[(size_t)m * (kBfMaxLv + 1) + kBfMaxLv - lvl] = (long long)b.unit_node.size();
-            if (lvl > dm) continue;
-            for (int t = 0; t < 2; t++) {
-                Item &it = c.items[(size_t)2 * m + t];
-                if (lvl > it.depth) continue;
-                const int G = groups_at(it, lvl);
-                // input offsets of level lvl vectors (node order rho-major)
-                std::vector<long long> vin((size_t)(1 << lvl) * G);
-                long long off = region(t, lvl);
-                for (size_t q = 0; q < vin.size(); q++) {
-                    vin[q] = off;
-                    off += it.lv[lvl - 1][q].k;
-                }
-                std::vector<long long> vout;
-                if (lvl > 1) {
-                    const int Gp = groups_at(it, lvl - 1);
-                    vout.resize((size_t)(1 << (lvl - 1)) * Gp);
-                    long long o2 = region(t, lvl - 1);
-                    for (size_t q = 0; q < vout.size(); q++) {
-                        vout[q] = o2;
-                        o2 += it.lv[lvl - 2][q].k;
+            // residual tasks
+            const long long rbase = d == 0 ? qbase : (voff[d].empty() ? 0 : voff[d][0]);
+            const int rreg = d == 0 ? RQ : RLEAF;
+            for (size_t q = 0; q + 3 < it.seg.size(); q += 4) {
+                const int l0 = it.seg[q], l1 = it.seg[q + 1], rend = it.seg[q + 3];
+                const int cnt = l1 - l0;
+                if (cnt <= 0) continue;
+                const int ntask = (cnt + kBfTaskRings - 1) / kBfTaskRings;
+                for (int tk = 0; tk < ntask; tk++) {
+                    const int c0 = l0 + (int)((long long)cnt * tk / ntask);
+                    const int c1 = l0 + (int)((long long)cnt * (tk + 1) / ntask);
+                    const int nl = c1 - c0;
+                    int imin = rend;
+                    for (int j = 0; j < nl; j++) imin = std::min(imin, it.lane[4 * (c0 + j) + 1]);
+                    b.res_task.insert(b.res_task.end(),
+                                      {t, imin, rend, nl, (int)(rbase + it.lane[4 * c0 + 3]), m, 0, 0});
+                    task_region.push_back(rreg);
+                    for (int j = 0; j < kBfTaskRings; j++) {
+                        if (j < nl) {
+                            const int *ln = &it.lane[4 * (c0 + j)];
+                            b.res_lane.insert(b.res_lane.end(), {ln[0], ln[1]});
+                            b.res_val.push_back(it.lval[2 * (c0 + j)]);
+                            b.res_val.push_back(it.lval[2 * (c0 + j) + 1]);
+                        } else {
+                            b.res_lane.insert(b.res_lane.end(), {0, INT32_MAX});
+                            b.res_val.push_back(0.0);
+                            b.res_val.push_back(0.0);
+                        }
                     }
+                    b.n_res_lanes += nl;
+                    b.res_exec += (long long)(rend - imin) * (nl > 64 ? 128 : 64);
                 }
+            }
+            // pair nodes of every level
+            for (int lvl = d; lvl >= 1; lvl--) {
+                const int G = groups_at(it, lvl);
                 for (int pi = 0; pi < (1 << (lvl - 1)); pi++)
                     for (int g = 0; g < G; g++) {
-                        const Node &c0 = it.lv[lvl - 1][(size_t)(2 * pi) * G + g];
-                        const Node &c1 = it.lv[lvl - 1][(size_t)(2 * pi + 1) * G + g];
+                        const size_t q0 = (size_t)(2 * pi) * G + g, q1 = (size_t)(2 * pi + 1) * G + g;
+                        const Node &c0 = it.lv[lvl - 1][q0];
+                        const Node &c1 = it.lv[lvl - 1][q1];
                         const int nn = c0.n;  // both children share the columns C
                         if (nn == 0) continue;
-                        const int node = (int)(b.node_i.size() / kBfNodeInts);
-                        long long out = lvl > 1 ? vout[(size_t)pi * groups_at(it, lvl - 1) + 2 * g]
-                                                : (long long)t * K + it.colb[g];
-                        const long long ubase = (long long)b.unit_node.size();
-                        b.node_i.insert(b.node_i.end(),
-                                        {(int)vin[(size_t)(2 * pi) * G + g], (int)vin[(size_t)(2 * pi + 1) * G + g],
-                                         c0.k, c1.k, c0.n - c0.k, c1.n - c1.k, (int)out, (int)ubase});
-                        b.node_T.push_back((long long)b.T.size());
-                        b.T.insert(b.T.end(), c0.T.begin(), c0.T.end());
-                        b.node_T.push_back((long long)b.T.size());
-                        b.T.insert(b.T.end(), c1.T.begin(), c1.T.end());
-                        for (int q = 0; q < nn; q++) {
-                            b.unit_node.push_back(node);
-                            b.code.push_back((c0.code[q] & 0xffff) | (int)((unsigned)(c1.code[q] & 0xffff) << 16));
+                        long long out;
+                        int oreg;
+                        if (lvl == 1) {
+                            out = qbase + it.colb[g];
+                            oreg = RQ;
+                        } else {
+                            out = voff[lvl - 1][(size_t)pi * groups_at(it, lvl - 1) + 2 * g];
+                            oreg = vreg[lvl - 1];
+                        }
+                        std::vector<int> &rec = lvnodes[lvl];
+                        const long long T0 = (long long)b.T.size(), T1 = T0 + (long long)c0.T.size();
+                        rec.insert(rec.end(), {(int)voff[lvl][q0], (int)voff[lvl][q1], c0.k, c1.k, c0.n - c0.k,
+                                               c1.n - c1.k, (int)out, (int)b.perm.size(), vreg[lvl] | (oreg << 2), m,
+                                               t, lvl, (int)(T0 & 0xffffffff), (int)(T0 >> 32),
+                                               (int)(T1 & 0xffffffff), (int)(T1 >> 32)});
+                        for (const Node *ch : {&c0, &c1}) b.T.insert(b.T.end(), ch->T.begin(), ch->T.end());
+                        // per child: skeleton positions (s order), then dense positions (d order)
+                        for (const Node *ch : {&c0, &c1}) {
+                            std::vector<int16_t> sk(ch->k), dn(nn - ch->k);
+                            for (int q = 0; q < nn; q++) {
+                                const int cd = ch->code[q];
+                                if (cd >= 0)
+                                    sk[cd] = (int16_t)q;
+                                else
+                                    dn[-1 - cd] = (int16_t)q;
+                            }
+                            b.perm.insert(b.perm.end(), sk.begin(), sk.end());
+                            b.perm.insert(b.perm.end(), dn.begin(), dn.end());
                         }
                         b.n_nodes++;
+                        b.n_units += nn;
                     }
             }
-        }
-        b.unit_off[(size_t)m * (kBfMaxLv + 1) + kBfMaxLv] = (long long)b.unit_node.size();
-        // free the item's trees
-        for (int t = 0; t < 2; t++) {
-            Item &it = c.items[(size_t)2 * m + t];
             std::vector<std::vector<Node>>().swap(it.lv);
+            std::vector<int>().swap(it.lane);
+            std::vector<double>().swap(it.lval);
+            std::vector<int>().swap(it.seg);
         }
     }
-    b.res_off[L + 1] = (long long)b.res_rec.size() / 4;
-    b.order.resize(L + 1);
-    std::iota(b.order.begin(), b.order.end(), 0);
-    std::stable_sort(b.order.begin(), b.order.end(), [&](int x, int y) { return work[x] > work[y]; });
-    if (b.slot_entries > INT32_MAX / 2 || (long long)b.unit_node.size() > INT32_MAX)
+    // region bases and absolute offsets.  Every region except LEAF is
+    // doubled: the two ID blocks of a pair node write their halves of u to
+    // the two copies, and the reader adds them.
+    long long r0 = 0, r1 = 0;
+    for (int i = 1; i <= kBfMaxLv; i++) (i & 1 ? r1 : r0) = std::max(i & 1 ? r1 : r0, lvl_cnt[i]);
+    const long long qsz = 2LL * K * (L + 1);
+    const long long base[4] = {0, 2 * qsz, 2 * qsz + leaf_cnt, 2 * qsz + leaf_cnt + 2 * r0};
+    b.region_size[0] = qsz;
+    b.region_size[1] = 0;
+    b.region_size[2] = r0;
+    b.region_size[3] = r1;
+    b.ws_entries = base[3] + 2 * r1;
+    if (b.ws_entries > INT32_MAX || (long long)b.perm.size() > INT32_MAX)
         return fail(SHT_EUNSUPPORTED, "butterfly plan exceeds 32-bit record offsets");
+    for (size_t q = 0; q < task_region.size(); q++) {
+        b.res_task[8 * q + 4] += (int)base[task_region[q]];
+        b.res_task[8 * q + 6] = task_region[q] == RQ ? (int)qsz : 0;  // partner copy to clear
+    }
+    // node records, deepest level first, with their launch ranges
+    b.lv_off.assign(kBfMaxLv + 2, 0);
+    for (int lvl = kBfMaxLv; lvl >= 1; lvl--) {
+        b.lv_off[lvl] = (long long)b.node_i.size() / kBfNodeInts;
+        std::vector<int> &rec = lvnodes[lvl];
+        for (size_t q = 0; q < rec.size(); q += kBfNodeInts) {
+            const int fl = rec[q + 8];
+            rec[q + 0] += (int)base[fl & 3];
+            rec[q + 1] += (int)base[fl & 3];
+            rec[q + 6] += (int)base[(fl >> 2) & 3];
+        }
+        b.node_i.insert(b.node_i.end(), rec.begin(), rec.end());
+        std::vector<int>().swap(rec);
+    }
+    b.lv_off[0] = (long long)b.node_i.size() / kBfNodeInts;  // end of level 1
+    b.n_tasks = (long long)task_region.size();
     b.built = 1;
     b.build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return SHT_OK;
@@ -504,54 +553,59 @@ int build_butterfly(sht_plan_s *p, const BflyInput &in) {
 // support: checks the factorization without a GPU).  x: n_t doubles (real
 // coefficients of the rows), y: K doubles.
 // ---------------------------------------------------------------------
+static long long node_T_off(const int *ni, int ch) {
+    return (long long)(unsigned)ni[12 + 2 * ch] | ((long long)ni[13 + 2 * ch] << 32);
+}
+
 int butterfly_apply_host(const sht_plan_s *p, int m, int t, const double *x, double *y) {
     const BflyPlan &b = p->bf;
     const int K = b.K;
-    std::vector<double> slot((size_t)b.slot_entries, 0.0);
+    std::vector<double> ws((size_t)b.ws_entries, 0.0);
     const double *cf = p->coef_hi.data() + 4 * p->coef_off[m];
-    for (long long r = b.res_off[m]; r < b.res_off[m + 1]; r++) {
-        const int *rec = &b.res_rec[(size_t)4 * r];
-        if ((rec[3] & 1) != t) continue;
-        const int k = rec[0], i0 = rec[1], i1 = rec[2];
-        const long long out = rec[3] >> 1;
-        double P0 = b.res_val[2 * r], P1 = b.res_val[2 * r + 1], acc = 0.0;
-        const double z2 = p->z2_hi[k];
-        for (int i = i0; i < i1; i++) {
-            acc += P0 * x[i];
-            const double *e = cf + 4 * (t + 2 * i + 2);
-            double P2 = (z2 * e[0] + e[1]) * P1 + e[2] * P0;
-            P0 = P1;
-            P1 = P2;
+    for (long long tk = 0; tk < b.n_tasks; tk++) {
+        const int *h = &b.res_task[(size_t)8 * tk];
+        if (h[0] != t || h[5] != m) continue;
+        for (int j = 0; j < h[3]; j++) {
+            const size_t li = (size_t)tk * kBfTaskRings + j;
+            const int k = b.res_lane[2 * li], i0 = b.res_lane[2 * li + 1];
+            double P0 = b.res_val[2 * li], P1 = b.res_val[2 * li + 1], acc = 0.0;
+            const double z2 = p->z2_hi[k];
+            for (int i = i0; i < h[2]; i++) {
+                acc += P0 * x[i];
+                const double *e = cf + 4 * (t + 2 * i + 2);
+                double P2 = (z2 * e[0] + e[1]) * P1 + e[2] * P0;
+                P0 = P1;
+                P1 = P2;
+            }
+            ws[(size_t)h[4] + j] = acc;
+            if (h[6]) ws[(size_t)h[4] + h[6] + j] = 0.0;
         }
-        slot[out] = acc;
     }
-    for (int q = 0; q < kBfMaxLv; q++) {
-        for (long long u = b.unit_off[(size_t)m * (kBfMaxLv + 1) + q];
-             u < b.unit_off[(size_t)m * (kBfMaxLv + 1) + q + 1]; u++) {
-            const int node = b.unit_node[u];
+    for (int lvl = kBfMaxLv; lvl >= 1; lvl--) {
+        const long long n0 = b.lv_off[lvl], n1 = lvl > 1 ? b.lv_off[lvl - 1] : b.lv_off[0];
+        for (long long node = n0; node < n1; node++) {
             const int *ni = &b.node_i[(size_t)node * kBfNodeInts];
-            // parity of the node: its output lies in the q^t rows or a parity region
-            const long long out = ni[6];
-            const int tn = out < 2LL * K ? (int)(out / K) : (int)((out - 2LL * K) / (2 * b.vmax));
-            if (tn != t) continue;
-            const int c = (int)(u - ni[7]);
-            const int code = b.code[u];
-            double acc = 0.0;
+            if (ni[9] != m || ni[10] != t) continue;
+            const int n = ni[2] + ni[4];
+            const long long pin = b.region_size[ni[8] & 3], pout = b.region_size[(ni[8] >> 2) & 3];
             for (int ch = 0; ch < 2; ch++) {
-                const int cd = (int16_t)((ch == 0 ? code : (code >> 16)) & 0xffff);
-                const long long vin = ni[ch];
-                if (cd >= 0) {
-                    acc += slot[vin + cd];
-                } else {
-                    const int d = -1 - cd, kk = ni[2 + ch], nd = ni[4 + ch];
-                    const double *Tp = b.T.data() + b.node_T[(size_t)2 * node + ch];
-                    for (int s = 0; s < kk; s++) acc += Tp[(size_t)s * nd + d] * slot[vin + s];
+                const int16_t *pm = b.perm.data() + ni[7] + (size_t)ch * n;
+                const int kk = ni[2 + ch], nd = ni[4 + ch];
+                std::vector<double> v(kk);
+                for (int s2 = 0; s2 < kk; s2++) v[s2] = ws[(size_t)ni[ch] + s2] + (pin ? ws[(size_t)ni[ch] + pin + s2] : 0.0);
+                const double *Tp = b.T.data() + node_T_off(ni, ch);
+                double *u = ws.data() + ni[6] + ch * pout;
+                for (int s2 = 0; s2 < kk; s2++) u[pm[s2]] = v[s2];
+                for (int d = 0; d < nd; d++) {
+                    double acc = 0.0;
+                    for (int s2 = 0; s2 < kk; s2++) acc += Tp[(size_t)s2 * nd + d] * v[s2];
+                    u[pm[kk + d]] = acc;
                 }
             }
-            slot[out + c] = acc;
         }
     }
-    for (int k = 0; k < K; k++) y[k] = slot[(size_t)t * K + k];
+    const size_t q = (size_t)(2 * m + t) * K;
+    for (int k = 0; k < K; k++) y[k] = ws[q + k] + ws[q + b.region_size[0] + k];
     return SHT_OK;
 }
 

@@ -32,7 +32,10 @@ void parallel_for(long n, int nthreads, void (*fn)(long, void *), void *ctx);
 
 // Butterfly records (butterfly_plan.cpp builds them, butterfly.hip walks them).
 constexpr int kBfMaxLv = 10;     // deepest level a plan may keep
-constexpr int kBfNodeInts = 8;   // vin0, vin1, k0, k1, nd0, nd1, out, ubase
+constexpr int kBfTaskRings = 128; // rings of one residual wave task (two per lane)
+constexpr int kBfNodeInts = 16;  // vin0, vin1, k0, k1, nd0, nd1, out, perm offset,
+                                 // region flags, m, t, level, T offsets of both
+                                 // children (64-bit, lo/hi)
 
 // Long-double inputs of the butterfly precompute (from the plan build).
 struct BflyInput {
@@ -44,20 +47,21 @@ struct BflyInput {
 struct BflyPlan {
     int built = 0;
     int K = 0;                        // columns: north rings
-    long long vmax = 0;               // entries of one parity's level vector region
-    long long slot_entries = 0;       // 2K + 4 vmax entries of 2B doubles per work slot
+    long long ws_entries = 0;         // vector entries (2B values each) of the workspace
+    long long region_size[4] = {};    // Q, LEAF, R0, R1 (Q, R0, R1 exist twice)
     std::vector<int> depth;           // [(L+1)*2] levels kept per (m, t)
-    std::vector<int> order;           // [L+1] m by decreasing work
-    std::vector<long long> res_off;   // [L+2] residual lanes of m
-    std::vector<int> res_rec;         // [lanes][4] ring, i0, i1, 2*out + t
-    std::vector<double> res_val;      // [lanes][2] Legendre values at i0, i0+1
-    std::vector<long long> unit_off;  // [L+1][kBfMaxLv+1] unit ranges, deepest level first
-    std::vector<int> unit_node;       // [units] pair node of the unit
-    std::vector<int> code;            // [units] (code0 & 0xffff) | code1 << 16
+    long long n_tasks = 0;
+    std::vector<int> res_task;        // [tasks][8] t, first row, end row, rings, output entry, m,
+                                      // offset of the output's second copy to clear (or 0)
+    std::vector<int> res_lane;        // [tasks*128][2] ring, first row of the ring
+    std::vector<double> res_val;      // [tasks*128][2] Legendre values at that row and the next
+    std::vector<long long> lv_off;    // [kBfMaxLv+2] first node of each level (lv_off[0]: end)
+    std::vector<int16_t> perm;        // per node and child: positions in C of the skeleton
+                                      // columns (s order), then of the dense ones (d order)
     std::vector<int> node_i;          // [nodes][kBfNodeInts]
-    std::vector<long long> node_T;    // [nodes][2] offsets of the dense blocks in T
     std::vector<double> T;            // interpolation matrices, dense part, [s][d]
-    long long T_entries = 0, res_elems = 0, n_nodes = 0;
+    long long T_entries = 0, res_elems = 0, n_nodes = 0, n_res_lanes = 0, n_units = 0;
+    long long res_exec = 0;           // lane-steps the residual tasks execute
     long long depth_hist[kBfMaxLv + 1] = {};
     double build_seconds = 0.0;
     bool host_T_kept = true;
@@ -118,11 +122,11 @@ struct sht_plan_s {
 
     // ---- butterfly (eps > 0) ------------------------------------------
     sht::BflyPlan bf;
-    int *d_bf_order = nullptr, *d_bf_depth = nullptr, *d_bf_res_rec = nullptr;
-    long long *d_bf_res_off = nullptr, *d_bf_unit_off = nullptr, *d_bf_node_T = nullptr;
+    int *d_bf_res_task = nullptr, *d_bf_res_lane = nullptr;
     double *d_bf_res_val = nullptr, *d_bf_T = nullptr;
     float *d_bf_T32 = nullptr;
-    int *d_bf_unit_node = nullptr, *d_bf_code = nullptr, *d_bf_node_i = nullptr;
+    int16_t *d_bf_perm = nullptr;
+    int *d_bf_node_i = nullptr;
 
 };
 
@@ -145,9 +149,8 @@ hipError_t launch_ring_analysis(const sht_plan_s *p, int nmaps, const double *ma
 hipError_t launch_legendre_adjoint(const sht_plan_s *p, int nmaps, const double *ybar, double *g,
                                    hipStream_t stream);
 // Butterfly Legendre phase (eps > 0 plans): alm -> folded q, like
-// launch_legendre; scratch holds bf_slots() slots of slot_entries * 2 * nmaps
+// launch_legendre; scratch holds ws_entries vector entries of up to 16
 // doubles (FP64) or floats (FP32).
-int bf_slots(const sht_plan_s *p);
 size_t bf_scratch_bytes(const sht_plan_s *p, int nmaps, int fp32);
 hipError_t launch_butterfly(const sht_plan_s *p, int nmaps, const double *alm, double *q, void *scratch,
                             int fp32, hipStream_t stream);

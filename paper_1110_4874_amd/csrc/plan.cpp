@@ -509,16 +509,11 @@ int upload_tables(sht_plan_s *p) {
         BflyPlan &f = p->bf;
 #define UPB(d, h) \
     if (e == hipSuccess) e = up(&p->d, f.h, &b)
-        UPB(d_bf_order, order);
-        UPB(d_bf_depth, depth);
-        UPB(d_bf_res_off, res_off);
-        UPB(d_bf_res_rec, res_rec);
+        UPB(d_bf_res_task, res_task);
+        UPB(d_bf_res_lane, res_lane);
         UPB(d_bf_res_val, res_val);
-        UPB(d_bf_unit_off, unit_off);
-        UPB(d_bf_unit_node, unit_node);
-        UPB(d_bf_code, code);
+        UPB(d_bf_perm, perm);
         UPB(d_bf_node_i, node_i);
-        UPB(d_bf_node_T, node_T);
         UPB(d_bf_T, T);
 #undef UPB
         if (e == hipSuccess && p->opts.store_fp32) {
@@ -554,9 +549,9 @@ void free_device_tables(sht_plan_s *p) {
                     p->d_ring_off,  p->d_ring_bs_off, p->d_coef_off, p->d_coef_hi,  p->d_coef_lo,
                     p->d_start_idx, p->d_start_val, p->d_start_lo,   p->d_grp_lo,   p->d_grp_hi,
                     p->d_tw,        p->d_bs_table,
-                    p->d_bf_order,  p->d_bf_depth,  p->d_bf_res_rec, p->d_bf_res_off, p->d_bf_unit_off,
-                    p->d_bf_node_T, p->d_bf_res_val, p->d_bf_T,      p->d_bf_T32,   p->d_bf_unit_node,
-                    p->d_bf_code,   p->d_bf_node_i};
+                    p->d_bf_res_task, p->d_bf_res_lane,
+                    p->d_bf_res_val, p->d_bf_T,      p->d_bf_T32,   p->d_bf_perm,
+                    p->d_bf_node_i};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     for (auto &rc : p->classes)
@@ -570,11 +565,11 @@ void free_device_tables(sht_plan_s *p) {
     p->d_start_val = p->d_start_lo = nullptr;
     p->d_grp_lo = p->d_grp_hi = nullptr;
     p->d_tw = p->d_bs_table = nullptr;
-    p->d_bf_order = p->d_bf_depth = p->d_bf_res_rec = nullptr;
-    p->d_bf_res_off = p->d_bf_unit_off = p->d_bf_node_T = nullptr;
+    p->d_bf_res_task = p->d_bf_res_lane = nullptr;
     p->d_bf_res_val = p->d_bf_T = nullptr;
     p->d_bf_T32 = nullptr;
-    p->d_bf_unit_node = p->d_bf_code = p->d_bf_node_i = nullptr;
+    p->d_bf_perm = nullptr;
+    p->d_bf_node_i = nullptr;
     p->device_bytes = 0;
 }
 

@@ -45,7 +45,7 @@ class PlanInfo(_c.Structure):
                 ("n_step_dd", _c.c_longlong), ("n_step_lanes", _c.c_longlong),
                 ("device_bytes", _c.c_size_t), ("build_seconds", _c.c_double),
                 ("bf_built", _c.c_int), ("bf_T_entries", _c.c_longlong), ("bf_res_elems", _c.c_longlong),
-                ("bf_nodes", _c.c_longlong), ("bf_units", _c.c_longlong), ("bf_res_lanes", _c.c_longlong),
+                ("bf_nodes", _c.c_longlong), ("bf_units", _c.c_longlong), ("bf_res_lanes", _c.c_longlong), ("bf_res_exec", _c.c_longlong),
                 ("bf_depth_hist", _c.c_longlong * 11), ("bf_build_seconds", _c.c_double)]
 
 
