@@ -113,6 +113,9 @@ typedef struct sht_plan_opts {
                           0 = default 1) */
     int store_fp32;    /* 1: also keep an FP32 copy of the interpolation
                           matrices for SHT_PREC_FP32 */
+    int batch_mib;     /* > 0: run the orders in batches whose level vectors (at
+                          4 maps, FP64) stay under this many MiB between
+                          launches; 0 (default): all orders in one batch */
 } sht_plan_opts;
 
 /* Options for one execution.  Fill with sht_exec_opts_default() first. */
@@ -156,6 +159,7 @@ typedef struct sht_plan_info {
     long long bf_res_exec;    /* lane-steps the residual kernel executes (>= bf_res_elems) */
     long long bf_depth_hist[11]; /* (m, parity) items per kept depth 0..10 */
     double bf_build_seconds;
+    int bf_nbatch;            /* order batches per transform */
 } sht_plan_info_t;
 
 void sht_plan_opts_default(sht_plan_opts *o);

@@ -146,6 +146,7 @@ void sht_plan_opts_default(sht_plan_opts *o) {
     o->chunk = 0;
     o->id_safety = 0.0;
     o->store_fp32 = 0;
+    o->batch_mib = 0;
 }
 
 void sht_exec_opts_default(sht_exec_opts *o) {
@@ -264,6 +265,7 @@ int sht_plan_info(const sht_plan_t *p, sht_plan_info_t *out) {
         out->bf_res_exec = b.res_exec;
         for (int i = 0; i <= kBfMaxLv; i++) out->bf_depth_hist[i] = b.depth_hist[i];
         out->bf_build_seconds = b.build_seconds;
+        out->bf_nbatch = b.nbatch;
     }
     return SHT_OK;
 }

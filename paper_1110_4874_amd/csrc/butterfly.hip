@@ -36,9 +36,7 @@ struct BfArgs {
     const double2 *__restrict__ alm;
     double2 *__restrict__ q;
     S *__restrict__ ws;  // vector workspace, entries of 2 NB values
-    long long rsize[4];  // region sizes (entries): distance to a region's second copy
     int L, K, nrings, nmaps, map0;
-    long long ntasks;
 };
 
 constexpr int kBfThreads = 256;
@@ -77,37 +75,32 @@ __device__ __forceinline__ int acc_row(int k4, int r) {
 }
 
 // One ID block (child ch of a pair node) on one wave:
-//   u_ch = A~_ch^T v_ch  over the columns C the two sibling row blocks share.
-// The identity rows copy v; the dense part T^T V (nd x k times k x NC) runs
-// on the matrix cores, 64 dense rows (four 16-row tiles sharing each V
-// operand) by kBfKSteps * 4 rows of T per batch of loads.  The two children of a node
-// write separate copies of u, which the reader adds, so no wave waits on
-// another's stores.  Input vectors from a previous level are likewise the
-// sum of two copies (leaf vectors from the residual are single).
+//   u += A~_ch^T v_ch  over the columns C the two sibling row blocks share.
+// The identity rows add v; the dense part T^T V (nd x k times k x NC) runs on
+// the matrix cores, 64 dense rows (four 16-row tiles sharing each V operand)
+// by kBfKSteps * 4 rows of T per batch of loads.  u is the workgroup's LDS
+// copy, zeroed before; the two children add into it with LDS atomics, and
+// since every entry receives exactly two addends onto zero the result does
+// not depend on their order.
 constexpr int kBfKSteps = 2;  // K-steps (4 rows of T each) per batch of loads
 
 template <int NB, typename S>
-__device__ __forceinline__ void id_block(const BfArgs<S> &a, int node, int ch, int lane) {
+__device__ __forceinline__ void id_block(const BfArgs<S> &a, int node, int ch, int lane, S *u) {
     constexpr int NC = 2 * NB;
     typedef typename Acc<S>::type acc_t;
     const int *ni = a.node_i + (size_t)node * kBfNodeInts;
     const int n = ni[2] + ni[4];
-    const int kk = ni[2 + ch], nd = ni[4 + ch], fl = ni[8];
-    const long long pin = a.rsize[fl & 3], pout = a.rsize[(fl >> 2) & 3];
-    const S *__restrict__ v0 = a.ws + (size_t)ni[ch] * NC;
-    const S *__restrict__ v1 = v0 + (size_t)pin * NC;  // read only when pin > 0
-    S *__restrict__ u = a.ws + ((size_t)ni[6] + (size_t)ch * pout) * NC;
+    const int kk = ni[2 + ch], nd = ni[4 + ch];
+    const S *__restrict__ v = a.ws + (size_t)ni[ch] * NC;
     const int16_t *__restrict__ pm = a.perm + ni[7] + (size_t)ch * n;
     const long long toff = (long long)(unsigned)ni[12 + 2 * ch] | ((long long)ni[13 + 2 * ch] << 32);
     const S *__restrict__ Tb = a.T + toff;
-    // 32-bit element offsets from wave-uniform bases (saddr addressing)
-    auto vin = [&](unsigned e) -> S { return pin ? v0[e] + v1[e] : v0[e]; };
     // identity rows
     for (int e = lane; e < kk * NC; e += 64) {
         const int s = e / NC, q = e - s * NC;
-        u[(unsigned)pm[s] * NC + q] = vin((unsigned)e);
+        atomicAdd(&u[pm[s] * NC + q], v[(unsigned)e]);
     }
-    // dense rows
+    // dense rows (32-bit element offsets from wave-uniform bases)
     const int i16 = lane & 15, k4 = lane >> 4;
     for (int g0 = 0; g0 < nd; g0 += 64) {
         const int ntile = min(4, (nd - g0 + 15) >> 4);
@@ -120,7 +113,7 @@ __device__ __forceinline__ void id_block(const BfArgs<S> &a, int node, int ch, i
             for (int j = 0; j < kBfKSteps; j++) {
                 const int s = s0 + 4 * j + k4;
                 const bool sv = s < kk;
-                bv[j] = (sv && i16 < NC) ? vin((unsigned)(s * NC + i16)) : (S)0;
+                bv[j] = (sv && i16 < NC) ? v[(unsigned)(s * NC + i16)] : (S)0;
 #pragma unroll
                 for (int tt = 0; tt < 4; tt++) {
                     const int d = g0 + 16 * tt + i16;
@@ -142,18 +135,18 @@ __device__ __forceinline__ void id_block(const BfArgs<S> &a, int node, int ch, i
 #pragma unroll
             for (int r = 0; r < 4; r++) {
                 const int dd = g0 + 16 * tt + acc_row<S>(k4, r);
-                if (dd < nd && i16 < NC) u[(unsigned)pm[kk + dd] * NC + i16] = acc[tt][r];
+                if (dd < nd && i16 < NC) atomicAdd(&u[pm[kk + dd] * NC + i16], acc[tt][r]);
             }
         }
     }
 }
 
-// One residual task on one wave: R rings per lane (lane j: rings j, j + 64),
+// One residual task on one wave: R rings per lane (lane j: rings j + 64 r),
 // rows [imin, iend) of one parity, outputs at entries outb + ring.
 template <int NB, int R, typename S>
 __device__ __forceinline__ void residual_task(const BfArgs<S> &a, S *__restrict__ slot, long long tk, int lane,
-                                              int t, int imin, int iend, int nl, int outb, int clear2,
-                                              c_double *ap, c_double *cfs, int astride) {
+                                              int t, int imin, int iend, int nl, int outb, c_double *ap,
+                                              c_double *cfs, int astride) {
     constexpr int NC = 2 * NB;
     int i0[R];
     double z2[R], v0[R], v1[R], P0[R], P1[R], acc[R][NC];
@@ -209,57 +202,65 @@ __device__ __forceinline__ void residual_task(const BfArgs<S> &a, S *__restrict_
             S *dst = slot + ((size_t)outb + j) * NC;
 #pragma unroll
             for (int c = 0; c < NC; c++) dst[c] = (S)acc[r][c];
-            if (clear2) {  // depth 0: the second copy of q^t stays zero
-                S *dst2 = dst + (size_t)clear2 * NC;
-#pragma unroll
-                for (int c = 0; c < NC; c++) dst2[c] = (S)0;
-            }
         }
     }
 }
 
 template <int NB, typename S>
-__global__ __launch_bounds__(kBfThreads) void k_bf_residual(BfArgs<S> a) {
+__global__ __launch_bounds__(kBfThreads) void k_bf_residual(BfArgs<S> a, long long t0, long long t1) {
     const int lane = threadIdx.x & 63;
-    const long long tk = (long long)blockIdx.x * (kBfThreads / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (tk >= a.ntasks) return;
+    const long long tk = t0 + (long long)blockIdx.x * (kBfThreads / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (tk >= t1) return;
     const int4 h = a.res_task[2 * tk], h2 = a.res_task[2 * tk + 1];
     const int t = __builtin_amdgcn_readfirstlane(h.x), imin = __builtin_amdgcn_readfirstlane(h.y);
     const int iend = __builtin_amdgcn_readfirstlane(h.z), nl = __builtin_amdgcn_readfirstlane(h.w);
     const int outb = __builtin_amdgcn_readfirstlane(h2.x), m = __builtin_amdgcn_readfirstlane(h2.y);
-    const int clear2 = __builtin_amdgcn_readfirstlane(h2.z);
     const size_t aoff = (size_t)m * (2 * a.L + 3 - m) / 2;
     c_double *ap = (c_double *)(a.alm + (aoff + t) * a.nmaps + a.map0);
     c_double *cfs = (c_double *)(a.coef + 4 * a.coef_off[m]);
     const int astride = 4 * a.nmaps;  // doubles between rows i and i+1
-    if (nl > 64)
-        residual_task<NB, 2>(a, a.ws, tk, lane, t, imin, iend, nl, outb, clear2, ap, cfs, astride);
+    if (nl > 192)
+        residual_task<NB, 4>(a, a.ws, tk, lane, t, imin, iend, nl, outb, ap, cfs, astride);
+    else if (nl > 128)
+        residual_task<NB, 3>(a, a.ws, tk, lane, t, imin, iend, nl, outb, ap, cfs, astride);
+    else if (nl > 64)
+        residual_task<NB, 2>(a, a.ws, tk, lane, t, imin, iend, nl, outb, ap, cfs, astride);
     else
-        residual_task<NB, 1>(a, a.ws, tk, lane, t, imin, iend, nl, outb, clear2, ap, cfs, astride);
+        residual_task<NB, 1>(a, a.ws, tk, lane, t, imin, iend, nl, outb, ap, cfs, astride);
 }
 
+// One workgroup of two waves per pair node: u (zeroed in LDS) collects both
+// children, then goes to the next level's vector in one coalesced store.
 template <int NB, typename S>
-__global__ __launch_bounds__(kBfThreads) void k_bf_level(BfArgs<S> a, long long n0, long long n1) {
-    const long long w = (long long)blockIdx.x * (kBfThreads / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const long long node = n0 + (w >> 1);
-    if (node >= n1) return;
-    id_block<NB, S>(a, (int)node, (int)(w & 1), threadIdx.x & 63);
+__global__ __launch_bounds__(128) void k_bf_level(BfArgs<S> a, long long n0) {
+    constexpr int NC = 2 * NB;
+    extern __shared__ char lds_raw[];
+    S *u = reinterpret_cast<S *>(lds_raw);
+    const int node = (int)(n0 + blockIdx.x);
+    const int *ni = a.node_i + (size_t)node * kBfNodeInts;
+    const int n = ni[2] + ni[4];
+    for (int e = threadIdx.x; e < n * NC; e += 128) u[e] = (S)0;
+    __syncthreads();
+    id_block<NB, S>(a, node, __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), threadIdx.x & 63, u);
+    __syncthreads();
+    S *__restrict__ out = a.ws + (size_t)ni[6] * NC;
+    for (int e = threadIdx.x; e < n * NC; e += 128) out[e] = u[e];
 }
 
+// Fold of one batch: slot j of the batch holds order m = batch + j nbatch.
 template <int NB, typename S>
-__global__ __launch_bounds__(kBfThreads) void k_bf_fold(BfArgs<S> a) {
+__global__ __launch_bounds__(kBfThreads) void k_bf_fold(BfArgs<S> a, int batch, int nbatch, int count) {
     constexpr int NC = 2 * NB;
     const int K = a.K;
     const long long e = (long long)blockIdx.x * kBfThreads + threadIdx.x;
-    if (e >= (long long)(a.L + 1) * K * NB) return;
+    if (e >= (long long)count * K * NB) return;
     const int b = (int)(e % NB);
-    const long long mk = e / NB;
-    const int k = (int)(mk % K), m = (int)(mk / K);
-    const S *qe = a.ws + ((size_t)(2 * m) * K + k) * NC + 2 * b;
-    const S *qo = a.ws + ((size_t)(2 * m + 1) * K + k) * NC + 2 * b;
-    const size_t p2 = (size_t)a.rsize[0] * NC;  // second copy of q^t
-    double er = (double)qe[0] + (double)qe[p2], ei = (double)qe[1] + (double)qe[p2 + 1];
-    double orr = (double)qo[0] + (double)qo[p2], oi = (double)qo[1] + (double)qo[p2 + 1];
+    const long long jk = e / NB;
+    const int k = (int)(jk % K), j = (int)(jk / K);
+    const int m = batch + j * nbatch;
+    const S *qe = a.ws + ((size_t)(2 * j) * K + k) * NC + 2 * b;
+    const S *qo = a.ws + ((size_t)(2 * j + 1) * K + k) * NC + 2 * b;
+    double er = (double)qe[0], ei = (double)qe[1], orr = (double)qo[0], oi = (double)qo[1];
     if (m == 0) ei = oi = 0.0;  // real field: Im a_l0 is ignored
     a.q[((size_t)m * a.nrings + k) * a.nmaps + a.map0 + b] = make_double2(er + orr, ei + oi);
     const int ks = a.nrings - 1 - k;
@@ -276,18 +277,23 @@ template <int NB, typename S>
 static hipError_t launch_bf_nb(const sht_plan_s *p, BfArgs<S> a, hipStream_t st) {
     constexpr int WPB = kBfThreads / 64;
     const BflyPlan &b = p->bf;
-    if (b.n_tasks > 0)
-        hipLaunchKernelGGL((k_bf_residual<NB, S>), dim3((unsigned)((b.n_tasks + WPB - 1) / WPB)), dim3(kBfThreads), 0,
-                           st, a);
-    for (int lvl = kBfMaxLv; lvl >= 1; lvl--) {
-        const long long n0 = b.lv_off[lvl], n1 = lvl > 1 ? b.lv_off[lvl - 1] : b.lv_off[0];
-        if (n1 <= n0) continue;
-        hipLaunchKernelGGL((k_bf_level<NB, S>), dim3((unsigned)((2 * (n1 - n0) + WPB - 1) / WPB)), dim3(kBfThreads),
-                           0, st, a, n0, n1);
+    for (int bt = 0; bt < b.nbatch; bt++) {
+        const long long t0 = b.batch_task[bt], t1 = b.batch_task[bt + 1];
+        if (t1 > t0)
+            hipLaunchKernelGGL((k_bf_residual<NB, S>), dim3((unsigned)((t1 - t0 + WPB - 1) / WPB)), dim3(kBfThreads), 0,
+                               st, a, t0, t1);
+        const long long *lo = b.lv_off.data() + (size_t)bt * (kBfMaxLv + 1);
+        for (int q = 0; q < kBfMaxLv; q++) {
+            const long long n0 = lo[q], n1 = lo[q + 1];
+            if (n1 <= n0) continue;
+            hipLaunchKernelGGL((k_bf_level<NB, S>), dim3((unsigned)(n1 - n0)), dim3(128),
+                               (size_t)b.max_n * 2 * NB * sizeof(S), st, a, n0);
+        }
+        const long long nf = (long long)b.batch_count[bt] * b.K * NB;
+        if (nf > 0)
+            hipLaunchKernelGGL((k_bf_fold<NB, S>), dim3((unsigned)((nf + kBfThreads - 1) / kBfThreads)),
+                               dim3(kBfThreads), 0, st, a, bt, b.nbatch, b.batch_count[bt]);
     }
-    const long long nf = (long long)(p->L + 1) * b.K * NB;
-    hipLaunchKernelGGL((k_bf_fold<NB, S>), dim3((unsigned)((nf + kBfThreads - 1) / kBfThreads)), dim3(kBfThreads), 0,
-                       st, a);
     return hipGetLastError();
 }
 
@@ -311,8 +317,6 @@ static hipError_t launch_bf(const sht_plan_s *p, int nmaps, const double *alm, d
     a.K = p->bf.K;
     a.nrings = p->nrings;
     a.nmaps = nmaps;
-    a.ntasks = p->bf.n_tasks;
-    for (int r = 0; r < 4; r++) a.rsize[r] = p->bf.region_size[r];
     hipError_t e = hipSuccess;
     for (int b = 0; b < nmaps && e == hipSuccess;) {
         const int nb = bf_nb(nmaps - b);

@@ -402,147 +402,185 @@ int build_butterfly(sht_plan_s *p, const BflyInput &in) {
     // vectors that level launches produce for even / odd levels.  Offsets
     // are region-relative while building and made absolute at the end.
     enum { RQ = 0, RLEAF = 1, RR0 = 2, RR1 = 3 };
-    long long leaf_cnt = 0, lvl_cnt[kBfMaxLv + 1] = {};
-    std::vector<std::vector<int>> lvnodes(kBfMaxLv + 1);  // per level: node records
-    std::vector<int> task_region;                          // per task: region of its output
-    for (int m = 0; m <= L; m++) {
-        for (int t = 0; t < 2; t++) {
-            Item &it = c.items[(size_t)2 * m + t];
-            const int d = it.depth;
-            b.depth[(size_t)2 * m + t] = d;
-            b.T_entries += it.T_entries;
-            b.res_elems += it.res_elems;
-            b.depth_hist[std::min(d, kBfMaxLv)]++;
-            const long long qbase = (long long)(2 * m + t) * K;
-            // offsets of this item's vectors at every level it has
-            std::vector<std::vector<long long>> voff(d + 1);  // voff[i][node index] (level i vectors)
-            std::vector<int> vreg(d + 1, RQ);
-            for (int i = 1; i <= d; i++) {
-                const auto &lvn = it.lv[i - 1];
-                voff[i].resize(lvn.size());
-                long long *cnt = (i == d) ? &leaf_cnt : &lvl_cnt[i];
-                vreg[i] = (i == d) ? RLEAF : ((i & 1) ? RR1 : RR0);
-                for (size_t q = 0; q < lvn.size(); q++) {
-                    voff[i][q] = *cnt;
-                    *cnt += lvn[q].k;
+    // Orders may be processed in batches (order m goes to batch m mod nb)
+    // whose live vectors fit a cache budget: each batch runs the residual,
+    // the level launches and the fold before the next one starts.
+    std::vector<long long> item_leaf(c.items.size(), 0), item_lvl((size_t)c.items.size() * (kBfMaxLv + 1), 0);
+    for (size_t q = 0; q < c.items.size(); q++) {
+        const Item &it = c.items[q];
+        for (int i = 1; i <= it.depth; i++) {
+            long long sz = 0;
+            for (const Node &nd : it.lv[i - 1]) sz += nd.k;
+            if (i == it.depth)
+                item_leaf[q] = sz;
+            else
+                item_lvl[q * (kBfMaxLv + 1) + i] = sz;
+        }
+    }
+    // (batch_mib = 0: one batch; measured faster on MI355X, where the level
+    // launches need every order's nodes in flight more than cache residency)
+    const double target = p->opts.batch_mib > 0 ? p->opts.batch_mib * 1048576.0 : 1e300;  // at 8 doubles per entry
+    int nb = 1;
+    for (;; nb++) {
+        double worst = 0;
+        for (int bt = 0; bt < nb; bt++) {
+            long long q = 0, leaf = 0, lv[kBfMaxLv + 1] = {};
+            for (int m = bt; m <= L; m += nb)
+                for (int t = 0; t < 2; t++) {
+                    const size_t ii = (size_t)2 * m + t;
+                    q += K;
+                    leaf += item_leaf[ii];
+                    for (int i = 1; i <= kBfMaxLv; i++) lv[i] += item_lvl[ii * (kBfMaxLv + 1) + i];
                 }
-            }
-            // residual tasks
-            const long long rbase = d == 0 ? qbase : (voff[d].empty() ? 0 : voff[d][0]);
-            const int rreg = d == 0 ? RQ : RLEAF;
-            for (size_t q = 0; q + 3 < it.seg.size(); q += 4) {
-                const int l0 = it.seg[q], l1 = it.seg[q + 1], rend = it.seg[q + 3];
-                const int cnt = l1 - l0;
-                if (cnt <= 0) continue;
-                const int ntask = (cnt + kBfTaskRings - 1) / kBfTaskRings;
-                for (int tk = 0; tk < ntask; tk++) {
-                    const int c0 = l0 + (int)((long long)cnt * tk / ntask);
-                    const int c1 = l0 + (int)((long long)cnt * (tk + 1) / ntask);
-                    const int nl = c1 - c0;
-                    int imin = rend;
-                    for (int j = 0; j < nl; j++) imin = std::min(imin, it.lane[4 * (c0 + j) + 1]);
-                    b.res_task.insert(b.res_task.end(),
-                                      {t, imin, rend, nl, (int)(rbase + it.lane[4 * c0 + 3]), m, 0, 0});
-                    task_region.push_back(rreg);
-                    for (int j = 0; j < kBfTaskRings; j++) {
-                        if (j < nl) {
-                            const int *ln = &it.lane[4 * (c0 + j)];
-                            b.res_lane.insert(b.res_lane.end(), {ln[0], ln[1]});
-                            b.res_val.push_back(it.lval[2 * (c0 + j)]);
-                            b.res_val.push_back(it.lval[2 * (c0 + j) + 1]);
-                        } else {
-                            b.res_lane.insert(b.res_lane.end(), {0, INT32_MAX});
-                            b.res_val.push_back(0.0);
-                            b.res_val.push_back(0.0);
-                        }
+            long long r0 = 0, r1 = 0;
+            for (int i = 1; i <= kBfMaxLv; i++) (i & 1 ? r1 : r0) = std::max(i & 1 ? r1 : r0, lv[i]);
+            worst = std::max(worst, 64.0 * (double)(q + leaf + r0 + r1));
+        }
+        if (worst <= target || nb > L) break;
+    }
+    b.nbatch = nb;
+    b.batch_task.assign(nb + 1, 0);
+    b.lv_off.assign((size_t)nb * (kBfMaxLv + 1) + 1, 0);
+    b.batch_count.assign(nb, 0);
+    for (int bt = 0; bt < nb; bt++) {
+        long long leaf_cnt = 0, lvl_cnt[kBfMaxLv + 1] = {};
+        std::vector<std::vector<int>> lvnodes(kBfMaxLv + 1);  // per level: node records
+        std::vector<int> task_region;                          // per task: region of its output
+        b.batch_task[bt] = (long long)b.res_task.size() / 8;
+        const size_t task0 = b.res_task.size() / 8;
+        int slot = 0;
+        for (int m = bt; m <= L; m += nb, slot++) {
+            for (int t = 0; t < 2; t++) {
+                Item &it = c.items[(size_t)2 * m + t];
+                const int d = it.depth;
+                b.depth[(size_t)2 * m + t] = d;
+                b.T_entries += it.T_entries;
+                b.res_elems += it.res_elems;
+                b.depth_hist[std::min(d, kBfMaxLv)]++;
+                const long long qbase = (long long)(2 * slot + t) * K;
+                // offsets of this item's vectors at every level it has
+                std::vector<std::vector<long long>> voff(d + 1);
+                std::vector<int> vreg(d + 1, RQ);
+                for (int i = 1; i <= d; i++) {
+                    const auto &lvn = it.lv[i - 1];
+                    voff[i].resize(lvn.size());
+                    long long *cnt = (i == d) ? &leaf_cnt : &lvl_cnt[i];
+                    vreg[i] = (i == d) ? RLEAF : ((i & 1) ? RR1 : RR0);
+                    for (size_t q = 0; q < lvn.size(); q++) {
+                        voff[i][q] = *cnt;
+                        *cnt += lvn[q].k;
                     }
-                    b.n_res_lanes += nl;
-                    b.res_exec += (long long)(rend - imin) * (nl > 64 ? 128 : 64);
                 }
-            }
-            // pair nodes of every level
-            for (int lvl = d; lvl >= 1; lvl--) {
-                const int G = groups_at(it, lvl);
-                for (int pi = 0; pi < (1 << (lvl - 1)); pi++)
-                    for (int g = 0; g < G; g++) {
-                        const size_t q0 = (size_t)(2 * pi) * G + g, q1 = (size_t)(2 * pi + 1) * G + g;
-                        const Node &c0 = it.lv[lvl - 1][q0];
-                        const Node &c1 = it.lv[lvl - 1][q1];
-                        const int nn = c0.n;  // both children share the columns C
-                        if (nn == 0) continue;
-                        long long out;
-                        int oreg;
-                        if (lvl == 1) {
-                            out = qbase + it.colb[g];
-                            oreg = RQ;
-                        } else {
-                            out = voff[lvl - 1][(size_t)pi * groups_at(it, lvl - 1) + 2 * g];
-                            oreg = vreg[lvl - 1];
-                        }
-                        std::vector<int> &rec = lvnodes[lvl];
-                        const long long T0 = (long long)b.T.size(), T1 = T0 + (long long)c0.T.size();
-                        rec.insert(rec.end(), {(int)voff[lvl][q0], (int)voff[lvl][q1], c0.k, c1.k, c0.n - c0.k,
-                                               c1.n - c1.k, (int)out, (int)b.perm.size(), vreg[lvl] | (oreg << 2), m,
-                                               t, lvl, (int)(T0 & 0xffffffff), (int)(T0 >> 32),
-                                               (int)(T1 & 0xffffffff), (int)(T1 >> 32)});
-                        for (const Node *ch : {&c0, &c1}) b.T.insert(b.T.end(), ch->T.begin(), ch->T.end());
-                        // per child: skeleton positions (s order), then dense positions (d order)
-                        for (const Node *ch : {&c0, &c1}) {
-                            std::vector<int16_t> sk(ch->k), dn(nn - ch->k);
-                            for (int q = 0; q < nn; q++) {
-                                const int cd = ch->code[q];
-                                if (cd >= 0)
-                                    sk[cd] = (int16_t)q;
-                                else
-                                    dn[-1 - cd] = (int16_t)q;
+                // residual tasks
+                const long long rbase = d == 0 ? qbase : (voff[d].empty() ? 0 : voff[d][0]);
+                const int rreg = d == 0 ? RQ : RLEAF;
+                for (size_t q = 0; q + 3 < it.seg.size(); q += 4) {
+                    const int l0 = it.seg[q], l1 = it.seg[q + 1], rend = it.seg[q + 3];
+                    const int cnt = l1 - l0;
+                    if (cnt <= 0) continue;
+                    const int ntask = (cnt + kBfTaskRings - 1) / kBfTaskRings;
+                    for (int tk = 0; tk < ntask; tk++) {
+                        const int c0 = l0 + (int)((long long)cnt * tk / ntask);
+                        const int c1 = l0 + (int)((long long)cnt * (tk + 1) / ntask);
+                        const int nl = c1 - c0;
+                        int imin = rend;
+                        for (int j = 0; j < nl; j++) imin = std::min(imin, it.lane[4 * (c0 + j) + 1]);
+                        b.res_task.insert(b.res_task.end(),
+                                          {t, imin, rend, nl, (int)(rbase + it.lane[4 * c0 + 3]), m, 0, 0});
+                        task_region.push_back(rreg);
+                        for (int j = 0; j < kBfTaskRings; j++) {
+                            if (j < nl) {
+                                const int *ln = &it.lane[4 * (c0 + j)];
+                                b.res_lane.insert(b.res_lane.end(), {ln[0], ln[1]});
+                                b.res_val.push_back(it.lval[2 * (c0 + j)]);
+                                b.res_val.push_back(it.lval[2 * (c0 + j) + 1]);
+                            } else {
+                                b.res_lane.insert(b.res_lane.end(), {0, INT32_MAX});
+                                b.res_val.push_back(0.0);
+                                b.res_val.push_back(0.0);
                             }
-                            b.perm.insert(b.perm.end(), sk.begin(), sk.end());
-                            b.perm.insert(b.perm.end(), dn.begin(), dn.end());
                         }
-                        b.n_nodes++;
-                        b.n_units += nn;
+                        b.n_res_lanes += nl;
+                        b.res_exec += (long long)(rend - imin) * 64 * ((nl + 63) / 64);
                     }
+                }
+                // pair nodes of every level
+                for (int lvl = d; lvl >= 1; lvl--) {
+                    const int G = groups_at(it, lvl);
+                    for (int pi = 0; pi < (1 << (lvl - 1)); pi++)
+                        for (int g = 0; g < G; g++) {
+                            const size_t q0 = (size_t)(2 * pi) * G + g, q1 = (size_t)(2 * pi + 1) * G + g;
+                            const Node &c0 = it.lv[lvl - 1][q0];
+                            const Node &c1 = it.lv[lvl - 1][q1];
+                            const int nn = c0.n;  // both children share the columns C
+                            if (nn == 0) continue;
+                            long long out;
+                            int oreg;
+                            if (lvl == 1) {
+                                out = qbase + it.colb[g];
+                                oreg = RQ;
+                            } else {
+                                out = voff[lvl - 1][(size_t)pi * groups_at(it, lvl - 1) + 2 * g];
+                                oreg = vreg[lvl - 1];
+                            }
+                            std::vector<int> &rec = lvnodes[lvl];
+                            const long long T0 = (long long)b.T.size(), T1 = T0 + (long long)c0.T.size();
+                            rec.insert(rec.end(), {(int)voff[lvl][q0], (int)voff[lvl][q1], c0.k, c1.k, c0.n - c0.k,
+                                                   c1.n - c1.k, (int)out, (int)b.perm.size(), vreg[lvl] | (oreg << 2),
+                                                   m, t, lvl, (int)(T0 & 0xffffffff), (int)(T0 >> 32),
+                                                   (int)(T1 & 0xffffffff), (int)(T1 >> 32)});
+                            for (const Node *ch : {&c0, &c1}) b.T.insert(b.T.end(), ch->T.begin(), ch->T.end());
+                            // per child: skeleton positions (s order), then dense positions (d order)
+                            for (const Node *ch : {&c0, &c1}) {
+                                std::vector<int16_t> sk(ch->k), dn(nn - ch->k);
+                                for (int q = 0; q < nn; q++) {
+                                    const int cd = ch->code[q];
+                                    if (cd >= 0)
+                                        sk[cd] = (int16_t)q;
+                                    else
+                                        dn[-1 - cd] = (int16_t)q;
+                                }
+                                b.perm.insert(b.perm.end(), sk.begin(), sk.end());
+                                b.perm.insert(b.perm.end(), dn.begin(), dn.end());
+                            }
+                            b.n_nodes++;
+                            b.n_units += nn;
+                            b.max_n = std::max(b.max_n, nn);
+                        }
+                }
+                std::vector<std::vector<Node>>().swap(it.lv);
+                std::vector<int>().swap(it.lane);
+                std::vector<double>().swap(it.lval);
+                std::vector<int>().swap(it.seg);
             }
-            std::vector<std::vector<Node>>().swap(it.lv);
-            std::vector<int>().swap(it.lane);
-            std::vector<double>().swap(it.lval);
-            std::vector<int>().swap(it.seg);
         }
-    }
-    // region bases and absolute offsets.  Every region except LEAF is
-    // doubled: the two ID blocks of a pair node write their halves of u to
-    // the two copies, and the reader adds them.
-    long long r0 = 0, r1 = 0;
-    for (int i = 1; i <= kBfMaxLv; i++) (i & 1 ? r1 : r0) = std::max(i & 1 ? r1 : r0, lvl_cnt[i]);
-    const long long qsz = 2LL * K * (L + 1);
-    const long long base[4] = {0, 2 * qsz, 2 * qsz + leaf_cnt, 2 * qsz + leaf_cnt + 2 * r0};
-    b.region_size[0] = qsz;
-    b.region_size[1] = 0;
-    b.region_size[2] = r0;
-    b.region_size[3] = r1;
-    b.ws_entries = base[3] + 2 * r1;
-    if (b.ws_entries > INT32_MAX || (long long)b.perm.size() > INT32_MAX)
-        return fail(SHT_EUNSUPPORTED, "butterfly plan exceeds 32-bit record offsets");
-    for (size_t q = 0; q < task_region.size(); q++) {
-        b.res_task[8 * q + 4] += (int)base[task_region[q]];
-        b.res_task[8 * q + 6] = task_region[q] == RQ ? (int)qsz : 0;  // partner copy to clear
-    }
-    // node records, deepest level first, with their launch ranges
-    b.lv_off.assign(kBfMaxLv + 2, 0);
-    for (int lvl = kBfMaxLv; lvl >= 1; lvl--) {
-        b.lv_off[lvl] = (long long)b.node_i.size() / kBfNodeInts;
-        std::vector<int> &rec = lvnodes[lvl];
-        for (size_t q = 0; q < rec.size(); q += kBfNodeInts) {
-            const int fl = rec[q + 8];
-            rec[q + 0] += (int)base[fl & 3];
-            rec[q + 1] += (int)base[fl & 3];
-            rec[q + 6] += (int)base[(fl >> 2) & 3];
+        b.batch_count[bt] = slot;
+        // batch-local region bases and absolute offsets
+        long long r0 = 0, r1 = 0;
+        for (int i = 1; i <= kBfMaxLv; i++) (i & 1 ? r1 : r0) = std::max(i & 1 ? r1 : r0, lvl_cnt[i]);
+        const long long qsz = 2LL * K * slot;
+        const long long base[4] = {0, qsz, qsz + leaf_cnt, qsz + leaf_cnt + r0};
+        b.ws_entries = std::max(b.ws_entries, base[3] + r1);
+        if (b.ws_entries > INT32_MAX || (long long)b.perm.size() > INT32_MAX)
+            return fail(SHT_EUNSUPPORTED, "butterfly plan exceeds 32-bit record offsets");
+        for (size_t q = 0; q < task_region.size(); q++) b.res_task[8 * (task0 + q) + 4] += (int)base[task_region[q]];
+        // node records, deepest level first, with their launch ranges
+        for (int lvl = kBfMaxLv; lvl >= 1; lvl--) {
+            b.lv_off[(size_t)bt * (kBfMaxLv + 1) + kBfMaxLv - lvl] = (long long)b.node_i.size() / kBfNodeInts;
+            std::vector<int> &rec = lvnodes[lvl];
+            for (size_t q = 0; q < rec.size(); q += kBfNodeInts) {
+                const int fl = rec[q + 8];
+                rec[q + 0] += (int)base[fl & 3];
+                rec[q + 1] += (int)base[fl & 3];
+                rec[q + 6] += (int)base[(fl >> 2) & 3];
+            }
+            b.node_i.insert(b.node_i.end(), rec.begin(), rec.end());
+            std::vector<int>().swap(rec);
         }
-        b.node_i.insert(b.node_i.end(), rec.begin(), rec.end());
-        std::vector<int>().swap(rec);
+        b.lv_off[(size_t)bt * (kBfMaxLv + 1) + kBfMaxLv] = (long long)b.node_i.size() / kBfNodeInts;
     }
-    b.lv_off[0] = (long long)b.node_i.size() / kBfNodeInts;  // end of level 1
-    b.n_tasks = (long long)task_region.size();
+    b.batch_task[nb] = (long long)b.res_task.size() / 8;
+    b.n_tasks = (long long)b.res_task.size() / 8;
     b.built = 1;
     b.build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return SHT_OK;
@@ -560,9 +598,10 @@ static long long node_T_off(const int *ni, int ch) {
 int butterfly_apply_host(const sht_plan_s *p, int m, int t, const double *x, double *y) {
     const BflyPlan &b = p->bf;
     const int K = b.K;
+    const int bt = m % b.nbatch, slot = m / b.nbatch;
     std::vector<double> ws((size_t)b.ws_entries, 0.0);
     const double *cf = p->coef_hi.data() + 4 * p->coef_off[m];
-    for (long long tk = 0; tk < b.n_tasks; tk++) {
+    for (long long tk = b.batch_task[bt]; tk < b.batch_task[bt + 1]; tk++) {
         const int *h = &b.res_task[(size_t)8 * tk];
         if (h[0] != t || h[5] != m) continue;
         for (int j = 0; j < h[3]; j++) {
@@ -578,34 +617,32 @@ int butterfly_apply_host(const sht_plan_s *p, int m, int t, const double *x, dou
                 P1 = P2;
             }
             ws[(size_t)h[4] + j] = acc;
-            if (h[6]) ws[(size_t)h[4] + h[6] + j] = 0.0;
         }
     }
-    for (int lvl = kBfMaxLv; lvl >= 1; lvl--) {
-        const long long n0 = b.lv_off[lvl], n1 = lvl > 1 ? b.lv_off[lvl - 1] : b.lv_off[0];
-        for (long long node = n0; node < n1; node++) {
+    const long long *lo = b.lv_off.data() + (size_t)bt * (kBfMaxLv + 1);
+    for (int q = 0; q < kBfMaxLv; q++) {
+        for (long long node = lo[q]; node < lo[q + 1]; node++) {
             const int *ni = &b.node_i[(size_t)node * kBfNodeInts];
             if (ni[9] != m || ni[10] != t) continue;
             const int n = ni[2] + ni[4];
-            const long long pin = b.region_size[ni[8] & 3], pout = b.region_size[(ni[8] >> 2) & 3];
+            std::vector<double> u(n, 0.0);
             for (int ch = 0; ch < 2; ch++) {
                 const int16_t *pm = b.perm.data() + ni[7] + (size_t)ch * n;
                 const int kk = ni[2 + ch], nd = ni[4 + ch];
-                std::vector<double> v(kk);
-                for (int s2 = 0; s2 < kk; s2++) v[s2] = ws[(size_t)ni[ch] + s2] + (pin ? ws[(size_t)ni[ch] + pin + s2] : 0.0);
+                const double *v = ws.data() + ni[ch];
                 const double *Tp = b.T.data() + node_T_off(ni, ch);
-                double *u = ws.data() + ni[6] + ch * pout;
-                for (int s2 = 0; s2 < kk; s2++) u[pm[s2]] = v[s2];
+                for (int s2 = 0; s2 < kk; s2++) u[pm[s2]] += v[s2];
                 for (int d = 0; d < nd; d++) {
                     double acc = 0.0;
                     for (int s2 = 0; s2 < kk; s2++) acc += Tp[(size_t)s2 * nd + d] * v[s2];
-                    u[pm[kk + d]] = acc;
+                    u[pm[kk + d]] += acc;
                 }
             }
+            for (int c2 = 0; c2 < n; c2++) ws[(size_t)ni[6] + c2] = u[c2];
         }
     }
-    const size_t q = (size_t)(2 * m + t) * K;
-    for (int k = 0; k < K; k++) y[k] = ws[q + k] + ws[q + b.region_size[0] + k];
+    const size_t q = (size_t)(2 * slot + t) * K;
+    for (int k = 0; k < K; k++) y[k] = ws[q + k];
     return SHT_OK;
 }
 

@@ -32,7 +32,7 @@ void parallel_for(long n, int nthreads, void (*fn)(long, void *), void *ctx);
 
 // Butterfly records (butterfly_plan.cpp builds them, butterfly.hip walks them).
 constexpr int kBfMaxLv = 10;     // deepest level a plan may keep
-constexpr int kBfTaskRings = 128; // rings of one residual wave task (two per lane)
+constexpr int kBfTaskRings = 256; // rings of one residual wave task (up to four per lane)
 constexpr int kBfNodeInts = 16;  // vin0, vin1, k0, k1, nd0, nd1, out, perm offset,
                                  // region flags, m, t, level, T offsets of both
                                  // children (64-bit, lo/hi)
@@ -48,14 +48,16 @@ struct BflyPlan {
     int built = 0;
     int K = 0;                        // columns: north rings
     long long ws_entries = 0;         // vector entries (2B values each) of the workspace
-    long long region_size[4] = {};    // Q, LEAF, R0, R1 (Q, R0, R1 exist twice)
+    int max_n = 0;                    // widest column set C of any pair node
     std::vector<int> depth;           // [(L+1)*2] levels kept per (m, t)
     long long n_tasks = 0;
-    std::vector<int> res_task;        // [tasks][8] t, first row, end row, rings, output entry, m,
-                                      // offset of the output's second copy to clear (or 0)
-    std::vector<int> res_lane;        // [tasks*128][2] ring, first row of the ring
-    std::vector<double> res_val;      // [tasks*128][2] Legendre values at that row and the next
-    std::vector<long long> lv_off;    // [kBfMaxLv+2] first node of each level (lv_off[0]: end)
+    std::vector<int> res_task;        // [tasks][8] t, first row, end row, rings, output entry, m
+    std::vector<int> res_lane;        // [tasks*256][2] ring, first row of the ring
+    std::vector<double> res_val;      // [tasks*256][2] Legendre values at that row and the next
+    int nbatch = 1;                   // orders m are run in batches m mod nbatch
+    std::vector<int> batch_count;     // [nbatch] orders in each batch
+    std::vector<long long> batch_task;  // [nbatch+1] residual task ranges
+    std::vector<long long> lv_off;    // [nbatch][kBfMaxLv+1] (+1) node ranges, deepest level first
     std::vector<int16_t> perm;        // per node and child: positions in C of the skeleton
                                       // columns (s order), then of the dense ones (d order)
     std::vector<int> node_i;          // [nodes][kBfNodeInts]

@@ -29,7 +29,7 @@ class PlanOpts(_c.Structure):
     _fields_ = [("cutoff", _c.c_double), ("dd_sin", _c.c_double), ("nthreads", _c.c_int),
                 ("rings_per_lane", _c.c_int), ("ring_threads", _c.c_int), ("host_only", _c.c_int),
                 ("rho", _c.c_double), ("max_levels", _c.c_int), ("chunk", _c.c_int),
-                ("id_safety", _c.c_double), ("store_fp32", _c.c_int)]
+                ("id_safety", _c.c_double), ("store_fp32", _c.c_int), ("batch_mib", _c.c_int)]
 
 
 class ExecOpts(_c.Structure):
@@ -46,7 +46,8 @@ class PlanInfo(_c.Structure):
                 ("device_bytes", _c.c_size_t), ("build_seconds", _c.c_double),
                 ("bf_built", _c.c_int), ("bf_T_entries", _c.c_longlong), ("bf_res_elems", _c.c_longlong),
                 ("bf_nodes", _c.c_longlong), ("bf_units", _c.c_longlong), ("bf_res_lanes", _c.c_longlong), ("bf_res_exec", _c.c_longlong),
-                ("bf_depth_hist", _c.c_longlong * 11), ("bf_build_seconds", _c.c_double)]
+                ("bf_depth_hist", _c.c_longlong * 11), ("bf_build_seconds", _c.c_double),
+                ("bf_nbatch", _c.c_int)]
 
 
 EXPORTS = {
@@ -132,7 +133,7 @@ class Plan:
 
     def __init__(self, L, nside, eps=0.0, *, cutoff=None, dd_sin=None, nthreads=0, rings_per_lane=0,
                  ring_threads=0, host_only=False, rho=0.0, max_levels=-1, chunk=0, id_safety=0.0,
-                 store_fp32=False):
+                 store_fp32=False, batch_mib=0):
         lib = load()
         o = PlanOpts()
         lib.sht_plan_opts_default(_c.byref(o))
@@ -141,6 +142,7 @@ class Plan:
         o.chunk = int(chunk)
         o.id_safety = float(id_safety)
         o.store_fp32 = 1 if store_fp32 else 0
+        o.batch_mib = int(batch_mib)
         if cutoff is not None:
             o.cutoff = cutoff
         if dd_sin is not None:

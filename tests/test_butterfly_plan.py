@@ -67,12 +67,15 @@ def _dense_apply(L, N, m, t, x):
     return np.array([np.dot(oracle.plm_ring(L, m, N, k + 1, ld=True)[t::2][:n], x) for k in range(2 * N)])
 
 
-@pytest.mark.parametrize("L,N,eps,levels", [(255, 128, 1e-12, 3), (255, 128, 1e-8, 2), (127, 64, 1e-12, -1),
-                                            (200, 64, 1e-10, 2), (511, 256, 1e-12, 4)])
-def test_compressed_operator_matches_dense(lib, L, N, eps, levels):
-    p = sht.Plan(L, N, eps, host_only=True, max_levels=levels)
+@pytest.mark.parametrize("L,N,eps,levels,batch", [(255, 128, 1e-12, 3, 0), (255, 128, 1e-8, 2, 1),
+                                                  (127, 64, 1e-12, -1, 0), (200, 64, 1e-10, 2, 1),
+                                                  (511, 256, 1e-12, 4, 0), (511, 256, 1e-12, 4, 2)])
+def test_compressed_operator_matches_dense(lib, L, N, eps, levels, batch):
+    p = sht.Plan(L, N, eps, host_only=True, max_levels=levels, batch_mib=batch)
     info = p.info()
     assert info["bf_built"] == 1
+    if batch:
+        assert info["bf_nbatch"] > 1
     if levels > 0:
         assert p.butterfly_depth(0, 0) == levels
     rng = np.random.default_rng(L)

@@ -27,13 +27,16 @@ def _dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-@pytest.mark.parametrize("L,N,eps,levels,B", [(127, 64, 1e-12, -1, 1), (127, 64, 1e-12, 2, 3),
-                                              (255, 128, 1e-12, 3, 4), (200, 64, 1e-8, 2, 2),
-                                              (511, 256, 1e-12, 4, 1), (300, 128, 1e-10, 3, 9),
-                                              (0, 1, 1e-12, -1, 1), (9, 2, 1e-12, 1, 2)])
-def test_butterfly_synthesis_parity(gpu, L, N, eps, levels, B):
+@pytest.mark.parametrize("L,N,eps,levels,B,batch", [(127, 64, 1e-12, -1, 1, 0), (127, 64, 1e-12, 2, 3, 0),
+                                                    (255, 128, 1e-12, 3, 4, 0), (200, 64, 1e-8, 2, 2, 0),
+                                                    (511, 256, 1e-12, 4, 1, 0), (300, 128, 1e-10, 3, 9, 0),
+                                                    (0, 1, 1e-12, -1, 1, 0), (9, 2, 1e-12, 1, 2, 0),
+                                                    (255, 128, 1e-12, 3, 4, 1), (511, 256, 1e-12, 4, 2, 2)])
+def test_butterfly_synthesis_parity(gpu, L, N, eps, levels, B, batch):
     alm = alm_gaussian(L, list(range(200, 200 + B)))
-    p = gpu.Plan(L, N, eps, max_levels=levels)
+    p = gpu.Plan(L, N, eps, max_levels=levels, batch_mib=batch)
+    if batch:
+        assert p.info()["bf_nbatch"] > 1
     f = p.synthesis(_dev(alm), path=sht.PATH_BUTTERFLY).cpu().numpy()
     ref = oracle.synthesis(L, N, alm)
     err = maxrel(f, ref)
