@@ -2,16 +2,19 @@
 """Throughput of HEALPix spherical harmonic synthesis on one MI355X.
 
 Workload: L = 4095, nside = 2048 (50.3M pixels, 8191 rings), 4 maps with
-seeded complex Gaussian a_lm (C_l = 1/(l+1)^2, seeds 400..403), FP64
-brute-force path: Legendre phase kernel + ring FFT kernel per step.
-
-Prints one JSON line.  `value` is maps/s of the whole step with inputs
-resident in HBM.  The roofline object covers the dominant kernel (the
-Legendre recurrence, FP64 vector ALU bound): algorithmic flops per launch
-(5 per recurrence step + 4 per map per step, over the plan's (l, ring) pairs
-above the cutoff) divided by its mean duration, measured with HIP events
-recorded on the execution stream around that stage during the timed steps.
-The CPU baseline times the oracle on a random sample of rings.
+seeded complex Gaussian a_lm (C_l = 1/(l+1)^2, seeds 400..403).  One plan
+(eps = 1e-12) holds both Legendre forms; each step is one synthesis of the
+4 maps (Legendre phase + ring FFT) with inputs resident in HBM:
+  brute      FP64 two-step recurrence over every (l, ring) above the cutoff
+  bf64       butterfly-compressed operator, FP64 products
+  bf32       butterfly-compressed operator, FP32 matrix-core products
+The headline `value` is the fastest FP64 path (maps/s over exactly --steps
+steps bracketed by device synchronisation); the other paths are timed the
+same way and reported under "paths".  The roofline object covers the
+dominant kernel of the headline path, measured with HIP events recorded on
+the execution stream around its stage.  The CPU baseline times the oracle on
+a random sample of rings; max_rel_err compares each path with the oracle's
+long-double mode on sampled rings.
 """
 import argparse
 import hashlib
@@ -25,7 +28,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "L=4095 synthesis maps/s: butterfly vs brute-force, FP64 vs FP32-MFMA, max rel err"
-FP64_PEAK_TFLOPS = 78.6  # 256 CU x 2.4 GHz x 128 FP64 flops/clk (vector FMA)
+FP64_PEAK_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 flops x 2.4 GHz (vector FMA)
+HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 LEGENDRE_SRC = os.path.join(ROOT, "paper_1110_4874_amd", "csrc", "legendre.hip")
 
@@ -63,6 +67,8 @@ def main():
     ap.add_argument("--L", type=int, default=4095)
     ap.add_argument("--nside", type=int, default=2048)
     ap.add_argument("--maps", type=int, default=4)
+    ap.add_argument("--eps", type=float, default=1e-12, help="butterfly tolerance (0: brute force only)")
+    ap.add_argument("--rho", type=float, default=0.0, help="butterfly depth cost ratio (0: plan default)")
     ap.add_argument("--cpu-rings", type=int, default=900, help="rings in the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip timing the adjoint")
@@ -88,12 +94,14 @@ def main():
     seeds = [400 + b for b in range(B)]
     log(f"[bench] L={L} nside={N} maps={B}: drawing inputs")
     alm = alm_gaussian(L, seeds)
-    log("[bench] building plan")
+    log(f"[bench] building plan (eps={args.eps})")
     t0 = time.perf_counter()
-    plan = sht.Plan(L, N, rings_per_lane=args.rings_per_lane, ring_threads=args.ring_threads)
+    plan = sht.Plan(L, N, args.eps, rings_per_lane=args.rings_per_lane, ring_threads=args.ring_threads,
+                    rho=args.rho, store_fp32=args.eps > 0)
     info = plan.info()
     log(f"[bench] plan built in {time.perf_counter() - t0:.1f}s: n_step={info['n_step']:.4e} "
-        f"exec={info['n_step_exec']:.4e} dd_rings={info['n_dd_rings']}")
+        f"dd_rings={info['n_dd_rings']} butterfly={info['bf_built']} T={info['bf_T_entries']:.4e} "
+        f"residual={info['bf_res_elems']:.4e} device={info['device_bytes'] / 1e9:.2f} GB")
 
     dev = torch.device("cuda:0")
     d_alm = torch.from_numpy(alm).to(dev)
@@ -110,32 +118,57 @@ def main():
     ev_sets = [new_events() for _ in range(args.steps)]
     torch.cuda.synchronize()
 
-    for i in range(args.warmup):
-        plan.synthesis(d_alm, out, workspace=ws)
-    torch.cuda.synchronize()
-    log(f"[bench] warmup done ({args.warmup} steps); timing {args.steps} steps")
+    paths = [("brute", sht.PATH_BRUTE, sht.PREC_FP64)]
+    if info["bf_built"]:
+        paths += [("bf64", sht.PATH_BUTTERFLY, sht.PREC_FP64), ("bf32", sht.PATH_BUTTERFLY, sht.PREC_FP32)]
 
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for k in range(args.steps):
-        plan.synthesis(d_alm, out, workspace=ws, events=ev_sets[k])
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    ms_per_step = 1e3 * elapsed / args.steps
-    value = B * args.steps / elapsed
+    results, maps_out = {}, {}
+    for name, path, prec in paths:
+        for _ in range(args.warmup):
+            plan.synthesis(d_alm, out, path=path, precision=prec, workspace=ws)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        for k in range(args.steps):
+            plan.synthesis(d_alm, out, path=path, precision=prec, workspace=ws, events=ev_sets[k])
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - ts
+        leg_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev_sets]))
+        ring_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in ev_sets]))
+        results[name] = {"maps_per_s": B * args.steps / elapsed, "ms_per_step": 1e3 * elapsed / args.steps,
+                         "legendre_ms": leg_ms, "ring_ms": ring_ms}
+        maps_out[name] = out.cpu().numpy()
+        log(f"[bench] {name}: {results[name]['ms_per_step']:.3f} ms/step, legendre {leg_ms:.3f} ms, "
+            f"ring {ring_ms:.3f} ms")
 
-    leg_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev_sets]))
-    ring_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in ev_sets]))
     flops = info["n_step"] * (5 + 4 * B)
-    achieved = flops / (leg_ms * 1e-3) / 1e12
-    log(f"[bench] {ms_per_step:.3f} ms/step, legendre {leg_ms:.3f} ms, ring {ring_ms:.3f} ms")
+    q_bytes = (L + 1) * plan.nrings * B * 16
+    alm_bytes = plan.nalm * B * 16
 
-    # the hand-written adjoint on the same workload (reported beside the metric)
+    def path_roofline(name):
+        r = results[name]
+        if name == "brute":
+            achieved = flops / (r["legendre_ms"] * 1e-3) / 1e12
+            return {"kernel": "k_legendre (brute-force Legendre phase)", "bound": "alu",
+                    "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+                    "traffic": measured_traffic(L, N, B), "flops_per_launch": flops}
+        tb = info["bf_T_entries"] * (8 if name == "bf64" else 4)
+        nbytes = tb + alm_bytes + q_bytes
+        achieved = nbytes / (r["legendre_ms"] * 1e-3) / 1e9
+        return {"kernel": "butterfly stage (k_bf_residual + k_bf_level + k_bf_fold)", "bound": "hbm",
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "bytes_per_launch": nbytes}
+
+    fp64 = [n for n in results if n != "bf32"]
+    head = max(fp64, key=lambda n: results[n]["maps_per_s"])
+    hr = results[head]
+    log(f"[bench] headline path: {head}")
+
     adj = None
     if not args.no_adjoint:
         y = out.clone()
         g = torch.empty((plan.nalm, B), dtype=torch.complex128, device=dev)
-        for i in range(args.warmup):
+        for _ in range(args.warmup):
             plan.adjoint(y, g, workspace=ws)
         torch.cuda.synchronize()
         ta = time.perf_counter()
@@ -145,7 +178,7 @@ def main():
         adj_elapsed = time.perf_counter() - ta
         ra_ms = float(np.mean([e[4].elapsed_time(e[5]) for e in ev_sets]))
         la_ms = float(np.mean([e[6].elapsed_time(e[7]) for e in ev_sets]))
-        adj = {"maps_per_s": round(B * args.steps / adj_elapsed, 3),
+        adj = {"path": "brute", "maps_per_s": round(B * args.steps / adj_elapsed, 3),
                "ms_per_step": round(1e3 * adj_elapsed / args.steps, 4),
                "stages_ms": {"ring_analysis": round(ra_ms, 4), "legendre_adjoint": round(la_ms, 4)},
                "legendre_adjoint_tflops": round(flops / (la_ms * 1e-3) / 1e12, 3)}
@@ -163,35 +196,42 @@ def main():
 
     line = {
         "metric": METRIC,
-        "value": round(value, 3),
+        "value": round(hr["maps_per_s"], 3),
         "unit": "maps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step": round(hr["ms_per_step"], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": f"HEALPix synthesis L={L} nside={N}, {B} maps per step, brute-force FP64 "
-                        "(Legendre recurrence + ring FFT)",
-            "L": L, "nside": N, "maps": B, "path": "brute", "precision": "fp64",
+            "workload": f"HEALPix synthesis L={L} nside={N}, {B} maps per step, FP64 "
+                        f"({'butterfly eps=%g' % args.eps if head != 'brute' else 'brute-force recurrence'}"
+                        " + ring FFT)",
+            "L": L, "nside": N, "maps": B, "path": head, "precision": "fp64", "eps": args.eps,
             "spectrum": "C_l=1/(l+1)^2", "seeds": seeds,
         },
-        "stages_ms": {"legendre": round(leg_ms, 4), "ring_fft": round(ring_ms, 4)},
-        "roofline": {
-            "kernel": "k_legendre (brute-force Legendre phase)",
-            "bound": "alu",
-            "achieved": round(achieved, 3),
-            "peak": FP64_PEAK_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
-            "traffic": measured_traffic(L, N, B),
-            "flops_per_launch": flops,
-        },
+        "stages_ms": {"legendre": round(hr["legendre_ms"], 4), "ring_fft": round(hr["ring_ms"], 4)},
+        "roofline": path_roofline(head),
     }
+    line["paths"] = {}
+    for name in results:
+        r = results[name]
+        line["paths"][name] = {
+            "maps_per_s": round(r["maps_per_s"], 3), "ms_per_step": round(r["ms_per_step"], 4),
+            "legendre_ms": round(r["legendre_ms"], 4), "ring_ms": round(r["ring_ms"], 4),
+            "speedup_vs_brute": round(r["maps_per_s"] / results["brute"]["maps_per_s"], 3),
+            "roofline": path_roofline(name),
+        }
+    if info["bf_built"]:
+        line["butterfly_plan"] = {"eps": args.eps, "T_entries": info["bf_T_entries"],
+                                  "residual_elements": info["bf_res_elems"], "nodes": info["bf_nodes"],
+                                  "depth_hist": info["bf_depth_hist"][:8],
+                                  "build_seconds": round(info["bf_build_seconds"], 1),
+                                  "device_gb": round(info["device_bytes"] / 1e9, 2)}
     if adj is not None:
         line["adjoint"] = adj
 
@@ -215,18 +255,20 @@ def main():
                       f"(one-step Legendre recurrence + direct per-ring DFT); {tcpu:.1f}s measured, "
                       f"scaled by {nr}/{k}",
         }
-        # accuracy of this GPU result on a few rings against the long-double oracle
+        # accuracy of each GPU path on a few rings against the long-double oracle
         chk = [1, 2, 100, 1000, 2 * N, 2 * N + 1, 3 * N, nr]
         ref = oracle.synthesis_rings(L, N, alm, chk, ld=True)
-        f = out.cpu().numpy()
-        fmax = np.max(np.abs(f), axis=1)
-        worst = 0.0
-        for ring, r in zip(chk, ref):
-            _, _, J, _, off = oracle.ring_info(N, ring)
-            worst = max(worst, float(np.max(np.max(np.abs(f[:, off:off + J] - r), axis=1) / fmax)))
-        line["max_rel_err"] = float(f"{worst:.3e}")
+        for name, f in maps_out.items():
+            fmax = np.max(np.abs(f), axis=1)
+            worst = 0.0
+            for ring, r in zip(chk, ref):
+                _, _, J, _, off = oracle.ring_info(N, ring)
+                worst = max(worst, float(np.max(np.max(np.abs(f[:, off:off + J] - r), axis=1) / fmax)))
+            line["paths"][name]["max_rel_err"] = float(f"{worst:.3e}")
+        line["max_rel_err"] = line["paths"][head]["max_rel_err"]
         line["max_rel_err_sample"] = f"rings {chk}, all maps, vs long-double oracle, relative to max|f| per map"
-        log(f"[bench] cpu baseline {line['cpu_baseline']['value']:.4f} maps/s; max rel err {worst:.3e}")
+        log(f"[bench] cpu baseline {line['cpu_baseline']['value']:.4f} maps/s; errors "
+            + ", ".join(f"{n} {line['paths'][n]['max_rel_err']:.2e}" for n in maps_out))
 
     print(json.dumps(line), flush=True)
 
