@@ -59,6 +59,70 @@ def measured_traffic(L, nside, nmaps):
     return rec.get("bytes_per_launch")
 
 
+def batch_bench(np, torch, sht, steps):
+    """64 queued syntheses of mixed L in {127, 255, 511, 1023}, nside =
+    (L+1)/2, 1-8 maps each (seed 500): one batch call (and its captured HIP
+    graph) against 64 sequential calls, FP64 brute force, plans with tuned
+    tile shapes."""
+    from paper_1110_4874_amd import autotune
+    from paper_1110_4874_amd.synthetic import alm_gaussian, mixed_requests
+
+    queue = mixed_requests(seed=500, n=64)
+    plans, reqs = {}, []
+    t0 = time.perf_counter()
+    for (L, N, B, seeds) in queue:
+        if (L, N) not in plans:
+            plans[(L, N)] = autotune.tuned_plan(L, N, 4)
+        alm = torch.from_numpy(alm_gaussian(L, seeds)).cuda()
+        out = torch.empty((B, 12 * N * N), dtype=torch.float64, device="cuda")
+        reqs.append((plans[(L, N)], alm, out))
+    tune_s = time.perf_counter() - t0
+    nmaps = sum(r[1].shape[1] for r in reqs)
+    wss = {id(p): p.workspace(max(r[1].shape[1] for r in reqs if r[0] is p)) for p in plans.values()}
+    batch = sht.Batch(reqs)
+
+    def seq():
+        for p, a, o in reqs:
+            p.synthesis(a, o, workspace=wss[id(p)])
+
+    def timed(fn, k):
+        fn()
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        for _ in range(k):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - ts) / k
+
+    t_seq = timed(seq, steps)
+    t_batch = timed(batch.run, steps)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        batch.run(stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        batch.run(stream=torch.cuda.current_stream())
+    t_graph = timed(g.replay, steps)
+    # the graph's results equal the sequential calls'
+    ref = [o.clone() for _, _, o in reqs]
+    seq()
+    torch.cuda.synchronize()
+    same = all(torch.equal(o, r) for (_, _, o), r in zip(reqs, ref))
+    res = {"requests": len(reqs), "maps": nmaps, "precision": "fp64", "path": "brute",
+           "sequential_maps_per_s": round(nmaps / t_seq, 2), "batch_maps_per_s": round(nmaps / t_batch, 2),
+           "graph_maps_per_s": round(nmaps / t_graph, 2), "graph_speedup_vs_sequential": round(t_seq / t_graph, 3),
+           "graph_matches_sequential": bool(same),
+           "tile_shapes": {f"{L}": {k: v for k, v in autotune.tune(L, N, 4).items() if k != "ms"}
+                           for (L, N) in plans},
+           "tuning_seconds": round(tune_s, 1)}
+    log(f"[bench] batching: sequential {res['sequential_maps_per_s']} maps/s, batch {res['batch_maps_per_s']}, "
+        f"graph {res['graph_maps_per_s']}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,6 +136,7 @@ def main():
     ap.add_argument("--cpu-rings", type=int, default=900, help="rings in the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip timing the adjoint")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-request batching measurement")
     ap.add_argument("--rings-per-lane", type=int, default=0, help="Legendre kernel tile (1, 2, 4; 0 = plan default)")
     ap.add_argument("--ring-threads", type=int, default=0, help="ring kernel workgroup size (256, 512, 1024; 0 = default)")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -185,6 +250,11 @@ def main():
         log(f"[bench] adjoint {adj['ms_per_step']:.3f} ms/step, ring analysis {ra_ms:.3f} ms, "
             f"legendre adjoint {la_ms:.3f} ms")
 
+    if not args.no_batch:
+        line_batch = batch_bench(np, torch, sht, args.steps)
+    else:
+        line_batch = None
+
     if args.copy_calibration:
         nbytes = args.copy_calibration << 20
         src = torch.empty(nbytes // 8, dtype=torch.float64, device=dev).normal_()
@@ -234,6 +304,8 @@ def main():
                                   "device_gb": round(info["device_bytes"] / 1e9, 2)}
     if adj is not None:
         line["adjoint"] = adj
+    if line_batch is not None:
+        line["batching"] = line_batch
 
     if not args.no_cpu_baseline:
         import oracle

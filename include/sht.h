@@ -203,6 +203,36 @@ int sht_adjoint(const sht_plan_t *plan, const double *map, double *alm);
 int sht_adjoint_ex(const sht_plan_t *plan, const sht_exec_opts *x, const double *map,
                    double *alm);
 
+/* ---- batches of requests ---------------------------------------------
+ * Many independent syntheses (possibly of different L, nside and map
+ * counts) in one call: the many-transform regime of Sec. 4.4.  Requests run
+ * longest first on the least-loaded of nstreams internal default-priority
+ * streams that fork from and join into o->stream through events; the call
+ * allocates nothing (the workspace is required) and only enqueues, so a
+ * whole batch can be captured into one HIP graph on o->stream.  Results are
+ * identical to sht_synthesis_ex of each request.  Requests must not share
+ * output buffers; all plans must live on one device.
+ * Callers: many-map pipelines and serving loops. */
+typedef struct sht_request {
+    const sht_plan_t *plan;
+    int nmaps;
+    const double *alm;        /* device, the plan's alm layout for nmaps maps */
+    double *map;              /* device, nmaps * Npix doubles */
+} sht_request;
+
+typedef struct sht_batch_opts {
+    void *stream;             /* hipStream_t the batch is ordered on */
+    int nstreams;             /* internal streams used, 1..8 (default 4) */
+    int path;                 /* SHT_PATH_* for every request */
+    int precision;            /* SHT_PREC_* for every request */
+    void *workspace;          /* device scratch of >= sht_batch_workspace_bytes() */
+    size_t workspace_bytes;
+} sht_batch_opts;
+
+void sht_batch_opts_default(sht_batch_opts *o);
+size_t sht_batch_workspace_bytes(const sht_request *reqs, int n, const sht_batch_opts *o);
+int sht_batch_execute(const sht_request *reqs, int n, const sht_batch_opts *o);
+
 const char *sht_last_error(void);
 
 /* ---- private test API (the paper's unit-test entry points, Sec. 4.1) ---- */

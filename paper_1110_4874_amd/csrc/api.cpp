@@ -8,6 +8,7 @@
 
 namespace sht {
 const char *last_error();
+size_t synth_ws_bytes_impl(const sht_plan_s *p, int nmaps, int path, int precision);
 }
 
 using namespace sht;
@@ -27,6 +28,9 @@ struct DeviceGuard {  // make the plan's device current for the call
     }
 };
 
+}  // namespace
+
+namespace sht {
 // The pointer must be device memory of `dev` with at least `bytes` bytes
 // left in its allocation; checked before any kernel may touch it.
 int check_dev_ptr(const void *ptr, size_t bytes, int dev, const char *name) {
@@ -53,6 +57,9 @@ int check_dev_ptr(const void *ptr, size_t bytes, int dev, const char *name) {
     if (((uintptr_t)ptr & 15) != 0) return fail(SHT_EINVAL, std::string(name) + " is not 16-byte aligned");
     return SHT_OK;
 }
+}  // namespace sht
+
+namespace {
 
 int check_plan(const sht_plan_t *p) {
     if (!p) return fail(SHT_EINVAL, "plan is NULL");
@@ -64,14 +71,12 @@ size_t nalm_of(int L) { return (size_t)(L + 1) * (L + 2) / 2; }
 size_t npix_of(int N) { return 12ull * N * N; }
 size_t q_bytes(const sht_plan_t *p, int B) { return (size_t)(p->L + 1) * p->nrings * B * 16; }
 
-bool use_butterfly(const sht_plan_t *p, const sht_exec_opts *x) {
-    return p->bf.built && (x->path == SHT_PATH_BUTTERFLY || (x->path == SHT_PATH_AUTO));
+bool use_bf(const sht_plan_t *p, int path) {
+    return p->bf.built && (path == SHT_PATH_BUTTERFLY || path == SHT_PATH_AUTO);
 }
 
 size_t synth_ws_bytes(const sht_plan_t *p, const sht_exec_opts *x) {
-    size_t b = q_bytes(p, x->nmaps);
-    if (use_butterfly(p, x)) b += bf_scratch_bytes(p, x->nmaps, x->precision == SHT_PREC_FP32);
-    return b;
+    return sht::synth_ws_bytes_impl(p, x->nmaps, x->path, x->precision);
 }
 
 int check_exec(const sht_plan_t *p, const sht_exec_opts *x) {
@@ -129,6 +134,44 @@ int hip_status(hipError_t e, const char *what) {
     return fail(SHT_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+}  // namespace
+
+namespace sht {
+size_t synth_ws_bytes_impl(const sht_plan_s *p, int nmaps, int path, int precision) {
+    size_t b = q_bytes(p, nmaps);
+    if (use_bf(p, path)) b += bf_scratch_bytes(p, nmaps, precision == SHT_PREC_FP32);
+    return b;
+}
+
+// Legendre phase and ring stage of one synthesis on stream st; ws holds
+// synth_ws_bytes_impl() bytes.  Events of x (if any) bracket the stages.
+static int synth_stages(const sht_plan_s *p, int B, int path, int precision, const double *alm, double *map,
+                        void *ws, hipStream_t st, const sht_exec_opts *x) {
+    int rc;
+    double *q = (double *)ws;
+    if (x) stage_event(x, SHT_STAGE_LEGENDRE, 0);
+    if (use_bf(p, path)) {
+        void *scr = (char *)ws + q_bytes(p, B);
+        if ((rc = hip_status(launch_butterfly(p, B, alm, q, scr, precision == SHT_PREC_FP32, st),
+                             "butterfly kernel launch")))
+            return rc;
+    } else if ((rc = hip_status(launch_legendre(p, B, alm, q, st), "Legendre kernel launch"))) {
+        return rc;
+    }
+    if (x) stage_event(x, SHT_STAGE_LEGENDRE, 1);
+    if (x) stage_event(x, SHT_STAGE_RING, 0);
+    rc = hip_status(launch_ring_synthesis(p, B, q, map, st), "ring kernel launch");
+    if (x) stage_event(x, SHT_STAGE_RING, 1);
+    return rc;
+}
+
+int synth_launch(const sht_plan_s *p, int nmaps, int path, int precision, const double *alm, double *map,
+                 void *ws, hipStream_t st) {
+    return synth_stages(p, nmaps, path, precision, alm, map, ws, st, nullptr);
+}
+}  // namespace sht
+
+namespace {
 }  // namespace
 
 extern "C" {
@@ -292,22 +335,7 @@ int sht_synthesis_ex(const sht_plan_t *p, const sht_exec_opts *x, const double *
     if ((rc = check_dev_ptr(map, npix_of(p->nside) * B * 8, p->device, "map"))) return rc;
     Scratch ws;
     if ((rc = ws.get(x, synth_ws_bytes(p, x), p->device))) return rc;
-    hipStream_t st = (hipStream_t)x->stream;
-    double *q = (double *)ws.ptr;
-    stage_event(x, SHT_STAGE_LEGENDRE, 0);
-    if (use_butterfly(p, x)) {
-        void *scr = (char *)ws.ptr + q_bytes(p, B);
-        if ((rc = hip_status(launch_butterfly(p, B, alm, q, scr, x->precision == SHT_PREC_FP32, st),
-                             "butterfly kernel launch")))
-            return rc;
-    } else if ((rc = hip_status(launch_legendre(p, B, alm, q, st), "Legendre kernel launch"))) {
-        return rc;
-    }
-    stage_event(x, SHT_STAGE_LEGENDRE, 1);
-    stage_event(x, SHT_STAGE_RING, 0);
-    rc = hip_status(launch_ring_synthesis(p, B, q, map, st), "ring kernel launch");
-    stage_event(x, SHT_STAGE_RING, 1);
-    return rc;
+    return synth_stages(p, B, x->path, x->precision, alm, map, ws.ptr, (hipStream_t)x->stream, x);
 }
 
 int sht_adjoint(const sht_plan_t *p, const double *map, double *alm) {

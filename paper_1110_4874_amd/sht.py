@@ -50,7 +50,19 @@ class PlanInfo(_c.Structure):
                 ("bf_nbatch", _c.c_int)]
 
 
+class Request(_c.Structure):
+    _fields_ = [("plan", _c.c_void_p), ("nmaps", _c.c_int), ("alm", _c.c_void_p), ("map", _c.c_void_p)]
+
+
+class BatchOpts(_c.Structure):
+    _fields_ = [("stream", _c.c_void_p), ("nstreams", _c.c_int), ("path", _c.c_int), ("precision", _c.c_int),
+                ("workspace", _c.c_void_p), ("workspace_bytes", _c.c_size_t)]
+
+
 EXPORTS = {
+    "sht_batch_opts_default": (None, [_c.POINTER(BatchOpts)]),
+    "sht_batch_workspace_bytes": (_c.c_size_t, [_c.POINTER(Request), _c.c_int, _c.POINTER(BatchOpts)]),
+    "sht_batch_execute": (_c.c_int, [_c.POINTER(Request), _c.c_int, _c.POINTER(BatchOpts)]),
     "sht_plan_opts_default": (None, [_c.POINTER(PlanOpts)]),
     "sht_exec_opts_default": (None, [_c.POINTER(ExecOpts)]),
     "sht_plan": (_c.c_void_p, [_c.c_int, _c.c_int, _c.c_double]),
@@ -320,6 +332,43 @@ class Plan:
         vals = (_c.c_double * 2)()
         _check(load().sht_debug_start(self._h, int(m), int(t), int(k), _c.byref(idx), vals))
         return idx.value, (vals[0], vals[1])
+
+
+class Batch:
+    """A fixed list of synthesis requests (plan, alm, out) run by one
+    sht_batch_execute call: longest first over a few internal streams."""
+
+    def __init__(self, requests, *, nstreams=4, path=PATH_AUTO, precision=PREC_FP64):
+        lib = load()
+        self.items = []
+        for plan, alm, out in requests:
+            a = plan._alm_arg(alm)
+            if out.dtype != torch.float64 or not out.is_cuda or not out.is_contiguous():
+                raise TypeError("out must be a contiguous float64 CUDA tensor")
+            if out.numel() != a.shape[1] * plan.npix:
+                raise ValueError("out has the wrong size")
+            self.items.append((plan, a, out))
+        n = len(self.items)
+        self._reqs = (Request * max(n, 1))()
+        for i, (plan, a, out) in enumerate(self.items):
+            self._reqs[i].plan = plan._h
+            self._reqs[i].nmaps = a.shape[1]
+            self._reqs[i].alm = _c.c_void_p(a.data_ptr())
+            self._reqs[i].map = _c.c_void_p(out.data_ptr())
+        self.n = n
+        o = BatchOpts()
+        lib.sht_batch_opts_default(_c.byref(o))
+        o.nstreams, o.path, o.precision = int(nstreams), int(path), int(precision)
+        self._opts = o
+        nb = int(lib.sht_batch_workspace_bytes(self._reqs, n, _c.byref(o)))
+        dev = self.items[0][1].device if n else torch.device("cuda")
+        self.workspace = torch.empty(max(nb, 1), dtype=torch.uint8, device=dev)
+        o.workspace = _c.c_void_p(self.workspace.data_ptr())
+        o.workspace_bytes = self.workspace.numel()
+
+    def run(self, stream=None):
+        self._opts.stream = _stream_handle(stream)
+        _check(load().sht_batch_execute(self._reqs, self.n, _c.byref(self._opts)))
 
 
 class _Synthesis(torch.autograd.Function):
