@@ -26,8 +26,8 @@
  *   - map layout: float64, stacked maps, RING order: map[b*Npix + p].
  *     (The paper interleaves output maps; stacked maps are kept here so that
  *     each ring is one contiguous, coalesced run per map.)
- *   - q layout (Legendre phase): complex128, m-major then ring then map:
- *         q[2*((m*nrings + k)*nmaps + b) + {0,1}],  ring k = 0..4nside-2
+ *   - q layout (Legendre phase): complex128, ring-major then m then map:
+ *         q[2*((k*(L+1) + m)*nmaps + b) + {0,1}],  ring k = 0..4nside-2
  *     (k = 0 is the northernmost ring).
  *   - Work is enqueued on the stream given in sht_exec_opts (NULL = the
  *     default stream) and is asynchronous with respect to the host.  Errors

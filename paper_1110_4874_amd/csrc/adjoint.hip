@@ -30,7 +30,7 @@ struct AdjArgs {
     const double *__restrict__ start_lo;
     const int *__restrict__ grp_lo;
     const int *__restrict__ grp_hi;
-    const double2 *__restrict__ ybar;  // [m][ring][nmaps]
+    const double2 *__restrict__ ybar;  // [ring][m][nmaps]
     double *__restrict__ g;            // [nalm][nmaps] complex
     int L, nrings, n_north, np, n_dd_pad, ng;
     int nmaps, map0;
@@ -141,8 +141,8 @@ __global__ __launch_bounds__(T) void k_legendre_adj(AdjArgs a) {
         }
         // unfold the ring and its mirror into even/odd parts
         const int ks = a.nrings - 1 - kk;
-        const double2 *yn = a.ybar + ((size_t)m * a.nrings + kk) * a.nmaps + a.map0;
-        const double2 *ys = a.ybar + ((size_t)m * a.nrings + ks) * a.nmaps + a.map0;
+        const double2 *yn = a.ybar + ((size_t)kk * (a.L + 1) + m) * a.nmaps + a.map0;
+        const double2 *ys = a.ybar + ((size_t)ks * (a.L + 1) + m) * a.nmaps + a.map0;
 #pragma unroll
         for (int b = 0; b < NB; b++) {
             double2 vn = val[r] ? yn[b] : make_double2(0.0, 0.0);

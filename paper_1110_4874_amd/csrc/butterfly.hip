@@ -262,9 +262,9 @@ __global__ __launch_bounds__(kBfThreads) void k_bf_fold(BfArgs<S> a, int batch, 
     const S *qo = a.ws + ((size_t)(2 * j + 1) * K + k) * NC + 2 * b;
     double er = (double)qe[0], ei = (double)qe[1], orr = (double)qo[0], oi = (double)qo[1];
     if (m == 0) ei = oi = 0.0;  // real field: Im a_l0 is ignored
-    a.q[((size_t)m * a.nrings + k) * a.nmaps + a.map0 + b] = make_double2(er + orr, ei + oi);
+    a.q[((size_t)k * (a.L + 1) + m) * a.nmaps + a.map0 + b] = make_double2(er + orr, ei + oi);
     const int ks = a.nrings - 1 - k;
-    if (ks != k) a.q[((size_t)m * a.nrings + ks) * a.nmaps + a.map0 + b] = make_double2(er - orr, ei - oi);
+    if (ks != k) a.q[((size_t)ks * (a.L + 1) + m) * a.nmaps + a.map0 + b] = make_double2(er - orr, ei - oi);
 }
 
 static int bf_nb(int nmaps) { return nmaps >= 8 ? 8 : nmaps >= 4 ? 4 : nmaps >= 2 ? 2 : 1; }

@@ -244,8 +244,8 @@ __device__ __forceinline__ void legendre_wave(const LegArgs &a, const int m, con
     for (int r = 0; r < R; r++) {
         if (!gv[r] || k[r] >= a.n_north) continue;
         const int kn = k[r], ks = a.nrings - 1 - k[r];
-        double *qn = a.q + 2 * (((size_t)m * a.nrings + kn) * a.nmaps + a.map0);
-        double *qs = a.q + 2 * (((size_t)m * a.nrings + ks) * a.nmaps + a.map0);
+        double *qn = a.q + 2 * (((size_t)kn * (a.L + 1) + m) * a.nmaps + a.map0);
+        double *qs = a.q + 2 * (((size_t)ks * (a.L + 1) + m) * a.nmaps + a.map0);
 #pragma unroll
         for (int b = 0; b < NB; b++) {
             double nr = accE_r[r][b] + accO_r[r][b], ni = accE_i[r][b] + accO_i[r][b];

@@ -19,9 +19,10 @@
 // two, otherwise Bluestein's chirp convolution with a power-of-two M >= 2n-1
 // (forward decimation in frequency, pointwise product with the plan's chirp
 // spectrum, backward decimation in time).  LDS indices are padded by one
-// entry per 16 to spread strided accesses over the banks.  Workgroups are
-// ordered so the 8 (ring, map) items whose q entries share a 128-byte line
-// run back to back on the same XCD (dispatch is round-robin over 8 XCDs).
+// entry per 16 to spread strided accesses over the banks.  One workgroup
+// owns one (ring, map); the maps of a ring are adjacent in the ring-major q
+// layout and their workgroups run back to back on the same XCD (dispatch is
+// round-robin over 8 XCDs), so lines read from HBM serve them all from L2.
 #include "internal.h"
 
 namespace sht {
@@ -256,14 +257,15 @@ __global__ __launch_bounds__(T) void k_ring_synth(RingArgs a) {
     const int J = a.ring_J[rho], s = a.ring_s[rho], M = a.ring_M[rho];
     const int n = J / 2, lgn = ilog2_dev(n);
     const bool bs = M > 0;
-    const int S = bs ? M : n, lgS = ilog2_dev(S);
     double2 *buf = sm;
     double2 *stage = sm + a.fft_entries;  // a.stage entries (wrapped rings only)
-    const double2 *qr = a.q + (size_t)rho * a.nmaps + b;
-    const size_t qstride = (size_t)a.nrings * a.nmaps;
     const int tid = threadIdx.x;
     const int L = a.L;
     const int npair = n / 2 + 1;
+    // ring-major q: the maps of one ring interleave in one contiguous block,
+    // and their workgroups run back to back on one XCD (shared L2 lines)
+    const size_t qstride = (size_t)a.nmaps;
+    const double2 *qr = a.q + (size_t)rho * (L + 1) * a.nmaps + b;
 
     if (bs)
         for (int i = n + tid; i < M; i += T) buf[pidx(i)] = make_double2(0.0, 0.0);
@@ -393,8 +395,7 @@ static hipError_t launch_classes(const sht_plan_s *p, RingArgs a, int nmaps, hip
         // staging chunk: as much of the 160 KiB LDS as the FFT buffer leaves
         const int room = (int)(160 * 1024 / sizeof(double2)) - a.fft_entries;
         a.stage = std::min(kMaxStage, room / T * T);
-        long long items = (long long)a.count * nmaps;
-        long long grid = (items + 63) / 64 * 64;
+        long long grid = ((long long)a.count * nmaps + 63) / 64 * 64;
         size_t lds = (size_t)(a.fft_entries + (rc.wrap ? a.stage : 0)) * sizeof(double2);
         hipLaunchKernelGGL(k_ring_synth<T>, dim3((unsigned)grid), dim3(T), lds, stream, a);
         hipError_t e = hipGetLastError();
@@ -453,8 +454,8 @@ __global__ __launch_bounds__(T) void k_ring_analysis(RingArgs a) {
     double2 *buf = sm;
     const int tid = threadIdx.x;
     const int L = a.L;
-    const size_t qstride = (size_t)a.nrings * a.nmaps;
-    double2 *yr = a.ybar + (size_t)rho * a.nmaps + b;
+    const size_t qstride = (size_t)a.nmaps;
+    double2 *yr = a.ybar + (size_t)rho * (L + 1) * a.nmaps + b;
 
     if (bs)
         for (int i = n + tid; i < M; i += T) buf[pidx(i)] = make_double2(0.0, 0.0);
@@ -517,8 +518,7 @@ static hipError_t launch_analysis_classes(const sht_plan_s *p, RingArgs a, int n
         a.rings = rc.d_rings;
         a.count = (int)rc.rings.size();
         a.fft_entries = rc.lds_entries + rc.lds_entries / 16;
-        long long items = (long long)a.count * nmaps;
-        long long grid = (items + 63) / 64 * 64;
+        long long grid = ((long long)a.count * nmaps + 63) / 64 * 64;
         size_t lds = (size_t)a.fft_entries * sizeof(double2);
         hipLaunchKernelGGL(k_ring_analysis<T>, dim3((unsigned)grid), dim3(T), lds, stream, a);
         hipError_t e = hipGetLastError();

@@ -280,17 +280,17 @@ class Plan:
         return out
 
     def ring_analysis(self, maps, *, stream=None, convention=ADJ_TRANSPOSE):
-        """ybar (L+1, nrings, B) complex128 (private test entry point)."""
+        """ybar (nrings, L+1, B) complex128 (private test entry point)."""
         m = self._map_arg(maps)
         B = m.shape[0]
-        yb = torch.empty((self.L + 1, self.nrings, B), dtype=torch.complex128, device=m.device)
+        yb = torch.empty((self.nrings, self.L + 1, B), dtype=torch.complex128, device=m.device)
         x = self._exec(B, stream=stream, convention=convention)
         _check(load().sht_debug_ring_analysis(self._h, _c.byref(x), _c.c_void_p(m.data_ptr()),
                                               _c.c_void_p(yb.data_ptr())))
         return yb
 
     def legendre_adjoint(self, ybar, *, stream=None):
-        """alm (nalm, B) from ybar (L+1, nrings, B) (private test entry point)."""
+        """alm (nalm, B) from ybar (nrings, L+1, B) (private test entry point)."""
         yb = ybar.contiguous()
         B = yb.shape[2]
         out = torch.empty((self.nalm, B), dtype=torch.complex128, device=yb.device)
@@ -300,17 +300,17 @@ class Plan:
         return out
 
     def legendre_phase(self, alm, *, stream=None):
-        """q (L+1, nrings, B) complex128 (private test entry point)."""
+        """q (nrings, L+1, B) complex128 (private test entry point)."""
         a = self._alm_arg(alm)
         B = a.shape[1]
-        q = torch.empty((self.L + 1, self.nrings, B), dtype=torch.complex128, device=a.device)
+        q = torch.empty((self.nrings, self.L + 1, B), dtype=torch.complex128, device=a.device)
         x = self._exec(B, stream=stream)
         _check(load().sht_debug_legendre_phase(self._h, _c.byref(x), _c.c_void_p(a.data_ptr()),
                                                _c.c_void_p(q.data_ptr())))
         return q
 
     def ring_synthesis(self, q, out=None, *, stream=None):
-        """maps (B, Npix) from q (L+1, nrings, B) complex128 (private test entry point)."""
+        """maps (B, Npix) from q (nrings, L+1, B) complex128 (private test entry point)."""
         q = q.contiguous()
         B = q.shape[2]
         if out is None:

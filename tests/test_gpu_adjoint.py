@@ -33,7 +33,7 @@ def _maps(N, B, seed0):
 
 
 def _ybar_numpy(L, N, maps, wpos):
-    """Direct per-ring DFT in numpy: (L+1, nrings, B), weights applied."""
+    """Direct per-ring DFT in numpy: (nrings, L+1, B), weights applied."""
     nr = 4 * N - 1
     B = maps.shape[0]
     out = np.zeros((L + 1, nr, B), dtype=np.complex128)
@@ -45,7 +45,7 @@ def _ybar_numpy(L, N, maps, wpos):
         ph = np.exp(-1j * np.pi * np.outer(m, 2 * j + s) / J)  # (L+1, J)
         out[:, ring - 1, :] = (ph @ maps[:, off:off + J].T) * w[:, None]
     out[0, :, :] = out[0, :, :].real
-    return out
+    return np.ascontiguousarray(np.transpose(out, (1, 0, 2)))
 
 
 @pytest.mark.parametrize("L,N,B", [(0, 1, 1), (5, 1, 1), (31, 16, 2), (40, 16, 3), (70, 12, 1),

@@ -28,10 +28,9 @@ def _dev(a):
 
 
 def _oracle_q_layout(L, N, alm):
-    """Oracle Legendre phase in the library's q layout (L+1, nrings, B)."""
+    """Oracle Legendre phase in the library's q layout (nrings, L+1, B)."""
     rings = np.arange(1, 4 * N)
-    q = oracle.legendre_phase_rings(L, N, alm, rings)  # (nr, L+1, B)
-    return np.ascontiguousarray(np.transpose(q, (1, 0, 2)))
+    return np.ascontiguousarray(oracle.legendre_phase_rings(L, N, alm, rings))  # (nr, L+1, B)
 
 
 @pytest.mark.parametrize("L,N,B", [(63, 32, 1), (40, 16, 3), (31, 16, 2), (0, 1, 1), (5, 1, 1),
