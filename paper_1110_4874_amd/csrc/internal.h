@@ -109,6 +109,8 @@ struct sht_plan_s {
     std::vector<int> ring_M;                   // [nrings] 0 = radix-2 size J/2, else Bluestein size
     std::vector<long long> ring_bs_off;        // [nrings] offset (complex entries) of the chirp spectrum
     std::vector<double> bs_table;              // chirp spectra, bit-reversed, scaled by 1/M
+    std::vector<double> chirp;                 // exp(+i pi k^2 / n), k < n, per distinct Bluestein n
+    std::vector<long long> ring_chirp_off;     // [nrings] offset (complex entries) into chirp
     std::vector<sht::RingClass> classes;
 
     // ---- device copies ------------------------------------------------
@@ -119,7 +121,8 @@ struct sht_plan_s {
     int *d_start_idx = nullptr;
     double *d_start_val = nullptr, *d_start_lo = nullptr;
     int *d_grp_lo = nullptr, *d_grp_hi = nullptr;
-    double *d_tw = nullptr, *d_bs_table = nullptr;
+    double *d_tw = nullptr, *d_bs_table = nullptr, *d_chirp = nullptr;
+    long long *d_ring_chirp_off = nullptr;
     size_t device_bytes = 0;
 
     // ---- butterfly (eps > 0) ------------------------------------------

@@ -107,7 +107,7 @@ __device__ __forceinline__ void legendre_wave(const LegArgs &a, const int m, con
     if (lo < n0) {
         double z2h[R], z2l[R];
         int sid[R][2];
-        dd st0[R][2], st1[R][2], p0[R][2], p1[R][2];
+        dd p0[R][2], p1[R][2];
 #pragma unroll
         for (int r = 0; r < R; r++) {
             const int kk = gv[r] ? k[r] : 0;
@@ -117,10 +117,6 @@ __device__ __forceinline__ void legendre_wave(const LegArgs &a, const int m, con
             for (int t = 0; t < 2; t++) {
                 size_t row = (size_t)(2 * m + t);
                 sid[r][t] = gv[r] ? a.start_idx[row * a.np + kk] : kDead;
-                st0[r][t].h = a.start_val[(row * 2 + 0) * a.np + kk];
-                st1[r][t].h = a.start_val[(row * 2 + 1) * a.np + kk];
-                st0[r][t].l = DD ? a.start_lo[(row * 2 + 0) * a.n_dd_pad + kk] : 0.0;
-                st1[r][t].l = DD ? a.start_lo[(row * 2 + 1) * a.n_dd_pad + kk] : 0.0;
                 p0[r][t] = {0.0, 0.0};
                 p1[r][t] = {0.0, 0.0};
             }
@@ -138,8 +134,14 @@ __device__ __forceinline__ void legendre_wave(const LegArgs &a, const int m, con
 #pragma unroll
                 for (int t = 0; t < 2; t++)
                     if (sid[r][t] == c) {
-                        p0[r][t] = st0[r][t];
-                        p1[r][t] = st1[r][t];
+                        // start values are read when the chain joins (once per
+                        // chain), not kept in registers for the whole wave
+                        const size_t row = (size_t)(2 * m + t);
+                        const int kk = k[r];
+                        p0[r][t].h = a.start_val[(row * 2 + 0) * a.np + kk];
+                        p1[r][t].h = a.start_val[(row * 2 + 1) * a.np + kk];
+                        p0[r][t].l = DD ? a.start_lo[(row * 2 + 0) * a.n_dd_pad + kk] : 0.0;
+                        p1[r][t].l = DD ? a.start_lo[(row * 2 + 1) * a.n_dd_pad + kk] : 0.0;
                     }
         };
 

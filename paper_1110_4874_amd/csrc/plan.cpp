@@ -284,7 +284,8 @@ static void host_fft_forward(std::vector<ld> &re, std::vector<ld> &im) {
 struct BsCtx {
     sht_plan_s *p;
     std::vector<int> ns;            // distinct Bluestein sizes n
-    std::vector<long long> offs;    // table offset per entry
+    std::vector<long long> offs;    // spectrum table offset per entry
+    std::vector<long long> coffs;   // chirp table offset per entry
 };
 
 // Spectrum of the Bluestein chirp for a length-n DFT padded to M: the
@@ -305,6 +306,14 @@ static void bs_worker(long idx, void *vctx) {
             re[M - j] = re[j];
             im[M - j] = im[j];
         }
+    }
+    // the chirp itself, w_k = exp(+i pi k^2 / n), k < n (pre- and post-multiplier)
+    double *cw = c->p->chirp.data() + 2 * c->coffs[idx];
+    for (int j = 0; j < n; j++) {
+        long long r = ((long long)j * j) % (2LL * n);
+        ld ang = kPi * (ld)r / (ld)n;
+        cw[2 * j] = (double)cosl(ang);
+        cw[2 * j + 1] = (double)sinl(ang);
     }
     host_fft_forward(re, im);
     int lg = ilog2(M);
@@ -407,10 +416,11 @@ int build_host_tables(sht_plan_s *p) {
     int maxS = 2;
     p->ring_M.assign(p->nrings, 0);
     p->ring_bs_off.assign(p->nrings, -1);
-    std::vector<long long> bs_of_n(4 * N + 1, -1);
+    p->ring_chirp_off.assign(p->nrings, 0);
+    std::vector<long long> bs_of_n(4 * N + 1, -1), chirp_of_n(4 * N + 1, -1);
     BsCtx bctx;
     bctx.p = p;
-    long long bs_total = 0;
+    long long bs_total = 0, chirp_total = 0;
     for (int r = 0; r < p->nrings; r++) {
         int n = p->ring_J[r] / 2;
         if (is_pow2(n)) {
@@ -422,15 +432,20 @@ int build_host_tables(sht_plan_s *p) {
         maxS = std::max(maxS, M);
         if (bs_of_n[n] < 0) {
             bs_of_n[n] = bs_total;
+            chirp_of_n[n] = chirp_total;
             bctx.ns.push_back(n);
             bctx.offs.push_back(bs_total);
+            bctx.coffs.push_back(chirp_total);
             bs_total += M;
+            chirp_total += n;
         }
         p->ring_bs_off[r] = bs_of_n[n];
+        p->ring_chirp_off[r] = chirp_of_n[n];
     }
     if (maxS > 8192)
         return fail(SHT_EUNSUPPORTED, "ring FFT larger than the 8192-point LDS limit (nside > 2048)");
     p->bs_table.assign(2 * (size_t)std::max(bs_total, 1LL), 0.0);
+    p->chirp.assign(2 * (size_t)std::max(chirp_total, 1LL), 0.0);
     parallel_for((long)bctx.ns.size(), nth, bs_worker, &bctx);
     p->tw_log = std::max(1, ilog2(maxS));
     int half = 1 << (p->tw_log - 1);
@@ -502,6 +517,8 @@ int upload_tables(sht_plan_s *p) {
     UP(d_grp_hi, grp_hi);
     UP(d_tw, tw);
     UP(d_bs_table, bs_table);
+    UP(d_chirp, chirp);
+    UP(d_ring_chirp_off, ring_chirp_off);
 #undef UP
     for (auto &rc : p->classes)
         if (e == hipSuccess) e = up(&rc.d_rings, rc.rings, &b);
@@ -548,7 +565,7 @@ void free_device_tables(sht_plan_s *p) {
     void *ptrs[] = {p->d_z2_hi,     p->d_z2_lo,     p->d_ring_J,     p->d_ring_s,   p->d_ring_M,
                     p->d_ring_off,  p->d_ring_bs_off, p->d_coef_off, p->d_coef_hi,  p->d_coef_lo,
                     p->d_start_idx, p->d_start_val, p->d_start_lo,   p->d_grp_lo,   p->d_grp_hi,
-                    p->d_tw,        p->d_bs_table,
+                    p->d_tw,        p->d_bs_table,  p->d_chirp,      p->d_ring_chirp_off,
                     p->d_bf_res_task, p->d_bf_res_lane,
                     p->d_bf_res_val, p->d_bf_T,      p->d_bf_T32,   p->d_bf_perm,
                     p->d_bf_node_i};
@@ -564,7 +581,8 @@ void free_device_tables(sht_plan_s *p) {
     p->d_start_idx = nullptr;
     p->d_start_val = p->d_start_lo = nullptr;
     p->d_grp_lo = p->d_grp_hi = nullptr;
-    p->d_tw = p->d_bs_table = nullptr;
+    p->d_tw = p->d_bs_table = p->d_chirp = nullptr;
+    p->d_ring_chirp_off = nullptr;
     p->d_bf_res_task = p->d_bf_res_lane = nullptr;
     p->d_bf_res_val = p->d_bf_T = nullptr;
     p->d_bf_T32 = nullptr;

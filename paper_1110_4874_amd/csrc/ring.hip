@@ -38,6 +38,8 @@ struct RingArgs {
     const double2 *__restrict__ tw;
     int tw_log;
     const double2 *__restrict__ bs_table;
+    const double2 *__restrict__ chirp;
+    const long long *__restrict__ ring_chirp_off;
     const double2 *__restrict__ q;
     double *__restrict__ map;
     int L, nrings, nmaps;
@@ -186,11 +188,12 @@ __device__ void fft_dif_fwd(double2 *a, int lg, const double2 *__restrict__ tw, 
 
 // Unnormalised backward DFT of size n in LDS: z_p = sum_k Z_k e^{+2 pi i k p/n}.
 // On entry the buffer holds Z_k at pidx(bitrev(k)) (n a power of two, M = 0)
-// or the chirp-weighted u_k = Z_k e^{i pi k^2/n} at pidx(k) with zeros up to
-// M (Bluestein); on exit z_p is at pidx(p), p < n.
+// or the chirp-weighted u_k = Z_k W_k, W_k = e^{i pi k^2/n}, at pidx(k) with
+// zeros up to M (Bluestein); on exit z_p is at pidx(p), p < n.
 template <int T>
 __device__ __forceinline__ void backward_dft(double2 *buf, int n, int M, const double2 *__restrict__ V,
-                                             const double2 *__restrict__ tw, int tw_log) {
+                                             const double2 *__restrict__ W, const double2 *__restrict__ tw,
+                                             int tw_log) {
     const int tid = threadIdx.x;
     if (M == 0) {
         fft_dit_inv(buf, ilog2_dev(n), tw, tw_log);
@@ -201,16 +204,14 @@ __device__ __forceinline__ void backward_dft(double2 *buf, int n, int M, const d
     for (int i = tid; i < M; i += T) buf[pidx(i)] = cmul(buf[pidx(i)], V[i]);
     __syncthreads();
     fft_dit_inv(buf, lgM, tw, tw_log);
-    for (int p = tid; p < n; p += T) {
-        long long r = ((long long)p * p) % (2LL * n);
-        buf[pidx(p)] = cmul(buf[pidx(p)], expipi((double)r / n));
-    }
+    for (int p = tid; p < n; p += T) buf[pidx(p)] = cmul(buf[pidx(p)], W[p]);
     __syncthreads();
 }
 
-// First j >= jlo with j = g (mod G).
-__device__ __forceinline__ long long first_in_class(long long jlo, int g, int G) {
-    long long d = ((long long)g - jlo) % G;
+// First j >= jlo with j = g (mod G) (32-bit: m < 2^15, J <= 8192).
+__device__ __forceinline__ int first_in_class(int jlo, int g, int G) {
+    if (G == 1) return jlo;
+    int d = (g - jlo) % G;
     if (d < 0) d += G;
     return jlo + d;
 }
@@ -220,12 +221,11 @@ __device__ __forceinline__ long long first_in_class(long long jlo, int g, int G)
 __device__ __forceinline__ double2 bin_chunk(const double2 *st, int m0, int cnt, int J, int s, int b, int g,
                                              int G) {
     double2 acc = make_double2(0.0, 0.0);
-    const long long m1 = (long long)m0 + cnt;  // exclusive
+    const int m1 = m0 + cnt;  // exclusive
     // class 1: m = b + jJ, j >= 0
-    long long jlo = (m0 - b + (long long)J - 1) / J;
-    if ((long long)m0 - b <= 0) jlo = 0;
-    for (long long j = first_in_class(jlo, g, G);; j += G) {
-        long long m = b + j * J;
+    const int jlo = m0 - b <= 0 ? 0 : (m0 - b + J - 1) / J;
+    for (int j = first_in_class(jlo, g, G);; j += G) {
+        const int m = b + j * J;
         if (m >= m1) break;
         double2 v = st[m - m0];
         if (m == 0) v = make_double2(v.x, 0.0);  // real part of q_0 only
@@ -233,10 +233,10 @@ __device__ __forceinline__ double2 bin_chunk(const double2 *st, int m0, int cnt,
         acc = cadd(acc, v);
     }
     // class 2: m = jJ - b, j >= 1
-    long long jlo2 = ((long long)m0 + b + J - 1) / J;
+    int jlo2 = (m0 + b + J - 1) / J;
     if (jlo2 < 1) jlo2 = 1;
-    for (long long j = first_in_class(jlo2, g, G);; j += G) {
-        long long m = j * J - b;
+    for (int j = first_in_class(jlo2, g, G);; j += G) {
+        const int m = j * J - b;
         if (m >= m1) break;
         double2 v = cconj(st[m - m0]);
         if (s & j & 1) v = make_double2(-v.x, -v.y);
@@ -257,6 +257,7 @@ __global__ __launch_bounds__(T) void k_ring_synth(RingArgs a) {
     const int J = a.ring_J[rho], s = a.ring_s[rho], M = a.ring_M[rho];
     const int n = J / 2, lgn = ilog2_dev(n);
     const bool bs = M > 0;
+    const double2 *__restrict__ W = a.chirp + (bs ? a.ring_chirp_off[rho] : 0);
     double2 *buf = sm;
     double2 *stage = sm + a.fft_entries;  // a.stage entries (wrapped rings only)
     const int tid = threadIdx.x;
@@ -364,17 +365,13 @@ __global__ __launch_bounds__(T) void k_ring_synth(RingArgs a) {
             buf[pidx(bitrev(k, lgn))] = Zk;
             if (two) buf[pidx(bitrev(n - k, lgn))] = Znk;
         } else {
-            long long r1 = ((long long)k * k) % (2LL * n);
-            buf[pidx(k)] = cmul(Zk, expipi((double)r1 / n));
-            if (two) {
-                long long r2 = ((long long)(n - k) * (n - k)) % (2LL * n);
-                buf[pidx(n - k)] = cmul(Znk, expipi((double)r2 / n));
-            }
+            buf[pidx(k)] = cmul(Zk, W[k]);
+            if (two) buf[pidx(n - k)] = cmul(Znk, W[n - k]);
         }
     }
     __syncthreads();
 
-    backward_dft<T>(buf, n, M, a.bs_table + (bs ? a.ring_bs_off[rho] : 0), a.tw, a.tw_log);
+    backward_dft<T>(buf, n, M, a.bs_table + (bs ? a.ring_bs_off[rho] : 0), W, a.tw, a.tw_log);
     // pixel 2p = Re z_p, pixel 2p+1 = Im z_p
     double2 *out = reinterpret_cast<double2 *>(a.map + (size_t)b * a.npix + a.ring_off[rho]);
     for (int p = tid; p < n; p += T) out[p] = buf[pidx(p)];
@@ -415,6 +412,8 @@ hipError_t launch_ring_synthesis(const sht_plan_s *p, int nmaps, const double *q
     a.tw = reinterpret_cast<const double2 *>(p->d_tw);
     a.tw_log = p->tw_log;
     a.bs_table = reinterpret_cast<const double2 *>(p->d_bs_table);
+    a.chirp = reinterpret_cast<const double2 *>(p->d_chirp);
+    a.ring_chirp_off = p->d_ring_chirp_off;
     a.q = reinterpret_cast<const double2 *>(q);
     a.map = map;
     a.map_in = nullptr;
@@ -451,6 +450,7 @@ __global__ __launch_bounds__(T) void k_ring_analysis(RingArgs a) {
     const int J = a.ring_J[rho], s = a.ring_s[rho], M = a.ring_M[rho];
     const int n = J / 2, lgn = ilog2_dev(n);
     const bool bs = M > 0;
+    const double2 *__restrict__ W = a.chirp + (bs ? a.ring_chirp_off[rho] : 0);
     double2 *buf = sm;
     const int tid = threadIdx.x;
     const int L = a.L;
@@ -465,12 +465,11 @@ __global__ __launch_bounds__(T) void k_ring_analysis(RingArgs a) {
         if (!bs) {
             buf[pidx(bitrev(p, lgn))] = zc;
         } else {
-            long long r1 = ((long long)p * p) % (2LL * n);
-            buf[pidx(p)] = cmul(zc, expipi((double)r1 / n));
+            buf[pidx(p)] = cmul(zc, W[p]);
         }
     }
     __syncthreads();
-    backward_dft<T>(buf, n, M, a.bs_table + (bs ? a.ring_bs_off[rho] : 0), a.tw, a.tw_log);
+    backward_dft<T>(buf, n, M, a.bs_table + (bs ? a.ring_bs_off[rho] : 0), W, a.tw, a.tw_log);
 
     // bins b = 0..n, split over G groups of the residue classes for small rings
     const int nb = n + 1;
@@ -538,6 +537,8 @@ hipError_t launch_ring_analysis(const sht_plan_s *p, int nmaps, const double *ma
     a.tw = reinterpret_cast<const double2 *>(p->d_tw);
     a.tw_log = p->tw_log;
     a.bs_table = reinterpret_cast<const double2 *>(p->d_bs_table);
+    a.chirp = reinterpret_cast<const double2 *>(p->d_chirp);
+    a.ring_chirp_off = p->d_ring_chirp_off;
     a.q = nullptr;
     a.map = nullptr;
     a.map_in = map;
