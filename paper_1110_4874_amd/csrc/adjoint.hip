@@ -8,13 +8,13 @@
 //
 // (the equator ring counts once).  The recurrence runs along l for every
 // ring, but the outputs are indexed by l and summed over rings, so one
-// workgroup owns one order m and every ring it needs: each thread runs the
-// two-step recurrence (App. A.2 Eq. A2) for R rings, forms per-step partial
-// sums over them, and the workgroup adds the partials of two chain steps at
-// a time through LDS in a fixed order (deterministic, no atomics, no
+// workgroup owns one order m and a block of rings: each thread runs the
+// two-step recurrence (App. A.2 Eq. A2) for R rings and forms per-step
+// partial sums over them, and the workgroup adds the partials of each step
+// through double-buffered LDS in a fixed order (deterministic, no atomics, no
 // partial-sum workspace).  Rings nearest the poles run the recurrence in
-// double-double arithmetic in their own, smaller workgroups (launched first,
-// writing g); the FP64 workgroups then add their share to g in place.
+// double-double arithmetic in their own launch (writing g); the FP64 ring
+// blocks then add their share to g in place, launch after launch.
 #include "internal.h"
 
 namespace sht {
@@ -68,21 +68,60 @@ __device__ __forceinline__ dd2 dd2_add(dd2 a, dd2 b) {
 }
 #pragma clang fp contract(on)
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+// Lane shuffle of a double within a row of 16 lanes (DPP control CTRL).
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+    const long long x = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(x >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Sum over each row of 16 lanes, every lane of the row receiving the total:
+// pairs, quads, mirrored quads, mirrored halves.  Partners add the same two
+// numbers, so the result is the same in every lane.
+__device__ __forceinline__ double row16_sum(double v) {
+    v += dpp_d<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_d<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_d<0x141>(v);  // row_half_mirror
+    v += dpp_d<0x140>(v);  // row_mirror
     return v;
 }
 
-// T threads, R rings per thread (ring k0 + tid + r*T), NB maps per pass.
-// LDS: partials red[2 steps][4*NB components][T].
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// T = 256 threads, R rings per thread (rings k0 + tid*R + r, so each wave
+// holds a contiguous block of rings), NB maps per pass.  A group of G chain
+// steps (G * 4 * NB = 16 outputs) is written to one of two LDS buffers as
+// per-thread partial sums red[G][4*NB][T]; after one barrier, 16 lanes per
+// output add 16 partials each and finish with a 16-lane DPP tree, while the
+// next group fills the other buffer.  Outputs already in g (accumulating
+// launches) are fetched one group ahead.  The recurrence coefficients of the
+// order stream through LDS in blocks of kAdjCB steps, each block fetched from
+// memory two blocks ahead of its use, so that the chain never waits on HBM.
+constexpr int kAdjCB = 32;  // chain steps per LDS coefficient block
+
 template <int T, int R, int NB, bool DD>
 __global__ __launch_bounds__(T) void k_legendre_adj(AdjArgs a) {
-    constexpr int NV = 4 * NB;  // (parity, map, re/im) components per step
-    constexpr int NW = T / 64;  // waves
+    static_assert(T == 256, "the reduction maps 16 outputs x 16 slices onto 256 threads");
+    constexpr int NV = 4 * NB;     // (parity, map, re/im) components per step
+    constexpr int G = 16 / NV;     // chain steps per LDS group
+    constexpr int SL = T / 16;     // partial-sum slices per output
+    constexpr int PS = T / SL;     // partials added by one slice
+    constexpr int CW = 8;          // doubles per step and table: even B, AB, G, pad, odd B, AB, G, pad
+    constexpr int CE = kAdjCB * CW / T;  // table entries per thread and block
+    static_assert(kAdjCB % G == 0 && kAdjCB > G && CE >= 1, "coefficient block shape");
     extern __shared__ double red[];
+    constexpr int GO = kAdjCB / G * 16;  // outputs per coefficient block
+    static_assert(GO <= T, "one staged output per thread");
+    __shared__ double cbuf[2][(DD ? 2 : 1) * kAdjCB * CW];
+    __shared__ double gbuf_acc[2][GO];  // outputs already in g, for accumulating launches
     const int m = blockIdx.x;
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int tid = threadIdx.x, lane = tid & 63;
     const int L = a.L;
     const int n0 = (L - m) / 2 + 1;
     const int n1 = (L - m >= 1) ? (L - m - 1) / 2 + 1 : 0;
@@ -102,16 +141,11 @@ __global__ __launch_bounds__(T) void k_legendre_adj(AdjArgs a) {
     __syncthreads();
     const int lo = s_lo, hi = s_hi;
 
-    auto store = [&](int l, int b, int ri, double v) {
-        double *dst = a.g + 2 * ((aoff + l - m) * a.nmaps + a.map0 + b) + ri;
-        if (m == 0 && ri == 1) v = 0.0;
-        if (a.accumulate) *dst += v;
-        else *dst = v;
-    };
+    auto gaddr = [&](int l, int b, int ri) { return a.g + 2 * ((aoff + l - m) * a.nmaps + a.map0 + b) + ri; };
 
     if (lo >= n0) {  // every chain of these rings stays below the cutoff
         if (!a.accumulate)
-            for (int e = tid; e < (L - m + 1) * NB * 2; e += T) store(m + e / (NB * 2), (e / 2) % NB, e % 2, 0.0);
+            for (int e = tid; e < (L - m + 1) * NB * 2; e += T) *gaddr(m + e / (NB * 2), (e / 2) % NB, e % 2) = 0.0;
         return;
     }
 
@@ -121,17 +155,19 @@ __global__ __launch_bounds__(T) void k_legendre_adj(AdjArgs a) {
     int sid[R][2];
     dd2 st0[R][2], st1[R][2], p0[R][2], p1[R][2];
     double yer[R][NB], yei[R][NB], yor[R][NB], yoi[R][NB];
+    int wlo = kDead;
 #pragma unroll
     for (int r = 0; r < R; r++) {
-        k[r] = a.k0 + tid + r * T;
+        k[r] = a.k0 + tid * R + r;
         val[r] = k[r] < a.k1 && k[r] < a.n_north;
         const int kk = val[r] ? k[r] : a.k0;
         z2h[r] = a.z2_hi[kk];
         z2l[r] = DD ? a.z2_lo[kk] : 0.0;
 #pragma unroll
         for (int t = 0; t < 2; t++) {
-            size_t row = (size_t)(2 * m + t);
+            const size_t row = (size_t)(2 * m + t);
             sid[r][t] = val[r] ? a.start_idx[row * a.np + kk] : kDead;
+            wlo = min(wlo, sid[r][t]);
             st0[r][t].h = a.start_val[(row * 2 + 0) * a.np + kk];
             st1[r][t].h = a.start_val[(row * 2 + 1) * a.np + kk];
             st0[r][t].l = DD ? a.start_lo[(row * 2 + 0) * a.n_dd_pad + kk] : 0.0;
@@ -153,109 +189,192 @@ __global__ __launch_bounds__(T) void k_legendre_adj(AdjArgs a) {
             yoi[r][b] = vn.y - vs.y;
         }
     }
-    const long long cbase = a.coef_off[m];
-    const double *__restrict__ ch = a.coef_hi + 4 * cbase;
-    const double *__restrict__ cl = a.coef_lo + 4 * cbase;
+    // first chain step at which any ring of this wave is alive
+    wlo = __builtin_amdgcn_readfirstlane(wave_min(wlo));
 
-    for (int c = lo; c < n0; c += kChunk) {
-        if (c <= hi) {
-#pragma unroll
-            for (int r = 0; r < R; r++)
-#pragma unroll
-                for (int t = 0; t < 2; t++)
-                    if (sid[r][t] == c) {
-                        p0[r][t] = st0[r][t];
-                        p1[r][t] = st1[r][t];
-                    }
+    // coefficient blocks: block j holds chain steps lo + j*kAdjCB + s, s < kAdjCB,
+    // as the table entries 2*step + 2 (even chain) and 2*step + 3 (odd chain);
+    // steps past n0 are not fetched (the table is padded only a few steps)
+    const long long cbase = a.coef_off[m];
+    const double *__restrict__ chd = a.coef_hi + 4 * cbase;
+    const double *__restrict__ cld = a.coef_lo + 4 * cbase;
+    // staged outputs: thread tid < GO holds output tid % 16 of group tid / 16
+    const int so = tid % 16, sv = so % NV, sg = so / NV;
+    const int sb = sv / 4, st_ = (sv % 4) / 2, sri = sv % 2;
+    const int snt = st_ == 0 ? n0 : n1;
+    double creg[2][CE], greg = 0.0;
+    auto fetch_block = [&](int j) {
+        if (a.accumulate && tid < GO) {
+            const int step = lo + j * kAdjCB + (tid / 16) * G + sg;
+            greg = step < snt ? *gaddr(m + st_ + 2 * step, sb, sri) : 0.0;
         }
-        for (int u = 0; u < kChunk; u++) {
-            const int i = c + u;
-            if (i >= n0) break;
-            const int slot = i & 1;
-            // partial sums of this thread's rings: P(i) * ybar^t
-            double pe_r[NB], pe_i[NB], po_r[NB], po_i[NB];
 #pragma unroll
-            for (int b = 0; b < NB; b++) pe_r[b] = pe_i[b] = po_r[b] = po_i[b] = 0.0;
+        for (int e = 0; e < CE; e++) {
+            const int el = tid + e * T;
+            const int step = lo + j * kAdjCB + el / CW;
+            const size_t idx = (size_t)(2 * step + 2) * 4 + el % CW;
+            creg[0][e] = step <= n0 ? chd[idx] : 0.0;
+            if constexpr (DD) creg[1][e] = step <= n0 ? cld[idx] : 0.0;
+        }
+    };
+    auto stage_block = [&](int slot) {
 #pragma unroll
-            for (int r = 0; r < R; r++) {
-                const double pe = p0[r][0].h, po = p0[r][1].h;
+        for (int e = 0; e < CE; e++) {
+            cbuf[slot][tid + e * T] = creg[0][e];
+            if constexpr (DD) cbuf[slot][kAdjCB * CW + tid + e * T] = creg[1][e];
+        }
+        if (a.accumulate && tid < GO) gbuf_acc[slot][tid] = greg;
+    };
+    auto coef = [&](int i, double4 &e4, double4 &o4, double4 &el, double4 &ol) {
+        const int j = (i - lo) / kAdjCB, s = (i - lo) % kAdjCB;
+        const double4 *cb = reinterpret_cast<const double4 *>(&cbuf[j & 1][s * CW]);
+        e4 = cb[0];
+        o4 = cb[1];
+        if constexpr (DD) {
+            const double4 *cbl = reinterpret_cast<const double4 *>(&cbuf[j & 1][kAdjCB * CW + s * CW]);
+            el = cbl[0];
+            ol = cbl[1];
+        }
+    };
+    fetch_block(0);
+    stage_block(0);
+    fetch_block(1);
+    __syncthreads();
+
+    // reduction role of this thread: output (rg, rv) of a group, slice rs
+    const int ro = tid / SL, rs = tid % SL;
+    const int rg = ro / NV, rv = ro % NV;               // step in group, component
+    const int rb = rv / 4, rt = (rv % 4) / 2, rri = rv % 2;
+    const int nt = rt == 0 ? n0 : n1;
+
+
+    double4 e4, o4, el = {0, 0, 0, 0}, ol = {0, 0, 0, 0};
+    coef(lo, e4, o4, el, ol);
+
+    // Steps run in groups of G without a break: the last group may run past
+    // n0 (its extra partials are never stored, its coefficients are stale
+    // but finite table or LDS values).  A group whose steps all precede the
+    // first live chain of the wave (wlo and lo are multiples of kChunk, and
+    // G divides kChunk) only writes zero partials; chains join at the first
+    // step of a group.
+    int buf = 0;
+    for (int g0 = lo; g0 < n0; g0 += G, buf ^= 1) {
+        double *gbuf = red + (size_t)buf * G * NV * T;
+        double *rbuf = gbuf + tid;
+        if (g0 + G <= wlo) {
 #pragma unroll
-                for (int b = 0; b < NB; b++) {
-                    pe_r[b] = __builtin_fma(pe, yer[r][b], pe_r[b]);
-                    pe_i[b] = __builtin_fma(pe, yei[r][b], pe_i[b]);
-                    po_r[b] = __builtin_fma(po, yor[r][b], po_r[b]);
-                    po_i[b] = __builtin_fma(po, yoi[r][b], po_i[b]);
-                }
+            for (int v = 0; v < G * NV; v++) rbuf[v * T] = 0.0;
+            coef(g0 + G, e4, o4, el, ol);
+        } else {
+            if ((g0 % kChunk) == 0 && g0 <= hi) {
+#pragma unroll
+                for (int r = 0; r < R; r++)
+#pragma unroll
+                    for (int t = 0; t < 2; t++)
+                        if (sid[r][t] == g0) {
+                            p0[r][t] = st0[r][t];
+                            p1[r][t] = st1[r][t];
+                        }
             }
-            double *rs = red + (size_t)slot * NV * T;
 #pragma unroll
-            for (int b = 0; b < NB; b++) {
-                rs[(4 * b + 0) * T + tid] = pe_r[b];
-                rs[(4 * b + 1) * T + tid] = pe_i[b];
-                rs[(4 * b + 2) * T + tid] = po_r[b];
-                rs[(4 * b + 3) * T + tid] = po_i[b];
-            }
-            // advance the recurrence
-            const double4 *ce4 = reinterpret_cast<const double4 *>(ch) + (2 * i + 2);
-            const double4 e4 = ce4[0], o4 = ce4[1];
-            if constexpr (!DD) {
+            for (int u = 0; u < G; u++) {
+                const int i = g0 + u;
+                // coefficients of the next step
+                double4 e4n, o4n, eln = el, oln = ol;
+                coef(i + 1, e4n, o4n, eln, oln);
+                // partial sums of this thread's rings: P(i) * ybar^t
+                double pe_r[NB], pe_i[NB], po_r[NB], po_i[NB];
+#pragma unroll
+                for (int b = 0; b < NB; b++) pe_r[b] = pe_i[b] = po_r[b] = po_i[b] = 0.0;
 #pragma unroll
                 for (int r = 0; r < R; r++) {
                     const double pe = p0[r][0].h, po = p0[r][1].h;
-                    const double Ae = __builtin_fma(z2h[r], e4.x, e4.y);
-                    const double Ao = __builtin_fma(z2h[r], o4.x, o4.y);
-                    const double ne = __builtin_fma(Ae, p1[r][0].h, e4.z * pe);
-                    const double no = __builtin_fma(Ao, p1[r][1].h, o4.z * po);
-                    p0[r][0].h = p1[r][0].h;
-                    p1[r][0].h = ne;
-                    p0[r][1].h = p1[r][1].h;
-                    p1[r][1].h = no;
-                }
-            } else {
-                const double4 *cl4 = reinterpret_cast<const double4 *>(cl) + (2 * i + 2);
-                const double4 el = cl4[0], ol = cl4[1];
-                const dd2 Be = {e4.x, el.x}, ABe = {e4.y, el.y}, Ge = {e4.z, el.z};
-                const dd2 Bo = {o4.x, ol.x}, ABo = {o4.y, ol.y}, Go = {o4.z, ol.z};
 #pragma unroll
-                for (int r = 0; r < R; r++) {
-                    const dd2 z2 = {z2h[r], z2l[r]};
-                    const dd2 Ae = dd2_add(dd2_mul(z2, Be), ABe);
-                    const dd2 Ao = dd2_add(dd2_mul(z2, Bo), ABo);
-                    const dd2 ne = dd2_add(dd2_mul(Ae, p1[r][0]), dd2_mul(Ge, p0[r][0]));
-                    const dd2 no = dd2_add(dd2_mul(Ao, p1[r][1]), dd2_mul(Go, p0[r][1]));
-                    p0[r][0] = p1[r][0];
-                    p1[r][0] = ne;
-                    p0[r][1] = p1[r][1];
-                    p1[r][1] = no;
+                    for (int b = 0; b < NB; b++) {
+                        pe_r[b] = __builtin_fma(pe, yer[r][b], pe_r[b]);
+                        pe_i[b] = __builtin_fma(pe, yei[r][b], pe_i[b]);
+                        po_r[b] = __builtin_fma(po, yor[r][b], po_r[b]);
+                        po_i[b] = __builtin_fma(po, yoi[r][b], po_i[b]);
+                    }
                 }
-            }
-            // every second step (and at the end) the workgroup reduces the
-            // partials of the steps held in LDS: wave w sums component w
-            if (slot == 1 || i == n0 - 1) {
-                __syncthreads();
-                const int nsteps = slot + 1;
-                for (int o = wave; o < nsteps * NV; o += NW) {
-                    const int sl = o / NV, v = o % NV;
-                    const double *rv = red + ((size_t)sl * NV + v) * T;
-                    double acc = 0.0;
+                double *rs_ = rbuf + (size_t)u * NV * T;
 #pragma unroll
-                    for (int j = 0; j < T / 64; j++) acc += rv[lane + 64 * j];
-                    acc = wave_sum(acc);
-                    const int is = i - slot + sl;  // chain index of that step
-                    const int b = v / 4, comp = v % 4;
-                    const int t = comp / 2, ri = comp % 2;
-                    if (lane == 0 && is < (t == 0 ? n0 : n1)) store(m + t + 2 * is, b, ri, acc);
+                for (int b = 0; b < NB; b++) {
+                    rs_[(4 * b + 0) * T] = pe_r[b];
+                    rs_[(4 * b + 1) * T] = pe_i[b];
+                    rs_[(4 * b + 2) * T] = po_r[b];
+                    rs_[(4 * b + 3) * T] = po_i[b];
                 }
-                __syncthreads();
+                // advance the recurrence
+                if constexpr (!DD) {
+#pragma unroll
+                    for (int r = 0; r < R; r++) {
+                        const double pe = p0[r][0].h, po = p0[r][1].h;
+                        const double Ae = __builtin_fma(z2h[r], e4.x, e4.y);
+                        const double Ao = __builtin_fma(z2h[r], o4.x, o4.y);
+                        const double ne = __builtin_fma(Ae, p1[r][0].h, e4.z * pe);
+                        const double no = __builtin_fma(Ao, p1[r][1].h, o4.z * po);
+                        p0[r][0].h = p1[r][0].h;
+                        p1[r][0].h = ne;
+                        p0[r][1].h = p1[r][1].h;
+                        p1[r][1].h = no;
+                    }
+                } else {
+                    const dd2 Be = {e4.x, el.x}, ABe = {e4.y, el.y}, Ge = {e4.z, el.z};
+                    const dd2 Bo = {o4.x, ol.x}, ABo = {o4.y, ol.y}, Go = {o4.z, ol.z};
+#pragma unroll
+                    for (int r = 0; r < R; r++) {
+                        const dd2 z2 = {z2h[r], z2l[r]};
+                        const dd2 Ae = dd2_add(dd2_mul(z2, Be), ABe);
+                        const dd2 Ao = dd2_add(dd2_mul(z2, Bo), ABo);
+                        const dd2 ne = dd2_add(dd2_mul(Ae, p1[r][0]), dd2_mul(Ge, p0[r][0]));
+                        const dd2 no = dd2_add(dd2_mul(Ao, p1[r][1]), dd2_mul(Go, p0[r][1]));
+                        p0[r][0] = p1[r][0];
+                        p1[r][0] = ne;
+                        p0[r][1] = p1[r][1];
+                        p1[r][1] = no;
+                    }
+                }
+                e4 = e4n;
+                o4 = o4n;
+                if constexpr (DD) {
+                    el = eln;
+                    ol = oln;
+                }
             }
         }
+        __syncthreads();
+        // after the first group of block j, block j + 1 goes to LDS (its slot
+        // was last read before this barrier) and block j + 2 is fetched
+        if ((g0 - lo) % kAdjCB == 0) {
+            const int j = (g0 - lo) / kAdjCB;
+            stage_block((j + 1) & 1);
+            fetch_block(j + 2);
+        }
+        // reduce the group: slice rs of output (rg, rv) adds partials rs + SL*j
+        const double *rp = gbuf + ((size_t)rg * NV + rv) * T + rs;
+        double acc0 = 0.0, acc1 = 0.0;
+#pragma unroll
+        for (int j = 0; j < PS; j += 2) {
+            acc0 += rp[SL * j];
+            acc1 += rp[SL * (j + 1)];
+        }
+        double acc = row16_sum(acc0 + acc1);
+        const int is = g0 + rg;  // chain step of this output
+        if (rs == 0 && is < nt) {
+            if (a.accumulate) {
+                const int j = (g0 - lo) / kAdjCB, q = ((g0 - lo) % kAdjCB) / G;
+                acc += gbuf_acc[j & 1][q * 16 + ro];
+            }
+            if (m == 0 && rri == 1) acc = 0.0;
+            *gaddr(m + rt + 2 * is, rb, rri) = acc;
+        }
     }
-    // chains that never start inside [lo, n0) leave their l untouched only if
-    // the whole order is dead, handled above; entries before lo are zero
+    // entries before lo are zero
     if (!a.accumulate) {
         for (int e = tid; e < 2 * lo * NB * 2 && e < (L - m + 1) * NB * 2; e += T) {
             const int l = m + e / (NB * 2);
-            if (l - m < 2 * lo) store(l, (e / 2) % NB, e % 2, 0.0);
+            if (l - m < 2 * lo) *gaddr(l, (e / 2) % NB, e % 2) = 0.0;
         }
     }
 }
@@ -263,7 +382,7 @@ __global__ __launch_bounds__(T) void k_legendre_adj(AdjArgs a) {
 template <int T, int R, int NB, bool DD>
 static hipError_t launch_adj_cfg(const sht_plan_s *p, AdjArgs a, hipStream_t st) {
     static bool attr_set = false;
-    const size_t lds = (size_t)2 * 4 * NB * T * sizeof(double);
+    const size_t lds = (size_t)2 * 16 * T * sizeof(double);
     if (!attr_set) {
         (void)hipFuncSetAttribute((const void *)k_legendre_adj<T, R, NB, DD>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -273,14 +392,15 @@ static hipError_t launch_adj_cfg(const sht_plan_s *p, AdjArgs a, hipStream_t st)
     return hipGetLastError();
 }
 
-// FP64 rings: 512 threads, R rings each (R = 1, 2, 4 by the ring count, at
-// most 2048 rings per launch).
+// FP64 rings: 256 threads, R rings each (R = 1, 2, 4 by the ring count, at
+// most kAdjFpRings rings per launch).
+constexpr int kAdjFpRings = 1024;
 template <int NB>
 static hipError_t launch_adj_fp(const sht_plan_s *p, AdjArgs a, hipStream_t st) {
     const int nr = a.k1 - a.k0;
-    if (nr <= 512) return launch_adj_cfg<512, 1, NB, false>(p, a, st);
-    if (nr <= 1024) return launch_adj_cfg<512, 2, NB, false>(p, a, st);
-    return launch_adj_cfg<512, 4, NB, false>(p, a, st);
+    if (nr <= 256) return launch_adj_cfg<256, 1, NB, false>(p, a, st);
+    if (nr <= 512) return launch_adj_cfg<256, 2, NB, false>(p, a, st);
+    return launch_adj_cfg<256, 4, NB, false>(p, a, st);
 }
 
 // Double-double rings: 256 threads, one ring each (at most 256 per launch).
@@ -325,10 +445,10 @@ hipError_t launch_legendre_adjoint(const sht_plan_s *p, int nmaps, const double 
             e = nb == 2 ? launch_adj_dd<2>(p, a, stream) : launch_adj_dd<1>(p, a, stream);
             wrote = true;
         }
-        // the remaining rings in FP64, in chunks of up to 2048 rings
-        for (int k0 = kdd; k0 < p->n_north && e == hipSuccess; k0 += 2048) {
+        // the remaining rings in FP64, in chunks of up to kAdjFpRings rings
+        for (int k0 = kdd; k0 < p->n_north && e == hipSuccess; k0 += kAdjFpRings) {
             a.k0 = k0;
-            a.k1 = std::min(p->n_north, k0 + 2048);
+            a.k1 = std::min(p->n_north, k0 + kAdjFpRings);
             a.accumulate = wrote ? 1 : 0;
             e = nb == 2 ? launch_adj_fp<2>(p, a, stream) : launch_adj_fp<1>(p, a, stream);
             wrote = true;
