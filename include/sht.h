@@ -109,8 +109,10 @@ typedef struct sht_plan_opts {
     int max_levels;    /* -1: depth from the rho cost model; 0: no compression;
                           > 0: exactly this many levels where the rows allow */
     int chunk;         /* column block width at level 1 (0 = default 64) */
-    double id_safety;  /* IDs are taken at tolerance eps / id_safety (>= 1;
-                          0 = default 1) */
+    double id_safety;  /* IDs are taken at tolerance eps / id_safety (values
+                          below 1 count as 1; 0 = default 2, which keeps both
+                          the compressed synthesis and its transpose within
+                          eps of the exact operator) */
     int store_fp32;    /* 1: also keep an FP32 copy of the interpolation
                           matrices for SHT_PREC_FP32 */
     int batch_mib;     /* > 0: run the orders in batches whose level vectors (at
@@ -181,9 +183,9 @@ sht_plan_t *sht_plan_ex(int L, int nside, double eps, const sht_plan_opts *opts)
 void sht_plan_free(sht_plan_t *plan);
 int sht_plan_info(const sht_plan_t *plan, sht_plan_info_t *out);
 
-/* Device scratch needed by one execution with these options: the Legendre
- * phase buffer, nmaps * (L+1) * nrings complex values, plus on the butterfly
- * path one vector slot per resident workgroup. */
+/* Device scratch needed by one synthesis or adjoint with these options: the
+ * Legendre phase buffer, nmaps * (L+1) * nrings complex values, plus on the
+ * butterfly path the plan's vector workspace for up to 8 maps. */
 size_t sht_workspace_bytes(const sht_plan_t *plan, const sht_exec_opts *x);
 
 /* Synthesis f = Y a for one map (sht_synthesis) or x->nmaps maps. */
@@ -198,7 +200,14 @@ int sht_synthesis_ex(const sht_plan_t *plan, const sht_exec_opts *x,
  * w_0 = 1 (Im g_l0 = 0), w_m = 2 for m >= 1, so that
  * <synthesis(a), y> = sum Re a Re g + Im a Im g for real-field a.
  * map: x->nmaps stacked maps (input); alm: output in the alm layout.
- * The Legendre functions are recomputed (nothing is kept from synthesis). */
+ * The Legendre functions are recomputed (nothing is kept from synthesis).
+ * x->path picks the Legendre part as for synthesis: the brute-force
+ * recurrence (deterministic), or on an eps > 0 plan the transposed butterfly
+ * (Sec. 4.2 factorization applied backwards; x->precision FP32 runs its
+ * interpolation products on FP32 matrix cores), which is the exact transpose
+ * of that plan's compressed synthesis.  The butterfly adjoint adds the
+ * residual rows into alm with device atomics, so its last bits may differ
+ * between runs.  The workspace is sht_workspace_bytes() of the same options. */
 int sht_adjoint(const sht_plan_t *plan, const double *map, double *alm);
 int sht_adjoint_ex(const sht_plan_t *plan, const sht_exec_opts *x, const double *map,
                    double *alm);

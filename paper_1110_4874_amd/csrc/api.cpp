@@ -361,7 +361,7 @@ int sht_adjoint_ex(const sht_plan_t *p, const sht_exec_opts *x, const double *ma
     if ((rc = check_dev_ptr(map, npix_of(p->nside) * B * 8, p->device, "map"))) return rc;
     if ((rc = check_dev_ptr(alm, nalm_of(p->L) * B * 16, p->device, "alm"))) return rc;
     Scratch ws;
-    if ((rc = ws.get(x, q_bytes(p, B), p->device))) return rc;
+    if ((rc = ws.get(x, synth_ws_bytes(p, x), p->device))) return rc;
     hipStream_t st = (hipStream_t)x->stream;
     double *ybar = (double *)ws.ptr;
     const double wpos = x->adjoint_convention == SHT_ADJ_DAGGER ? 1.0 : 2.0;
@@ -369,7 +369,12 @@ int sht_adjoint_ex(const sht_plan_t *p, const sht_exec_opts *x, const double *ma
     if ((rc = hip_status(launch_ring_analysis(p, B, map, ybar, wpos, st), "ring analysis launch"))) return rc;
     stage_event(x, SHT_STAGE_RING_ADJ, 1);
     stage_event(x, SHT_STAGE_LEGENDRE_ADJ, 0);
-    rc = hip_status(launch_legendre_adjoint(p, B, ybar, alm, st), "adjoint Legendre launch");
+    if (use_bf(p, x->path))
+        rc = hip_status(launch_butterfly_adjoint(p, B, ybar, alm, (char *)ws.ptr + q_bytes(p, B),
+                                                 x->precision == SHT_PREC_FP32, st),
+                        "adjoint butterfly launch");
+    else
+        rc = hip_status(launch_legendre_adjoint(p, B, ybar, alm, st), "adjoint Legendre launch");
     stage_event(x, SHT_STAGE_LEGENDRE_ADJ, 1);
     return rc;
 }

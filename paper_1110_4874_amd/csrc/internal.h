@@ -159,5 +159,9 @@ hipError_t launch_legendre_adjoint(const sht_plan_s *p, int nmaps, const double 
 size_t bf_scratch_bytes(const sht_plan_s *p, int nmaps, int fp32);
 hipError_t launch_butterfly(const sht_plan_s *p, int nmaps, const double *alm, double *q, void *scratch,
                             int fp32, hipStream_t stream);
+// Its transpose: unfolded ybar (ring-major, like q) -> g (written whole),
+// with the same scratch.
+hipError_t launch_butterfly_adjoint(const sht_plan_s *p, int nmaps, const double *ybar, double *g, void *scratch,
+                                    int fp32, hipStream_t stream);
 
 }  // namespace sht

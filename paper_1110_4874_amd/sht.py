@@ -266,15 +266,19 @@ class Plan:
         return m.contiguous()
 
     def adjoint(self, maps, out=None, *, path=PATH_AUTO, stream=None, workspace=None, events=None,
-                convention=ADJ_TRANSPOSE):
-        """alm (nalm, B) complex128 = A^T maps, maps (B, Npix) or (Npix,) float64."""
+                convention=ADJ_TRANSPOSE, precision=PREC_FP64):
+        """alm (nalm, B) complex128 = A^T maps, maps (B, Npix) or (Npix,) float64.
+
+        path and precision select the Legendre part as for synthesis (the
+        butterfly adjoint is the exact transpose of that plan's compressed
+        synthesis)."""
         m = self._map_arg(maps)
         B = m.shape[0]
         if out is None:
             out = torch.empty((self.nalm, B), dtype=torch.complex128, device=m.device)
         if workspace is None:
-            workspace = self.workspace(B, m.device)
-        x = self._exec(B, path, stream, workspace, events, convention)
+            workspace = self.workspace(B, m.device, path, precision)
+        x = self._exec(B, path, stream, workspace, events, convention, precision)
         _check(load().sht_adjoint_ex(self._h, _c.byref(x), _c.c_void_p(m.data_ptr()),
                                      _c.c_void_p(out.data_ptr())))
         return out
@@ -380,17 +384,23 @@ class _Synthesis(torch.autograd.Function):
     """
 
     @staticmethod
-    def forward(ctx, plan, alm):
+    def forward(ctx, plan, alm, path, precision):
         ctx.plan = plan
         ctx.shape = alm.shape
-        return plan.synthesis(alm.detach())
+        ctx.path = path
+        ctx.precision = precision
+        return plan.synthesis(alm.detach(), path=path, precision=precision)
 
     @staticmethod
     def backward(ctx, grad_maps):
-        g = ctx.plan.adjoint(grad_maps.contiguous(), convention=ADJ_TRANSPOSE)
-        return None, g.reshape(ctx.shape)
+        g = ctx.plan.adjoint(grad_maps.contiguous(), convention=ADJ_TRANSPOSE, path=ctx.path,
+                             precision=ctx.precision)
+        return None, g.reshape(ctx.shape), None, None
 
 
-def synthesis_fn(plan, alm):
-    """Differentiable synthesis: alm (nalm, B) or (nalm,) complex128 -> maps."""
-    return _Synthesis.apply(plan, alm)
+def synthesis_fn(plan, alm, *, path=PATH_AUTO, precision=PREC_FP64):
+    """Differentiable synthesis: alm (nalm, B) or (nalm,) complex128 -> maps.
+
+    The backward runs the adjoint with the same path and precision, so on a
+    butterfly plan the gradient is exact for the compressed operator."""
+    return _Synthesis.apply(plan, alm, path, precision)
