@@ -374,7 +374,10 @@ int build_butterfly(sht_plan_s *p, const BflyInput &in) {
     c.p = p;
     c.in = &in;
     c.items.resize((size_t)(L + 1) * 2);
-    c.eps_id = p->eps / std::max(1.0, p->opts.id_safety);
+    // IDs at eps / 2 by default: the transpose of a block truncated at eps
+    // (the adjoint) reaches about 1.7 eps in max norm on white-noise maps,
+    // while eps / 2 keeps both directions within eps for ~1% more entries.
+    c.eps_id = p->eps / (p->opts.id_safety > 0 ? std::max(1.0, p->opts.id_safety) : 2.0);
     c.rho = p->opts.rho > 0 ? p->opts.rho : 2.5;
     c.chunk = p->opts.chunk > 0 ? p->opts.chunk : 64;
     c.max_levels = p->opts.max_levels;
