@@ -10,7 +10,10 @@ seeded complex Gaussian a_lm (C_l = 1/(l+1)^2, seeds 400..403).  One plan
   bf32       butterfly-compressed operator, FP32 matrix-core products
 The headline `value` is the fastest FP64 path (maps/s over exactly --steps
 steps bracketed by device synchronisation); the other paths are timed the
-same way and reported under "paths".  The roofline object covers the
+same way and reported under "paths".  Under "adjoint", every path is also
+timed on the map-fitting gradient: forward + backward of
+||synthesis(a) - d||^2 through autograd, whose backward is the hand-written
+adjoint of the same path, and on the adjoint alone.  The roofline object covers the
 dominant kernel of the headline path, measured with HIP events recorded on
 the execution stream around its stage.  The CPU baseline times the oracle on
 a random sample of rings; max_rel_err compares each path with the oracle's
@@ -123,6 +126,81 @@ def batch_bench(np, torch, sht, steps):
     return res
 
 
+def gradient_bench(np, torch, sht, plan, info, paths, d_alm, f_true, ws, ev_sets, args, flops):
+    """Forward + backward of the map-fitting loss ||synthesis(a) - d||^2 per path.
+
+    d = synthesis(a_true) + white noise of sigma = 0.1 rms (seeds 410..),
+    evaluated at a = a_true + 0.1 * (draw of seed 420, same spectrum); the
+    backward is the hand-written adjoint of the same path and precision
+    (autograd through synthesis_fn).  Also times the adjoint alone with its
+    two stages, and compares each path's gradient with the brute-force one.
+    """
+    from paper_1110_4874_amd.synthetic import alm_gaussian, gaussian_map
+    B = f_true.shape[0]
+    L, dev = plan.L, d_alm.device
+    sig = 0.1 * np.sqrt(np.mean(f_true ** 2, axis=1))
+    d = torch.from_numpy(f_true + gaussian_map(plan.npix, [410 + b for b in range(B)], sig)).to(dev)
+    pert = torch.from_numpy(alm_gaussian(L, [420] * B)).to(dev)
+    a0 = (d_alm + 0.1 * pert).detach()
+    out = {"loss_at_zero": None, "paths": {}}
+    with torch.no_grad():
+        out["loss_at_zero"] = float((d ** 2).sum())
+    grads = {}
+    g = torch.empty((plan.nalm, B), dtype=torch.complex128, device=dev)
+    for name, path, prec in paths:
+        a = a0.clone().requires_grad_(True)
+
+        def step():
+            a.grad = None
+            f = sht.synthesis_fn(plan, a, path=path, precision=prec)
+            loss = ((f - d) ** 2).sum()
+            loss.backward()
+            return loss
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        for _ in range(args.steps):
+            loss = step()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - ts
+        grads[name] = a.grad.detach().cpu().numpy()
+        # adjoint alone, with stage events
+        y = d.clone()
+        for _ in range(args.warmup):
+            plan.adjoint(y, g, workspace=ws, path=path, precision=prec)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        for k in range(args.steps):
+            plan.adjoint(y, g, workspace=ws, path=path, precision=prec, events=ev_sets[k])
+        torch.cuda.synchronize()
+        adj_el = time.perf_counter() - ta
+        ra_ms = float(np.mean([e[4].elapsed_time(e[5]) for e in ev_sets]))
+        la_ms = float(np.mean([e[6].elapsed_time(e[7]) for e in ev_sets]))
+        rec = {"fwd_bwd_ms_per_step": round(1e3 * el / args.steps, 4),
+               "fwd_bwd_maps_per_s": round(B * args.steps / el, 3),
+               "loss": float(loss),
+               "adjoint_ms_per_step": round(1e3 * adj_el / args.steps, 4),
+               "adjoint_maps_per_s": round(B * args.steps / adj_el, 3),
+               "adjoint_stages_ms": {"ring_analysis": round(ra_ms, 4), "legendre_adjoint": round(la_ms, 4)}}
+        if name == "brute":
+            rec["legendre_adjoint_tflops"] = round(flops / (la_ms * 1e-3) / 1e12, 3)
+        out["paths"][name] = rec
+        log(f"[bench] gradient {name}: fwd+bwd {rec['fwd_bwd_ms_per_step']:.3f} ms/step, adjoint "
+            f"{rec['adjoint_ms_per_step']:.3f} ms (ring analysis {ra_ms:.3f}, Legendre {la_ms:.3f})")
+    gb = grads["brute"]
+    for name in grads:
+        if name == "brute":
+            continue
+        err = max(float(np.max(np.abs(grads[name][:, b] - gb[:, b])) / np.max(np.abs(gb[:, b])))
+                  for b in range(B))
+        out["paths"][name]["grad_max_rel_vs_brute"] = float(f"{err:.3e}")
+        out["paths"][name]["adjoint_speedup_vs_brute"] = round(
+            out["paths"]["brute"]["adjoint_ms_per_step"] / out["paths"][name]["adjoint_ms_per_step"], 3)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -231,24 +309,7 @@ def main():
 
     adj = None
     if not args.no_adjoint:
-        y = out.clone()
-        g = torch.empty((plan.nalm, B), dtype=torch.complex128, device=dev)
-        for _ in range(args.warmup):
-            plan.adjoint(y, g, workspace=ws)
-        torch.cuda.synchronize()
-        ta = time.perf_counter()
-        for k in range(args.steps):
-            plan.adjoint(y, g, workspace=ws, events=ev_sets[k])
-        torch.cuda.synchronize()
-        adj_elapsed = time.perf_counter() - ta
-        ra_ms = float(np.mean([e[4].elapsed_time(e[5]) for e in ev_sets]))
-        la_ms = float(np.mean([e[6].elapsed_time(e[7]) for e in ev_sets]))
-        adj = {"path": "brute", "maps_per_s": round(B * args.steps / adj_elapsed, 3),
-               "ms_per_step": round(1e3 * adj_elapsed / args.steps, 4),
-               "stages_ms": {"ring_analysis": round(ra_ms, 4), "legendre_adjoint": round(la_ms, 4)},
-               "legendre_adjoint_tflops": round(flops / (la_ms * 1e-3) / 1e12, 3)}
-        log(f"[bench] adjoint {adj['ms_per_step']:.3f} ms/step, ring analysis {ra_ms:.3f} ms, "
-            f"legendre adjoint {la_ms:.3f} ms")
+        adj = gradient_bench(np, torch, sht, plan, info, paths, d_alm, maps_out["brute"], ws, ev_sets, args, flops)
 
     if not args.no_batch:
         line_batch = batch_bench(np, torch, sht, args.steps)
