@@ -234,14 +234,18 @@ __global__ __launch_bounds__(kBfThreads) void k_bf_residual(BfArgs<S> a, long lo
     c_double *ap = (c_double *)(a.alm + (aoff + t) * a.nmaps + a.map0);
     c_double *cfs = (c_double *)(a.coef + 4 * a.coef_off[m]);
     const int astride = 4 * a.nmaps;  // doubles between rows i and i+1
-    if (nl > 192)
-        residual_task<NB, 4>(a, a.ws, tk, lane, t, imin, iend, nl, outb, ap, cfs, astride);
-    else if (nl > 128)
-        residual_task<NB, 3>(a, a.ws, tk, lane, t, imin, iend, nl, outb, ap, cfs, astride);
-    else if (nl > 64)
-        residual_task<NB, 2>(a, a.ws, tk, lane, t, imin, iend, nl, outb, ap, cfs, astride);
-    else
-        residual_task<NB, 1>(a, a.ws, tk, lane, t, imin, iend, nl, outb, ap, cfs, astride);
+    // only the ring counts a task can have are instantiated (registers, and
+    // with them occupancy, follow the largest)
+    if constexpr (kBfTaskRings > 192) {
+        if (nl > 192) return residual_task<NB, 4>(a, a.ws, tk, lane, t, imin, iend, nl, outb, ap, cfs, astride);
+    }
+    if constexpr (kBfTaskRings > 128) {
+        if (nl > 128) return residual_task<NB, 3>(a, a.ws, tk, lane, t, imin, iend, nl, outb, ap, cfs, astride);
+    }
+    if constexpr (kBfTaskRings > 64) {
+        if (nl > 64) return residual_task<NB, 2>(a, a.ws, tk, lane, t, imin, iend, nl, outb, ap, cfs, astride);
+    }
+    residual_task<NB, 1>(a, a.ws, tk, lane, t, imin, iend, nl, outb, ap, cfs, astride);
 }
 
 // One workgroup of two waves per pair node: u (zeroed in LDS) collects both
@@ -314,11 +318,15 @@ __global__ __launch_bounds__(kBfThreads) void k_bf_unfold(BfArgs<S> a, int batch
 //   v_ch = A~_ch u:  v[s] = u[perm s] + sum_d T[s][d] u[perm (k + d)].
 // The dense part runs on the matrix cores with the skeleton rows s as the
 // output rows (four 16-row tiles sharing each U operand) and the dense
-// columns d as the reduction: lane (i, kq) holds columns d0 + 4 kq + j,
-// j < 4, so each lane reads 32 contiguous bytes of a row of T per batch.
+// columns d as the reduction: per batch of kBfTJ K-steps, lane (i, kq) holds
+// columns d0 + kBfTJ kq + j, j < kBfTJ, so each lane reads kBfTJ contiguous
+// entries of a row of T.
+constexpr int kBfTJ = 2;  // K-steps per batch of loads in the transposed level
+
 template <int NB, typename S>
 __device__ __forceinline__ void id_block_t(const BfArgs<S> &a, int node, int ch, int lane, const S *u) {
     constexpr int NC = 2 * NB;
+    constexpr int DB = 4 * kBfTJ;  // dense columns per batch
     typedef typename Acc<S>::type acc_t;
     const int *ni = a.node_i + (size_t)node * kBfNodeInts;
     const int n = ni[2] + ni[4];
@@ -333,11 +341,11 @@ __device__ __forceinline__ void id_block_t(const BfArgs<S> &a, int node, int ch,
         acc_t acc[4];
 #pragma unroll
         for (int tt = 0; tt < 4; tt++) acc[tt] = acc_t{0, 0, 0, 0};
-        for (int d0 = 0; d0 < nd; d0 += 16) {
-            S av[4][4], bv[4];
+        for (int d0 = 0; d0 < nd; d0 += DB) {
+            S av[4][kBfTJ], bv[kBfTJ];
 #pragma unroll
-            for (int j = 0; j < 4; j++) {
-                const int d = d0 + 4 * k4 + j;
+            for (int j = 0; j < kBfTJ; j++) {
+                const int d = d0 + kBfTJ * k4 + j;
                 const bool dv = d < nd;
                 bv[j] = (dv && i16 < NC) ? u[pm[kk + d] * NC + i16] : (S)0;
 #pragma unroll
@@ -347,7 +355,7 @@ __device__ __forceinline__ void id_block_t(const BfArgs<S> &a, int node, int ch,
                 }
             }
 #pragma unroll
-            for (int j = 0; j < 4; j++)
+            for (int j = 0; j < kBfTJ; j++)
 #pragma unroll
                 for (int tt = 0; tt < 4; tt++)
                     if (tt < ntile) acc[tt] = mfma_16x16x4(av[tt][j], bv[j], acc[tt]);
@@ -540,14 +548,16 @@ __global__ __launch_bounds__(kBfThreads) void k_bf_residual_t(BfArgs<S> a, long 
     const int iend = __builtin_amdgcn_readfirstlane(h.z), nl = __builtin_amdgcn_readfirstlane(h.w);
     const int outb = __builtin_amdgcn_readfirstlane(h2.x), m = __builtin_amdgcn_readfirstlane(h2.y);
     c_double *cfs = (c_double *)(a.coef + 4 * a.coef_off[m]);
-    if (nl > 192)
-        residual_task_t<NB, 4>(a, tk, lane, t, imin, iend, nl, outb, m, cfs);
-    else if (nl > 128)
-        residual_task_t<NB, 3>(a, tk, lane, t, imin, iend, nl, outb, m, cfs);
-    else if (nl > 64)
-        residual_task_t<NB, 2>(a, tk, lane, t, imin, iend, nl, outb, m, cfs);
-    else
-        residual_task_t<NB, 1>(a, tk, lane, t, imin, iend, nl, outb, m, cfs);
+    if constexpr (kBfTaskRings > 192) {
+        if (nl > 192) return residual_task_t<NB, 4>(a, tk, lane, t, imin, iend, nl, outb, m, cfs);
+    }
+    if constexpr (kBfTaskRings > 128) {
+        if (nl > 128) return residual_task_t<NB, 3>(a, tk, lane, t, imin, iend, nl, outb, m, cfs);
+    }
+    if constexpr (kBfTaskRings > 64) {
+        if (nl > 64) return residual_task_t<NB, 2>(a, tk, lane, t, imin, iend, nl, outb, m, cfs);
+    }
+    residual_task_t<NB, 1>(a, tk, lane, t, imin, iend, nl, outb, m, cfs);
 }
 
 // g = 0 over the nalm rows of maps [map0, map0 + nb) (a kernel, not a
