@@ -38,6 +38,7 @@ namespace sht {
 template <typename S>
 struct BfArgs {
     const int4 *__restrict__ res_task;
+    const int4 *__restrict__ res_sub;
     const int2 *__restrict__ res_lane;
     const double2 *__restrict__ res_val;
     const int16_t *__restrict__ perm;
@@ -156,10 +157,11 @@ __device__ __forceinline__ void id_block(const BfArgs<S> &a, int node, int ch, i
     }
 }
 
-// One residual task on one wave: R rings per lane (lane j: rings j + 64 r),
-// rows [imin, iend) of one parity, outputs at entries outb + ring.
+// One residual piece on one wave: R rings per lane (lane j: rings j + 64 r,
+// lane records from lbase), rows [imin, iend) of one parity, outputs at
+// entries outb + ring.
 template <int NB, int R, typename S>
-__device__ __forceinline__ void residual_task(const BfArgs<S> &a, S *__restrict__ slot, long long tk, int lane,
+__device__ __forceinline__ void residual_task(const BfArgs<S> &a, S *__restrict__ slot, long long lbase, int lane,
                                               int t, int imin, int iend, int nl, int outb, c_double *ap,
                                               c_double *cfs, int astride) {
     constexpr int NC = 2 * NB;
@@ -167,7 +169,7 @@ __device__ __forceinline__ void residual_task(const BfArgs<S> &a, S *__restrict_
     double z2[R], v0[R], v1[R], P0[R], P1[R], acc[R][NC];
 #pragma unroll
     for (int r = 0; r < R; r++) {
-        const size_t li = (size_t)tk * kBfTaskRings + r * 64 + lane;
+        const size_t li = (size_t)lbase + r * 64 + lane;
         const int2 ln = a.res_lane[li];
         const double2 sv = a.res_val[li];
         i0[r] = ln.y;
@@ -221,31 +223,24 @@ __device__ __forceinline__ void residual_task(const BfArgs<S> &a, S *__restrict_
     }
 }
 
+// One wave per residual piece (up to 64 skeleton rings of one task, one per
+// lane): short waves keep the register count, and with it the occupancy, of
+// the one-ring case.
 template <int NB, typename S>
 __global__ __launch_bounds__(kBfThreads) void k_bf_residual(BfArgs<S> a, long long t0, long long t1) {
     const int lane = threadIdx.x & 63;
     const long long tk = t0 + (long long)blockIdx.x * (kBfThreads / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (tk >= t1) return;
-    const int4 h = a.res_task[2 * tk], h2 = a.res_task[2 * tk + 1];
+    const int4 h = a.res_sub[2 * tk], h2 = a.res_sub[2 * tk + 1];
     const int t = __builtin_amdgcn_readfirstlane(h.x), imin = __builtin_amdgcn_readfirstlane(h.y);
     const int iend = __builtin_amdgcn_readfirstlane(h.z), nl = __builtin_amdgcn_readfirstlane(h.w);
     const int outb = __builtin_amdgcn_readfirstlane(h2.x), m = __builtin_amdgcn_readfirstlane(h2.y);
+    const long long lbase = (unsigned)__builtin_amdgcn_readfirstlane(h2.z);
     const size_t aoff = (size_t)m * (2 * a.L + 3 - m) / 2;
     c_double *ap = (c_double *)(a.alm + (aoff + t) * a.nmaps + a.map0);
     c_double *cfs = (c_double *)(a.coef + 4 * a.coef_off[m]);
     const int astride = 4 * a.nmaps;  // doubles between rows i and i+1
-    // only the ring counts a task can have are instantiated (registers, and
-    // with them occupancy, follow the largest)
-    if constexpr (kBfTaskRings > 192) {
-        if (nl > 192) return residual_task<NB, 4>(a, a.ws, tk, lane, t, imin, iend, nl, outb, ap, cfs, astride);
-    }
-    if constexpr (kBfTaskRings > 128) {
-        if (nl > 128) return residual_task<NB, 3>(a, a.ws, tk, lane, t, imin, iend, nl, outb, ap, cfs, astride);
-    }
-    if constexpr (kBfTaskRings > 64) {
-        if (nl > 64) return residual_task<NB, 2>(a, a.ws, tk, lane, t, imin, iend, nl, outb, ap, cfs, astride);
-    }
-    residual_task<NB, 1>(a, a.ws, tk, lane, t, imin, iend, nl, outb, ap, cfs, astride);
+    residual_task<NB, 1>(a, a.ws, lbase, lane, t, imin, iend, nl, outb, ap, cfs, astride);
 }
 
 // One workgroup of two waves per pair node: u (zeroed in LDS) collects both
@@ -581,7 +576,7 @@ static hipError_t launch_bf_nb(const sht_plan_s *p, BfArgs<S> a, hipStream_t st)
     constexpr int WPB = kBfThreads / 64;
     const BflyPlan &b = p->bf;
     for (int bt = 0; bt < b.nbatch; bt++) {
-        const long long t0 = b.batch_task[bt], t1 = b.batch_task[bt + 1];
+        const long long t0 = b.batch_sub[bt], t1 = b.batch_sub[bt + 1];
         if (t1 > t0)
             hipLaunchKernelGGL((k_bf_residual<NB, S>), dim3((unsigned)((t1 - t0 + WPB - 1) / WPB)), dim3(kBfThreads), 0,
                                st, a, t0, t1);
@@ -605,6 +600,7 @@ static hipError_t launch_bf(const sht_plan_s *p, int nmaps, const double *alm, d
                             hipStream_t st) {
     BfArgs<S> a;
     a.res_task = reinterpret_cast<const int4 *>(p->d_bf_res_task);
+    a.res_sub = reinterpret_cast<const int4 *>(p->d_bf_res_sub);
     a.res_lane = reinterpret_cast<const int2 *>(p->d_bf_res_lane);
     a.res_val = reinterpret_cast<const double2 *>(p->d_bf_res_val);
     a.perm = p->d_bf_perm;
@@ -669,6 +665,7 @@ static hipError_t launch_bf_adj(const sht_plan_s *p, int nmaps, const double *yb
                                 hipStream_t st) {
     BfArgs<S> a;
     a.res_task = reinterpret_cast<const int4 *>(p->d_bf_res_task);
+    a.res_sub = reinterpret_cast<const int4 *>(p->d_bf_res_sub);
     a.res_lane = reinterpret_cast<const int2 *>(p->d_bf_res_lane);
     a.res_val = reinterpret_cast<const double2 *>(p->d_bf_res_val);
     a.perm = p->d_bf_perm;

@@ -443,6 +443,7 @@ int build_butterfly(sht_plan_s *p, const BflyInput &in) {
     }
     b.nbatch = nb;
     b.batch_task.assign(nb + 1, 0);
+    b.batch_sub.assign(nb + 1, 0);
     b.lv_off.assign((size_t)nb * (kBfMaxLv + 1) + 1, 0);
     b.batch_count.assign(nb, 0);
     for (int bt = 0; bt < nb; bt++) {
@@ -504,7 +505,6 @@ int build_butterfly(sht_plan_s *p, const BflyInput &in) {
                             }
                         }
                         b.n_res_lanes += nl;
-                        b.res_exec += (long long)(rend - imin) * 64 * ((nl + 63) / 64);
                     }
                 }
                 // pair nodes of every level
@@ -567,6 +567,21 @@ int build_butterfly(sht_plan_s *p, const BflyInput &in) {
         if (b.ws_entries > INT32_MAX || (long long)b.perm.size() > INT32_MAX)
             return fail(SHT_EUNSUPPORTED, "butterfly plan exceeds 32-bit record offsets");
         for (size_t q = 0; q < task_region.size(); q++) b.res_task[8 * (task0 + q) + 4] += (int)base[task_region[q]];
+        // the same tasks in pieces of up to 64 rings (one wave, one ring per
+        // lane) for the forward kernel, each starting at its own first row
+        b.batch_sub[bt] = (long long)b.res_sub.size() / 8;
+        for (size_t tk = task0; tk < b.res_task.size() / 8; tk++) {
+            const int *h = &b.res_task[8 * tk];
+            for (int q0 = 0; q0 < h[3]; q0 += 64) {
+                const int nq = std::min(64, h[3] - q0);
+                int imin = h[2];
+                for (int j = 0; j < nq; j++)
+                    imin = std::min(imin, b.res_lane[2 * (tk * kBfTaskRings + q0 + j) + 1]);
+                b.res_sub.insert(b.res_sub.end(),
+                                 {h[0], imin, h[2], nq, h[4] + q0, h[5], (int)(tk * kBfTaskRings + q0), 0});
+                b.res_exec += (long long)(h[2] - imin) * 64;
+            }
+        }
         // node records, deepest level first, with their launch ranges
         for (int lvl = kBfMaxLv; lvl >= 1; lvl--) {
             b.lv_off[(size_t)bt * (kBfMaxLv + 1) + kBfMaxLv - lvl] = (long long)b.node_i.size() / kBfNodeInts;
@@ -583,6 +598,9 @@ int build_butterfly(sht_plan_s *p, const BflyInput &in) {
         b.lv_off[(size_t)bt * (kBfMaxLv + 1) + kBfMaxLv] = (long long)b.node_i.size() / kBfNodeInts;
     }
     b.batch_task[nb] = (long long)b.res_task.size() / 8;
+    b.batch_sub[nb] = (long long)b.res_sub.size() / 8;
+    if ((long long)b.res_lane.size() / 2 > INT32_MAX)
+        return fail(SHT_EUNSUPPORTED, "butterfly plan exceeds 32-bit lane record offsets");
     b.n_tasks = (long long)b.res_task.size() / 8;
     b.built = 1;
     b.build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

@@ -54,9 +54,13 @@ struct BflyPlan {
     std::vector<int> res_task;        // [tasks][8] t, first row, end row, rings, output entry, m
     std::vector<int> res_lane;        // [tasks*256][2] ring, first row of the ring
     std::vector<double> res_val;      // [tasks*256][2] Legendre values at that row and the next
+    std::vector<int> res_sub;         // [subtasks][8] the tasks cut into 64-ring pieces for the
+                                      // forward kernel: t, first row of the piece, end row,
+                                      // rings, output entry, m, first lane record, 0
     int nbatch = 1;                   // orders m are run in batches m mod nbatch
     std::vector<int> batch_count;     // [nbatch] orders in each batch
     std::vector<long long> batch_task;  // [nbatch+1] residual task ranges
+    std::vector<long long> batch_sub;   // [nbatch+1] sub-task ranges
     std::vector<long long> lv_off;    // [nbatch][kBfMaxLv+1] (+1) node ranges, deepest level first
     std::vector<int16_t> perm;        // per node and child: positions in C of the skeleton
                                       // columns (s order), then of the dense ones (d order)
@@ -127,7 +131,7 @@ struct sht_plan_s {
 
     // ---- butterfly (eps > 0) ------------------------------------------
     sht::BflyPlan bf;
-    int *d_bf_res_task = nullptr, *d_bf_res_lane = nullptr;
+    int *d_bf_res_task = nullptr, *d_bf_res_lane = nullptr, *d_bf_res_sub = nullptr;
     double *d_bf_res_val = nullptr, *d_bf_T = nullptr;
     float *d_bf_T32 = nullptr;
     int16_t *d_bf_perm = nullptr;

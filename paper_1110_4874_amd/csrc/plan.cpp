@@ -527,6 +527,7 @@ int upload_tables(sht_plan_s *p) {
 #define UPB(d, h) \
     if (e == hipSuccess) e = up(&p->d, f.h, &b)
         UPB(d_bf_res_task, res_task);
+        UPB(d_bf_res_sub, res_sub);
         UPB(d_bf_res_lane, res_lane);
         UPB(d_bf_res_val, res_val);
         UPB(d_bf_perm, perm);
@@ -566,7 +567,7 @@ void free_device_tables(sht_plan_s *p) {
                     p->d_ring_off,  p->d_ring_bs_off, p->d_coef_off, p->d_coef_hi,  p->d_coef_lo,
                     p->d_start_idx, p->d_start_val, p->d_start_lo,   p->d_grp_lo,   p->d_grp_hi,
                     p->d_tw,        p->d_bs_table,  p->d_chirp,      p->d_ring_chirp_off,
-                    p->d_bf_res_task, p->d_bf_res_lane,
+                    p->d_bf_res_task, p->d_bf_res_lane, p->d_bf_res_sub,
                     p->d_bf_res_val, p->d_bf_T,      p->d_bf_T32,   p->d_bf_perm,
                     p->d_bf_node_i};
     for (void *q : ptrs)
@@ -583,7 +584,7 @@ void free_device_tables(sht_plan_s *p) {
     p->d_grp_lo = p->d_grp_hi = nullptr;
     p->d_tw = p->d_bs_table = p->d_chirp = nullptr;
     p->d_ring_chirp_off = nullptr;
-    p->d_bf_res_task = p->d_bf_res_lane = nullptr;
+    p->d_bf_res_task = p->d_bf_res_lane = p->d_bf_res_sub = nullptr;
     p->d_bf_res_val = p->d_bf_T = nullptr;
     p->d_bf_T32 = nullptr;
     p->d_bf_perm = nullptr;
