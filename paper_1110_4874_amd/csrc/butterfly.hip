@@ -99,10 +99,12 @@ __device__ __forceinline__ int acc_row(int k4, int r) {
 // since every entry receives exactly two addends onto zero the result does
 // not depend on their order.
 constexpr int kBfKSteps = 2;  // K-steps (4 rows of T each) per batch of loads
+constexpr int kBfHalves = 1;  // waves per child: each takes 4 / kBfHalves of a group's 16-row tiles
 
 template <int NB, typename S>
-__device__ __forceinline__ void id_block(const BfArgs<S> &a, int node, int ch, int lane, S *u) {
+__device__ __forceinline__ void id_block(const BfArgs<S> &a, int node, int ch, int half, int lane, S *u) {
     constexpr int NC = 2 * NB;
+    constexpr int TPW = 4 / kBfHalves;  // tiles per wave
     typedef typename Acc<S>::type acc_t;
     const int *ni = a.node_i + (size_t)node * kBfNodeInts;
     const int n = ni[2] + ni[4];
@@ -112,27 +114,29 @@ __device__ __forceinline__ void id_block(const BfArgs<S> &a, int node, int ch, i
     const long long toff = (long long)(unsigned)ni[12 + 2 * ch] | ((long long)ni[13 + 2 * ch] << 32);
     const S *__restrict__ Tb = a.T + toff;
     // identity rows
-    for (int e = lane; e < kk * NC; e += 64) {
+    for (int e = lane + 64 * half; e < kk * NC; e += 64 * kBfHalves) {
         const int s = e / NC, q = e - s * NC;
         atomicAdd(&u[pm[s] * NC + q], v[(unsigned)e]);
     }
     // dense rows (32-bit element offsets from wave-uniform bases)
     const int i16 = lane & 15, k4 = lane >> 4;
     for (int g0 = 0; g0 < nd; g0 += 64) {
-        const int ntile = min(4, (nd - g0 + 15) >> 4);
-        acc_t acc[4];
+        const int ntile = min(4, (nd - g0 + 15) >> 4) - half * TPW;  // tiles of this wave
+        if (ntile <= 0) continue;
+        const int gw = g0 + 16 * TPW * half;
+        acc_t acc[TPW];
 #pragma unroll
-        for (int tt = 0; tt < 4; tt++) acc[tt] = acc_t{0, 0, 0, 0};
+        for (int tt = 0; tt < TPW; tt++) acc[tt] = acc_t{0, 0, 0, 0};
         for (int s0 = 0; s0 < kk; s0 += 4 * kBfKSteps) {
-            S av[kBfKSteps][4], bv[kBfKSteps];
+            S av[kBfKSteps][TPW], bv[kBfKSteps];
 #pragma unroll
             for (int j = 0; j < kBfKSteps; j++) {
                 const int s = s0 + 4 * j + k4;
                 const bool sv = s < kk;
                 bv[j] = (sv && i16 < NC) ? v[(unsigned)(s * NC + i16)] : (S)0;
 #pragma unroll
-                for (int tt = 0; tt < 4; tt++) {
-                    const int d = g0 + 16 * tt + i16;
+                for (int tt = 0; tt < TPW; tt++) {
+                    const int d = gw + 16 * tt + i16;
                     av[j][tt] = (sv && d < nd) ? Tb[(unsigned)(s * nd + d)] : (S)0;
                 }
             }
@@ -141,16 +145,16 @@ __device__ __forceinline__ void id_block(const BfArgs<S> &a, int node, int ch, i
             for (int j = 0; j < kBfKSteps; j++) {
                 if (j >= nj) break;
 #pragma unroll
-                for (int tt = 0; tt < 4; tt++)
+                for (int tt = 0; tt < TPW; tt++)
                     if (tt < ntile) acc[tt] = mfma_16x16x4(av[j][tt], bv[j], acc[tt]);
             }
         }
 #pragma unroll
-        for (int tt = 0; tt < 4; tt++) {
+        for (int tt = 0; tt < TPW; tt++) {
             if (tt >= ntile) break;
 #pragma unroll
             for (int r = 0; r < 4; r++) {
-                const int dd = g0 + 16 * tt + acc_row<S>(k4, r);
+                const int dd = gw + 16 * tt + acc_row<S>(k4, r);
                 if (dd < nd && i16 < NC) atomicAdd(&u[pm[kk + dd] * NC + i16], acc[tt][r]);
             }
         }
@@ -243,22 +247,26 @@ __global__ __launch_bounds__(kBfThreads) void k_bf_residual(BfArgs<S> a, long lo
     residual_task<NB, 1>(a, a.ws, lbase, lane, t, imin, iend, nl, outb, ap, cfs, astride);
 }
 
-// One workgroup of two waves per pair node: u (zeroed in LDS) collects both
-// children, then goes to the next level's vector in one coalesced store.
+// One workgroup of 2 kBfHalves waves per pair node (wave w: child w % 2,
+// half w / 2): u (zeroed in LDS) collects both children, then goes to the
+// next level's vector in one coalesced store.
+constexpr int kBfLevelThreads = 128 * kBfHalves;
+
 template <int NB, typename S>
-__global__ __launch_bounds__(128) void k_bf_level(BfArgs<S> a, long long n0) {
+__global__ __launch_bounds__(kBfLevelThreads) void k_bf_level(BfArgs<S> a, long long n0) {
     constexpr int NC = 2 * NB;
     extern __shared__ char lds_raw[];
     S *u = reinterpret_cast<S *>(lds_raw);
     const int node = (int)(n0 + blockIdx.x);
     const int *ni = a.node_i + (size_t)node * kBfNodeInts;
     const int n = ni[2] + ni[4];
-    for (int e = threadIdx.x; e < n * NC; e += 128) u[e] = (S)0;
+    for (int e = threadIdx.x; e < n * NC; e += kBfLevelThreads) u[e] = (S)0;
     __syncthreads();
-    id_block<NB, S>(a, node, __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), threadIdx.x & 63, u);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    id_block<NB, S>(a, node, w & 1, w >> 1, threadIdx.x & 63, u);
     __syncthreads();
     S *__restrict__ out = a.ws + (size_t)ni[6] * NC;
-    for (int e = threadIdx.x; e < n * NC; e += 128) out[e] = u[e];
+    for (int e = threadIdx.x; e < n * NC; e += kBfLevelThreads) out[e] = u[e];
 }
 
 // Fold of one batch: slot j of the batch holds order m = batch + j nbatch.
@@ -319,7 +327,8 @@ __global__ __launch_bounds__(kBfThreads) void k_bf_unfold(BfArgs<S> a, int batch
 constexpr int kBfTJ = 2;  // K-steps per batch of loads in the transposed level
 
 template <int NB, typename S>
-__device__ __forceinline__ void id_block_t(const BfArgs<S> &a, int node, int ch, int lane, const S *u) {
+__device__ __forceinline__ void id_block_t(const BfArgs<S> &a, int node, int ch, int half, int lane, const S *u) {
+    constexpr int TPW = 4 / kBfHalves;  // 16-row tiles per wave
     constexpr int NC = 2 * NB;
     constexpr int DB = 4 * kBfTJ;  // dense columns per batch
     typedef typename Acc<S>::type acc_t;
@@ -331,20 +340,22 @@ __device__ __forceinline__ void id_block_t(const BfArgs<S> &a, int node, int ch,
     const long long toff = (long long)(unsigned)ni[12 + 2 * ch] | ((long long)ni[13 + 2 * ch] << 32);
     const S *__restrict__ Tb = a.T + toff;
     const int i16 = lane & 15, k4 = lane >> 4;
-    for (int s0 = 0; s0 < kk; s0 += 64) {
-        const int ntile = min(4, (kk - s0 + 15) >> 4);
-        acc_t acc[4];
+    for (int s00 = 0; s00 < kk; s00 += 64) {
+        const int ntile = min(4, (kk - s00 + 15) >> 4) - half * TPW;  // tiles of this wave
+        if (ntile <= 0) continue;
+        const int s0 = s00 + 16 * TPW * half;
+        acc_t acc[TPW];
 #pragma unroll
-        for (int tt = 0; tt < 4; tt++) acc[tt] = acc_t{0, 0, 0, 0};
+        for (int tt = 0; tt < TPW; tt++) acc[tt] = acc_t{0, 0, 0, 0};
         for (int d0 = 0; d0 < nd; d0 += DB) {
-            S av[4][kBfTJ], bv[kBfTJ];
+            S av[TPW][kBfTJ], bv[kBfTJ];
 #pragma unroll
             for (int j = 0; j < kBfTJ; j++) {
                 const int d = d0 + kBfTJ * k4 + j;
                 const bool dv = d < nd;
                 bv[j] = (dv && i16 < NC) ? u[pm[kk + d] * NC + i16] : (S)0;
 #pragma unroll
-                for (int tt = 0; tt < 4; tt++) {
+                for (int tt = 0; tt < TPW; tt++) {
                     const int sr = s0 + 16 * tt + i16;
                     av[tt][j] = (dv && sr < kk) ? Tb[(unsigned)(sr * nd + d)] : (S)0;
                 }
@@ -352,11 +363,11 @@ __device__ __forceinline__ void id_block_t(const BfArgs<S> &a, int node, int ch,
 #pragma unroll
             for (int j = 0; j < kBfTJ; j++)
 #pragma unroll
-                for (int tt = 0; tt < 4; tt++)
+                for (int tt = 0; tt < TPW; tt++)
                     if (tt < ntile) acc[tt] = mfma_16x16x4(av[tt][j], bv[j], acc[tt]);
         }
 #pragma unroll
-        for (int tt = 0; tt < 4; tt++) {
+        for (int tt = 0; tt < TPW; tt++) {
             if (tt >= ntile) break;
 #pragma unroll
             for (int r = 0; r < 4; r++) {
@@ -367,10 +378,10 @@ __device__ __forceinline__ void id_block_t(const BfArgs<S> &a, int node, int ch,
     }
 }
 
-// One workgroup of two waves per pair node: u is staged in LDS, then wave ch
-// writes child ch's vector.
+// One workgroup of 2 kBfHalves waves per pair node: u is staged in LDS, then
+// wave w writes half w / 2 of the rows of child w % 2's vector.
 template <int NB, typename S>
-__global__ __launch_bounds__(128) void k_bf_level_t(BfArgs<S> a, long long n0) {
+__global__ __launch_bounds__(kBfLevelThreads) void k_bf_level_t(BfArgs<S> a, long long n0) {
     constexpr int NC = 2 * NB;
     extern __shared__ char lds_raw[];
     S *u = reinterpret_cast<S *>(lds_raw);
@@ -378,9 +389,10 @@ __global__ __launch_bounds__(128) void k_bf_level_t(BfArgs<S> a, long long n0) {
     const int *ni = a.node_i + (size_t)node * kBfNodeInts;
     const int n = ni[2] + ni[4];
     const S *__restrict__ in = a.ws + (size_t)ni[6] * NC;
-    for (int e = threadIdx.x; e < n * NC; e += 128) u[e] = in[e];
+    for (int e = threadIdx.x; e < n * NC; e += kBfLevelThreads) u[e] = in[e];
     __syncthreads();
-    id_block_t<NB, S>(a, node, __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), threadIdx.x & 63, u);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    id_block_t<NB, S>(a, node, w & 1, w >> 1, threadIdx.x & 63, u);
 }
 
 // Lane exchanges for the wave reductions.  permlane32_swap(a, b) leaves
@@ -584,7 +596,7 @@ static hipError_t launch_bf_nb(const sht_plan_s *p, BfArgs<S> a, hipStream_t st)
         for (int q = 0; q < kBfMaxLv; q++) {
             const long long n0 = lo[q], n1 = lo[q + 1];
             if (n1 <= n0) continue;
-            hipLaunchKernelGGL((k_bf_level<NB, S>), dim3((unsigned)(n1 - n0)), dim3(128),
+            hipLaunchKernelGGL((k_bf_level<NB, S>), dim3((unsigned)(n1 - n0)), dim3(kBfLevelThreads),
                                (size_t)b.max_n * 2 * NB * sizeof(S), st, a, n0);
         }
         const long long nf = (long long)b.batch_count[bt] * b.K * NB;
@@ -649,7 +661,7 @@ static hipError_t launch_bf_adj_nb(const sht_plan_s *p, BfArgs<S> a, hipStream_t
         for (int q = kBfMaxLv - 1; q >= 0; q--) {
             const long long n0 = lo[q], n1 = lo[q + 1];
             if (n1 <= n0) continue;
-            hipLaunchKernelGGL((k_bf_level_t<NB, S>), dim3((unsigned)(n1 - n0)), dim3(128),
+            hipLaunchKernelGGL((k_bf_level_t<NB, S>), dim3((unsigned)(n1 - n0)), dim3(kBfLevelThreads),
                                (size_t)b.max_n * 2 * NB * sizeof(S), st, a, n0);
         }
         const long long t0 = b.batch_task[bt], t1 = b.batch_task[bt + 1];
