@@ -163,12 +163,25 @@ __device__ __forceinline__ void id_block(const BfArgs<S> &a, int node, int ch, i
 
 // One residual piece on one wave: R rings per lane (lane j: rings j + 64 r,
 // lane records from lbase), rows [imin, iend) of one parity, outputs at
-// entries outb + ring.
+// entries outb + ring.  The a_lm rows and recurrence coefficients of each
+// aligned chunk of kChunk rows are fetched one chunk ahead with coalesced
+// vector loads and staged in the wave's own LDS slot (stg: two chunks), from
+// where every lane reads them as broadcasts; LDS operations of one wave
+// complete in order, so no barrier is needed.
+template <int NB>
+constexpr int bf_res_stage_doubles() {
+    return 2 * kChunk * (2 * NB + 4);
+}
+
 template <int NB, int R, typename S>
 __device__ __forceinline__ void residual_task(const BfArgs<S> &a, S *__restrict__ slot, long long lbase, int lane,
-                                              int t, int imin, int iend, int nl, int outb, c_double *ap,
-                                              c_double *cfs, int astride) {
+                                              int t, int imin, int iend, int nl, int outb,
+                                              const double *__restrict__ ap, const double *__restrict__ cfs,
+                                              int astride, double *stg) {
     constexpr int NC = 2 * NB;
+    constexpr int CW = NC + 4;          // per row: a_lm components, then B, AB, G and a pad
+    constexpr int CS = kChunk * CW;     // doubles per staged chunk
+    constexpr int E = (CS + 63) / 64;   // staged doubles per lane
     int i0[R];
     double z2[R], v0[R], v1[R], P0[R], P1[R], acc[R][NC];
 #pragma unroll
@@ -184,13 +197,33 @@ __device__ __forceinline__ void residual_task(const BfArgs<S> &a, S *__restrict_
 #pragma unroll
         for (int c = 0; c < NC; c++) acc[r][c] = 0.0;
     }
-    auto step = [&](int i) {
-        c_double *ai = ap + (size_t)i * astride;
-        c_double *e = cfs + 4 * (t + 2 * i + 2);
-        const double eb = e[0], eab = e[1], eg = e[2];
+    double pre[E];
+    auto fetch = [&](int c0) {
+#pragma unroll
+        for (int e = 0; e < E; e++) {
+            const int idx = lane + 64 * e, i = c0 + idx / CW, comp = idx % CW;
+            double v = 0.0;
+            if (idx < CS && i < iend) {
+                if (comp < NC)
+                    v = ap[(size_t)i * astride + comp];
+                else if (comp < NC + 3)
+                    v = cfs[4 * (t + 2 * i + 2) + comp - NC];
+            }
+            pre[e] = v;
+        }
+    };
+    auto stage = [&](int sl) {
+#pragma unroll
+        for (int e = 0; e < E; e++) {
+            const int idx = lane + 64 * e;
+            if (idx < CS) stg[sl * CS + idx] = pre[e];
+        }
+    };
+    auto step = [&](const double *row) {
         double av[NC];
 #pragma unroll
-        for (int c = 0; c < NC; c++) av[c] = ai[c];
+        for (int c = 0; c < NC; c++) av[c] = row[c];
+        const double eb = row[NC], eab = row[NC + 1], eg = row[NC + 2];
 #pragma unroll
         for (int r = 0; r < R; r++) {
 #pragma unroll
@@ -200,21 +233,29 @@ __device__ __forceinline__ void residual_task(const BfArgs<S> &a, S *__restrict_
             P1[r] = P2;
         }
     };
-    for (int c = imin; c < iend;) {
+    int c0 = imin & ~(kChunk - 1), sl = 0;
+    fetch(c0);
+    stage(0);
+    if (c0 + kChunk < iend) fetch(c0 + kChunk);
+    for (; c0 < iend; c0 += kChunk, sl ^= 1) {
+        const int cs = max(c0, imin), ce = min(iend, c0 + kChunk);
 #pragma unroll
         for (int r = 0; r < R; r++)
-            if (i0[r] == c) {
+            if (i0[r] == cs) {
                 P0[r] = v0[r];
                 P1[r] = v1[r];
             }
-        const int ce = min(iend, (c & ~(kChunk - 1)) + kChunk);
-        if (ce - c == kChunk) {
+        const double *cur = stg + sl * CS;
+        if (cs == c0 && ce - c0 == kChunk) {
 #pragma unroll
-            for (int u = 0; u < kChunk; u++) step(c + u);
+            for (int u = 0; u < kChunk; u++) step(cur + u * CW);
         } else {
-            for (int i = c; i < ce; i++) step(i);
+            for (int i = cs; i < ce; i++) step(cur + (i - c0) * CW);
         }
-        c = ce;
+        if (c0 + kChunk < iend) {
+            stage(sl ^ 1);
+            if (c0 + 2 * kChunk < iend) fetch(c0 + 2 * kChunk);
+        }
     }
 #pragma unroll
     for (int r = 0; r < R; r++) {
@@ -232,8 +273,10 @@ __device__ __forceinline__ void residual_task(const BfArgs<S> &a, S *__restrict_
 // the one-ring case.
 template <int NB, typename S>
 __global__ __launch_bounds__(kBfThreads) void k_bf_residual(BfArgs<S> a, long long t0, long long t1) {
+    __shared__ double stg_all[kBfThreads / 64][bf_res_stage_doubles<NB>()];
     const int lane = threadIdx.x & 63;
-    const long long tk = t0 + (long long)blockIdx.x * (kBfThreads / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const long long tk = t0 + (long long)blockIdx.x * (kBfThreads / 64) + w;
     if (tk >= t1) return;
     const int4 h = a.res_sub[2 * tk], h2 = a.res_sub[2 * tk + 1];
     const int t = __builtin_amdgcn_readfirstlane(h.x), imin = __builtin_amdgcn_readfirstlane(h.y);
@@ -241,10 +284,10 @@ __global__ __launch_bounds__(kBfThreads) void k_bf_residual(BfArgs<S> a, long lo
     const int outb = __builtin_amdgcn_readfirstlane(h2.x), m = __builtin_amdgcn_readfirstlane(h2.y);
     const long long lbase = (unsigned)__builtin_amdgcn_readfirstlane(h2.z);
     const size_t aoff = (size_t)m * (2 * a.L + 3 - m) / 2;
-    c_double *ap = (c_double *)(a.alm + (aoff + t) * a.nmaps + a.map0);
-    c_double *cfs = (c_double *)(a.coef + 4 * a.coef_off[m]);
+    const double *ap = reinterpret_cast<const double *>(a.alm + (aoff + t) * a.nmaps + a.map0);
+    const double *cfs = a.coef + 4 * a.coef_off[m];
     const int astride = 4 * a.nmaps;  // doubles between rows i and i+1
-    residual_task<NB, 1>(a, a.ws, lbase, lane, t, imin, iend, nl, outb, ap, cfs, astride);
+    residual_task<NB, 1>(a, a.ws, lbase, lane, t, imin, iend, nl, outb, ap, cfs, astride, stg_all[w]);
 }
 
 // One workgroup of 2 kBfHalves waves per pair node (wave w: child w % 2,
