@@ -97,7 +97,7 @@ typedef struct sht_plan_opts {
     int rings_per_lane;/* rings each lane of the FP64 Legendre kernel owns:
                           1, 2 or 4 (0 = default 2); a tuning knob */
     int ring_threads;  /* workgroup size of the ring FFT kernel: 256, 512 or
-                          1024 (0 = default 1024); a tuning knob */
+                          1024 (0 = default 512); a tuning knob */
     int host_only;     /* 1: build host tables only (no device memory); such a
                           plan can be inspected but not executed */
     /* Butterfly compression (eps > 0 plans only; Sec. 4.2 and 4.4): */

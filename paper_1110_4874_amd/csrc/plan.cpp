@@ -331,7 +331,7 @@ int build_host_tables(sht_plan_s *p) {
     const int L = p->L, N = p->nside;
     const int nth = p->opts.nthreads;
     p->rings_per_lane = (p->opts.rings_per_lane == 1 || p->opts.rings_per_lane == 4) ? p->opts.rings_per_lane : 2;
-    p->ring_threads = (p->opts.ring_threads == 256 || p->opts.ring_threads == 512) ? p->opts.ring_threads : 1024;
+    p->ring_threads = (p->opts.ring_threads == 256 || p->opts.ring_threads == 1024) ? p->opts.ring_threads : 512;
     p->nrings = 4 * N - 1;
     p->n_north = 2 * N;
     p->n_north_pad = (p->n_north + kLanes - 1) / kLanes * kLanes;
@@ -427,23 +427,26 @@ int build_host_tables(sht_plan_s *p) {
             maxS = std::max(maxS, n);
             continue;
         }
-        int M = 1 << ilog2(2LL * n - 1);
+        // n = J/2 is even (J = 4i or 4 nside); the kernels split the DFT into
+        // its even and odd halves and run Bluestein on length h = n/2
+        const int h = n / 2;
+        int M = 1 << ilog2(2LL * h - 1);
         p->ring_M[r] = M;
         maxS = std::max(maxS, M);
-        if (bs_of_n[n] < 0) {
-            bs_of_n[n] = bs_total;
-            chirp_of_n[n] = chirp_total;
-            bctx.ns.push_back(n);
+        if (bs_of_n[h] < 0) {
+            bs_of_n[h] = bs_total;
+            chirp_of_n[h] = chirp_total;
+            bctx.ns.push_back(h);
             bctx.offs.push_back(bs_total);
             bctx.coffs.push_back(chirp_total);
             bs_total += M;
-            chirp_total += n;
+            chirp_total += h;
         }
-        p->ring_bs_off[r] = bs_of_n[n];
-        p->ring_chirp_off[r] = chirp_of_n[n];
+        p->ring_bs_off[r] = bs_of_n[h];
+        p->ring_chirp_off[r] = chirp_of_n[h];
     }
-    if (maxS > 8192)
-        return fail(SHT_EUNSUPPORTED, "ring FFT larger than the 8192-point LDS limit (nside > 2048)");
+    if (maxS > 8192 || N > 2048)
+        return fail(SHT_EUNSUPPORTED, "ring FFT larger than the kernels' limit (nside > 2048)");
     p->bs_table.assign(2 * (size_t)std::max(bs_total, 1LL), 0.0);
     p->chirp.assign(2 * (size_t)std::max(chirp_total, 1LL), 0.0);
     parallel_for((long)bctx.ns.size(), nth, bs_worker, &bctx);

@@ -16,9 +16,13 @@
 // and reduce bin sums in a fixed order (deterministic, no atomics).  The
 // half-length DFT runs in LDS with in-place radix-8 passes (radix-4/2 for the
 // remainder): decimation in time on bit-reversed input when n is a power of
-// two, otherwise Bluestein's chirp convolution with a power-of-two M >= 2n-1
-// (forward decimation in frequency, pointwise product with the plan's chirp
-// spectrum, backward decimation in time).  LDS indices are padded by one
+// two.  Otherwise n = 2h (J is a multiple of 4) and the DFT is split into its
+// even- and odd-index halves, two length-h DFTs run one after the other in
+// the same buffer by Bluestein's chirp convolution with a power-of-two
+// M >= 2h-1 (forward decimation in frequency, pointwise product with the
+// plan's chirp spectrum, backward decimation in time), the first result
+// waiting in registers; z_p = A_p + w^p B_p, z_{p+h} = A_p - w^p B_p with
+// w = e^{2 pi i/n}.  This halves the LDS of the longest polar rings.  LDS indices are padded by one
 // entry per 16 to spread strided accesses over the banks.  One workgroup
 // owns one (ring, map); the maps of a ring are adjacent in the ring-major q
 // layout and their workgroups run back to back on the same XCD (dispatch is
@@ -54,6 +58,7 @@ struct RingArgs {
 
 constexpr int kMaxStage = 2048;     // staged q entries per chunk (at most)
 constexpr int kMaxPairs = 2049;     // Hermitian bin pairs of the largest ring (n = 4096)
+constexpr int kMaxHalf = 2048;      // half length h of the largest Bluestein ring (n = 2h <= 4096)
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -268,9 +273,6 @@ __global__ __launch_bounds__(T) void k_ring_synth(RingArgs a) {
     const size_t qstride = (size_t)a.nmaps;
     const double2 *qr = a.q + (size_t)rho * (L + 1) * a.nmaps + b;
 
-    if (bs)
-        for (int i = n + tid; i < M; i += T) buf[pidx(i)] = make_double2(0.0, 0.0);
-
     // raw bin sums for the pairs (k, n-k) owned by this thread
     double2 xa[kPairsPerThread], xb[kPairsPerThread];
 #pragma unroll
@@ -338,7 +340,10 @@ __global__ __launch_bounds__(T) void k_ring_synth(RingArgs a) {
         }
     }
 
-    // phase shift, Hermitian pre-twiddle, store into the DFT input
+    // phase shift, Hermitian pre-twiddle, store into the DFT input: natural
+    // bit-reversed order for power-of-two n; for split Bluestein rings even k
+    // at k/2 and odd k at h + (k-1)/2 (n = 2h), weighted by the chirp
+    const int h = n / 2;
 #pragma unroll
     for (int j = 0; j < kPairsPerThread; j++) {
         const int k = tid + j * T;
@@ -365,16 +370,58 @@ __global__ __launch_bounds__(T) void k_ring_synth(RingArgs a) {
             buf[pidx(bitrev(k, lgn))] = Zk;
             if (two) buf[pidx(bitrev(n - k, lgn))] = Znk;
         } else {
-            buf[pidx(k)] = cmul(Zk, W[k]);
-            if (two) buf[pidx(n - k)] = cmul(Znk, W[n - k]);
+            const int odd = k & 1, kp = (k - odd) / 2;
+            buf[pidx(kp + odd * h)] = cmul(Zk, W[kp]);
+            if (two) {
+                const int kq = (n - k - odd) / 2;
+                buf[pidx(kq + odd * h)] = cmul(Znk, W[kq]);
+            }
         }
     }
     __syncthreads();
-
-    backward_dft<T>(buf, n, M, a.bs_table + (bs ? a.ring_bs_off[rho] : 0), W, a.tw, a.tw_log);
     // pixel 2p = Re z_p, pixel 2p+1 = Im z_p
     double2 *out = reinterpret_cast<double2 *>(a.map + (size_t)b * a.npix + a.ring_off[rho]);
-    for (int p = tid; p < n; p += T) out[p] = buf[pidx(p)];
+    if (!bs) {
+        backward_dft<T>(buf, n, 0, nullptr, nullptr, a.tw, a.tw_log);
+        for (int p = tid; p < n; p += T) out[p] = buf[pidx(p)];
+        return;
+    }
+
+    // split Bluestein: the odd half waits in registers while the even half
+    // (A) is transformed, then A waits while the odd half (B) is
+    constexpr int kHalfPerThread = (kMaxHalf + T - 1) / T;
+    const double2 *__restrict__ V = a.bs_table + a.ring_bs_off[rho];
+    double2 R[kHalfPerThread];
+#pragma unroll
+    for (int jj = 0; jj < kHalfPerThread; jj++) {
+        const int p = tid + jj * T;
+        if (p < h) R[jj] = buf[pidx(h + p)];
+    }
+    __syncthreads();
+    for (int i = h + tid; i < M; i += T) buf[pidx(i)] = make_double2(0.0, 0.0);
+    __syncthreads();
+    backward_dft<T>(buf, h, M, V, W, a.tw, a.tw_log);
+#pragma unroll
+    for (int jj = 0; jj < kHalfPerThread; jj++) {
+        const int p = tid + jj * T;
+        if (p < h) {
+            const double2 odd_in = R[jj];
+            R[jj] = buf[pidx(p)];  // A_p
+            buf[pidx(p)] = odd_in;
+        }
+    }
+    for (int i = h + tid; i < M; i += T) buf[pidx(i)] = make_double2(0.0, 0.0);
+    __syncthreads();
+    backward_dft<T>(buf, h, M, V, W, a.tw, a.tw_log);
+#pragma unroll
+    for (int jj = 0; jj < kHalfPerThread; jj++) {
+        const int p = tid + jj * T;
+        if (p < h) {
+            const double2 t = cmul(buf[pidx(p)], expipi(2.0 * p / n));
+            out[p] = cadd(R[jj], t);
+            out[p + h] = csub(R[jj], t);
+        }
+    }
 }
 
 template <int T>
@@ -389,9 +436,11 @@ static hipError_t launch_classes(const sht_plan_s *p, RingArgs a, int nmaps, hip
         a.rings = rc.d_rings;
         a.count = (int)rc.rings.size();
         a.fft_entries = rc.lds_entries + rc.lds_entries / 16;
-        // staging chunk: as much of the 160 KiB LDS as the FFT buffer leaves
-        const int room = (int)(160 * 1024 / sizeof(double2)) - a.fft_entries;
-        a.stage = std::min(kMaxStage, room / T * T);
+        // staging chunk: what the FFT buffer leaves of 80 KiB (two workgroups
+        // per CU) when that is at least a quarter of the block, else of 160 KiB
+        const int cap2 = (int)(80 * 1024 / sizeof(double2));
+        const int room = (a.fft_entries + T / 4 <= cap2 ? cap2 : (int)(160 * 1024 / sizeof(double2))) - a.fft_entries;
+        a.stage = std::min(kMaxStage, room >= T ? room / T * T : room);
         long long grid = ((long long)a.count * nmaps + 63) / 64 * 64;
         size_t lds = (size_t)(a.fft_entries + (rc.wrap ? a.stage : 0)) * sizeof(double2);
         hipLaunchKernelGGL(k_ring_synth<T>, dim3((unsigned)grid), dim3(T), lds, stream, a);
@@ -457,19 +506,45 @@ __global__ __launch_bounds__(T) void k_ring_analysis(RingArgs a) {
     const size_t qstride = (size_t)a.nmaps;
     double2 *yr = a.ybar + (size_t)rho * (L + 1) * a.nmaps + b;
 
-    if (bs)
-        for (int i = n + tid; i < M; i += T) buf[pidx(i)] = make_double2(0.0, 0.0);
     const double2 *pix = reinterpret_cast<const double2 *>(a.map_in + (size_t)b * a.npix + a.ring_off[rho]);
-    for (int p = tid; p < n; p += T) {
-        const double2 zc = cconj(pix[p]);
-        if (!bs) {
-            buf[pidx(bitrev(p, lgn))] = zc;
-        } else {
-            buf[pidx(p)] = cmul(zc, W[p]);
+    if (!bs) {
+        for (int p = tid; p < n; p += T) buf[pidx(bitrev(p, lgn))] = cconj(pix[p]);
+        __syncthreads();
+        backward_dft<T>(buf, n, 0, nullptr, nullptr, a.tw, a.tw_log);
+    } else {
+        // split Bluestein: even inputs (hh = 0), then odd inputs (hh = 1)
+        constexpr int kHalfPerThread = (kMaxHalf + T - 1) / T;
+        const int h = n / 2;
+        const double2 *__restrict__ V = a.bs_table + a.ring_bs_off[rho];
+        double2 A[kHalfPerThread];
+        for (int hh = 0; hh < 2; hh++) {
+            for (int i = h + tid; i < M; i += T) buf[pidx(i)] = make_double2(0.0, 0.0);
+            for (int p = tid; p < h; p += T) buf[pidx(p)] = cmul(cconj(pix[2 * p + hh]), W[p]);
+            __syncthreads();
+            backward_dft<T>(buf, h, M, V, W, a.tw, a.tw_log);
+            if (hh == 0) {
+#pragma unroll
+                for (int jj = 0; jj < kHalfPerThread; jj++) {
+                    const int p = tid + jj * T;
+                    if (p < h) A[jj] = buf[pidx(p)];
+                }
+                __syncthreads();
+            }
         }
+        // Z_p = A_p + w^p B_p and Z_{p+h} = A_p - w^p B_p in place (each
+        // thread reads B_p before writing p and p + h, which no other thread
+        // reads)
+#pragma unroll
+        for (int jj = 0; jj < kHalfPerThread; jj++) {
+            const int p = tid + jj * T;
+            if (p < h) {
+                const double2 t = cmul(buf[pidx(p)], expipi(2.0 * p / n));
+                buf[pidx(p)] = cadd(A[jj], t);
+                buf[pidx(p + h)] = csub(A[jj], t);
+            }
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    backward_dft<T>(buf, n, M, a.bs_table + (bs ? a.ring_bs_off[rho] : 0), W, a.tw, a.tw_log);
 
     // bins b = 0..n, split over G groups of the residue classes for small rings
     const int nb = n + 1;
