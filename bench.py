@@ -34,32 +34,36 @@ METRIC = "L=4095 synthesis maps/s: butterfly vs brute-force, FP64 vs FP32-MFMA, 
 FP64_PEAK_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 flops x 2.4 GHz (vector FMA)
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
-LEGENDRE_SRC = os.path.join(ROOT, "paper_1110_4874_amd", "csrc", "legendre.hip")
+CSRC = os.path.join(ROOT, "paper_1110_4874_amd", "csrc")
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_source_sha():
-    with open(LEGENDRE_SRC, "rb") as fh:
+def source_sha(src):
+    with open(os.path.join(CSRC, src), "rb") as fh:
         return hashlib.sha256(fh.read()).hexdigest()
 
 
-def measured_traffic(L, nside, nmaps):
-    """HBM bytes per Legendre launch from the committed rocprofv3 counter
+def measured_traffic(kernel, L, nside, nmaps):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary, if it was taken on the current kernel source and workload."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     try:
-        rec = json.load(open(TRAFFIC_FILE))
-    except ValueError:
+        recs = json.load(open(TRAFFIC_FILE)).get("records", [])
+    except (ValueError, AttributeError):
         return None
-    if rec.get("source_sha256") != kernel_source_sha():
-        return None
-    if (rec.get("L"), rec.get("nside"), rec.get("nmaps")) != (L, nside, nmaps):
-        return None
-    return rec.get("bytes_per_launch")
+    for rec in recs:
+        if not rec.get("kernel", "").startswith(kernel):
+            continue
+        if rec.get("source_sha256") != source_sha(rec.get("source", "")):
+            return None
+        if (rec.get("L"), rec.get("nside"), rec.get("nmaps")) != (L, nside, nmaps):
+            return None
+        return rec.get("bytes_per_launch")
+    return None
 
 
 def batch_bench(np, torch, sht, steps):
@@ -279,6 +283,11 @@ def main():
         ring_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in ev_sets]))
         results[name] = {"maps_per_s": B * args.steps / elapsed, "ms_per_step": 1e3 * elapsed / args.steps,
                          "legendre_ms": leg_ms, "ring_ms": ring_ms}
+        if path == sht.PATH_BUTTERFLY and info["bf_nbatch"] == 1:
+            # the residual launch and the level launches, bracketed inside the stage
+            s8, s10 = 2 * sht.STAGE_BF_RESIDUAL, 2 * sht.STAGE_BF_LEVELS
+            results[name]["residual_ms"] = float(np.mean([e[s8].elapsed_time(e[s8 + 1]) for e in ev_sets]))
+            results[name]["levels_ms"] = float(np.mean([e[s10].elapsed_time(e[s10 + 1]) for e in ev_sets]))
         maps_out[name] = out.cpu().numpy()
         log(f"[bench] {name}: {results[name]['ms_per_step']:.3f} ms/step, legendre {leg_ms:.3f} ms, "
             f"ring {ring_ms:.3f} ms")
@@ -287,20 +296,40 @@ def main():
     q_bytes = (L + 1) * plan.nrings * B * 16
     alm_bytes = plan.nalm * B * 16
 
+    # level launches per pass: one per depth that any (m, parity) reaches
+    nlev = max([d for d, c in enumerate(info["bf_depth_hist"]) if c > 0] + [0]) if info["bf_built"] else 0
+
     def path_roofline(name):
         r = results[name]
         if name == "brute":
             achieved = flops / (r["legendre_ms"] * 1e-3) / 1e12
-            return {"kernel": "k_legendre (brute-force Legendre phase)", "bound": "alu",
+            return {"kernel": "k_legendre (brute-force Legendre phase, one launch)", "bound": "alu",
                     "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                     "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
-                    "traffic": measured_traffic(L, N, B), "flops_per_launch": flops}
-        tb = info["bf_T_entries"] * (8 if name == "bf64" else 4)
-        nbytes = tb + alm_bytes + q_bytes
-        achieved = nbytes / (r["legendre_ms"] * 1e-3) / 1e9
-        return {"kernel": "butterfly stage (k_bf_residual + k_bf_level + k_bf_fold)", "bound": "hbm",
-                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "bytes_per_launch": nbytes}
+                    "traffic": measured_traffic("void sht::k_legendre<", L, N, B), "flops_per_launch": flops}
+        sz = 8 if name == "bf64" else 4
+        if "levels_ms" not in r or nlev == 0:
+            nbytes = info["bf_T_entries"] * sz + alm_bytes + q_bytes
+            achieved = nbytes / (r["legendre_ms"] * 1e-3) / 1e9
+            return {"kernel": "butterfly stage (k_bf_residual + k_bf_level + k_bf_fold)", "bound": "hbm",
+                    "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "bytes_per_launch": nbytes}
+        if r["levels_ms"] >= r["residual_ms"]:
+            # interpolation matrices streamed once, child vectors read and parent vectors written once
+            lvl_bytes = info["bf_T_entries"] * sz + 2 * info["bf_units"] * 2 * B * sz
+            per_launch = lvl_bytes / nlev
+            achieved = per_launch / (r["levels_ms"] / nlev * 1e-3) / 1e9
+            kern = "void sht::k_bf_level<%d, %s>" % (min(B, 8) if B in (1, 2, 4, 8) else 4, "double" if sz == 8 else "float")
+            return {"kernel": f"k_bf_level ({nlev} launches per pass, one per level)", "bound": "hbm",
+                    "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": measured_traffic(kern, L, N, B), "bytes_per_launch": int(per_launch),
+                    "launch_ms": round(r["levels_ms"] / nlev, 4)}
+        rflops = info["bf_res_elems"] * (5 + 4 * B)
+        achieved = rflops / (r["residual_ms"] * 1e-3) / 1e12
+        return {"kernel": "k_bf_residual (one launch)", "bound": "alu", "achieved": round(achieved, 3),
+                "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+                "traffic": None, "flops_per_launch": rflops, "launch_ms": round(r["residual_ms"], 4)}
 
     fp64 = [n for n in results if n != "bf32"]
     head = max(fp64, key=lambda n: results[n]["maps_per_s"])
@@ -355,6 +384,8 @@ def main():
             "maps_per_s": round(r["maps_per_s"], 3), "ms_per_step": round(r["ms_per_step"], 4),
             "legendre_ms": round(r["legendre_ms"], 4), "ring_ms": round(r["ring_ms"], 4),
             "speedup_vs_brute": round(r["maps_per_s"] / results["brute"]["maps_per_s"], 3),
+            **({"residual_ms": round(r["residual_ms"], 4), "levels_ms": round(r["levels_ms"], 4)}
+               if "levels_ms" in r else {}),
             "roofline": path_roofline(name),
         }
     if info["bf_built"]:

@@ -73,7 +73,10 @@ enum {
     SHT_STAGE_RING = 1,          /* synthesis: phase shift, wrap, ring FFT */
     SHT_STAGE_RING_ADJ = 2,      /* adjoint: ring FFT, unwrap, weights */
     SHT_STAGE_LEGENDRE_ADJ = 3,  /* adjoint: transposed Legendre transform */
-    SHT_NSTAGES = 4
+    SHT_STAGE_BF_RESIDUAL = 4,   /* butterfly synthesis: the residual launch */
+    SHT_STAGE_BF_LEVELS = 5,     /* butterfly synthesis: the level launches (from the
+                                    first to the last; recorded for one-batch plans) */
+    SHT_NSTAGES = 6
 };
 
 /* Adjoint conventions (sht_exec_opts.adjoint_convention). */

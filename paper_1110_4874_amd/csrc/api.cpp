@@ -152,7 +152,8 @@ static int synth_stages(const sht_plan_s *p, int B, int path, int precision, con
     if (x) stage_event(x, SHT_STAGE_LEGENDRE, 0);
     if (use_bf(p, path)) {
         void *scr = (char *)ws + q_bytes(p, B);
-        if ((rc = hip_status(launch_butterfly(p, B, alm, q, scr, precision == SHT_PREC_FP32, st),
+        if ((rc = hip_status(launch_butterfly(p, B, alm, q, scr, precision == SHT_PREC_FP32, st,
+                                              x ? x->stage_events : nullptr),
                              "butterfly kernel launch")))
             return rc;
     } else if ((rc = hip_status(launch_legendre(p, B, alm, q, st), "Legendre kernel launch"))) {

@@ -626,15 +626,24 @@ size_t bf_scratch_bytes(const sht_plan_s *p, int nmaps, int fp32) {
     return (size_t)p->bf.ws_entries * 2 * bf_nb(nmaps) * (fp32 ? sizeof(float) : sizeof(double));
 }
 
+// Records the caller's stage event (which = 0 before, 1 after) if given.
+static void bf_event(void *const *ev, int stage, int which, hipStream_t st) {
+    if (ev && ev[2 * stage + which]) (void)hipEventRecord((hipEvent_t)ev[2 * stage + which], st);
+}
+
 template <int NB, typename S>
-static hipError_t launch_bf_nb(const sht_plan_s *p, BfArgs<S> a, hipStream_t st) {
+static hipError_t launch_bf_nb(const sht_plan_s *p, BfArgs<S> a, hipStream_t st, void *const *ev) {
     constexpr int WPB = kBfThreads / 64;
     const BflyPlan &b = p->bf;
+    if (b.nbatch != 1) ev = nullptr;
     for (int bt = 0; bt < b.nbatch; bt++) {
         const long long t0 = b.batch_sub[bt], t1 = b.batch_sub[bt + 1];
+        bf_event(ev, SHT_STAGE_BF_RESIDUAL, 0, st);
         if (t1 > t0)
             hipLaunchKernelGGL((k_bf_residual<NB, S>), dim3((unsigned)((t1 - t0 + WPB - 1) / WPB)), dim3(kBfThreads), 0,
                                st, a, t0, t1);
+        bf_event(ev, SHT_STAGE_BF_RESIDUAL, 1, st);
+        bf_event(ev, SHT_STAGE_BF_LEVELS, 0, st);
         const long long *lo = b.lv_off.data() + (size_t)bt * (kBfMaxLv + 1);
         for (int q = 0; q < kBfMaxLv; q++) {
             const long long n0 = lo[q], n1 = lo[q + 1];
@@ -642,6 +651,7 @@ static hipError_t launch_bf_nb(const sht_plan_s *p, BfArgs<S> a, hipStream_t st)
             hipLaunchKernelGGL((k_bf_level<NB, S>), dim3((unsigned)(n1 - n0)), dim3(kBfLevelThreads),
                                (size_t)b.max_n * 2 * NB * sizeof(S), st, a, n0);
         }
+        bf_event(ev, SHT_STAGE_BF_LEVELS, 1, st);
         const long long nf = (long long)b.batch_count[bt] * b.K * NB;
         if (nf > 0)
             hipLaunchKernelGGL((k_bf_fold<NB, S>), dim3((unsigned)((nf + kBfThreads - 1) / kBfThreads)),
@@ -652,7 +662,7 @@ static hipError_t launch_bf_nb(const sht_plan_s *p, BfArgs<S> a, hipStream_t st)
 
 template <typename S>
 static hipError_t launch_bf(const sht_plan_s *p, int nmaps, const double *alm, double *q, S *ws, const S *T,
-                            hipStream_t st) {
+                            hipStream_t st, void *const *ev) {
     BfArgs<S> a;
     a.res_task = reinterpret_cast<const int4 *>(p->d_bf_res_task);
     a.res_sub = reinterpret_cast<const int4 *>(p->d_bf_res_sub);
@@ -678,10 +688,10 @@ static hipError_t launch_bf(const sht_plan_s *p, int nmaps, const double *alm, d
         const int nb = bf_nb(nmaps - b);
         a.map0 = b;
         switch (nb) {
-            case 8: e = launch_bf_nb<8, S>(p, a, st); break;
-            case 4: e = launch_bf_nb<4, S>(p, a, st); break;
-            case 2: e = launch_bf_nb<2, S>(p, a, st); break;
-            default: e = launch_bf_nb<1, S>(p, a, st); break;
+            case 8: e = launch_bf_nb<8, S>(p, a, st, ev); break;
+            case 4: e = launch_bf_nb<4, S>(p, a, st, ev); break;
+            case 2: e = launch_bf_nb<2, S>(p, a, st, ev); break;
+            default: e = launch_bf_nb<1, S>(p, a, st, ev); break;
         }
         b += nb;
     }
@@ -760,9 +770,9 @@ hipError_t launch_butterfly_adjoint(const sht_plan_s *p, int nmaps, const double
 }
 
 hipError_t launch_butterfly(const sht_plan_s *p, int nmaps, const double *alm, double *q, void *scratch,
-                            int fp32, hipStream_t stream) {
-    if (fp32) return launch_bf<float>(p, nmaps, alm, q, (float *)scratch, p->d_bf_T32, stream);
-    return launch_bf<double>(p, nmaps, alm, q, (double *)scratch, p->d_bf_T, stream);
+                            int fp32, hipStream_t stream, void *const *stage_events) {
+    if (fp32) return launch_bf<float>(p, nmaps, alm, q, (float *)scratch, p->d_bf_T32, stream, stage_events);
+    return launch_bf<double>(p, nmaps, alm, q, (double *)scratch, p->d_bf_T, stream, stage_events);
 }
 
 }  // namespace sht

@@ -161,8 +161,10 @@ hipError_t launch_legendre_adjoint(const sht_plan_s *p, int nmaps, const double 
 // launch_legendre; scratch holds ws_entries vector entries of up to 16
 // doubles (FP64) or floats (FP32).
 size_t bf_scratch_bytes(const sht_plan_s *p, int nmaps, int fp32);
+// stage_events: NULL or the caller's 2*SHT_NSTAGES event handles; the
+// residual and level launches are bracketed for one-batch plans.
 hipError_t launch_butterfly(const sht_plan_s *p, int nmaps, const double *alm, double *q, void *scratch,
-                            int fp32, hipStream_t stream);
+                            int fp32, hipStream_t stream, void *const *stage_events = nullptr);
 // Its transpose: unfolded ybar (ring-major, like q) -> g (written whole),
 // with the same scratch.
 hipError_t launch_butterfly_adjoint(const sht_plan_s *p, int nmaps, const double *ybar, double *g, void *scratch,

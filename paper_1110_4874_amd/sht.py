@@ -18,7 +18,8 @@ LIB_PATH = os.path.join(HERE, "libsht.so")
 SHT_OK, SHT_EINVAL, SHT_ENOMEM, SHT_EDEVICE, SHT_ECORRUPT, SHT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 PATH_AUTO, PATH_BRUTE, PATH_BUTTERFLY = 0, 1, 2
 PREC_FP64, PREC_FP32 = 0, 1
-STAGE_LEGENDRE, STAGE_RING, STAGE_RING_ADJ, STAGE_LEGENDRE_ADJ, NSTAGES = 0, 1, 2, 3, 4
+STAGE_LEGENDRE, STAGE_RING, STAGE_RING_ADJ, STAGE_LEGENDRE_ADJ = 0, 1, 2, 3
+STAGE_BF_RESIDUAL, STAGE_BF_LEVELS, NSTAGES = 4, 5, 6
 ADJ_TRANSPOSE, ADJ_DAGGER = 0, 1
 
 _c = ctypes
