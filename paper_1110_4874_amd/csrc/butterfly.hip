@@ -268,9 +268,8 @@ __device__ __forceinline__ void residual_task(const BfArgs<S> &a, S *__restrict_
     }
 }
 
-// One wave per residual piece (up to 64 skeleton rings of one task, one per
-// lane): short waves keep the register count, and with it the occupancy, of
-// the one-ring case.
+// One wave per residual piece (up to kBfPieceRings skeleton rings of one
+// task): short waves keep the register count, and with it the occupancy, low.
 template <int NB, typename S>
 __global__ __launch_bounds__(kBfThreads) void k_bf_residual(BfArgs<S> a, long long t0, long long t1) {
     __shared__ double stg_all[kBfThreads / 64][bf_res_stage_doubles<NB>()];
@@ -287,7 +286,8 @@ __global__ __launch_bounds__(kBfThreads) void k_bf_residual(BfArgs<S> a, long lo
     const double *ap = reinterpret_cast<const double *>(a.alm + (aoff + t) * a.nmaps + a.map0);
     const double *cfs = a.coef + 4 * a.coef_off[m];
     const int astride = 4 * a.nmaps;  // doubles between rows i and i+1
-    residual_task<NB, 1>(a, a.ws, lbase, lane, t, imin, iend, nl, outb, ap, cfs, astride, stg_all[w]);
+    residual_task<NB, kBfPieceRings / 64>(a, a.ws, lbase, lane, t, imin, iend, nl, outb, ap, cfs, astride,
+                                          stg_all[w]);
 }
 
 // One workgroup of 2 kBfHalves waves per pair node (wave w: child w % 2,

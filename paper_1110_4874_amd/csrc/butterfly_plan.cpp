@@ -567,19 +567,19 @@ int build_butterfly(sht_plan_s *p, const BflyInput &in) {
         if (b.ws_entries > INT32_MAX || (long long)b.perm.size() > INT32_MAX)
             return fail(SHT_EUNSUPPORTED, "butterfly plan exceeds 32-bit record offsets");
         for (size_t q = 0; q < task_region.size(); q++) b.res_task[8 * (task0 + q) + 4] += (int)base[task_region[q]];
-        // the same tasks in pieces of up to 64 rings (one wave, one ring per
-        // lane) for the forward kernel, each starting at its own first row
+        // the same tasks in pieces of up to kBfPieceRings rings (one wave) for
+        // the forward kernel, each starting at its own first row
         b.batch_sub[bt] = (long long)b.res_sub.size() / 8;
         for (size_t tk = task0; tk < b.res_task.size() / 8; tk++) {
             const int *h = &b.res_task[8 * tk];
-            for (int q0 = 0; q0 < h[3]; q0 += 64) {
-                const int nq = std::min(64, h[3] - q0);
+            for (int q0 = 0; q0 < h[3]; q0 += kBfPieceRings) {
+                const int nq = std::min(kBfPieceRings, h[3] - q0);
                 int imin = h[2];
                 for (int j = 0; j < nq; j++)
                     imin = std::min(imin, b.res_lane[2 * (tk * kBfTaskRings + q0 + j) + 1]);
                 b.res_sub.insert(b.res_sub.end(),
                                  {h[0], imin, h[2], nq, h[4] + q0, h[5], (int)(tk * kBfTaskRings + q0), 0});
-                b.res_exec += (long long)(h[2] - imin) * 64;
+                b.res_exec += (long long)(h[2] - imin) * kBfPieceRings;
             }
         }
         // node records, deepest level first, with their launch ranges

@@ -33,6 +33,7 @@ void parallel_for(long n, int nthreads, void (*fn)(long, void *), void *ctx);
 // Butterfly records (butterfly_plan.cpp builds them, butterfly.hip walks them).
 constexpr int kBfMaxLv = 10;     // deepest level a plan may keep
 constexpr int kBfTaskRings = 256; // rings of one residual wave task (up to four per lane)
+constexpr int kBfPieceRings = 128; // rings of one forward residual piece (64 or 128: one or two per lane)
 constexpr int kBfNodeInts = 16;  // vin0, vin1, k0, k1, nd0, nd1, out, perm offset,
                                  // region flags, m, t, level, T offsets of both
                                  // children (64-bit, lo/hi)
