@@ -69,28 +69,19 @@ def measured_traffic(kernel, L, nside, nmaps):
 def batch_bench(np, torch, sht, steps):
     """64 queued syntheses of mixed L in {127, 255, 511, 1023}, nside =
     (L+1)/2, 1-8 maps each (seed 500): one batch call (and its captured HIP
-    graph) against 64 sequential calls, FP64 brute force, plans with tuned
-    tile shapes."""
+    graph) against 64 sequential calls, with plans of tuned tile shapes: FP64
+    brute force, then butterfly plans (eps 1e-12, depth from the cost model)
+    with FP64 and FP32 matrix-core level products."""
     from paper_1110_4874_amd import autotune
     from paper_1110_4874_amd.synthetic import alm_gaussian, mixed_requests
 
     queue = mixed_requests(seed=500, n=64)
-    plans, reqs = {}, []
-    t0 = time.perf_counter()
+    inputs = []
     for (L, N, B, seeds) in queue:
-        if (L, N) not in plans:
-            plans[(L, N)] = autotune.tuned_plan(L, N, 4)
         alm = torch.from_numpy(alm_gaussian(L, seeds)).cuda()
         out = torch.empty((B, 12 * N * N), dtype=torch.float64, device="cuda")
-        reqs.append((plans[(L, N)], alm, out))
-    tune_s = time.perf_counter() - t0
-    nmaps = sum(r[1].shape[1] for r in reqs)
-    wss = {id(p): p.workspace(max(r[1].shape[1] for r in reqs if r[0] is p)) for p in plans.values()}
-    batch = sht.Batch(reqs)
-
-    def seq():
-        for p, a, o in reqs:
-            p.synthesis(a, o, workspace=wss[id(p)])
+        inputs.append((L, N, alm, out))
+    nmaps = sum(x[2].shape[1] for x in inputs)
 
     def timed(fn, k):
         fn()
@@ -101,32 +92,57 @@ def batch_bench(np, torch, sht, steps):
         torch.cuda.synchronize()
         return (time.perf_counter() - ts) / k
 
-    t_seq = timed(seq, steps)
-    t_batch = timed(batch.run, steps)
-    s = torch.cuda.Stream()
-    s.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(s):
-        batch.run(stream=s)
-    torch.cuda.current_stream().wait_stream(s)
-    torch.cuda.synchronize()
-    g = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g):
-        batch.run(stream=torch.cuda.current_stream())
-    t_graph = timed(g.replay, steps)
-    # the graph's results equal the sequential calls'
-    ref = [o.clone() for _, _, o in reqs]
-    seq()
-    torch.cuda.synchronize()
-    same = all(torch.equal(o, r) for (_, _, o), r in zip(reqs, ref))
-    res = {"requests": len(reqs), "maps": nmaps, "precision": "fp64", "path": "brute",
-           "sequential_maps_per_s": round(nmaps / t_seq, 2), "batch_maps_per_s": round(nmaps / t_batch, 2),
-           "graph_maps_per_s": round(nmaps / t_graph, 2), "graph_speedup_vs_sequential": round(t_seq / t_graph, 3),
-           "graph_matches_sequential": bool(same),
+    def run_config(plans, path, prec):
+        reqs = [(plans[(L, N)], alm, out) for (L, N, alm, out) in inputs]
+        wss = {id(p): p.workspace(max(r[1].shape[1] for r in reqs if r[0] is p), path=path, precision=prec)
+               for p in plans.values()}
+        batch = sht.Batch(reqs, path=path, precision=prec)
+
+        def seq():
+            for p, a, o in reqs:
+                p.synthesis(a, o, workspace=wss[id(p)], path=path, precision=prec)
+
+        t_seq = timed(seq, steps)
+        t_batch = timed(batch.run, steps)
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            batch.run(stream=s)
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            batch.run(stream=torch.cuda.current_stream())
+        t_graph = timed(g.replay, steps)
+        # the graph's results equal the sequential calls'
+        ref = [o.clone() for _, _, o in reqs]
+        seq()
+        torch.cuda.synchronize()
+        same = all(torch.equal(o, r) for (_, _, o), r in zip(reqs, ref))
+        return {"sequential_maps_per_s": round(nmaps / t_seq, 2), "batch_maps_per_s": round(nmaps / t_batch, 2),
+                "graph_maps_per_s": round(nmaps / t_graph, 2),
+                "graph_speedup_vs_sequential": round(t_seq / t_graph, 3), "graph_matches_sequential": bool(same)}
+
+    t0 = time.perf_counter()
+    plans = {}
+    for (L, N, _, _) in inputs:
+        if (L, N) not in plans:
+            plans[(L, N)] = autotune.tuned_plan(L, N, 4)
+    tune_s = time.perf_counter() - t0
+    res = {"requests": len(inputs), "maps": nmaps, "tuning_seconds": round(tune_s, 1),
            "tile_shapes": {f"{L}": {k: v for k, v in autotune.tune(L, N, 4).items() if k != "ms"}
                            for (L, N) in plans},
-           "tuning_seconds": round(tune_s, 1)}
-    log(f"[bench] batching: sequential {res['sequential_maps_per_s']} maps/s, batch {res['batch_maps_per_s']}, "
-        f"graph {res['graph_maps_per_s']}")
+           "brute_fp64": run_config(plans, sht.PATH_BRUTE, sht.PREC_FP64)}
+    bf_plans = {(L, N): autotune.tuned_plan(L, N, 4, plan_eps=1e-12, plan_kw={"store_fp32": True})
+                for (L, N) in plans}
+    res["butterfly_depth_hist"] = {f"{L}": p.info()["bf_depth_hist"][:6] for (L, _), p in bf_plans.items()}
+    res["butterfly_fp64"] = run_config(bf_plans, sht.PATH_BUTTERFLY, sht.PREC_FP64)
+    res["butterfly_fp32"] = run_config(bf_plans, sht.PATH_BUTTERFLY, sht.PREC_FP32)
+    for p in list(plans.values()) + list(bf_plans.values()):
+        p.close()
+    for k in ("brute_fp64", "butterfly_fp64", "butterfly_fp32"):
+        log(f"[bench] batching {k}: sequential {res[k]['sequential_maps_per_s']} maps/s, "
+            f"batch {res[k]['batch_maps_per_s']}, graph {res[k]['graph_maps_per_s']}")
     return res
 
 

@@ -81,7 +81,12 @@ def tune(L, nside, nmaps, eps=0.0, *, steps=5, cache_file=None, verbose=False):
     return best
 
 
-def tuned_plan(L, nside, nmaps, eps=0.0, **kw):
-    """A plan built with the tuned tile shape for (L, nside, nmaps, eps)."""
+def tuned_plan(L, nside, nmaps, eps=0.0, plan_eps=None, plan_kw=None, **kw):
+    """A plan built with the tuned tile shape for (L, nside, nmaps, eps).
+
+    plan_eps (default eps) and plan_kw (e.g. store_fp32) apply to the plan
+    that is returned; the tile shapes are those tuned at eps, so a butterfly
+    plan can reuse shapes tuned on the brute-force path."""
     best = tune(L, nside, nmaps, eps, **kw)
-    return sht.Plan(L, nside, eps, rings_per_lane=best["rings_per_lane"], ring_threads=best["ring_threads"])
+    return sht.Plan(L, nside, eps if plan_eps is None else plan_eps, rings_per_lane=best["rings_per_lane"],
+                    ring_threads=best["ring_threads"], **(plan_kw or {}))
