@@ -648,8 +648,9 @@ static hipError_t launch_bf_nb(const sht_plan_s *p, BfArgs<S> a, hipStream_t st,
         for (int q = 0; q < kBfMaxLv; q++) {
             const long long n0 = lo[q], n1 = lo[q + 1];
             if (n1 <= n0) continue;
-            hipLaunchKernelGGL((k_bf_level<NB, S>), dim3((unsigned)(n1 - n0)), dim3(kBfLevelThreads),
-                               (size_t)b.max_n * 2 * NB * sizeof(S), st, a, n0);
+            // LDS for the widest column set of this level only
+            const size_t lds = (size_t)b.lv_max_n[(size_t)bt * kBfMaxLv + q] * 2 * NB * sizeof(S);
+            hipLaunchKernelGGL((k_bf_level<NB, S>), dim3((unsigned)(n1 - n0)), dim3(kBfLevelThreads), lds, st, a, n0);
         }
         bf_event(ev, SHT_STAGE_BF_LEVELS, 1, st);
         const long long nf = (long long)b.batch_count[bt] * b.K * NB;
@@ -714,8 +715,9 @@ static hipError_t launch_bf_adj_nb(const sht_plan_s *p, BfArgs<S> a, hipStream_t
         for (int q = kBfMaxLv - 1; q >= 0; q--) {
             const long long n0 = lo[q], n1 = lo[q + 1];
             if (n1 <= n0) continue;
-            hipLaunchKernelGGL((k_bf_level_t<NB, S>), dim3((unsigned)(n1 - n0)), dim3(kBfLevelThreads),
-                               (size_t)b.max_n * 2 * NB * sizeof(S), st, a, n0);
+            const size_t lds = (size_t)b.lv_max_n[(size_t)bt * kBfMaxLv + q] * 2 * NB * sizeof(S);
+            hipLaunchKernelGGL((k_bf_level_t<NB, S>), dim3((unsigned)(n1 - n0)), dim3(kBfLevelThreads), lds, st, a,
+                               n0);
         }
         const long long t0 = b.batch_task[bt], t1 = b.batch_task[bt + 1];
         if (t1 > t0)

@@ -445,9 +445,11 @@ int build_butterfly(sht_plan_s *p, const BflyInput &in) {
     b.batch_task.assign(nb + 1, 0);
     b.batch_sub.assign(nb + 1, 0);
     b.lv_off.assign((size_t)nb * (kBfMaxLv + 1) + 1, 0);
+    b.lv_max_n.assign((size_t)nb * kBfMaxLv, 0);
     b.batch_count.assign(nb, 0);
     for (int bt = 0; bt < nb; bt++) {
         long long leaf_cnt = 0, lvl_cnt[kBfMaxLv + 1] = {};
+        int lvl_max_n[kBfMaxLv + 1] = {};
         std::vector<std::vector<int>> lvnodes(kBfMaxLv + 1);  // per level: node records
         std::vector<int> task_region;                          // per task: region of its output
         b.batch_task[bt] = (long long)b.res_task.size() / 8;
@@ -549,6 +551,7 @@ int build_butterfly(sht_plan_s *p, const BflyInput &in) {
                             b.n_nodes++;
                             b.n_units += nn;
                             b.max_n = std::max(b.max_n, nn);
+                            lvl_max_n[lvl] = std::max(lvl_max_n[lvl], nn);
                         }
                 }
                 std::vector<std::vector<Node>>().swap(it.lv);
@@ -585,6 +588,7 @@ int build_butterfly(sht_plan_s *p, const BflyInput &in) {
         // node records, deepest level first, with their launch ranges
         for (int lvl = kBfMaxLv; lvl >= 1; lvl--) {
             b.lv_off[(size_t)bt * (kBfMaxLv + 1) + kBfMaxLv - lvl] = (long long)b.node_i.size() / kBfNodeInts;
+            b.lv_max_n[(size_t)bt * kBfMaxLv + kBfMaxLv - lvl] = lvl_max_n[lvl];
             std::vector<int> &rec = lvnodes[lvl];
             for (size_t q = 0; q < rec.size(); q += kBfNodeInts) {
                 const int fl = rec[q + 8];

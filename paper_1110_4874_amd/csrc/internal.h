@@ -63,6 +63,7 @@ struct BflyPlan {
     std::vector<long long> batch_task;  // [nbatch+1] residual task ranges
     std::vector<long long> batch_sub;   // [nbatch+1] sub-task ranges
     std::vector<long long> lv_off;    // [nbatch][kBfMaxLv+1] (+1) node ranges, deepest level first
+    std::vector<int> lv_max_n;        // [nbatch][kBfMaxLv] widest column set of each range
     std::vector<int16_t> perm;        // per node and child: positions in C of the skeleton
                                       // columns (s order), then of the dense ones (d order)
     std::vector<int> node_i;          // [nodes][kBfNodeInts]
