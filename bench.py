@@ -331,16 +331,19 @@ def main():
                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "bytes_per_launch": nbytes}
         if r["levels_ms"] >= r["residual_ms"]:
-            # interpolation matrices streamed once, child vectors read and parent vectors written once
-            lvl_bytes = info["bf_T_entries"] * sz + 2 * info["bf_units"] * 2 * B * sz
-            per_launch = lvl_bytes / nlev
-            achieved = per_launch / (r["levels_ms"] / nlev * 1e-3) / 1e9
+            # levels >= 2 (level 1 runs fused with the fold): interpolation matrices streamed
+            # once, child vectors read and parent vectors written once
+            lvls = range(2, nlev + 1)
+            lvl_bytes = sum(info["bf_level_T"][i] * sz + 2 * info["bf_level_units"][i] * 2 * B * sz for i in lvls)
+            nl = max(nlev - 1, 1)
+            per_launch = lvl_bytes / nl
+            achieved = per_launch / (r["levels_ms"] / nl * 1e-3) / 1e9
             kern = "void sht::k_bf_level<%d, %s>" % (min(B, 8) if B in (1, 2, 4, 8) else 4, "double" if sz == 8 else "float")
-            return {"kernel": f"k_bf_level ({nlev} launches per pass, one per level)", "bound": "hbm",
+            return {"kernel": f"k_bf_level ({nl} launches per pass, one per level 2..{nlev})", "bound": "hbm",
                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4),
                     "traffic": measured_traffic(kern, L, N, B), "bytes_per_launch": int(per_launch),
-                    "launch_ms": round(r["levels_ms"] / nlev, 4)}
+                    "launch_ms": round(r["levels_ms"] / nl, 4)}
         rflops = info["bf_res_elems"] * (5 + 4 * B)
         achieved = rflops / (r["residual_ms"] * 1e-3) / 1e12
         return {"kernel": "k_bf_residual (one launch)", "bound": "alu", "achieved": round(achieved, 3),

@@ -165,6 +165,8 @@ typedef struct sht_plan_info {
     long long bf_depth_hist[11]; /* (m, parity) items per kept depth 0..10 */
     double bf_build_seconds;
     int bf_nbatch;            /* order batches per transform */
+    long long bf_level_T[11];     /* dense entries of the pair nodes of level 0..10 */
+    long long bf_level_units[11]; /* output columns of the pair nodes of level 0..10 */
 } sht_plan_info_t;
 
 void sht_plan_opts_default(sht_plan_opts *o);

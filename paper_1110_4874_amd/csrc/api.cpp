@@ -310,6 +310,10 @@ int sht_plan_info(const sht_plan_t *p, sht_plan_info_t *out) {
         for (int i = 0; i <= kBfMaxLv; i++) out->bf_depth_hist[i] = b.depth_hist[i];
         out->bf_build_seconds = b.build_seconds;
         out->bf_nbatch = b.nbatch;
+        for (int i = 0; i <= kBfMaxLv; i++) {
+            out->bf_level_T[i] = b.level_T[i];
+            out->bf_level_units[i] = b.level_units[i];
+        }
     }
     return SHT_OK;
 }

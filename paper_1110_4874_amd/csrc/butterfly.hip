@@ -296,11 +296,10 @@ __global__ __launch_bounds__(kBfThreads) void k_bf_residual(BfArgs<S> a, long lo
 constexpr int kBfLevelThreads = 128 * kBfHalves;
 
 template <int NB, typename S>
-__global__ __launch_bounds__(kBfLevelThreads) void k_bf_level(BfArgs<S> a, long long n0) {
+__device__ __forceinline__ void level_node(const BfArgs<S> &a, int node) {
     constexpr int NC = 2 * NB;
     extern __shared__ char lds_raw[];
     S *u = reinterpret_cast<S *>(lds_raw);
-    const int node = (int)(n0 + blockIdx.x);
     const int *ni = a.node_i + (size_t)node * kBfNodeInts;
     const int n = ni[2] + ni[4];
     for (int e = threadIdx.x; e < n * NC; e += kBfLevelThreads) u[e] = (S)0;
@@ -312,16 +311,63 @@ __global__ __launch_bounds__(kBfLevelThreads) void k_bf_level(BfArgs<S> a, long 
     for (int e = threadIdx.x; e < n * NC; e += kBfLevelThreads) out[e] = u[e];
 }
 
-// Fold of one batch: slot j of the batch holds order m = batch + j nbatch.
 template <int NB, typename S>
-__global__ __launch_bounds__(kBfThreads) void k_bf_fold(BfArgs<S> a, int batch, int nbatch, int count) {
+__global__ __launch_bounds__(kBfLevelThreads) void k_bf_level(BfArgs<S> a, long long n0) {
+    level_node<NB, S>(a, (int)(n0 + blockIdx.x));
+}
+
+// Level-1 nodes that run alone (their order is folded afterwards).
+template <int NB, typename S>
+__global__ __launch_bounds__(kBfLevelThreads) void k_bf_level_list(BfArgs<S> a, const int *__restrict__ list,
+                                                                   long long n0) {
+    level_node<NB, S>(a, list[n0 + blockIdx.x]);
+}
+
+// Level 1 fused with the even/odd fold (Eqs. 13-14): one workgroup per unit
+// {even node, odd node, first ring k0, slot}; both nodes cover the rings
+// k0 .. k0+n-1 of one order, so q^even and q^odd of those rings meet in LDS
+// and q(z) = q^e + q^o, q(-z) = q^e - q^o go straight to q.
+constexpr int kBfFoldThreads = 2 * kBfLevelThreads;
+
+template <int NB, typename S>
+__global__ __launch_bounds__(kBfFoldThreads) void k_bf_level1_fold(BfArgs<S> a, const int4 *__restrict__ units,
+                                                                   long long u0, int batch, int nbatch) {
+    constexpr int NC = 2 * NB;
+    extern __shared__ char lds_raw[];
+    const int4 un = units[u0 + blockIdx.x];
+    const int *nie = a.node_i + (size_t)un.x * kBfNodeInts;
+    const int n = nie[2] + nie[4];
+    S *uE = reinterpret_cast<S *>(lds_raw);
+    S *uO = uE + (size_t)n * NC;
+    for (int e = threadIdx.x; e < 2 * n * NC; e += kBfFoldThreads) uE[e] = (S)0;
+    __syncthreads();
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int par = w / (2 * kBfHalves), wc = w % (2 * kBfHalves);
+    id_block<NB, S>(a, par ? un.y : un.x, wc & 1, wc >> 1, threadIdx.x & 63, par ? uO : uE);
+    __syncthreads();
+    const int m = batch + un.w * nbatch, k0 = un.z;
+    for (int e = threadIdx.x; e < n * NB; e += kBfFoldThreads) {
+        const int c = e / NB, b = e % NB;
+        double er = (double)uE[c * NC + 2 * b], ei = (double)uE[c * NC + 2 * b + 1];
+        double orr = (double)uO[c * NC + 2 * b], oi = (double)uO[c * NC + 2 * b + 1];
+        if (m == 0) ei = oi = 0.0;  // real field: Im a_l0 is ignored
+        const int k = k0 + c, ks = a.nrings - 1 - k;
+        a.q[((size_t)k * (a.L + 1) + m) * a.nmaps + a.map0 + b] = make_double2(er + orr, ei + oi);
+        if (ks != k) a.q[((size_t)ks * (a.L + 1) + m) * a.nmaps + a.map0 + b] = make_double2(er - orr, ei - oi);
+    }
+}
+
+// Fold of the listed slots of one batch: slot j holds order m = batch + j nbatch.
+template <int NB, typename S>
+__global__ __launch_bounds__(kBfThreads) void k_bf_fold(BfArgs<S> a, int batch, int nbatch, const int *__restrict__ slots,
+                                                        int count) {
     constexpr int NC = 2 * NB;
     const int K = a.K;
     const long long e = (long long)blockIdx.x * kBfThreads + threadIdx.x;
     if (e >= (long long)count * K * NB) return;
     const int b = (int)(e % NB);
     const long long jk = e / NB;
-    const int k = (int)(jk % K), j = (int)(jk / K);
+    const int k = (int)(jk % K), j = slots[jk / K];
     const int m = batch + j * nbatch;
     const S *qe = a.ws + ((size_t)(2 * j) * K + k) * NC + 2 * b;
     const S *qo = a.ws + ((size_t)(2 * j + 1) * K + k) * NC + 2 * b;
@@ -645,7 +691,7 @@ static hipError_t launch_bf_nb(const sht_plan_s *p, BfArgs<S> a, hipStream_t st,
         bf_event(ev, SHT_STAGE_BF_RESIDUAL, 1, st);
         bf_event(ev, SHT_STAGE_BF_LEVELS, 0, st);
         const long long *lo = b.lv_off.data() + (size_t)bt * (kBfMaxLv + 1);
-        for (int q = 0; q < kBfMaxLv; q++) {
+        for (int q = 0; q < kBfMaxLv - 1; q++) {  // levels >= 2
             const long long n0 = lo[q], n1 = lo[q + 1];
             if (n1 <= n0) continue;
             // LDS for the widest column set of this level only
@@ -653,10 +699,21 @@ static hipError_t launch_bf_nb(const sht_plan_s *p, BfArgs<S> a, hipStream_t st,
             hipLaunchKernelGGL((k_bf_level<NB, S>), dim3((unsigned)(n1 - n0)), dim3(kBfLevelThreads), lds, st, a, n0);
         }
         bf_event(ev, SHT_STAGE_BF_LEVELS, 1, st);
-        const long long nf = (long long)b.batch_count[bt] * b.K * NB;
+        // level 1: fused with the fold where both parities have levels
+        const size_t lds1 = (size_t)b.lv_max_n[(size_t)bt * kBfMaxLv + kBfMaxLv - 1] * 2 * NB * sizeof(S);
+        const long long p0 = b.l1_off[bt], p1 = b.l1_off[bt + 1];
+        if (p1 > p0)
+            hipLaunchKernelGGL((k_bf_level_list<NB, S>), dim3((unsigned)(p1 - p0)), dim3(kBfLevelThreads), lds1, st, a,
+                               p->d_bf_l1_plain, p0);
+        const long long f0 = b.f1_off[bt], f1 = b.f1_off[bt + 1];
+        if (f1 > f0)
+            hipLaunchKernelGGL((k_bf_level1_fold<NB, S>), dim3((unsigned)(f1 - f0)), dim3(kBfFoldThreads), 2 * lds1, st,
+                               a, reinterpret_cast<const int4 *>(p->d_bf_f1_unit), f0, bt, b.nbatch);
+        const long long s0 = b.fold_off[bt], s1 = b.fold_off[bt + 1];
+        const long long nf = (s1 - s0) * b.K * NB;
         if (nf > 0)
             hipLaunchKernelGGL((k_bf_fold<NB, S>), dim3((unsigned)((nf + kBfThreads - 1) / kBfThreads)),
-                               dim3(kBfThreads), 0, st, a, bt, b.nbatch, b.batch_count[bt]);
+                               dim3(kBfThreads), 0, st, a, bt, b.nbatch, p->d_bf_fold_slot + s0, (int)(s1 - s0));
     }
     return hipGetLastError();
 }

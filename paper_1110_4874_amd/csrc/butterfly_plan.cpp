@@ -445,6 +445,9 @@ int build_butterfly(sht_plan_s *p, const BflyInput &in) {
     b.batch_task.assign(nb + 1, 0);
     b.batch_sub.assign(nb + 1, 0);
     b.lv_off.assign((size_t)nb * (kBfMaxLv + 1) + 1, 0);
+    b.f1_off.assign(nb + 1, 0);
+    b.l1_off.assign(nb + 1, 0);
+    b.fold_off.assign(nb + 1, 0);
     b.lv_max_n.assign((size_t)nb * kBfMaxLv, 0);
     b.batch_count.assign(nb, 0);
     for (int bt = 0; bt < nb; bt++) {
@@ -550,6 +553,8 @@ int build_butterfly(sht_plan_s *p, const BflyInput &in) {
                             }
                             b.n_nodes++;
                             b.n_units += nn;
+                            b.level_T[lvl] += (long long)(c0.T.size() + c1.T.size());
+                            b.level_units[lvl] += nn;
                             b.max_n = std::max(b.max_n, nn);
                             lvl_max_n[lvl] = std::max(lvl_max_n[lvl], nn);
                         }
@@ -598,10 +603,44 @@ int build_butterfly(sht_plan_s *p, const BflyInput &in) {
             }
             b.node_i.insert(b.node_i.end(), rec.begin(), rec.end());
             std::vector<int>().swap(rec);
+            if (lvl != 1) continue;
+            // level 1: pair the even and odd nodes of an order over the same
+            // ring chunk (both parities share the chunk boundaries) when both
+            // parities have levels; otherwise run them alone and fold later
+            const long long l1a = b.lv_off[(size_t)bt * (kBfMaxLv + 1) + kBfMaxLv - 1];
+            const long long l1b = (long long)b.node_i.size() / kBfNodeInts;
+            b.f1_off[bt] = (long long)b.f1_unit.size() / 4;
+            b.l1_off[bt] = (long long)b.l1_plain.size();
+            b.fold_off[bt] = (long long)b.fold_slot.size();
+            std::vector<std::vector<std::pair<int, int>>> per_m(slot);  // (k0 * 2 + t, node)
+            for (long long nd = l1a; nd < l1b; nd++) {
+                const int *ni = &b.node_i[(size_t)nd * kBfNodeInts];
+                const int m = ni[9], t = ni[10], sl = (m - bt) / nb;
+                const int k0 = ni[6] - (2 * sl + t) * K;
+                per_m[sl].push_back({2 * k0 + t, (int)nd});
+            }
+            for (int sl = 0; sl < slot; sl++) {
+                const int m = bt + sl * nb;
+                auto &v = per_m[sl];
+                std::sort(v.begin(), v.end());
+                bool fuse = b.depth[(size_t)2 * m] >= 1 && b.depth[(size_t)2 * m + 1] >= 1 && v.size() % 2 == 0;
+                for (size_t i = 0; fuse && i < v.size(); i += 2)
+                    fuse = (v[i].first & 1) == 0 && v[i + 1].first == v[i].first + 1;
+                if (fuse) {
+                    for (size_t i = 0; i < v.size(); i += 2)
+                        b.f1_unit.insert(b.f1_unit.end(), {v[i].second, v[i + 1].second, v[i].first / 2, sl});
+                } else {
+                    for (auto &x : v) b.l1_plain.push_back(x.second);
+                    b.fold_slot.push_back(sl);
+                }
+            }
         }
         b.lv_off[(size_t)bt * (kBfMaxLv + 1) + kBfMaxLv] = (long long)b.node_i.size() / kBfNodeInts;
     }
     b.batch_task[nb] = (long long)b.res_task.size() / 8;
+    b.f1_off[nb] = (long long)b.f1_unit.size() / 4;
+    b.l1_off[nb] = (long long)b.l1_plain.size();
+    b.fold_off[nb] = (long long)b.fold_slot.size();
     b.batch_sub[nb] = (long long)b.res_sub.size() / 8;
     if ((long long)b.res_lane.size() / 2 > INT32_MAX)
         return fail(SHT_EUNSUPPORTED, "butterfly plan exceeds 32-bit lane record offsets");

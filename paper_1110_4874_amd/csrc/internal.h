@@ -69,6 +69,13 @@ struct BflyPlan {
     std::vector<int> node_i;          // [nodes][kBfNodeInts]
     std::vector<double> T;            // interpolation matrices, dense part, [s][d]
     long long T_entries = 0, res_elems = 0, n_nodes = 0, n_res_lanes = 0, n_units = 0;
+    long long level_T[kBfMaxLv + 1] = {};      // dense entries of the pair nodes of each level
+    long long level_units[kBfMaxLv + 1] = {};  // columns (output entries) of each level
+    // Level 1 of orders whose two parities both have levels runs fused with
+    // the even/odd fold: units {even node, odd node, first ring, slot}; the
+    // other level-1 nodes run alone and their orders are folded afterwards.
+    std::vector<int> f1_unit, l1_plain, fold_slot;
+    std::vector<long long> f1_off, l1_off, fold_off;  // [nbatch+1] ranges
     long long res_exec = 0;           // lane-steps the residual tasks execute
     long long depth_hist[kBfMaxLv + 1] = {};
     double build_seconds = 0.0;
@@ -138,6 +145,7 @@ struct sht_plan_s {
     float *d_bf_T32 = nullptr;
     int16_t *d_bf_perm = nullptr;
     int *d_bf_node_i = nullptr;
+    int *d_bf_f1_unit = nullptr, *d_bf_l1_plain = nullptr, *d_bf_fold_slot = nullptr;
 
 };
 

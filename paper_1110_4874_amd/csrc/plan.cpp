@@ -535,6 +535,9 @@ int upload_tables(sht_plan_s *p) {
         UPB(d_bf_res_val, res_val);
         UPB(d_bf_perm, perm);
         UPB(d_bf_node_i, node_i);
+        UPB(d_bf_f1_unit, f1_unit);
+        UPB(d_bf_l1_plain, l1_plain);
+        UPB(d_bf_fold_slot, fold_slot);
         UPB(d_bf_T, T);
 #undef UPB
         if (e == hipSuccess && p->opts.store_fp32) {
@@ -572,7 +575,7 @@ void free_device_tables(sht_plan_s *p) {
                     p->d_tw,        p->d_bs_table,  p->d_chirp,      p->d_ring_chirp_off,
                     p->d_bf_res_task, p->d_bf_res_lane, p->d_bf_res_sub,
                     p->d_bf_res_val, p->d_bf_T,      p->d_bf_T32,   p->d_bf_perm,
-                    p->d_bf_node_i};
+                    p->d_bf_node_i, p->d_bf_f1_unit, p->d_bf_l1_plain, p->d_bf_fold_slot};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     for (auto &rc : p->classes)
@@ -592,6 +595,7 @@ void free_device_tables(sht_plan_s *p) {
     p->d_bf_T32 = nullptr;
     p->d_bf_perm = nullptr;
     p->d_bf_node_i = nullptr;
+    p->d_bf_f1_unit = p->d_bf_l1_plain = p->d_bf_fold_slot = nullptr;
     p->device_bytes = 0;
 }
 

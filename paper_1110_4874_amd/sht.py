@@ -48,7 +48,8 @@ class PlanInfo(_c.Structure):
                 ("bf_built", _c.c_int), ("bf_T_entries", _c.c_longlong), ("bf_res_elems", _c.c_longlong),
                 ("bf_nodes", _c.c_longlong), ("bf_units", _c.c_longlong), ("bf_res_lanes", _c.c_longlong), ("bf_res_exec", _c.c_longlong),
                 ("bf_depth_hist", _c.c_longlong * 11), ("bf_build_seconds", _c.c_double),
-                ("bf_nbatch", _c.c_int)]
+                ("bf_nbatch", _c.c_int), ("bf_level_T", _c.c_longlong * 11),
+                ("bf_level_units", _c.c_longlong * 11)]
 
 
 class Request(_c.Structure):
@@ -192,6 +193,8 @@ class Plan:
         _check(load().sht_plan_info(self._h, _c.byref(inf)))
         d = {f: getattr(inf, f) for f, _ in PlanInfo._fields_}
         d["bf_depth_hist"] = list(inf.bf_depth_hist)
+        d["bf_level_T"] = list(inf.bf_level_T)
+        d["bf_level_units"] = list(inf.bf_level_units)
         return d
 
     def butterfly_apply_host(self, m, t, x):
