@@ -8,87 +8,25 @@
 // which gives the GPU tens of thousands of independent waves to stream the
 // interpolation matrices with; vectors between levels live in a device
 // workspace (read and written once per level):
-//  1. k_bf_residual: one wave per residual task (up to 128 skeleton rings of
+//  1. k_bf_residual: one wave per residual piece (up to 128 skeleton rings of
 //     one row block, two per lane) regenerates the Legendre values with the
 //     two-step recurrence (App. A.2, Eq. A2) over the block's rows from two
 //     stored values per ring and accumulates v = sum_l a_lm P~_l^m(z) for
-//     every map; a_lm and the coefficients are wave-uniform scalar loads;
-//  2. k_bf_level, deepest level first: one wave per pair node (two sibling
-//     row blocks sharing the column set C) computes
-//     u = A~_0^T v_0 + A~_1^T v_1: identity rows copy v, the dense part
-//     T^T V runs on the matrix cores; level 1 yields q^t per north ring;
-//  3. k_bf_fold: q rows k and 4 nside - k from q^even +- q^odd.
+//     every map; the a_lm rows and coefficients are staged through LDS;
+//  2. k_bf_level, deepest level first down to level 2: one workgroup (a wave
+//     per child) per pair node (two sibling row blocks sharing the column set
+//     C) computes u = A~_0^T v_0 + A~_1^T v_1: identity rows copy v, the
+//     dense part T^T V runs on the matrix cores;
+//  3. level 1 yields q^even and q^odd per north ring: k_bf_level1_fold runs
+//     the two level-1 nodes of one order and ring range together and writes
+//     q rows k and 4 nside - k from q^even +- q^odd (Eqs. 13-14); orders
+//     whose parities split differently run k_bf_level_list, then k_bf_fold.
 //
-// The adjoint g^t = Lambda ybar^t (Sec. 2.4 Eq. 12 transposed) runs the same
-// factorization backwards, per batch of orders:
-//  1. k_bf_unfold: the level-1 vectors get ybar(z) +- ybar(-z) per north ring;
-//  2. k_bf_level_t, level 1 first: each pair node splits u into its children,
-//     v_ch = A~_ch u (identity rows gather u, the dense part T U runs on the
-//     matrix cores), so no two waves write one entry;
-//  3. k_bf_residual_t: one wave per residual task regenerates the Legendre
-//     values of its skeleton rings row by row, reduces sum_z P~(z) v(z) over
-//     the wave with lane swaps and DPP, and adds the row's result to g with
-//     one atomic per component (several tasks share a row block's rows, so
-//     the order of those few addends, and the last bits of g, may vary from
-//     run to run).
-#include "internal.h"
+// The adjoint runs the same factorization backwards in butterfly_adjoint.hip.
+#include "butterfly_common.h"
 
 namespace sht {
 
-template <typename S>
-struct BfArgs {
-    const int4 *__restrict__ res_task;
-    const int4 *__restrict__ res_sub;
-    const int2 *__restrict__ res_lane;
-    const double2 *__restrict__ res_val;
-    const int16_t *__restrict__ perm;
-    const int *__restrict__ node_i;
-    const S *__restrict__ T;
-    const double *__restrict__ z2;
-    const long long *__restrict__ coef_off;
-    const double *__restrict__ coef;
-    const double2 *__restrict__ alm;
-    double2 *__restrict__ q;
-    S *__restrict__ ws;  // vector workspace, entries of 2 NB values
-    const double2 *__restrict__ ybar;  // adjoint input [ring][m][nmaps]
-    double *__restrict__ g;            // adjoint output [nalm][nmaps] complex
-    int L, K, nrings, nmaps, map0;
-};
-
-constexpr int kBfThreads = 256;
-
-// Read-only operands that every lane of a wave needs at the same address
-// (a_lm rows, recurrence coefficients) are read through the constant
-// address space so that they arrive by scalar loads into SGPRs.
-typedef const __attribute__((address_space(4))) double c_double;
-
-typedef double d4_t __attribute__((ext_vector_type(4)));
-typedef float f4_t __attribute__((ext_vector_type(4)));
-template <typename S>
-struct Acc;
-template <>
-struct Acc<double> {
-    typedef d4_t type;
-};
-template <>
-struct Acc<float> {
-    typedef f4_t type;
-};
-
-// D(16x16) += A(16x4) B(4x16) on the matrix cores.  Lane l supplies
-// A[l % 16][l / 16] and B[l / 16][l % 16].  Element r of the accumulator of
-// lane l is D[acc_row(l / 16, r)][l % 16]: row 4 (l / 16) + r for FP32, row
-// l / 16 + 4 r for FP64 (measured on gfx950).
-__device__ __forceinline__ d4_t mfma_16x16x4(double a, double b, d4_t c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-__device__ __forceinline__ f4_t mfma_16x16x4(float a, float b, f4_t c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-template <typename S>
-__device__ __forceinline__ int acc_row(int k4, int r) {
-    return sizeof(S) == 8 ? k4 + 4 * r : 4 * k4 + r;
-}
 
 // One ID block (child ch of a pair node) on one wave:
 //   u += A~_ch^T v_ch  over the columns C the two sibling row blocks share.
@@ -99,7 +37,6 @@ __device__ __forceinline__ int acc_row(int k4, int r) {
 // since every entry receives exactly two addends onto zero the result does
 // not depend on their order.
 constexpr int kBfKSteps = 2;  // K-steps (4 rows of T each) per batch of loads
-constexpr int kBfHalves = 1;  // waves per child: each takes 4 / kBfHalves of a group's 16-row tiles
 
 template <int NB, typename S>
 __device__ __forceinline__ void id_block(const BfArgs<S> &a, int node, int ch, int half, int lane, S *u) {
@@ -293,7 +230,6 @@ __global__ __launch_bounds__(kBfThreads) void k_bf_residual(BfArgs<S> a, long lo
 // One workgroup of 2 kBfHalves waves per pair node (wave w: child w % 2,
 // half w / 2): u (zeroed in LDS) collects both children, then goes to the
 // next level's vector in one coalesced store.
-constexpr int kBfLevelThreads = 128 * kBfHalves;
 
 template <int NB, typename S>
 __device__ __forceinline__ void level_node(const BfArgs<S> &a, int node) {
@@ -378,296 +314,6 @@ __global__ __launch_bounds__(kBfThreads) void k_bf_fold(BfArgs<S> a, int batch, 
     if (ks != k) a.q[((size_t)ks * (a.L + 1) + m) * a.nmaps + a.map0 + b] = make_double2(er - orr, ei - oi);
 }
 
-// ---------------------------------------------------------------------
-// Adjoint
-// ---------------------------------------------------------------------
-
-// Unfold of one batch: slot j (order m = batch + j nbatch) gets ybar^even and
-// ybar^odd of every north ring in its level-1 vectors (the equator once).
-template <int NB, typename S>
-__global__ __launch_bounds__(kBfThreads) void k_bf_unfold(BfArgs<S> a, int batch, int nbatch, int count) {
-    constexpr int NC = 2 * NB;
-    const int K = a.K;
-    const long long e = (long long)blockIdx.x * kBfThreads + threadIdx.x;
-    if (e >= (long long)count * K * NB) return;
-    const int b = (int)(e % NB);
-    const long long jk = e / NB;
-    const int k = (int)(jk % K), j = (int)(jk / K);
-    const int m = batch + j * nbatch;
-    const int ks = a.nrings - 1 - k;
-    const double2 yn = a.ybar[((size_t)k * (a.L + 1) + m) * a.nmaps + a.map0 + b];
-    const double2 ys =
-        ks != k ? a.ybar[((size_t)ks * (a.L + 1) + m) * a.nmaps + a.map0 + b] : make_double2(0.0, 0.0);
-    S *qe = a.ws + ((size_t)(2 * j) * K + k) * NC + 2 * b;
-    S *qo = a.ws + ((size_t)(2 * j + 1) * K + k) * NC + 2 * b;
-    qe[0] = (S)(yn.x + ys.x);
-    qe[1] = (S)(yn.y + ys.y);
-    qo[0] = (S)(yn.x - ys.x);
-    qo[1] = (S)(yn.y - ys.y);
-}
-
-// One ID block transposed (child ch of a pair node) on one wave:
-//   v_ch = A~_ch u:  v[s] = u[perm s] + sum_d T[s][d] u[perm (k + d)].
-// The dense part runs on the matrix cores with the skeleton rows s as the
-// output rows (four 16-row tiles sharing each U operand) and the dense
-// columns d as the reduction: per batch of kBfTJ K-steps, lane (i, kq) holds
-// columns d0 + kBfTJ kq + j, j < kBfTJ, so each lane reads kBfTJ contiguous
-// entries of a row of T.
-constexpr int kBfTJ = 2;  // K-steps per batch of loads in the transposed level
-
-template <int NB, typename S>
-__device__ __forceinline__ void id_block_t(const BfArgs<S> &a, int node, int ch, int half, int lane, const S *u) {
-    constexpr int TPW = 4 / kBfHalves;  // 16-row tiles per wave
-    constexpr int NC = 2 * NB;
-    constexpr int DB = 4 * kBfTJ;  // dense columns per batch
-    typedef typename Acc<S>::type acc_t;
-    const int *ni = a.node_i + (size_t)node * kBfNodeInts;
-    const int n = ni[2] + ni[4];
-    const int kk = ni[2 + ch], nd = ni[4 + ch];
-    S *__restrict__ v = a.ws + (size_t)ni[ch] * NC;
-    const int16_t *__restrict__ pm = a.perm + ni[7] + (size_t)ch * n;
-    const long long toff = (long long)(unsigned)ni[12 + 2 * ch] | ((long long)ni[13 + 2 * ch] << 32);
-    const S *__restrict__ Tb = a.T + toff;
-    const int i16 = lane & 15, k4 = lane >> 4;
-    for (int s00 = 0; s00 < kk; s00 += 64) {
-        const int ntile = min(4, (kk - s00 + 15) >> 4) - half * TPW;  // tiles of this wave
-        if (ntile <= 0) continue;
-        const int s0 = s00 + 16 * TPW * half;
-        acc_t acc[TPW];
-#pragma unroll
-        for (int tt = 0; tt < TPW; tt++) acc[tt] = acc_t{0, 0, 0, 0};
-        for (int d0 = 0; d0 < nd; d0 += DB) {
-            S av[TPW][kBfTJ], bv[kBfTJ];
-#pragma unroll
-            for (int j = 0; j < kBfTJ; j++) {
-                const int d = d0 + kBfTJ * k4 + j;
-                const bool dv = d < nd;
-                bv[j] = (dv && i16 < NC) ? u[pm[kk + d] * NC + i16] : (S)0;
-#pragma unroll
-                for (int tt = 0; tt < TPW; tt++) {
-                    const int sr = s0 + 16 * tt + i16;
-                    av[tt][j] = (dv && sr < kk) ? Tb[(unsigned)(sr * nd + d)] : (S)0;
-                }
-            }
-#pragma unroll
-            for (int j = 0; j < kBfTJ; j++)
-#pragma unroll
-                for (int tt = 0; tt < TPW; tt++)
-                    if (tt < ntile) acc[tt] = mfma_16x16x4(av[tt][j], bv[j], acc[tt]);
-        }
-#pragma unroll
-        for (int tt = 0; tt < TPW; tt++) {
-            if (tt >= ntile) break;
-#pragma unroll
-            for (int r = 0; r < 4; r++) {
-                const int sr = s0 + 16 * tt + acc_row<S>(k4, r);
-                if (sr < kk && i16 < NC) v[sr * NC + i16] = acc[tt][r] + u[pm[sr] * NC + i16];
-            }
-        }
-    }
-}
-
-// One workgroup of 2 kBfHalves waves per pair node: u is staged in LDS, then
-// wave w writes half w / 2 of the rows of child w % 2's vector.
-template <int NB, typename S>
-__global__ __launch_bounds__(kBfLevelThreads) void k_bf_level_t(BfArgs<S> a, long long n0) {
-    constexpr int NC = 2 * NB;
-    extern __shared__ char lds_raw[];
-    S *u = reinterpret_cast<S *>(lds_raw);
-    const int node = (int)(n0 + blockIdx.x);
-    const int *ni = a.node_i + (size_t)node * kBfNodeInts;
-    const int n = ni[2] + ni[4];
-    const S *__restrict__ in = a.ws + (size_t)ni[6] * NC;
-    for (int e = threadIdx.x; e < n * NC; e += kBfLevelThreads) u[e] = in[e];
-    __syncthreads();
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    id_block_t<NB, S>(a, node, w & 1, w >> 1, threadIdx.x & 63, u);
-}
-
-// Lane exchanges for the wave reductions.  permlane32_swap(a, b) leaves
-// a = [a lanes 0-31, b lanes 0-31] and b = [a lanes 32-63, b lanes 32-63];
-// permlane16_swap does the same with rows of 16 (a keeps its even rows and
-// b's even rows, b gets the odd rows of both), as measured on gfx950.
-__device__ __forceinline__ void swap32(double &a, double &b) {
-    const long long ia = __builtin_bit_cast(long long, a), ib = __builtin_bit_cast(long long, b);
-    const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)ia, (unsigned)ib, false, false);
-    const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(ia >> 32), (unsigned)(ib >> 32), false, false);
-    a = __builtin_bit_cast(double, ((long long)hi[0] << 32) | (long long)lo[0]);
-    b = __builtin_bit_cast(double, ((long long)hi[1] << 32) | (long long)lo[1]);
-}
-__device__ __forceinline__ void swap16(double &a, double &b) {
-    const long long ia = __builtin_bit_cast(long long, a), ib = __builtin_bit_cast(long long, b);
-    const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)ia, (unsigned)ib, false, false);
-    const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(ia >> 32), (unsigned)(ib >> 32), false, false);
-    a = __builtin_bit_cast(double, ((long long)hi[0] << 32) | (long long)lo[0]);
-    b = __builtin_bit_cast(double, ((long long)hi[1] << 32) | (long long)lo[1]);
-}
-template <int CTRL>
-__device__ __forceinline__ double dpp_mov(double v) {
-    const long long x = __builtin_bit_cast(long long, v);
-    const int lo = __builtin_amdgcn_mov_dpp((int)x, CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_mov_dpp((int)(x >> 32), CTRL, 0xF, 0xF, false);
-    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
-}
-// One in-row stage at lane distance given by CTRL (a DPP pattern pairing
-// lanes that differ in bit BIT): with h > 0 it halves the values (value j
-// stays where the bit is clear, value j + h where it is set), with h = 0 it
-// adds the partner's single value.
-template <int CTRL, int BIT, int N>
-__device__ __forceinline__ void row_stage(double (&x)[N], int h, int lane) {
-    const bool hi = (lane >> BIT) & 1;
-    if (h == 0) {
-        x[0] += dpp_mov<CTRL>(x[0]);
-        return;
-    }
-#pragma unroll
-    for (int j = 0; j < N / 2; j++) {
-        if (j >= h) break;
-        const double keep = hi ? x[j + h] : x[j], send = hi ? x[j] : x[j + h];
-        x[j] = keep + dpp_mov<CTRL>(send);
-    }
-}
-
-// Sum of x[c] over the 64 lanes of a wave for N = 2^A values per lane
-// (N <= 16): afterwards value c = lane >> (6 - A) is complete in every lane
-// of its group.  Lane distances 32 and 16 use lane swaps (each pair of
-// values costs two swaps and one add), 8, 4, 2, 1 use DPP.
-template <int N>
-__device__ __forceinline__ double wave_transpose_sum(double (&x)[N], int lane) {
-    static_assert(N == 1 || N == 2 || N == 4 || N == 8 || N == 16, "value count");
-    int h = N / 2;
-    if (h > 0) {
-#pragma unroll
-        for (int j = 0; j < N / 2; j++) {
-            swap32(x[j], x[j + N / 2]);
-            x[j] += x[j + N / 2];
-        }
-    } else {
-        double y = x[0];
-        swap32(x[0], y);
-        x[0] += y;
-    }
-    h /= 2;
-    if (h > 0) {
-#pragma unroll
-        for (int j = 0; j < N / 4; j++) {
-            swap16(x[j], x[j + N / 4]);
-            x[j] += x[j + N / 4];
-        }
-    } else {
-        double y = x[0];
-        swap16(x[0], y);
-        x[0] += y;
-    }
-    h /= 2;
-    row_stage<0x128, 3>(x, h, lane);  // row_ror:8
-    h /= 2;
-    row_stage<0x141, 2>(x, h, lane);  // row_half_mirror
-    h /= 2;
-    row_stage<0x4E, 1>(x, h, lane);   // quad_perm [2,3,0,1]
-    h /= 2;
-    row_stage<0xB1, 0>(x, h, lane);   // quad_perm [1,0,3,2]
-    return x[0];
-}
-
-// One transposed residual task on one wave: R rings per lane, rows
-// [imin, iend) of parity t; each row's sum over the task's rings goes to g.
-template <int NB, int R, typename S>
-__device__ __forceinline__ void residual_task_t(const BfArgs<S> &a, long long tk, int lane, int t, int imin,
-                                                int iend, int nl, int outb, int m, c_double *cfs) {
-    constexpr int NC = 2 * NB;
-    constexpr int A = NC == 2 ? 1 : NC == 4 ? 2 : NC == 8 ? 3 : 4;
-    int i0[R];
-    double z2[R], v0[R], v1[R], P0[R], P1[R], w[R][NC];
-#pragma unroll
-    for (int r = 0; r < R; r++) {
-        const size_t li = (size_t)tk * kBfTaskRings + r * 64 + lane;
-        const int2 ln = a.res_lane[li];
-        const double2 sv = a.res_val[li];
-        i0[r] = ln.y;
-        z2[r] = a.z2[ln.x];
-        v0[r] = sv.x;
-        v1[r] = sv.y;
-        P0[r] = P1[r] = 0.0;
-        const int j = r * 64 + lane;
-#pragma unroll
-        for (int c = 0; c < NC; c++) w[r][c] = j < nl ? (double)a.ws[((size_t)outb + j) * NC + c] : 0.0;
-    }
-    const size_t aoff = (size_t)m * (2 * a.L + 3 - m) / 2;
-    // component c = 2 b + (re, im) of row i lives at gb[i * 4 nmaps + c]
-    double *gb = a.g + 2 * ((aoff + t) * a.nmaps + a.map0);
-    const size_t gstride = 4 * (size_t)a.nmaps;
-    const int c_own = lane >> (6 - A);
-    const bool writer = (lane & ((1 << (6 - A)) - 1)) == 0 && !(m == 0 && (c_own & 1));
-    auto step = [&](int i) {
-        c_double *e = cfs + 4 * (t + 2 * i + 2);
-        const double eb = e[0], eab = e[1], eg = e[2];
-        double part[NC];
-#pragma unroll
-        for (int c = 0; c < NC; c++) part[c] = 0.0;
-#pragma unroll
-        for (int r = 0; r < R; r++) {
-#pragma unroll
-            for (int c = 0; c < NC; c++) part[c] = __builtin_fma(P0[r], w[r][c], part[c]);
-            const double P2 = __builtin_fma(__builtin_fma(z2[r], eb, eab), P1[r], eg * P0[r]);
-            P0[r] = P1[r];
-            P1[r] = P2;
-        }
-        const double tot = wave_transpose_sum<NC>(part, lane);
-        if (writer) atomicAdd(gb + (size_t)i * gstride + c_own, tot);
-    };
-    for (int c = imin; c < iend;) {
-#pragma unroll
-        for (int r = 0; r < R; r++)
-            if (i0[r] == c) {
-                P0[r] = v0[r];
-                P1[r] = v1[r];
-            }
-        const int ce = min(iend, (c & ~(kChunk - 1)) + kChunk);
-        if (ce - c == kChunk) {
-#pragma unroll
-            for (int u = 0; u < kChunk; u++) step(c + u);
-        } else {
-            for (int i = c; i < ce; i++) step(i);
-        }
-        c = ce;
-    }
-}
-
-template <int NB, typename S>
-__global__ __launch_bounds__(kBfThreads) void k_bf_residual_t(BfArgs<S> a, long long t0, long long t1) {
-    const int lane = threadIdx.x & 63;
-    const long long tk = t0 + (long long)blockIdx.x * (kBfThreads / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (tk >= t1) return;
-    const int4 h = a.res_task[2 * tk], h2 = a.res_task[2 * tk + 1];
-    const int t = __builtin_amdgcn_readfirstlane(h.x), imin = __builtin_amdgcn_readfirstlane(h.y);
-    const int iend = __builtin_amdgcn_readfirstlane(h.z), nl = __builtin_amdgcn_readfirstlane(h.w);
-    const int outb = __builtin_amdgcn_readfirstlane(h2.x), m = __builtin_amdgcn_readfirstlane(h2.y);
-    c_double *cfs = (c_double *)(a.coef + 4 * a.coef_off[m]);
-    if constexpr (kBfTaskRings > 192) {
-        if (nl > 192) return residual_task_t<NB, 4>(a, tk, lane, t, imin, iend, nl, outb, m, cfs);
-    }
-    if constexpr (kBfTaskRings > 128) {
-        if (nl > 128) return residual_task_t<NB, 3>(a, tk, lane, t, imin, iend, nl, outb, m, cfs);
-    }
-    if constexpr (kBfTaskRings > 64) {
-        if (nl > 64) return residual_task_t<NB, 2>(a, tk, lane, t, imin, iend, nl, outb, m, cfs);
-    }
-    residual_task_t<NB, 1>(a, tk, lane, t, imin, iend, nl, outb, m, cfs);
-}
-
-// g = 0 over the nalm rows of maps [map0, map0 + nb) (a kernel, not a
-// memset, so that the adjoint can be captured into a graph).
-__global__ __launch_bounds__(kBfThreads) void k_bf_zero(double *g, long long nalm, int nmaps, int map0, int nb) {
-    const long long e = (long long)blockIdx.x * kBfThreads + threadIdx.x;
-    if (e >= nalm * nb * 2) return;
-    const long long row = e / (2 * nb);
-    const int rest = (int)(e % (2 * nb));
-    g[2 * (row * nmaps + map0) + rest] = 0.0;
-}
-
-static int bf_nb(int nmaps) { return nmaps >= 8 ? 8 : nmaps >= 4 ? 4 : nmaps >= 2 ? 2 : 1; }
-
 size_t bf_scratch_bytes(const sht_plan_s *p, int nmaps, int fp32) {
     return (size_t)p->bf.ws_entries * 2 * bf_nb(nmaps) * (fp32 ? sizeof(float) : sizeof(double));
 }
@@ -721,26 +367,9 @@ static hipError_t launch_bf_nb(const sht_plan_s *p, BfArgs<S> a, hipStream_t st,
 template <typename S>
 static hipError_t launch_bf(const sht_plan_s *p, int nmaps, const double *alm, double *q, S *ws, const S *T,
                             hipStream_t st, void *const *ev) {
-    BfArgs<S> a;
-    a.res_task = reinterpret_cast<const int4 *>(p->d_bf_res_task);
-    a.res_sub = reinterpret_cast<const int4 *>(p->d_bf_res_sub);
-    a.res_lane = reinterpret_cast<const int2 *>(p->d_bf_res_lane);
-    a.res_val = reinterpret_cast<const double2 *>(p->d_bf_res_val);
-    a.perm = p->d_bf_perm;
-    a.node_i = p->d_bf_node_i;
-    a.T = T;
-    a.z2 = p->d_z2_hi;
-    a.coef_off = p->d_coef_off;
-    a.coef = p->d_coef_hi;
+    BfArgs<S> a = bf_args<S>(p, nmaps, T, ws);
     a.alm = reinterpret_cast<const double2 *>(alm);
     a.q = reinterpret_cast<double2 *>(q);
-    a.ws = ws;
-    a.ybar = nullptr;
-    a.g = nullptr;
-    a.L = p->L;
-    a.K = p->bf.K;
-    a.nrings = p->nrings;
-    a.nmaps = nmaps;
     hipError_t e = hipSuccess;
     for (int b = 0; b < nmaps && e == hipSuccess;) {
         const int nb = bf_nb(nmaps - b);
@@ -754,78 +383,6 @@ static hipError_t launch_bf(const sht_plan_s *p, int nmaps, const double *alm, d
         b += nb;
     }
     return e;
-}
-
-template <int NB, typename S>
-static hipError_t launch_bf_adj_nb(const sht_plan_s *p, BfArgs<S> a, hipStream_t st) {
-    constexpr int WPB = kBfThreads / 64;
-    const BflyPlan &b = p->bf;
-    const long long nalm = (long long)(p->L + 1) * (p->L + 2) / 2;
-    hipLaunchKernelGGL(k_bf_zero, dim3((unsigned)((nalm * NB * 2 + kBfThreads - 1) / kBfThreads)), dim3(kBfThreads), 0,
-                       st, a.g, nalm, a.nmaps, a.map0, NB);
-    for (int bt = 0; bt < b.nbatch; bt++) {
-        const long long nf = (long long)b.batch_count[bt] * b.K * NB;
-        if (nf > 0)
-            hipLaunchKernelGGL((k_bf_unfold<NB, S>), dim3((unsigned)((nf + kBfThreads - 1) / kBfThreads)),
-                               dim3(kBfThreads), 0, st, a, bt, b.nbatch, b.batch_count[bt]);
-        const long long *lo = b.lv_off.data() + (size_t)bt * (kBfMaxLv + 1);
-        for (int q = kBfMaxLv - 1; q >= 0; q--) {
-            const long long n0 = lo[q], n1 = lo[q + 1];
-            if (n1 <= n0) continue;
-            const size_t lds = (size_t)b.lv_max_n[(size_t)bt * kBfMaxLv + q] * 2 * NB * sizeof(S);
-            hipLaunchKernelGGL((k_bf_level_t<NB, S>), dim3((unsigned)(n1 - n0)), dim3(kBfLevelThreads), lds, st, a,
-                               n0);
-        }
-        const long long t0 = b.batch_task[bt], t1 = b.batch_task[bt + 1];
-        if (t1 > t0)
-            hipLaunchKernelGGL((k_bf_residual_t<NB, S>), dim3((unsigned)((t1 - t0 + WPB - 1) / WPB)),
-                               dim3(kBfThreads), 0, st, a, t0, t1);
-    }
-    return hipGetLastError();
-}
-
-template <typename S>
-static hipError_t launch_bf_adj(const sht_plan_s *p, int nmaps, const double *ybar, double *g, S *ws, const S *T,
-                                hipStream_t st) {
-    BfArgs<S> a;
-    a.res_task = reinterpret_cast<const int4 *>(p->d_bf_res_task);
-    a.res_sub = reinterpret_cast<const int4 *>(p->d_bf_res_sub);
-    a.res_lane = reinterpret_cast<const int2 *>(p->d_bf_res_lane);
-    a.res_val = reinterpret_cast<const double2 *>(p->d_bf_res_val);
-    a.perm = p->d_bf_perm;
-    a.node_i = p->d_bf_node_i;
-    a.T = T;
-    a.z2 = p->d_z2_hi;
-    a.coef_off = p->d_coef_off;
-    a.coef = p->d_coef_hi;
-    a.alm = nullptr;
-    a.q = nullptr;
-    a.ws = ws;
-    a.ybar = reinterpret_cast<const double2 *>(ybar);
-    a.g = g;
-    a.L = p->L;
-    a.K = p->bf.K;
-    a.nrings = p->nrings;
-    a.nmaps = nmaps;
-    hipError_t e = hipSuccess;
-    for (int b = 0; b < nmaps && e == hipSuccess;) {
-        const int nb = bf_nb(nmaps - b);
-        a.map0 = b;
-        switch (nb) {
-            case 8: e = launch_bf_adj_nb<8, S>(p, a, st); break;
-            case 4: e = launch_bf_adj_nb<4, S>(p, a, st); break;
-            case 2: e = launch_bf_adj_nb<2, S>(p, a, st); break;
-            default: e = launch_bf_adj_nb<1, S>(p, a, st); break;
-        }
-        b += nb;
-    }
-    return e;
-}
-
-hipError_t launch_butterfly_adjoint(const sht_plan_s *p, int nmaps, const double *ybar, double *g, void *scratch,
-                                    int fp32, hipStream_t stream) {
-    if (fp32) return launch_bf_adj<float>(p, nmaps, ybar, g, (float *)scratch, p->d_bf_T32, stream);
-    return launch_bf_adj<double>(p, nmaps, ybar, g, (double *)scratch, p->d_bf_T, stream);
 }
 
 hipError_t launch_butterfly(const sht_plan_s *p, int nmaps, const double *alm, double *q, void *scratch,

@@ -1,0 +1,100 @@
+// Shared pieces of the butterfly kernels (Sec. 4.2, App. A.1): the argument
+// block every butterfly kernel receives, the wave shapes of the level
+// launches, and the 16x16x4 matrix-core product with its lane layout.
+#pragma once
+#include "internal.h"
+
+namespace sht {
+
+
+template <typename S>
+struct BfArgs {
+    const int4 *__restrict__ res_task;
+    const int4 *__restrict__ res_sub;
+    const int2 *__restrict__ res_lane;
+    const double2 *__restrict__ res_val;
+    const int16_t *__restrict__ perm;
+    const int *__restrict__ node_i;
+    const S *__restrict__ T;
+    const double *__restrict__ z2;
+    const long long *__restrict__ coef_off;
+    const double *__restrict__ coef;
+    const double2 *__restrict__ alm;
+    double2 *__restrict__ q;
+    S *__restrict__ ws;  // vector workspace, entries of 2 NB values
+    const double2 *__restrict__ ybar;  // adjoint input [ring][m][nmaps]
+    double *__restrict__ g;            // adjoint output [nalm][nmaps] complex
+    int L, K, nrings, nmaps, map0;
+};
+
+constexpr int kBfThreads = 256;
+
+// Read-only operands that every lane of a wave needs at the same address
+// (a_lm rows, recurrence coefficients) are read through the constant
+// address space so that they arrive by scalar loads into SGPRs.
+typedef const __attribute__((address_space(4))) double c_double;
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+template <typename S>
+struct Acc;
+template <>
+struct Acc<double> {
+    typedef d4_t type;
+};
+template <>
+struct Acc<float> {
+    typedef f4_t type;
+};
+
+// D(16x16) += A(16x4) B(4x16) on the matrix cores.  Lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16].  Element r of the accumulator of
+// lane l is D[acc_row(l / 16, r)][l % 16]: row 4 (l / 16) + r for FP32, row
+// l / 16 + 4 r for FP64 (measured on gfx950).
+__device__ __forceinline__ d4_t mfma_16x16x4(double a, double b, d4_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4_t mfma_16x16x4(float a, float b, f4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+template <typename S>
+__device__ __forceinline__ int acc_row(int k4, int r) {
+    return sizeof(S) == 8 ? k4 + 4 * r : 4 * k4 + r;
+}
+
+// Waves per child of a pair node: each takes 4 / kBfHalves of a group's
+// 16-row tiles; a level workgroup holds one wave per child and half.
+constexpr int kBfHalves = 1;
+constexpr int kBfLevelThreads = 128 * kBfHalves;
+
+inline int bf_nb(int nmaps) { return nmaps >= 8 ? 8 : nmaps >= 4 ? 4 : nmaps >= 2 ? 2 : 1; }
+
+// The plan-dependent fields of BfArgs; the caller sets the operands of its
+// direction (alm, q or ybar, g) and map0.
+template <typename S>
+inline BfArgs<S> bf_args(const sht_plan_s *p, int nmaps, const S *T, S *ws) {
+    BfArgs<S> a;
+    a.res_task = reinterpret_cast<const int4 *>(p->d_bf_res_task);
+    a.res_sub = reinterpret_cast<const int4 *>(p->d_bf_res_sub);
+    a.res_lane = reinterpret_cast<const int2 *>(p->d_bf_res_lane);
+    a.res_val = reinterpret_cast<const double2 *>(p->d_bf_res_val);
+    a.perm = p->d_bf_perm;
+    a.node_i = p->d_bf_node_i;
+    a.T = T;
+    a.z2 = p->d_z2_hi;
+    a.coef_off = p->d_coef_off;
+    a.coef = p->d_coef_hi;
+    a.alm = nullptr;
+    a.q = nullptr;
+    a.ws = ws;
+    a.ybar = nullptr;
+    a.g = nullptr;
+    a.L = p->L;
+    a.K = p->bf.K;
+    a.nrings = p->nrings;
+    a.nmaps = nmaps;
+    a.map0 = 0;
+    return a;
+}
+
+}  // namespace sht
