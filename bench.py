@@ -259,8 +259,9 @@ def main():
     alm = alm_gaussian(L, seeds)
     log(f"[bench] building plan (eps={args.eps})")
     t0 = time.perf_counter()
+    # the transposed matrix copy serves the adjoint of the gradient measurement
     plan = sht.Plan(L, N, args.eps, rings_per_lane=args.rings_per_lane, ring_threads=args.ring_threads,
-                    rho=args.rho, store_fp32=args.eps > 0)
+                    rho=args.rho, store_fp32=args.eps > 0, store_transpose=args.eps > 0 and not args.no_adjoint)
     info = plan.info()
     log(f"[bench] plan built in {time.perf_counter() - t0:.1f}s: n_step={info['n_step']:.4e} "
         f"dd_rings={info['n_dd_rings']} butterfly={info['bf_built']} T={info['bf_T_entries']:.4e} "

@@ -121,6 +121,13 @@ typedef struct sht_plan_opts {
     int batch_mib;     /* > 0: run the orders in batches whose level vectors (at
                           4 maps, FP64) stay under this many MiB between
                           launches; 0 (default): all orders in one batch */
+    int store_transpose; /* 1: also keep every interpolation matrix transposed
+                          (and, with store_fp32, its FP32 copy), so that the
+                          adjoint streams them with the same coalesced loads as
+                          the synthesis; doubles the device memory of the
+                          matrices.  0 (default): the adjoint reads the
+                          synthesis copy with strided loads (same results up
+                          to rounding, slower) */
 } sht_plan_opts;
 
 /* Options for one execution.  Fill with sht_exec_opts_default() first. */

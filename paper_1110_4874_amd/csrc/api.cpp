@@ -191,6 +191,7 @@ void sht_plan_opts_default(sht_plan_opts *o) {
     o->id_safety = 0.0;
     o->store_fp32 = 0;
     o->batch_mib = 0;
+    o->store_transpose = 0;
 }
 
 void sht_exec_opts_default(sht_exec_opts *o) {

@@ -1,10 +1,15 @@
 // Adjoint of the butterfly-compressed Legendre phase (Sec. 4.2 and App. A.1
 // of the Wavemoth paper): g^t = Lambda ybar^t (Sec. 2.4 Eq. 12 transposed)
 // runs the factorization backwards, per batch of orders:
-//  1. k_bf_unfold: the level-1 vectors get ybar(z) +- ybar(-z) per north ring;
-//  2. k_bf_level_t, level 1 first: each pair node splits u into its children,
-//     v_ch = A~_ch u (identity rows gather u, the dense part T U runs on the
-//     matrix cores), so no two waves write one entry;
+//  1. level 1 takes ybar^even = ybar(z) + ybar(-z) and ybar^odd =
+//     ybar(z) - ybar(-z) per north ring (Eqs. 13-14 transposed):
+//     k_bf_unfold_level1 builds both for the two level-1 nodes of one order
+//     and ring range in LDS and splits them at once; orders whose parities
+//     split differently get their level-1 vectors from k_bf_unfold and run
+//     k_bf_level_t over the listed level-1 nodes;
+//  2. k_bf_level_t, level 2 and down: each pair node splits u into its
+//     children, v_ch = A~_ch u (identity rows gather u, the dense part T U
+//     runs on the matrix cores), so no two waves write one entry;
 //  3. k_bf_residual_t: one wave per residual task regenerates the Legendre
 //     values of its skeleton rings row by row, reduces sum_z P~(z) v(z) over
 //     the wave with lane swaps and DPP, and adds the row's result to g with
@@ -15,17 +20,19 @@
 
 namespace sht {
 
-// Unfold of one batch: slot j (order m = batch + j nbatch) gets ybar^even and
-// ybar^odd of every north ring in its level-1 vectors (the equator once).
+// Unfold of the listed slots of one batch: slot j (order m = batch + j
+// nbatch) gets ybar^even and ybar^odd of every north ring in its level-1
+// vectors (the equator once).
 template <int NB, typename S>
-__global__ __launch_bounds__(kBfThreads) void k_bf_unfold(BfArgs<S> a, int batch, int nbatch, int count) {
+__global__ __launch_bounds__(kBfThreads) void k_bf_unfold(BfArgs<S> a, int batch, int nbatch,
+                                                          const int *__restrict__ slots, int count) {
     constexpr int NC = 2 * NB;
     const int K = a.K;
     const long long e = (long long)blockIdx.x * kBfThreads + threadIdx.x;
     if (e >= (long long)count * K * NB) return;
     const int b = (int)(e % NB);
     const long long jk = e / NB;
-    const int k = (int)(jk % K), j = (int)(jk / K);
+    const int k = (int)(jk % K), j = slots[jk / K];
     const int m = batch + j * nbatch;
     const int ks = a.nrings - 1 - k;
     const double2 yn = a.ybar[((size_t)k * (a.L + 1) + m) * a.nmaps + a.map0 + b];
@@ -43,12 +50,14 @@ __global__ __launch_bounds__(kBfThreads) void k_bf_unfold(BfArgs<S> a, int batch
 //   v_ch = A~_ch u:  v[s] = u[perm s] + sum_d T[s][d] u[perm (k + d)].
 // The dense part runs on the matrix cores with the skeleton rows s as the
 // output rows (four 16-row tiles sharing each U operand) and the dense
-// columns d as the reduction: per batch of kBfTJ K-steps, lane (i, kq) holds
-// columns d0 + kBfTJ kq + j, j < kBfTJ, so each lane reads kBfTJ contiguous
-// entries of a row of T.
+// columns d as the reduction, kBfTJ K-steps per batch of loads.  With the
+// transposed copy (TT, T^T row-major) lane (i, kq) of K-step j reads
+// T^T[d0 + 4 j + kq][s0 + i], 16 consecutive entries per row as in the
+// synthesis; otherwise it reads T[s0 + i][d0 + kBfTJ kq + j], kBfTJ
+// contiguous entries of 16 different rows.
 constexpr int kBfTJ = 2;  // K-steps per batch of loads in the transposed level
 
-template <int NB, typename S>
+template <int NB, bool TT, typename S>
 __device__ __forceinline__ void id_block_t(const BfArgs<S> &a, int node, int ch, int half, int lane, const S *u) {
     constexpr int TPW = 4 / kBfHalves;  // 16-row tiles per wave
     constexpr int NC = 2 * NB;
@@ -73,13 +82,13 @@ __device__ __forceinline__ void id_block_t(const BfArgs<S> &a, int node, int ch,
             S av[TPW][kBfTJ], bv[kBfTJ];
 #pragma unroll
             for (int j = 0; j < kBfTJ; j++) {
-                const int d = d0 + kBfTJ * k4 + j;
+                const int d = TT ? d0 + 4 * j + k4 : d0 + kBfTJ * k4 + j;
                 const bool dv = d < nd;
                 bv[j] = (dv && i16 < NC) ? u[pm[kk + d] * NC + i16] : (S)0;
 #pragma unroll
                 for (int tt = 0; tt < TPW; tt++) {
                     const int sr = s0 + 16 * tt + i16;
-                    av[tt][j] = (dv && sr < kk) ? Tb[(unsigned)(sr * nd + d)] : (S)0;
+                    av[tt][j] = (dv && sr < kk) ? Tb[TT ? (unsigned)(d * kk + sr) : (unsigned)(sr * nd + d)] : (S)0;
                 }
             }
 #pragma unroll
@@ -102,19 +111,64 @@ __device__ __forceinline__ void id_block_t(const BfArgs<S> &a, int node, int ch,
 
 // One workgroup of 2 kBfHalves waves per pair node: u is staged in LDS, then
 // wave w writes half w / 2 of the rows of child w % 2's vector.
-template <int NB, typename S>
-__global__ __launch_bounds__(kBfLevelThreads) void k_bf_level_t(BfArgs<S> a, long long n0) {
+template <int NB, bool TT, typename S>
+__device__ __forceinline__ void level_node_t(const BfArgs<S> &a, int node) {
     constexpr int NC = 2 * NB;
     extern __shared__ char lds_raw[];
     S *u = reinterpret_cast<S *>(lds_raw);
-    const int node = (int)(n0 + blockIdx.x);
     const int *ni = a.node_i + (size_t)node * kBfNodeInts;
     const int n = ni[2] + ni[4];
     const S *__restrict__ in = a.ws + (size_t)ni[6] * NC;
     for (int e = threadIdx.x; e < n * NC; e += kBfLevelThreads) u[e] = in[e];
     __syncthreads();
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    id_block_t<NB, S>(a, node, w & 1, w >> 1, threadIdx.x & 63, u);
+    id_block_t<NB, TT, S>(a, node, w & 1, w >> 1, threadIdx.x & 63, u);
+}
+
+template <int NB, bool TT, typename S>
+__global__ __launch_bounds__(kBfLevelThreads) void k_bf_level_t(BfArgs<S> a, long long n0) {
+    level_node_t<NB, TT, S>(a, (int)(n0 + blockIdx.x));
+}
+
+// Level-1 nodes that run alone (their order was unfolded beforehand).
+template <int NB, bool TT, typename S>
+__global__ __launch_bounds__(kBfLevelThreads) void k_bf_level_t_list(BfArgs<S> a, const int *__restrict__ list,
+                                                                     long long n0) {
+    level_node_t<NB, TT, S>(a, list[n0 + blockIdx.x]);
+}
+
+// Unfold fused with level 1 (Eqs. 13-14 transposed): one workgroup per unit
+// {even node, odd node, first ring k0, slot}; both nodes cover the rings
+// k0 .. k0+n-1 of one order, so ybar^even and ybar^odd of those rings are
+// built in LDS from the two hemispheres' ybar and split by both nodes at once.
+constexpr int kBfUnfoldThreads = 2 * kBfLevelThreads;
+
+template <int NB, bool TT, typename S>
+__global__ __launch_bounds__(kBfUnfoldThreads) void k_bf_unfold_level1(BfArgs<S> a, const int4 *__restrict__ units,
+                                                                       long long u0, int batch, int nbatch) {
+    constexpr int NC = 2 * NB;
+    extern __shared__ char lds_raw[];
+    const int4 un = units[u0 + blockIdx.x];
+    const int *nie = a.node_i + (size_t)un.x * kBfNodeInts;
+    const int n = nie[2] + nie[4];
+    S *uE = reinterpret_cast<S *>(lds_raw);
+    S *uO = uE + (size_t)n * NC;
+    const int m = batch + un.w * nbatch, k0 = un.z;
+    for (int e = threadIdx.x; e < n * NB; e += kBfUnfoldThreads) {
+        const int c = e / NB, b = e % NB;
+        const int k = k0 + c, ks = a.nrings - 1 - k;
+        const double2 yn = a.ybar[((size_t)k * (a.L + 1) + m) * a.nmaps + a.map0 + b];
+        const double2 ys =
+            ks != k ? a.ybar[((size_t)ks * (a.L + 1) + m) * a.nmaps + a.map0 + b] : make_double2(0.0, 0.0);
+        uE[c * NC + 2 * b] = (S)(yn.x + ys.x);
+        uE[c * NC + 2 * b + 1] = (S)(yn.y + ys.y);
+        uO[c * NC + 2 * b] = (S)(yn.x - ys.x);
+        uO[c * NC + 2 * b + 1] = (S)(yn.y - ys.y);
+    }
+    __syncthreads();
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int par = w / (2 * kBfHalves), wc = w % (2 * kBfHalves);
+    id_block_t<NB, TT, S>(a, par ? un.y : un.x, wc & 1, wc >> 1, threadIdx.x & 63, par ? uO : uE);
 }
 
 // Lane exchanges for the wave reductions.  permlane32_swap(a, b) leaves
@@ -299,7 +353,7 @@ __global__ __launch_bounds__(kBfThreads) void k_bf_zero(double *g, long long nal
     g[2 * (row * nmaps + map0) + rest] = 0.0;
 }
 
-template <int NB, typename S>
+template <int NB, bool TT, typename S>
 static hipError_t launch_bf_adj_nb(const sht_plan_s *p, BfArgs<S> a, hipStream_t st) {
     constexpr int WPB = kBfThreads / 64;
     const BflyPlan &b = p->bf;
@@ -307,16 +361,27 @@ static hipError_t launch_bf_adj_nb(const sht_plan_s *p, BfArgs<S> a, hipStream_t
     hipLaunchKernelGGL(k_bf_zero, dim3((unsigned)((nalm * NB * 2 + kBfThreads - 1) / kBfThreads)), dim3(kBfThreads), 0,
                        st, a.g, nalm, a.nmaps, a.map0, NB);
     for (int bt = 0; bt < b.nbatch; bt++) {
-        const long long nf = (long long)b.batch_count[bt] * b.K * NB;
+        // level 1: fused with the unfold where both parities have levels
+        const long long s0 = b.fold_off[bt], s1 = b.fold_off[bt + 1];
+        const long long nf = (s1 - s0) * b.K * NB;
         if (nf > 0)
             hipLaunchKernelGGL((k_bf_unfold<NB, S>), dim3((unsigned)((nf + kBfThreads - 1) / kBfThreads)),
-                               dim3(kBfThreads), 0, st, a, bt, b.nbatch, b.batch_count[bt]);
+                               dim3(kBfThreads), 0, st, a, bt, b.nbatch, p->d_bf_fold_slot + s0, (int)(s1 - s0));
+        const size_t lds1 = (size_t)b.lv_max_n[(size_t)bt * kBfMaxLv + kBfMaxLv - 1] * 2 * NB * sizeof(S);
+        const long long p0 = b.l1_off[bt], p1 = b.l1_off[bt + 1];
+        if (p1 > p0)
+            hipLaunchKernelGGL((k_bf_level_t_list<NB, TT, S>), dim3((unsigned)(p1 - p0)), dim3(kBfLevelThreads), lds1, st,
+                               a, p->d_bf_l1_plain, p0);
+        const long long f0 = b.f1_off[bt], f1 = b.f1_off[bt + 1];
+        if (f1 > f0)
+            hipLaunchKernelGGL((k_bf_unfold_level1<NB, TT, S>), dim3((unsigned)(f1 - f0)), dim3(kBfUnfoldThreads), 2 * lds1,
+                               st, a, reinterpret_cast<const int4 *>(p->d_bf_f1_unit), f0, bt, b.nbatch);
         const long long *lo = b.lv_off.data() + (size_t)bt * (kBfMaxLv + 1);
-        for (int q = kBfMaxLv - 1; q >= 0; q--) {
+        for (int q = kBfMaxLv - 2; q >= 0; q--) {  // levels >= 2
             const long long n0 = lo[q], n1 = lo[q + 1];
             if (n1 <= n0) continue;
             const size_t lds = (size_t)b.lv_max_n[(size_t)bt * kBfMaxLv + q] * 2 * NB * sizeof(S);
-            hipLaunchKernelGGL((k_bf_level_t<NB, S>), dim3((unsigned)(n1 - n0)), dim3(kBfLevelThreads), lds, st, a,
+            hipLaunchKernelGGL((k_bf_level_t<NB, TT, S>), dim3((unsigned)(n1 - n0)), dim3(kBfLevelThreads), lds, st, a,
                                n0);
         }
         const long long t0 = b.batch_task[bt], t1 = b.batch_task[bt + 1];
@@ -329,19 +394,28 @@ static hipError_t launch_bf_adj_nb(const sht_plan_s *p, BfArgs<S> a, hipStream_t
 
 template <typename S>
 static hipError_t launch_bf_adj(const sht_plan_s *p, int nmaps, const double *ybar, double *g, S *ws, const S *T,
-                                hipStream_t st) {
-    BfArgs<S> a = bf_args<S>(p, nmaps, T, ws);
+                                const S *Tt, hipStream_t st) {
+    BfArgs<S> a = bf_args<S>(p, nmaps, Tt ? Tt : T, ws);
     a.ybar = reinterpret_cast<const double2 *>(ybar);
     a.g = g;
     hipError_t e = hipSuccess;
     for (int b = 0; b < nmaps && e == hipSuccess;) {
         const int nb = bf_nb(nmaps - b);
         a.map0 = b;
-        switch (nb) {
-            case 8: e = launch_bf_adj_nb<8, S>(p, a, st); break;
-            case 4: e = launch_bf_adj_nb<4, S>(p, a, st); break;
-            case 2: e = launch_bf_adj_nb<2, S>(p, a, st); break;
-            default: e = launch_bf_adj_nb<1, S>(p, a, st); break;
+        if (Tt) {
+            switch (nb) {
+                case 8: e = launch_bf_adj_nb<8, true, S>(p, a, st); break;
+                case 4: e = launch_bf_adj_nb<4, true, S>(p, a, st); break;
+                case 2: e = launch_bf_adj_nb<2, true, S>(p, a, st); break;
+                default: e = launch_bf_adj_nb<1, true, S>(p, a, st); break;
+            }
+        } else {
+            switch (nb) {
+                case 8: e = launch_bf_adj_nb<8, false, S>(p, a, st); break;
+                case 4: e = launch_bf_adj_nb<4, false, S>(p, a, st); break;
+                case 2: e = launch_bf_adj_nb<2, false, S>(p, a, st); break;
+                default: e = launch_bf_adj_nb<1, false, S>(p, a, st); break;
+            }
         }
         b += nb;
     }
@@ -350,8 +424,47 @@ static hipError_t launch_bf_adj(const sht_plan_s *p, int nmaps, const double *yb
 
 hipError_t launch_butterfly_adjoint(const sht_plan_s *p, int nmaps, const double *ybar, double *g, void *scratch,
                                     int fp32, hipStream_t stream) {
-    if (fp32) return launch_bf_adj<float>(p, nmaps, ybar, g, (float *)scratch, p->d_bf_T32, stream);
-    return launch_bf_adj<double>(p, nmaps, ybar, g, (double *)scratch, p->d_bf_T, stream);
+    if (fp32) return launch_bf_adj<float>(p, nmaps, ybar, g, (float *)scratch, p->d_bf_T32, p->d_bf_Tt32, stream);
+    return launch_bf_adj<double>(p, nmaps, ybar, g, (double *)scratch, p->d_bf_T, p->d_bf_Tt, stream);
+}
+
+// Transposed copy of every interpolation block: child ch of a pair node keeps
+// its kk x nd matrix T row-major at toff; Tt receives the nd x kk transpose
+// at the same offset.  One workgroup per (node, child).
+template <typename S>
+__global__ __launch_bounds__(kBfThreads) void k_bf_transpose_blocks(const int *__restrict__ node_i,
+                                                                    const S *__restrict__ T, S *__restrict__ Tt) {
+    const int *ni = node_i + (size_t)(blockIdx.x >> 1) * kBfNodeInts;
+    const int ch = blockIdx.x & 1;
+    const int kk = ni[2 + ch], nd = ni[4 + ch];
+    const long long toff = (long long)(unsigned)ni[12 + 2 * ch] | ((long long)ni[13 + 2 * ch] << 32);
+    const int n = kk * nd;
+    for (int f = threadIdx.x; f < n; f += kBfThreads) {
+        const int d = f / kk, s = f - d * kk;
+        Tt[toff + f] = T[toff + (long long)s * nd + d];
+    }
+}
+
+hipError_t bf_store_transposed(sht_plan_s *p, size_t nT, size_t nnodes, size_t *bytes) {
+    const size_t n = std::max<size_t>(nT, 1);
+    if (2 * nnodes > 0xFFFFFFFFull) return hipErrorInvalidValue;
+    hipError_t e = hipMalloc((void **)&p->d_bf_Tt, n * sizeof(double));
+    if (e != hipSuccess) return e;
+    *bytes += n * sizeof(double);
+    if (nnodes)
+        hipLaunchKernelGGL(k_bf_transpose_blocks<double>, dim3((unsigned)(2 * nnodes)), dim3(kBfThreads), 0, 0,
+                           p->d_bf_node_i, p->d_bf_T, p->d_bf_Tt);
+    if (p->d_bf_T32) {
+        e = hipMalloc((void **)&p->d_bf_Tt32, n * sizeof(float));
+        if (e != hipSuccess) return e;
+        *bytes += n * sizeof(float);
+        if (nnodes)
+            hipLaunchKernelGGL(k_bf_transpose_blocks<float>, dim3((unsigned)(2 * nnodes)), dim3(kBfThreads), 0, 0,
+                               p->d_bf_node_i, p->d_bf_T32, p->d_bf_Tt32);
+    }
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    return e;
 }
 
 }  // namespace sht

@@ -143,6 +143,8 @@ struct sht_plan_s {
     int *d_bf_res_task = nullptr, *d_bf_res_lane = nullptr, *d_bf_res_sub = nullptr;
     double *d_bf_res_val = nullptr, *d_bf_T = nullptr;
     float *d_bf_T32 = nullptr;
+    double *d_bf_Tt = nullptr;  // transposed copies for the adjoint (store_transpose)
+    float *d_bf_Tt32 = nullptr;
     int16_t *d_bf_perm = nullptr;
     int *d_bf_node_i = nullptr;
     int *d_bf_f1_unit = nullptr, *d_bf_l1_plain = nullptr, *d_bf_fold_slot = nullptr;
@@ -179,5 +181,9 @@ hipError_t launch_butterfly(const sht_plan_s *p, int nmaps, const double *alm, d
 // with the same scratch.
 hipError_t launch_butterfly_adjoint(const sht_plan_s *p, int nmaps, const double *ybar, double *g, void *scratch,
                                     int fp32, hipStream_t stream);
+// Device-side transposed copies of the interpolation matrices (d_bf_Tt and,
+// when the FP32 copy exists, d_bf_Tt32) from the uploaded ones; nT entries,
+// nnodes pair nodes.  Adds the allocated bytes to *bytes.
+hipError_t bf_store_transposed(sht_plan_s *p, size_t nT, size_t nnodes, size_t *bytes);
 
 }  // namespace sht

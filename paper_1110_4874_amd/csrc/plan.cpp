@@ -553,6 +553,8 @@ int upload_tables(sht_plan_s *p) {
                 e = hipMemcpy(p->d_bf_T32 + o, buf.data(), cnt * sizeof(float), hipMemcpyHostToDevice);
             }
         }
+        if (e == hipSuccess && p->opts.store_transpose)
+            e = bf_store_transposed(p, f.T.size(), f.node_i.size() / kBfNodeInts, &b);
         // large interpolation data lives on the device only
         if (e == hipSuccess && f.T.size() * sizeof(double) > ((size_t)256 << 20)) {
             std::vector<double>().swap(f.T);
@@ -574,7 +576,7 @@ void free_device_tables(sht_plan_s *p) {
                     p->d_start_idx, p->d_start_val, p->d_start_lo,   p->d_grp_lo,   p->d_grp_hi,
                     p->d_tw,        p->d_bs_table,  p->d_chirp,      p->d_ring_chirp_off,
                     p->d_bf_res_task, p->d_bf_res_lane, p->d_bf_res_sub,
-                    p->d_bf_res_val, p->d_bf_T,      p->d_bf_T32,   p->d_bf_perm,
+                    p->d_bf_res_val, p->d_bf_T,      p->d_bf_T32,   p->d_bf_Tt,    p->d_bf_Tt32, p->d_bf_perm,
                     p->d_bf_node_i, p->d_bf_f1_unit, p->d_bf_l1_plain, p->d_bf_fold_slot};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
@@ -593,6 +595,8 @@ void free_device_tables(sht_plan_s *p) {
     p->d_bf_res_task = p->d_bf_res_lane = p->d_bf_res_sub = nullptr;
     p->d_bf_res_val = p->d_bf_T = nullptr;
     p->d_bf_T32 = nullptr;
+    p->d_bf_Tt = nullptr;
+    p->d_bf_Tt32 = nullptr;
     p->d_bf_perm = nullptr;
     p->d_bf_node_i = nullptr;
     p->d_bf_f1_unit = p->d_bf_l1_plain = p->d_bf_fold_slot = nullptr;

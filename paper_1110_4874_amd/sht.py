@@ -30,7 +30,8 @@ class PlanOpts(_c.Structure):
     _fields_ = [("cutoff", _c.c_double), ("dd_sin", _c.c_double), ("nthreads", _c.c_int),
                 ("rings_per_lane", _c.c_int), ("ring_threads", _c.c_int), ("host_only", _c.c_int),
                 ("rho", _c.c_double), ("max_levels", _c.c_int), ("chunk", _c.c_int),
-                ("id_safety", _c.c_double), ("store_fp32", _c.c_int), ("batch_mib", _c.c_int)]
+                ("id_safety", _c.c_double), ("store_fp32", _c.c_int), ("batch_mib", _c.c_int),
+                ("store_transpose", _c.c_int)]
 
 
 class ExecOpts(_c.Structure):
@@ -147,7 +148,7 @@ class Plan:
 
     def __init__(self, L, nside, eps=0.0, *, cutoff=None, dd_sin=None, nthreads=0, rings_per_lane=0,
                  ring_threads=0, host_only=False, rho=0.0, max_levels=-1, chunk=0, id_safety=0.0,
-                 store_fp32=False, batch_mib=0):
+                 store_fp32=False, batch_mib=0, store_transpose=False):
         lib = load()
         o = PlanOpts()
         lib.sht_plan_opts_default(_c.byref(o))
@@ -157,6 +158,7 @@ class Plan:
         o.id_safety = float(id_safety)
         o.store_fp32 = 1 if store_fp32 else 0
         o.batch_mib = int(batch_mib)
+        o.store_transpose = 1 if store_transpose else 0
         if cutoff is not None:
             o.cutoff = cutoff
         if dd_sin is not None:

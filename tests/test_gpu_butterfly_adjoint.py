@@ -38,25 +38,27 @@ def _maps(N, B, seed0):
                                                     (511, 256, 1e-12, 4, 1, 0), (300, 128, 1e-10, 3, 9, 0),
                                                     (0, 1, 1e-12, -1, 1, 0), (9, 2, 1e-12, 1, 2, 0),
                                                     (255, 128, 1e-12, 3, 4, 1), (511, 256, 1e-12, 4, 2, 2)])
-def test_butterfly_adjoint_parity(gpu, L, N, eps, levels, B, batch):
+@pytest.mark.parametrize("tr", [False, True])
+def test_butterfly_adjoint_parity(gpu, L, N, eps, levels, B, batch, tr):
     maps = _maps(N, B, 700)
-    p = gpu.Plan(L, N, eps, max_levels=levels, batch_mib=batch)
+    p = gpu.Plan(L, N, eps, max_levels=levels, batch_mib=batch, store_transpose=tr)
     if batch:
         assert p.info()["bf_nbatch"] > 1
     g = p.adjoint(_dev(maps), path=sht.PATH_BUTTERFLY).cpu().numpy()
     ref = oracle.adjoint(L, N, maps)
     err = maxrel_cols(g, ref)
-    print(f"L={L} N={N} eps={eps} levels={levels} B={B} hist={p.info()['bf_depth_hist'][:6]} "
-          f"adjoint maxrel={err:.3e}")
+    print(f"L={L} N={N} eps={eps} levels={levels} B={B} transposed copy={tr} "
+          f"hist={p.info()['bf_depth_hist'][:6]} adjoint maxrel={err:.3e}")
     assert err <= eps + 1e-12
 
 
 @pytest.mark.parametrize("prec,tol", [(sht.PREC_FP64, 1e-13), (sht.PREC_FP32, 1e-5)])
-def test_butterfly_adjoint_is_transpose_of_butterfly_synthesis(gpu, prec, tol):
+@pytest.mark.parametrize("tr", [False, True])
+def test_butterfly_adjoint_is_transpose_of_butterfly_synthesis(gpu, prec, tol, tr):
     L, N, B = 255, 128, 3
     alm = alm_gaussian(L, [41, 42, 43])
     maps = _maps(N, B, 720)
-    p = gpu.Plan(L, N, 1e-8, max_levels=3, store_fp32=True)
+    p = gpu.Plan(L, N, 1e-8, max_levels=3, store_fp32=True, store_transpose=tr)
     f = p.synthesis(_dev(alm), path=sht.PATH_BUTTERFLY, precision=prec).cpu().numpy()
     g = p.adjoint(_dev(maps), path=sht.PATH_BUTTERFLY, precision=prec).cpu().numpy()
     for b in range(B):
@@ -67,10 +69,11 @@ def test_butterfly_adjoint_is_transpose_of_butterfly_synthesis(gpu, prec, tol):
         assert abs(lhs - rhs) <= tol * scale, (lhs, rhs)
 
 
-def test_butterfly_adjoint_fp32(gpu):
+@pytest.mark.parametrize("tr", [False, True])
+def test_butterfly_adjoint_fp32(gpu, tr):
     L, N, B = 255, 128, 4
     maps = _maps(N, B, 740)
-    p = gpu.Plan(L, N, 1e-7, max_levels=3, store_fp32=True)
+    p = gpu.Plan(L, N, 1e-7, max_levels=3, store_fp32=True, store_transpose=tr)
     g32 = p.adjoint(_dev(maps), path=sht.PATH_BUTTERFLY, precision=sht.PREC_FP32).cpu().numpy()
     g64 = p.adjoint(_dev(maps), path=sht.PATH_BUTTERFLY, precision=sht.PREC_FP64).cpu().numpy()
     ref = oracle.adjoint(L, N, maps)
@@ -78,6 +81,21 @@ def test_butterfly_adjoint_fp32(gpu):
     print(f"FP32 transposed level products maxrel={e32:.3e} (FP64 {e64:.3e})")
     assert e64 <= 1e-7 + 1e-12
     assert e32 <= 2e-5
+
+
+def test_butterfly_adjoint_transposed_copy_matches_strided(gpu):
+    # the transposed copy only changes the order of the dense sums
+    L, N, B = 511, 256, 4
+    maps = _dev(_maps(N, B, 750))
+    pa = gpu.Plan(L, N, 1e-12, max_levels=4, store_fp32=True)
+    pb = gpu.Plan(L, N, 1e-12, max_levels=4, store_fp32=True, store_transpose=True)
+    assert pb.info()["device_bytes"] > pa.info()["device_bytes"]
+    for prec, tol in ((sht.PREC_FP64, 1e-14), (sht.PREC_FP32, 1e-6)):
+        ga = pa.adjoint(maps, path=sht.PATH_BUTTERFLY, precision=prec)
+        gb = pb.adjoint(maps, path=sht.PATH_BUTTERFLY, precision=prec)
+        err = float((ga - gb).abs().max() / ga.abs().max())
+        print(f"prec={prec} strided vs transposed copy: {err:.3e}")
+        assert err <= tol
 
 
 def test_butterfly_adjoint_every_entry_written(gpu):
