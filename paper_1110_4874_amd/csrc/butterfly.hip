@@ -28,20 +28,75 @@
 namespace sht {
 
 
-// One ID block (child ch of a pair node) on one wave:
-//   u += A~_ch^T v_ch  over the columns C the two sibling row blocks share.
-// The identity rows add v; the dense part T^T V (nd x k times k x NC) runs on
-// the matrix cores, 64 dense rows (four 16-row tiles sharing each V operand)
-// by kBfKSteps * 4 rows of T per batch of loads.  u is the workgroup's LDS
-// copy, zeroed before; the two children add into it with LDS atomics, and
-// since every entry receives exactly two addends onto zero the result does
-// not depend on their order.
-constexpr int kBfKSteps = 2;  // K-steps (4 rows of T each) per batch of loads
+// One ID block (child ch of a pair node) on one wave: child ch's share of
+//   u = A~_0^T v_0 + A~_1^T v_1
+// over the columns C the two sibling row blocks share.  Its column
+// permutation places every column of C exactly once, as a skeleton column
+// (u[perm s] = v[s]) or a dense one (u[perm (k + d)] = sum_s T[s][d] v[s]),
+// so the wave writes each entry of its own LDS buffer uc once, with plain
+// stores, and the two buffers are summed afterwards.  The dense part T^T V
+// (nd x k times k x NC) runs on the matrix cores, up to 64 dense rows (four
+// 16-row tiles sharing each V operand) by kBfKSteps * 4 rows of T per batch
+// of loads.  Loads take clamped (in-block) addresses and rows s past k are
+// masked by multiplying V with 0, so a batch issues all its loads without
+// branches; dense rows past nd and columns past NC only reach outputs that
+// are not stored.
+constexpr int kBfKSteps = 4;    // K-steps (4 rows of T each) per batch of loads
+constexpr int kBfIdUnroll = 4;  // identity entries per lane in flight
+
+// NT 16-row tiles of dense rows gw .. gw + 16 NT - 1 of one ID block:
+// uc[perm (k + d)] = sum_s T[s][d] v[s] (32-bit element offsets from
+// wave-uniform bases; the tile count is a template parameter so that the
+// products run back to back, without branches between them).
+template <int NT, int NB, typename S>
+__device__ __forceinline__ void dense_tiles(const S *__restrict__ v, const S *__restrict__ Tb,
+                                            const int16_t *__restrict__ pm, int kk, int nd, int gw, int lane,
+                                            S *uc) {
+    constexpr int NC = 2 * NB;
+    constexpr int KS = kBfKSteps;
+    typedef typename Acc<S>::type acc_t;
+    const int i16 = lane & 15, k4 = lane >> 4;
+    const int ic = min(i16, NC - 1);
+    acc_t acc[NT];
+#pragma unroll
+    for (int tt = 0; tt < NT; tt++) acc[tt] = acc_t{0, 0, 0, 0};
+    for (int s0 = 0; s0 < kk; s0 += 4 * KS) {
+        S av[KS][NT], bv[KS];
+#pragma unroll
+        for (int j = 0; j < KS; j++) {
+            const int s = s0 + 4 * j + k4, sc = min(s, kk - 1);
+            bv[j] = ld32(v, sc * NC + ic) * (S)(s < kk);
+#pragma unroll
+            for (int tt = 0; tt < NT; tt++) av[j][tt] = ld32(Tb, sc * nd + min(gw + 16 * tt + i16, nd - 1));
+        }
+#pragma unroll
+        for (int j = 0; j < KS; j++)
+#pragma unroll
+            for (int tt = 0; tt < NT; tt++) acc[tt] = mfma_16x16x4(av[j][tt], bv[j], acc[tt]);
+    }
+    // the output rows' positions in C, all loads issued before the first
+    // store (the empty asm keeps the compiler from moving each load into
+    // its store's branch, which would wait on them one by one)
+    int pr[NT][4];
+#pragma unroll
+    for (int tt = 0; tt < NT; tt++)
+#pragma unroll
+        for (int r = 0; r < 4; r++) pr[tt][r] = pm[kk + min(gw + 16 * tt + acc_row<S>(k4, r), nd - 1)];
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int tt = 0; tt < NT; tt++)
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const int dd = gw + 16 * tt + acc_row<S>(k4, r);
+            if (dd < nd && i16 < NC) uc[pr[tt][r] * NC + i16] = acc[tt][r];
+        }
+}
 
 template <int NB, typename S>
-__device__ __forceinline__ void id_block(const BfArgs<S> &a, int node, int ch, int half, int lane, S *u) {
+__device__ __forceinline__ void id_block(const BfArgs<S> &a, int node, int ch, int half, int lane, S *uc) {
     constexpr int NC = 2 * NB;
     constexpr int TPW = 4 / kBfHalves;  // tiles per wave
+    constexpr int KS = kBfKSteps;
     typedef typename Acc<S>::type acc_t;
     const int *ni = a.node_i + (size_t)node * kBfNodeInts;
     const int n = ni[2] + ni[4];
@@ -50,50 +105,33 @@ __device__ __forceinline__ void id_block(const BfArgs<S> &a, int node, int ch, i
     const int16_t *__restrict__ pm = a.perm + ni[7] + (size_t)ch * n;
     const long long toff = (long long)(unsigned)ni[12 + 2 * ch] | ((long long)ni[13 + 2 * ch] << 32);
     const S *__restrict__ Tb = a.T + toff;
-    // identity rows
-    for (int e = lane + 64 * half; e < kk * NC; e += 64 * kBfHalves) {
-        const int s = e / NC, q = e - s * NC;
-        atomicAdd(&u[pm[s] * NC + q], v[(unsigned)e]);
-    }
-    // dense rows (32-bit element offsets from wave-uniform bases)
-    const int i16 = lane & 15, k4 = lane >> 4;
-    for (int g0 = 0; g0 < nd; g0 += 64) {
-        const int ntile = min(4, (nd - g0 + 15) >> 4) - half * TPW;  // tiles of this wave
-        if (ntile <= 0) continue;
-        const int gw = g0 + 16 * TPW * half;
-        acc_t acc[TPW];
+    // identity rows (lanes past the end repeat the last entry's store)
+    const int ne = kk * NC;
+    for (int e0 = 64 * half; e0 < ne; e0 += 64 * kBfHalves * kBfIdUnroll) {
+        S x[kBfIdUnroll];
+        int px[kBfIdUnroll];
 #pragma unroll
-        for (int tt = 0; tt < TPW; tt++) acc[tt] = acc_t{0, 0, 0, 0};
-        for (int s0 = 0; s0 < kk; s0 += 4 * kBfKSteps) {
-            S av[kBfKSteps][TPW], bv[kBfKSteps];
-#pragma unroll
-            for (int j = 0; j < kBfKSteps; j++) {
-                const int s = s0 + 4 * j + k4;
-                const bool sv = s < kk;
-                bv[j] = (sv && i16 < NC) ? v[(unsigned)(s * NC + i16)] : (S)0;
-#pragma unroll
-                for (int tt = 0; tt < TPW; tt++) {
-                    const int d = gw + 16 * tt + i16;
-                    av[j][tt] = (sv && d < nd) ? Tb[(unsigned)(s * nd + d)] : (S)0;
-                }
-            }
-            const int nj = min(kBfKSteps, (kk - s0 + 3) >> 2);
-#pragma unroll
-            for (int j = 0; j < kBfKSteps; j++) {
-                if (j >= nj) break;
-#pragma unroll
-                for (int tt = 0; tt < TPW; tt++)
-                    if (tt < ntile) acc[tt] = mfma_16x16x4(av[j][tt], bv[j], acc[tt]);
-            }
+        for (int j = 0; j < kBfIdUnroll; j++) {
+            const int ec = min(e0 + lane + 64 * kBfHalves * j, ne - 1);
+            x[j] = ld32(v, ec);
+            px[j] = pm[ec / NC];
         }
 #pragma unroll
-        for (int tt = 0; tt < TPW; tt++) {
-            if (tt >= ntile) break;
-#pragma unroll
-            for (int r = 0; r < 4; r++) {
-                const int dd = gw + 16 * tt + acc_row<S>(k4, r);
-                if (dd < nd && i16 < NC) atomicAdd(&u[pm[kk + dd] * NC + i16], acc[tt][r]);
-            }
+        for (int j = 0; j < kBfIdUnroll; j++) {
+            const int ec = min(e0 + lane + 64 * kBfHalves * j, ne - 1);
+            uc[px[j] * NC + ec % NC] = x[j];
+        }
+    }
+    // dense rows, in groups of 64
+    for (int g0 = 0; g0 < nd; g0 += 64) {
+        const int ntile = min(TPW, min(4, (nd - g0 + 15) >> 4) - half * TPW);  // tiles of this wave
+        const int gw = g0 + 16 * TPW * half;
+        switch (ntile) {
+            case 1: dense_tiles<1, NB, S>(v, Tb, pm, kk, nd, gw, lane, uc); break;
+            case 2: dense_tiles<2, NB, S>(v, Tb, pm, kk, nd, gw, lane, uc); break;
+            case 3: dense_tiles<3, NB, S>(v, Tb, pm, kk, nd, gw, lane, uc); break;
+            case 4: dense_tiles<4, NB, S>(v, Tb, pm, kk, nd, gw, lane, uc); break;
+            default: break;
         }
     }
 }
@@ -235,16 +273,15 @@ template <int NB, typename S>
 __device__ __forceinline__ void level_node(const BfArgs<S> &a, int node) {
     constexpr int NC = 2 * NB;
     extern __shared__ char lds_raw[];
-    S *u = reinterpret_cast<S *>(lds_raw);
+    S *u0 = reinterpret_cast<S *>(lds_raw);
     const int *ni = a.node_i + (size_t)node * kBfNodeInts;
     const int n = ni[2] + ni[4];
-    for (int e = threadIdx.x; e < n * NC; e += kBfLevelThreads) u[e] = (S)0;
-    __syncthreads();
+    S *u1 = u0 + (size_t)n * NC;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    id_block<NB, S>(a, node, w & 1, w >> 1, threadIdx.x & 63, u);
+    id_block<NB, S>(a, node, w & 1, w >> 1, threadIdx.x & 63, (w & 1) ? u1 : u0);
     __syncthreads();
     S *__restrict__ out = a.ws + (size_t)ni[6] * NC;
-    for (int e = threadIdx.x; e < n * NC; e += kBfLevelThreads) out[e] = u[e];
+    for (int e = threadIdx.x; e < n * NC; e += kBfLevelThreads) out[e] = u0[e] + u1[e];
 }
 
 template <int NB, typename S>
@@ -273,19 +310,19 @@ __global__ __launch_bounds__(kBfFoldThreads) void k_bf_level1_fold(BfArgs<S> a, 
     const int4 un = units[u0 + blockIdx.x];
     const int *nie = a.node_i + (size_t)un.x * kBfNodeInts;
     const int n = nie[2] + nie[4];
-    S *uE = reinterpret_cast<S *>(lds_raw);
-    S *uO = uE + (size_t)n * NC;
-    for (int e = threadIdx.x; e < 2 * n * NC; e += kBfFoldThreads) uE[e] = (S)0;
-    __syncthreads();
+    S *uE = reinterpret_cast<S *>(lds_raw);  // even node: children 0 and 1, then the odd node's
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int par = w / (2 * kBfHalves), wc = w % (2 * kBfHalves);
-    id_block<NB, S>(a, par ? un.y : un.x, wc & 1, wc >> 1, threadIdx.x & 63, par ? uO : uE);
+    id_block<NB, S>(a, par ? un.y : un.x, wc & 1, wc >> 1, threadIdx.x & 63,
+                    uE + (size_t)(2 * par + (wc & 1)) * n * NC);
     __syncthreads();
     const int m = batch + un.w * nbatch, k0 = un.z;
     for (int e = threadIdx.x; e < n * NB; e += kBfFoldThreads) {
         const int c = e / NB, b = e % NB;
-        double er = (double)uE[c * NC + 2 * b], ei = (double)uE[c * NC + 2 * b + 1];
-        double orr = (double)uO[c * NC + 2 * b], oi = (double)uO[c * NC + 2 * b + 1];
+        const S *e0 = uE + c * NC + 2 * b, *e1 = e0 + (size_t)n * NC, *o0 = e1 + (size_t)n * NC,
+                *o1 = o0 + (size_t)n * NC;
+        double er = (double)(e0[0] + e1[0]), ei = (double)(e0[1] + e1[1]);
+        double orr = (double)(o0[0] + o1[0]), oi = (double)(o0[1] + o1[1]);
         if (m == 0) ei = oi = 0.0;  // real field: Im a_l0 is ignored
         const int k = k0 + c, ks = a.nrings - 1 - k;
         a.q[((size_t)k * (a.L + 1) + m) * a.nmaps + a.map0 + b] = make_double2(er + orr, ei + oi);
@@ -341,12 +378,12 @@ static hipError_t launch_bf_nb(const sht_plan_s *p, BfArgs<S> a, hipStream_t st,
             const long long n0 = lo[q], n1 = lo[q + 1];
             if (n1 <= n0) continue;
             // LDS for the widest column set of this level only
-            const size_t lds = (size_t)b.lv_max_n[(size_t)bt * kBfMaxLv + q] * 2 * NB * sizeof(S);
+            const size_t lds = bf_level_lds<NB, S>(b.lv_max_n[(size_t)bt * kBfMaxLv + q]);
             hipLaunchKernelGGL((k_bf_level<NB, S>), dim3((unsigned)(n1 - n0)), dim3(kBfLevelThreads), lds, st, a, n0);
         }
         bf_event(ev, SHT_STAGE_BF_LEVELS, 1, st);
         // level 1: fused with the fold where both parities have levels
-        const size_t lds1 = (size_t)b.lv_max_n[(size_t)bt * kBfMaxLv + kBfMaxLv - 1] * 2 * NB * sizeof(S);
+        const size_t lds1 = bf_level_lds<NB, S>(b.lv_max_n[(size_t)bt * kBfMaxLv + kBfMaxLv - 1]);
         const long long p0 = b.l1_off[bt], p1 = b.l1_off[bt + 1];
         if (p1 > p0)
             hipLaunchKernelGGL((k_bf_level_list<NB, S>), dim3((unsigned)(p1 - p0)), dim3(kBfLevelThreads), lds1, st, a,

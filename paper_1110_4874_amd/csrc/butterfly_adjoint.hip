@@ -58,19 +58,19 @@ __global__ __launch_bounds__(kBfThreads) void k_bf_unfold(BfArgs<S> a, int batch
 constexpr int kBfTJ = 2;  // K-steps per batch of loads in the transposed level
 
 template <int NB, bool TT, typename S>
-__device__ __forceinline__ void id_block_t(const BfArgs<S> &a, int node, int ch, int half, int lane, const S *u) {
+__device__ __forceinline__ void id_block_t(const BfArgs<S> &a, int node, int ch, int half, int lane, const S *u,
+                                           const int16_t *pl) {
     constexpr int TPW = 4 / kBfHalves;  // 16-row tiles per wave
     constexpr int NC = 2 * NB;
     constexpr int DB = 4 * kBfTJ;  // dense columns per batch
     typedef typename Acc<S>::type acc_t;
     const int *ni = a.node_i + (size_t)node * kBfNodeInts;
-    const int n = ni[2] + ni[4];
     const int kk = ni[2 + ch], nd = ni[4 + ch];
     S *__restrict__ v = a.ws + (size_t)ni[ch] * NC;
-    const int16_t *__restrict__ pm = a.perm + ni[7] + (size_t)ch * n;
     const long long toff = (long long)(unsigned)ni[12 + 2 * ch] | ((long long)ni[13 + 2 * ch] << 32);
     const S *__restrict__ Tb = a.T + toff;
     const int i16 = lane & 15, k4 = lane >> 4;
+    const int ic = min(i16, NC - 1);
     for (int s00 = 0; s00 < kk; s00 += 64) {
         const int ntile = min(4, (kk - s00 + 15) >> 4) - half * TPW;  // tiles of this wave
         if (ntile <= 0) continue;
@@ -78,24 +78,24 @@ __device__ __forceinline__ void id_block_t(const BfArgs<S> &a, int node, int ch,
         acc_t acc[TPW];
 #pragma unroll
         for (int tt = 0; tt < TPW; tt++) acc[tt] = acc_t{0, 0, 0, 0};
+        // columns d past nd get U = 0; rows past k hold clamped rows that are
+        // not stored, so every tile multiplies without a branch
         for (int d0 = 0; d0 < nd; d0 += DB) {
             S av[TPW][kBfTJ], bv[kBfTJ];
 #pragma unroll
             for (int j = 0; j < kBfTJ; j++) {
-                const int d = TT ? d0 + 4 * j + k4 : d0 + kBfTJ * k4 + j;
-                const bool dv = d < nd;
-                bv[j] = (dv && i16 < NC) ? u[pm[kk + d] * NC + i16] : (S)0;
+                const int d = TT ? d0 + 4 * j + k4 : d0 + kBfTJ * k4 + j, dc = min(d, nd - 1);
+                bv[j] = u[pl[kk + dc] * NC + ic] * (S)(d < nd);
 #pragma unroll
                 for (int tt = 0; tt < TPW; tt++) {
-                    const int sr = s0 + 16 * tt + i16;
-                    av[tt][j] = (dv && sr < kk) ? Tb[TT ? (unsigned)(d * kk + sr) : (unsigned)(sr * nd + d)] : (S)0;
+                    const int sr = min(s0 + 16 * tt + i16, kk - 1);
+                    av[tt][j] = Tb[TT ? (unsigned)(dc * kk + sr) : (unsigned)(sr * nd + dc)];
                 }
             }
 #pragma unroll
             for (int j = 0; j < kBfTJ; j++)
 #pragma unroll
-                for (int tt = 0; tt < TPW; tt++)
-                    if (tt < ntile) acc[tt] = mfma_16x16x4(av[tt][j], bv[j], acc[tt]);
+                for (int tt = 0; tt < TPW; tt++) acc[tt] = mfma_16x16x4(av[tt][j], bv[j], acc[tt]);
         }
 #pragma unroll
         for (int tt = 0; tt < TPW; tt++) {
@@ -103,10 +103,17 @@ __device__ __forceinline__ void id_block_t(const BfArgs<S> &a, int node, int ch,
 #pragma unroll
             for (int r = 0; r < 4; r++) {
                 const int sr = s0 + 16 * tt + acc_row<S>(k4, r);
-                if (sr < kk && i16 < NC) v[sr * NC + i16] = acc[tt][r] + u[pm[sr] * NC + i16];
+                if (sr < kk && i16 < NC) v[sr * NC + i16] = acc[tt][r] + u[pl[sr] * NC + i16];
             }
         }
     }
+}
+
+// LDS of one transposed pair node with n columns: u (n entries of 2 NB
+// values) and both children's column permutations (2 n int16).
+template <int NB, typename S>
+inline size_t bf_level_t_lds(int n) {
+    return (size_t)n * (2 * NB * sizeof(S) + 2 * sizeof(int16_t));
 }
 
 // One workgroup of 2 kBfHalves waves per pair node: u is staged in LDS, then
@@ -118,11 +125,14 @@ __device__ __forceinline__ void level_node_t(const BfArgs<S> &a, int node) {
     S *u = reinterpret_cast<S *>(lds_raw);
     const int *ni = a.node_i + (size_t)node * kBfNodeInts;
     const int n = ni[2] + ni[4];
+    int16_t *pl = reinterpret_cast<int16_t *>(u + (size_t)n * NC);
     const S *__restrict__ in = a.ws + (size_t)ni[6] * NC;
+    const int16_t *__restrict__ pg = a.perm + ni[7];
     for (int e = threadIdx.x; e < n * NC; e += kBfLevelThreads) u[e] = in[e];
+    for (int e = threadIdx.x; e < 2 * n; e += kBfLevelThreads) pl[e] = pg[e];
     __syncthreads();
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    id_block_t<NB, TT, S>(a, node, w & 1, w >> 1, threadIdx.x & 63, u);
+    id_block_t<NB, TT, S>(a, node, w & 1, w >> 1, threadIdx.x & 63, u, pl + (w & 1) * n);
 }
 
 template <int NB, bool TT, typename S>
@@ -153,6 +163,10 @@ __global__ __launch_bounds__(kBfUnfoldThreads) void k_bf_unfold_level1(BfArgs<S>
     const int n = nie[2] + nie[4];
     S *uE = reinterpret_cast<S *>(lds_raw);
     S *uO = uE + (size_t)n * NC;
+    int16_t *pl = reinterpret_cast<int16_t *>(uO + (size_t)n * NC);  // even node's 2n entries, then odd's
+    const int16_t *__restrict__ pe = a.perm + nie[7];
+    const int16_t *__restrict__ po = a.perm + a.node_i[(size_t)un.y * kBfNodeInts + 7];
+    for (int e = threadIdx.x; e < 4 * n; e += kBfUnfoldThreads) pl[e] = e < 2 * n ? pe[e] : po[e - 2 * n];
     const int m = batch + un.w * nbatch, k0 = un.z;
     for (int e = threadIdx.x; e < n * NB; e += kBfUnfoldThreads) {
         const int c = e / NB, b = e % NB;
@@ -168,7 +182,8 @@ __global__ __launch_bounds__(kBfUnfoldThreads) void k_bf_unfold_level1(BfArgs<S>
     __syncthreads();
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int par = w / (2 * kBfHalves), wc = w % (2 * kBfHalves);
-    id_block_t<NB, TT, S>(a, par ? un.y : un.x, wc & 1, wc >> 1, threadIdx.x & 63, par ? uO : uE);
+    id_block_t<NB, TT, S>(a, par ? un.y : un.x, wc & 1, wc >> 1, threadIdx.x & 63, par ? uO : uE,
+                          pl + (2 * par + (wc & 1)) * n);
 }
 
 // Lane exchanges for the wave reductions.  permlane32_swap(a, b) leaves
@@ -367,7 +382,7 @@ static hipError_t launch_bf_adj_nb(const sht_plan_s *p, BfArgs<S> a, hipStream_t
         if (nf > 0)
             hipLaunchKernelGGL((k_bf_unfold<NB, S>), dim3((unsigned)((nf + kBfThreads - 1) / kBfThreads)),
                                dim3(kBfThreads), 0, st, a, bt, b.nbatch, p->d_bf_fold_slot + s0, (int)(s1 - s0));
-        const size_t lds1 = (size_t)b.lv_max_n[(size_t)bt * kBfMaxLv + kBfMaxLv - 1] * 2 * NB * sizeof(S);
+        const size_t lds1 = bf_level_t_lds<NB, S>(b.lv_max_n[(size_t)bt * kBfMaxLv + kBfMaxLv - 1]);
         const long long p0 = b.l1_off[bt], p1 = b.l1_off[bt + 1];
         if (p1 > p0)
             hipLaunchKernelGGL((k_bf_level_t_list<NB, TT, S>), dim3((unsigned)(p1 - p0)), dim3(kBfLevelThreads), lds1, st,
@@ -380,7 +395,7 @@ static hipError_t launch_bf_adj_nb(const sht_plan_s *p, BfArgs<S> a, hipStream_t
         for (int q = kBfMaxLv - 2; q >= 0; q--) {  // levels >= 2
             const long long n0 = lo[q], n1 = lo[q + 1];
             if (n1 <= n0) continue;
-            const size_t lds = (size_t)b.lv_max_n[(size_t)bt * kBfMaxLv + q] * 2 * NB * sizeof(S);
+            const size_t lds = bf_level_t_lds<NB, S>(b.lv_max_n[(size_t)bt * kBfMaxLv + q]);
             hipLaunchKernelGGL((k_bf_level_t<NB, TT, S>), dim3((unsigned)(n1 - n0)), dim3(kBfLevelThreads), lds, st, a,
                                n0);
         }

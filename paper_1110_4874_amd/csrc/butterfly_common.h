@@ -67,6 +67,21 @@ __device__ __forceinline__ int acc_row(int k4, int r) {
 constexpr int kBfHalves = 1;
 constexpr int kBfLevelThreads = 128 * kBfHalves;
 
+// base[idx] with a 32-bit byte offset, so that the load can take a
+// wave-uniform 64-bit base in SGPRs and one 32-bit VGPR per lane (blocks of
+// interpolation entries and level vectors stay far below 4 GiB).
+template <typename S>
+__device__ __forceinline__ S ld32(const S *base, unsigned idx) {
+    return *reinterpret_cast<const S *>(reinterpret_cast<const char *>(base) + idx * (unsigned)sizeof(S));
+}
+
+// LDS of one pair node with n columns: one vector of n entries of 2 NB
+// values per child.
+template <int NB, typename S>
+inline size_t bf_level_lds(int n) {
+    return (size_t)n * 2 * (2 * NB * sizeof(S));
+}
+
 inline int bf_nb(int nmaps) { return nmaps >= 8 ? 8 : nmaps >= 4 ? 4 : nmaps >= 2 ? 2 : 1; }
 
 // The plan-dependent fields of BfArgs; the caller sets the operands of its
