@@ -13,7 +13,9 @@ steps bracketed by device synchronisation); the other paths are timed the
 same way and reported under "paths".  Under "adjoint", every path is also
 timed on the map-fitting gradient: forward + backward of
 ||synthesis(a) - d||^2 through autograd, whose backward is the hand-written
-adjoint of the same path, and on the adjoint alone.  The roofline object covers the
+adjoint of the same path, and on the adjoint alone.  Under "analysis", every
+path runs the quadrature analysis (weight 4 pi / Npix) of the synthesized maps,
+without and with 3 Jacobi refinement steps.  The roofline object covers the
 dominant kernel of the headline path, measured with HIP events recorded on
 the execution stream around its stage.  The CPU baseline times the oracle on
 a random sample of rings; max_rel_err compares each path with the oracle's
@@ -221,6 +223,43 @@ def gradient_bench(np, torch, sht, plan, info, paths, d_alm, f_true, ws, ev_sets
     return out
 
 
+def analysis_bench(np, torch, sht, plan, paths, d_alm, f_true, args):
+    """Quadrature analysis with Jacobi refinement (sht_analysis_ex) per path.
+
+    The maps are the benchmark's own syntheses of a_true, so the error against
+    a_true shows what the Jacobi steps recover on a band-limited map at
+    L = 2 nside - 1.  Timed with iterations = 0 (one adjoint) and 3."""
+    B = f_true.shape[0]
+    dev = d_alm.device
+    f = torch.from_numpy(f_true).to(dev)
+    a_true = d_alm.cpu().numpy()
+    steps = max(1, min(args.steps, 5))
+    out = {"weight": "4 pi / Npix", "steps": steps, "paths": {}}
+    for name, path, prec in paths:
+        ws = plan.analysis_workspace(B, dev, path, prec)
+        a = torch.empty((plan.nalm, B), dtype=torch.complex128, device=dev)
+        rec = {}
+        for iters in (0, 3):
+            plan.analysis(f, a, iterations=iters, path=path, precision=prec, workspace=ws)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                plan.analysis(f, a, iterations=iters, path=path, precision=prec, workspace=ws)
+            torch.cuda.synchronize()
+            el = (time.perf_counter() - t0) / steps
+            an = a.cpu().numpy()
+            err = max(float(np.max(np.abs(an[:, b] - a_true[:, b])) / np.max(np.abs(a_true[:, b])))
+                      for b in range(B))
+            rec[f"iterations_{iters}"] = {"ms": round(1e3 * el, 3), "maps_per_s": round(B / el, 3),
+                                          "max_rel_err_vs_alm": float(f"{err:.3e}")}
+        out["paths"][name] = rec
+        log(f"[bench] analysis {name}: {rec['iterations_0']['ms']:.3f} ms (no refinement, error "
+            f"{rec['iterations_0']['max_rel_err_vs_alm']:.2e}), {rec['iterations_3']['ms']:.3f} ms with 3 Jacobi "
+            f"steps (error {rec['iterations_3']['max_rel_err_vs_alm']:.2e})")
+        del ws
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -235,6 +274,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip timing the adjoint")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-request batching measurement")
+    ap.add_argument("--no-analysis", action="store_true", help="skip timing the quadrature analysis")
     ap.add_argument("--rings-per-lane", type=int, default=0, help="Legendre kernel tile (1, 2, 4; 0 = plan default)")
     ap.add_argument("--ring-threads", type=int, default=0, help="ring kernel workgroup size (256, 512, 1024; 0 = default)")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -360,6 +400,10 @@ def main():
     if not args.no_adjoint:
         adj = gradient_bench(np, torch, sht, plan, info, paths, d_alm, maps_out["brute"], ws, ev_sets, args, flops)
 
+    ana = None
+    if not args.no_analysis:
+        ana = analysis_bench(np, torch, sht, plan, paths, d_alm, maps_out["brute"], args)
+
     if not args.no_batch:
         line_batch = batch_bench(np, torch, sht, args.steps)
     else:
@@ -416,6 +460,8 @@ def main():
                                   "device_gb": round(info["device_bytes"] / 1e9, 2)}
     if adj is not None:
         line["adjoint"] = adj
+    if ana is not None:
+        line["analysis"] = ana
     if line_batch is not None:
         line["batching"] = line_batch
 

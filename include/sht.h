@@ -224,6 +224,24 @@ int sht_adjoint(const sht_plan_t *plan, const double *map, double *alm);
 int sht_adjoint_ex(const sht_plan_t *plan, const sht_exec_opts *x, const double *map,
                    double *alm);
 
+/* Spherical-harmonic analysis by the quadrature rule of Sec. 2.2
+ * (a_lm = sum_j w_j f_j Y*_lm(theta_j, phi_j)) with the HEALPix grid's equal
+ * pixel weight w = 4 pi / Npix, followed by `iterations` >= 0 Jacobi steps
+ *     a <- a + w Y^dagger (f - Y a)
+ * that correct the grid's non-orthogonality (a band-limited map with
+ * L <= 2 nside - 1 is recovered to rounding in a dozen steps).  Y^dagger is
+ * the SHT_ADJ_DAGGER adjoint (m >= 0, Im a_l0 = 0).  map: x->nmaps stacked
+ * maps (input, not modified); alm: output in the alm layout.  Every step
+ * runs the synthesis and adjoint kernels of x->path and x->precision, plus
+ * element-wise update kernels.  x->adjoint_convention is ignored.  The
+ * workspace is sht_analysis_workspace_bytes() of the same options (the
+ * synthesis workspace plus one residual map set and one alm set); without
+ * one the call allocates it on x->stream.  Returns SHT_EINVAL for
+ * iterations < 0 or iterations > 1000. */
+size_t sht_analysis_workspace_bytes(const sht_plan_t *plan, const sht_exec_opts *x);
+int sht_analysis_ex(const sht_plan_t *plan, const sht_exec_opts *x, const double *map, double *alm,
+                    int iterations);
+
 /* ---- batches of requests ---------------------------------------------
  * Many independent syntheses (possibly of different L, nside and map
  * counts) in one call: the many-transform regime of Sec. 4.4.  Requests run

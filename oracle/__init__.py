@@ -184,3 +184,17 @@ def adjoint_msel(L, nside, maps, ms, conv: int = 0) -> np.ndarray:
                               ms.ctypes.data_as(ctypes.POINTER(_i)),
                               _ptr(out.view(np.float64)))
     return out
+
+
+def analysis(L, nside, maps, iterations: int = 0) -> np.ndarray:
+    """Quadrature analysis of Sec. 2.2, a_lm = sum_j w_j f_j Y*_lm(j), with the
+    HEALPix equal pixel weight w = 4 pi / Npix, then `iterations` Jacobi steps
+    a <- a + w Y^dagger (f - Y a): (nalm, B) complex.  Composed from the
+    synthesis and the dagger-convention adjoint above."""
+    maps = np.ascontiguousarray(np.atleast_2d(maps), dtype=np.float64)
+    w = 4.0 * np.pi / (12 * nside * nside)
+    a = w * adjoint(L, nside, maps, conv=1)
+    for _ in range(iterations):
+        r = maps - synthesis(L, nside, a)
+        a = a + w * adjoint(L, nside, r, conv=1)
+    return a

@@ -356,6 +356,28 @@ static int check_conv(const sht_exec_opts *x) {
     return SHT_OK;
 }
 
+// Ring analysis and transposed Legendre phase of one adjoint on x->stream;
+// ws holds synth_ws_bytes() bytes.
+static int adjoint_stages(const sht_plan_t *p, const sht_exec_opts *x, double wpos, const double *map,
+                          double *alm, void *ws) {
+    int rc;
+    const int B = x->nmaps;
+    hipStream_t st = (hipStream_t)x->stream;
+    double *ybar = (double *)ws;
+    stage_event(x, SHT_STAGE_RING_ADJ, 0);
+    if ((rc = hip_status(launch_ring_analysis(p, B, map, ybar, wpos, st), "ring analysis launch"))) return rc;
+    stage_event(x, SHT_STAGE_RING_ADJ, 1);
+    stage_event(x, SHT_STAGE_LEGENDRE_ADJ, 0);
+    if (use_bf(p, x->path))
+        rc = hip_status(launch_butterfly_adjoint(p, B, ybar, alm, (char *)ws + q_bytes(p, B),
+                                                 x->precision == SHT_PREC_FP32, st),
+                        "adjoint butterfly launch");
+    else
+        rc = hip_status(launch_legendre_adjoint(p, B, ybar, alm, st), "adjoint Legendre launch");
+    stage_event(x, SHT_STAGE_LEGENDRE_ADJ, 1);
+    return rc;
+}
+
 int sht_adjoint_ex(const sht_plan_t *p, const sht_exec_opts *x, const double *map, double *alm) {
     int rc = check_plan(p);
     if (!rc) rc = check_exec(p, x);
@@ -368,21 +390,45 @@ int sht_adjoint_ex(const sht_plan_t *p, const sht_exec_opts *x, const double *ma
     if ((rc = check_dev_ptr(alm, nalm_of(p->L) * B * 16, p->device, "alm"))) return rc;
     Scratch ws;
     if ((rc = ws.get(x, synth_ws_bytes(p, x), p->device))) return rc;
-    hipStream_t st = (hipStream_t)x->stream;
-    double *ybar = (double *)ws.ptr;
     const double wpos = x->adjoint_convention == SHT_ADJ_DAGGER ? 1.0 : 2.0;
-    stage_event(x, SHT_STAGE_RING_ADJ, 0);
-    if ((rc = hip_status(launch_ring_analysis(p, B, map, ybar, wpos, st), "ring analysis launch"))) return rc;
-    stage_event(x, SHT_STAGE_RING_ADJ, 1);
-    stage_event(x, SHT_STAGE_LEGENDRE_ADJ, 0);
-    if (use_bf(p, x->path))
-        rc = hip_status(launch_butterfly_adjoint(p, B, ybar, alm, (char *)ws.ptr + q_bytes(p, B),
-                                                 x->precision == SHT_PREC_FP32, st),
-                        "adjoint butterfly launch");
-    else
-        rc = hip_status(launch_legendre_adjoint(p, B, ybar, alm, st), "adjoint Legendre launch");
-    stage_event(x, SHT_STAGE_LEGENDRE_ADJ, 1);
-    return rc;
+    return adjoint_stages(p, x, wpos, map, alm, ws.ptr);
+}
+
+size_t sht_analysis_workspace_bytes(const sht_plan_t *p, const sht_exec_opts *x) {
+    if (!p || !x || x->nmaps < 1) return 0;
+    const size_t B = (size_t)x->nmaps;
+    return synth_ws_bytes(p, x) + npix_of(p->nside) * B * 8 + nalm_of(p->L) * B * 16;
+}
+
+int sht_analysis_ex(const sht_plan_t *p, const sht_exec_opts *x, const double *map, double *alm, int iterations) {
+    int rc = check_plan(p);
+    if (!rc) rc = check_exec(p, x);
+    if (rc) return rc;
+    if (iterations < 0 || iterations > 1000) return fail(SHT_EINVAL, "iterations must be in [0, 1000]");
+    DeviceGuard g(p->device);
+    if (!g.ok) return fail(SHT_EDEVICE, "cannot select the plan's device");
+    const int B = x->nmaps;
+    const long long nmap = (long long)npix_of(p->nside) * B, nalm2 = (long long)nalm_of(p->L) * B * 2;
+    if ((rc = check_dev_ptr(map, (size_t)nmap * 8, p->device, "map"))) return rc;
+    if ((rc = check_dev_ptr(alm, (size_t)nalm2 * 8, p->device, "alm"))) return rc;
+    Scratch ws;
+    if ((rc = ws.get(x, sht_analysis_workspace_bytes(p, x), p->device))) return rc;
+    hipStream_t st = (hipStream_t)x->stream;
+    const size_t base = synth_ws_bytes(p, x);
+    double *resid = (double *)((char *)ws.ptr + base);
+    double *gin = (double *)((char *)ws.ptr + base + (size_t)nmap * 8);
+    const double w = 4.0 * 3.14159265358979323846 / (double)npix_of(p->nside);
+    // a = w Y^dagger f
+    if ((rc = adjoint_stages(p, x, 1.0, map, alm, ws.ptr))) return rc;
+    if ((rc = hip_status(launch_axpby(alm, alm, w, 0.0, nalm2, st), "analysis scale launch"))) return rc;
+    for (int it = 0; it < iterations; it++) {
+        // r = f - Y a;  a += w Y^dagger r
+        if ((rc = synth_stages(p, B, x->path, x->precision, alm, resid, ws.ptr, st, nullptr))) return rc;
+        if ((rc = hip_status(launch_axpby(resid, map, 1.0, -1.0, nmap, st), "analysis residual launch"))) return rc;
+        if ((rc = adjoint_stages(p, x, 1.0, resid, gin, ws.ptr))) return rc;
+        if ((rc = hip_status(launch_axpby(alm, gin, w, 1.0, nalm2, st), "analysis update launch"))) return rc;
+    }
+    return SHT_OK;
 }
 
 int sht_debug_ring_analysis(const sht_plan_t *p, const sht_exec_opts *x, const double *map, double *ybar) {

@@ -33,7 +33,7 @@ void parallel_for(long n, int nthreads, void (*fn)(long, void *), void *ctx);
 // Butterfly records (butterfly_plan.cpp builds them, butterfly.hip walks them).
 constexpr int kBfMaxLv = 10;     // deepest level a plan may keep
 constexpr int kBfTaskRings = 256; // rings of one residual wave task (up to four per lane)
-constexpr int kBfPieceRings = 128; // rings of one forward residual piece (64 or 128: one or two per lane)
+constexpr int kBfPieceRings = 256; // rings of one forward residual piece (64, 128 or 256: one, two or four per lane)
 constexpr int kBfNodeInts = 16;  // vin0, vin1, k0, k1, nd0, nd1, out, perm offset,
                                  // region flags, m, t, level, T offsets of both
                                  // children (64-bit, lo/hi)
@@ -181,6 +181,8 @@ hipError_t launch_butterfly(const sht_plan_s *p, int nmaps, const double *alm, d
 // with the same scratch.
 hipError_t launch_butterfly_adjoint(const sht_plan_s *p, int nmaps, const double *ybar, double *g, void *scratch,
                                     int fp32, hipStream_t stream);
+// y = alpha x + beta y over n doubles (beta = 0: y = alpha x).
+hipError_t launch_axpby(double *y, const double *x, double alpha, double beta, long long n, hipStream_t st);
 // Device-side transposed copies of the interpolation matrices (d_bf_Tt and,
 // when the FP32 copy exists, d_bf_Tt32) from the uploaded ones; nT entries,
 // nnodes pair nodes.  Adds the allocated bytes to *bytes.

@@ -77,6 +77,8 @@ EXPORTS = {
     "sht_synthesis_ex": (_c.c_int, [_c.c_void_p, _c.POINTER(ExecOpts), _c.c_void_p, _c.c_void_p]),
     "sht_adjoint": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p]),
     "sht_adjoint_ex": (_c.c_int, [_c.c_void_p, _c.POINTER(ExecOpts), _c.c_void_p, _c.c_void_p]),
+    "sht_analysis_workspace_bytes": (_c.c_size_t, [_c.c_void_p, _c.POINTER(ExecOpts)]),
+    "sht_analysis_ex": (_c.c_int, [_c.c_void_p, _c.POINTER(ExecOpts), _c.c_void_p, _c.c_void_p, _c.c_int]),
     "sht_debug_ring_analysis": (_c.c_int, [_c.c_void_p, _c.POINTER(ExecOpts), _c.c_void_p, _c.c_void_p]),
     "sht_debug_legendre_adjoint": (_c.c_int, [_c.c_void_p, _c.POINTER(ExecOpts), _c.c_void_p, _c.c_void_p]),
     "sht_last_error": (_c.c_char_p, []),
@@ -287,6 +289,27 @@ class Plan:
         x = self._exec(B, path, stream, workspace, events, convention, precision)
         _check(load().sht_adjoint_ex(self._h, _c.byref(x), _c.c_void_p(m.data_ptr()),
                                      _c.c_void_p(out.data_ptr())))
+        return out
+
+    def analysis_workspace(self, nmaps=1, device="cuda", path=PATH_AUTO, precision=PREC_FP64):
+        x = self._exec(nmaps, path=path, precision=precision)
+        nbytes = int(load().sht_analysis_workspace_bytes(self._h, _c.byref(x)))
+        return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+    def analysis(self, maps, out=None, *, iterations=0, path=PATH_AUTO, stream=None, workspace=None,
+                 precision=PREC_FP64):
+        """alm (nalm, B) complex128 from maps (B, Npix) or (Npix,) float64: the
+        quadrature rule with weight 4 pi / Npix, then `iterations` Jacobi steps
+        a <- a + w Y^dagger (maps - Y a)."""
+        m = self._map_arg(maps)
+        B = m.shape[0]
+        if out is None:
+            out = torch.empty((self.nalm, B), dtype=torch.complex128, device=m.device)
+        if workspace is None:
+            workspace = self.analysis_workspace(B, m.device, path, precision)
+        x = self._exec(B, path, stream, workspace, None, ADJ_DAGGER, precision)
+        _check(load().sht_analysis_ex(self._h, _c.byref(x), _c.c_void_p(m.data_ptr()),
+                                      _c.c_void_p(out.data_ptr()), int(iterations)))
         return out
 
     def ring_analysis(self, maps, *, stream=None, convention=ADJ_TRANSPOSE):
