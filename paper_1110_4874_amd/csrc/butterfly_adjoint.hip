@@ -57,54 +57,66 @@ __global__ __launch_bounds__(kBfThreads) void k_bf_unfold(BfArgs<S> a, int batch
 // contiguous entries of 16 different rows.
 constexpr int kBfTJ = 2;  // K-steps per batch of loads in the transposed level
 
+// NT 16-row tiles of skeleton rows s0 .. s0 + 16 NT - 1 of one transposed ID
+// block (the tile count is a template parameter so that the products run
+// back to back).  Columns d past nd get U = 0; rows past k hold clamped rows
+// that are not stored.
+template <int NT, int NB, bool TT, typename S>
+__device__ __forceinline__ void split_tiles(const S *__restrict__ Tb, S *__restrict__ v, const S *u,
+                                            const int16_t *pl, int kk, int nd, int s0, int lane) {
+    constexpr int NC = 2 * NB;
+    constexpr int DB = 4 * kBfTJ;  // dense columns per batch
+    typedef typename Acc<S>::type acc_t;
+    const int i16 = lane & 15, k4 = lane >> 4;
+    const int ic = min(i16, NC - 1);
+    acc_t acc[NT];
+#pragma unroll
+    for (int tt = 0; tt < NT; tt++) acc[tt] = acc_t{0, 0, 0, 0};
+    for (int d0 = 0; d0 < nd; d0 += DB) {
+        S av[NT][kBfTJ], bv[kBfTJ];
+#pragma unroll
+        for (int j = 0; j < kBfTJ; j++) {
+            const int d = TT ? d0 + 4 * j + k4 : d0 + kBfTJ * k4 + j, dc = min(d, nd - 1);
+            bv[j] = u[pl[kk + dc] * NC + ic] * (S)(d < nd);
+#pragma unroll
+            for (int tt = 0; tt < NT; tt++) {
+                const int sr = min(s0 + 16 * tt + i16, kk - 1);
+                av[tt][j] = Tb[TT ? (unsigned)(dc * kk + sr) : (unsigned)(sr * nd + dc)];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kBfTJ; j++)
+#pragma unroll
+            for (int tt = 0; tt < NT; tt++) acc[tt] = mfma_16x16x4(av[tt][j], bv[j], acc[tt]);
+    }
+#pragma unroll
+    for (int tt = 0; tt < NT; tt++)
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const int sr = s0 + 16 * tt + acc_row<S>(k4, r);
+            if (sr < kk && i16 < NC) v[sr * NC + i16] = acc[tt][r] + u[pl[sr] * NC + i16];
+        }
+}
+
 template <int NB, bool TT, typename S>
 __device__ __forceinline__ void id_block_t(const BfArgs<S> &a, int node, int ch, int half, int lane, const S *u,
                                            const int16_t *pl) {
     constexpr int TPW = 4 / kBfHalves;  // 16-row tiles per wave
     constexpr int NC = 2 * NB;
-    constexpr int DB = 4 * kBfTJ;  // dense columns per batch
-    typedef typename Acc<S>::type acc_t;
     const int *ni = a.node_i + (size_t)node * kBfNodeInts;
     const int kk = ni[2 + ch], nd = ni[4 + ch];
     S *__restrict__ v = a.ws + (size_t)ni[ch] * NC;
     const long long toff = (long long)(unsigned)ni[12 + 2 * ch] | ((long long)ni[13 + 2 * ch] << 32);
     const S *__restrict__ Tb = a.T + toff;
-    const int i16 = lane & 15, k4 = lane >> 4;
-    const int ic = min(i16, NC - 1);
     for (int s00 = 0; s00 < kk; s00 += 64) {
-        const int ntile = min(4, (kk - s00 + 15) >> 4) - half * TPW;  // tiles of this wave
-        if (ntile <= 0) continue;
+        const int ntile = min(TPW, min(4, (kk - s00 + 15) >> 4) - half * TPW);  // tiles of this wave
         const int s0 = s00 + 16 * TPW * half;
-        acc_t acc[TPW];
-#pragma unroll
-        for (int tt = 0; tt < TPW; tt++) acc[tt] = acc_t{0, 0, 0, 0};
-        // columns d past nd get U = 0; rows past k hold clamped rows that are
-        // not stored, so every tile multiplies without a branch
-        for (int d0 = 0; d0 < nd; d0 += DB) {
-            S av[TPW][kBfTJ], bv[kBfTJ];
-#pragma unroll
-            for (int j = 0; j < kBfTJ; j++) {
-                const int d = TT ? d0 + 4 * j + k4 : d0 + kBfTJ * k4 + j, dc = min(d, nd - 1);
-                bv[j] = u[pl[kk + dc] * NC + ic] * (S)(d < nd);
-#pragma unroll
-                for (int tt = 0; tt < TPW; tt++) {
-                    const int sr = min(s0 + 16 * tt + i16, kk - 1);
-                    av[tt][j] = Tb[TT ? (unsigned)(dc * kk + sr) : (unsigned)(sr * nd + dc)];
-                }
-            }
-#pragma unroll
-            for (int j = 0; j < kBfTJ; j++)
-#pragma unroll
-                for (int tt = 0; tt < TPW; tt++) acc[tt] = mfma_16x16x4(av[tt][j], bv[j], acc[tt]);
-        }
-#pragma unroll
-        for (int tt = 0; tt < TPW; tt++) {
-            if (tt >= ntile) break;
-#pragma unroll
-            for (int r = 0; r < 4; r++) {
-                const int sr = s0 + 16 * tt + acc_row<S>(k4, r);
-                if (sr < kk && i16 < NC) v[sr * NC + i16] = acc[tt][r] + u[pl[sr] * NC + i16];
-            }
+        switch (ntile) {
+            case 1: split_tiles<1, NB, TT, S>(Tb, v, u, pl, kk, nd, s0, lane); break;
+            case 2: split_tiles<2, NB, TT, S>(Tb, v, u, pl, kk, nd, s0, lane); break;
+            case 3: split_tiles<3, NB, TT, S>(Tb, v, u, pl, kk, nd, s0, lane); break;
+            case 4: split_tiles<4, NB, TT, S>(Tb, v, u, pl, kk, nd, s0, lane); break;
+            default: break;
         }
     }
 }
