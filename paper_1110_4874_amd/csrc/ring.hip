@@ -71,6 +71,8 @@ __device__ __forceinline__ double2 expipi(double x) {  // e^{i pi x}
     sincospi(x, &s, &c);
     return make_double2(c, s);
 }
+// x * i conj(y): with y = e^{i pi k/J} and n = J/2, e^{i pi (n - k)/J} = i conj(y)
+__device__ __forceinline__ double2 i_conj(double2 y) { return make_double2(y.y, y.x); }
 __device__ __forceinline__ int ilog2_dev(int n) { return 31 - __clz(n); }
 __device__ __forceinline__ int bitrev(int k, int lg) { return lg == 0 ? 0 : (int)(__brev((unsigned)k) >> (32 - lg)); }
 __device__ __forceinline__ int pidx(int i) { return i + (i >> 4); }
@@ -344,14 +346,24 @@ __global__ __launch_bounds__(T) void k_ring_synth(RingArgs a) {
     // bit-reversed order for power-of-two n; for split Bluestein rings even k
     // at k/2 and odd k at h + (k-1)/2 (n = 2h), weighted by the chirp
     const int h = n / 2;
+    // e^{i pi k/J} and e^{i pi k/n} for k = tid + j T by products with the
+    // step e^{i pi T/J} (resp. n): two sincospi per thread instead of three
+    // per pair (the rounding grows by about an ulp per step)
+    double2 pJ = make_double2(1.0, 0.0), sJ = pJ;
+    if (s) {
+        pJ = expipi((double)tid / J);
+        sJ = expipi((double)T / J);
+    }
+    double2 pn = expipi((double)tid / n);
+    const double2 sn = expipi((double)T / n);
 #pragma unroll
     for (int j = 0; j < kPairsPerThread; j++) {
         const int k = tid + j * T;
-        if (k >= npair || (G > 1 && j > 0)) continue;
+        if (k < npair && !(G > 1 && j > 0)) {
         double2 Xk = xa[j], Xnk = xb[j];
         if (s) {
-            Xk = cmul(Xk, expipi((double)k / J));
-            Xnk = cmul(Xnk, expipi((double)(n - k) / J));
+            Xk = cmul(Xk, pJ);
+            Xnk = cmul(Xnk, i_conj(pJ));  // e^{i pi (n - k)/J}, n = J/2
         }
         double2 Zk, Znk = make_double2(0.0, 0.0);
         const bool two = (k != 0) && (2 * k != n);
@@ -362,7 +374,7 @@ __global__ __launch_bounds__(T) void k_ring_synth(RingArgs a) {
             Zk = make_double2(2.0 * Xk.x, -2.0 * Xk.y);
         } else {
             double2 e = cadd(Xk, cconj(Xnk));
-            double2 o = cmul(csub(Xk, cconj(Xnk)), expipi((double)k / n));
+            double2 o = cmul(csub(Xk, cconj(Xnk)), pn);
             Zk = make_double2(e.x - o.y, e.y + o.x);
             Znk = make_double2(e.x + o.y, -e.y + o.x);  // conj(e) + i conj(o)
         }
@@ -377,6 +389,9 @@ __global__ __launch_bounds__(T) void k_ring_synth(RingArgs a) {
                 buf[pidx(kq + odd * h)] = cmul(Znk, W[kq]);
             }
         }
+        }
+        pJ = cmul(pJ, sJ);
+        pn = cmul(pn, sn);
     }
     __syncthreads();
     // pixel 2p = Re z_p, pixel 2p+1 = Im z_p
@@ -413,14 +428,17 @@ __global__ __launch_bounds__(T) void k_ring_synth(RingArgs a) {
     for (int i = h + tid; i < M; i += T) buf[pidx(i)] = make_double2(0.0, 0.0);
     __syncthreads();
     backward_dft<T>(buf, h, M, V, W, a.tw, a.tw_log);
+    double2 wp = expipi(2.0 * tid / n);  // e^{2 pi i p/n}, stepped as above
+    const double2 ws = expipi(2.0 * T / n);
 #pragma unroll
     for (int jj = 0; jj < kHalfPerThread; jj++) {
         const int p = tid + jj * T;
         if (p < h) {
-            const double2 t = cmul(buf[pidx(p)], expipi(2.0 * p / n));
+            const double2 t = cmul(buf[pidx(p)], wp);
             out[p] = cadd(R[jj], t);
             out[p + h] = csub(R[jj], t);
         }
+        wp = cmul(wp, ws);
     }
 }
 
@@ -534,14 +552,17 @@ __global__ __launch_bounds__(T) void k_ring_analysis(RingArgs a) {
         // Z_p = A_p + w^p B_p and Z_{p+h} = A_p - w^p B_p in place (each
         // thread reads B_p before writing p and p + h, which no other thread
         // reads)
+        double2 wp = expipi(2.0 * tid / n);  // e^{2 pi i p/n}, stepped by products
+        const double2 ws = expipi(2.0 * T / n);
 #pragma unroll
         for (int jj = 0; jj < kHalfPerThread; jj++) {
             const int p = tid + jj * T;
             if (p < h) {
-                const double2 t = cmul(buf[pidx(p)], expipi(2.0 * p / n));
+                const double2 t = cmul(buf[pidx(p)], wp);
                 buf[pidx(p)] = cadd(A[jj], t);
                 buf[pidx(p + h)] = csub(A[jj], t);
             }
+            wp = cmul(wp, ws);
         }
         __syncthreads();
     }
@@ -549,15 +570,22 @@ __global__ __launch_bounds__(T) void k_ring_analysis(RingArgs a) {
     // bins b = 0..n, split over G groups of the residue classes for small rings
     const int nb = n + 1;
     const int G = nb >= T ? 1 : T / nb;
+    // e^{-i pi bin/n} and e^{-i pi bin/J}: with G = 1 a thread's bins are
+    // tid + j T, stepped by products; with G > 1 each thread has one bin
+    const int bin0 = tid % nb;
+    double2 qn = expipi(-(double)bin0 / n), qJ = s ? expipi(-(double)bin0 / J) : make_double2(1.0, 0.0);
+    const double2 sn = expipi(-(double)T / n), sJ = s ? expipi(-(double)T / J) : make_double2(1.0, 0.0);
     for (int u = tid; u < G * nb; u += T) {
         const int g = u / nb, bin = u % nb;
         const double2 Zb = cconj(buf[pidx(bin == n ? 0 : bin)]);
         const double2 Znb = cconj(buf[pidx(bin == 0 ? 0 : n - bin)]);
         // F_b = (Z_b + conj Z_{n-b})/2 - (i/2) e^{-2 pi i b/J} (Z_b - conj Z_{n-b})
         const double2 e = cadd(Zb, cconj(Znb));
-        const double2 d = cmul(csub(Zb, cconj(Znb)), expipi(-(double)bin / n));
+        const double2 d = cmul(csub(Zb, cconj(Znb)), qn);
         double2 F = make_double2(0.5 * (e.x + d.y), 0.5 * (e.y - d.x));
-        double2 Gb = s ? cmul(F, expipi(-(double)bin / J)) : F;
+        double2 Gb = s ? cmul(F, qJ) : F;
+        qn = cmul(qn, sn);
+        qJ = cmul(qJ, sJ);
         // class 1: m = bin + jJ (j >= 0)
         for (long long j = g;; j += G) {
             const long long m = bin + j * J;
