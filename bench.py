@@ -43,9 +43,26 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def _code_only(text):
+    """Source text without comments and blank space, so that editing a
+    comment does not count as changing a kernel."""
+    import re
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(line.strip() for line in text.splitlines() if line.strip())
+
+
 def source_sha(src):
-    with open(os.path.join(CSRC, src), "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()
+    """Hash of a kernel source file together with every header of the
+    library (its constants and shared device code), comments excluded."""
+    if not src or not os.path.exists(os.path.join(CSRC, src)):
+        return None
+    names = [src] + sorted(n for n in os.listdir(CSRC) if n.endswith(".h"))
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(CSRC, n)) as fh:
+            h.update(n.encode() + b"\0" + _code_only(fh.read()).encode() + b"\0")
+    return h.hexdigest()
 
 
 def measured_traffic(kernel, L, nside, nmaps):

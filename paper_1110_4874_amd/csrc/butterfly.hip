@@ -8,8 +8,8 @@
 // which gives the GPU tens of thousands of independent waves to stream the
 // interpolation matrices with; vectors between levels live in a device
 // workspace (read and written once per level):
-//  1. k_bf_residual: one wave per residual piece (up to 128 skeleton rings of
-//     one row block, two per lane) regenerates the Legendre values with the
+//  1. k_bf_residual: one wave per residual piece (up to kBfPieceRings skeleton
+//     rings of one row block, four per lane) regenerates the Legendre values with the
 //     two-step recurrence (App. A.2, Eq. A2) over the block's rows from two
 //     stored values per ring and accumulates v = sum_l a_lm P~_l^m(z) for
 //     every map; the a_lm rows and coefficients are staged through LDS;

@@ -55,7 +55,7 @@ struct BflyPlan {
     std::vector<int> res_task;        // [tasks][8] t, first row, end row, rings, output entry, m
     std::vector<int> res_lane;        // [tasks*256][2] ring, first row of the ring
     std::vector<double> res_val;      // [tasks*256][2] Legendre values at that row and the next
-    std::vector<int> res_sub;         // [subtasks][8] the tasks cut into 64-ring pieces for the
+    std::vector<int> res_sub;         // [subtasks][8] the tasks cut into kBfPieceRings pieces for the
                                       // forward kernel: t, first row of the piece, end row,
                                       // rings, output entry, m, first lane record, 0
     int nbatch = 1;                   // orders m are run in batches m mod nbatch
