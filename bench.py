@@ -301,7 +301,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus} GPUs, WORLD_SIZE={world}); "
-              "the transform is not sharded across GPUs in this build.", file=sys.stderr)
+              "the library does not shard a transform across GPUs.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

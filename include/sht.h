@@ -50,7 +50,7 @@ typedef enum {
     SHT_ENOMEM = -2,       /* host or device allocation failed, or workspace too small */
     SHT_EDEVICE = -3,      /* HIP runtime error, or a host-only plan used for compute */
     SHT_ECORRUPT = -4,     /* reserved: unreadable serialised plan */
-    SHT_EUNSUPPORTED = -5  /* valid request outside what this build supports */
+    SHT_EUNSUPPORTED = -5  /* valid request outside what the library supports */
 } sht_status;
 
 enum {
