@@ -379,15 +379,15 @@ __global__ __launch_bounds__(T) void k_legendre_adj(AdjArgs a) {
     }
 }
 
+// Defined with the ring kernels: raises a kernel's dynamic LDS limit once
+// per (kernel, device).
+hipError_t allow_dynamic_lds(const void *fn, int bytes);
+
 template <int T, int R, int NB, bool DD>
 static hipError_t launch_adj_cfg(const sht_plan_s *p, AdjArgs a, hipStream_t st) {
-    static bool attr_set = false;
     const size_t lds = (size_t)2 * 16 * T * sizeof(double);
-    if (!attr_set) {
-        (void)hipFuncSetAttribute((const void *)k_legendre_adj<T, R, NB, DD>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        attr_set = true;
-    }
+    hipError_t ea = allow_dynamic_lds((const void *)k_legendre_adj<T, R, NB, DD>, (int)lds);
+    if (ea != hipSuccess) return ea;
     hipLaunchKernelGGL((k_legendre_adj<T, R, NB, DD>), dim3((unsigned)(p->L + 1)), dim3(T), lds, st, a);
     return hipGetLastError();
 }

@@ -644,6 +644,18 @@ int build_butterfly(sht_plan_s *p, const BflyInput &in) {
     b.batch_sub[nb] = (long long)b.res_sub.size() / 8;
     if ((long long)b.res_lane.size() / 2 > INT32_MAX)
         return fail(SHT_EUNSUPPORTED, "butterfly plan exceeds 32-bit lane record offsets");
+    // every level launch keeps its workgroup's vectors in the default 64 KiB
+    // of dynamic LDS at 8 maps in FP64: the fused level 1 holds four vectors
+    // of n entries (128 B each), the other levels two
+    long long n1 = 0, nl = 0;
+    for (int bt = 0; bt < nb; bt++)
+        for (int q = 0; q < kBfMaxLv; q++) {
+            const long long n = b.lv_max_n[(size_t)bt * kBfMaxLv + q];
+            if (q == kBfMaxLv - 1) n1 = std::max(n1, n);
+            else nl = std::max(nl, n);
+        }
+    if (512 * n1 > 65536 || 256 * nl > 65536)
+        return fail(SHT_EUNSUPPORTED, "butterfly column sets too wide for the level kernels' LDS (use a smaller chunk)");
     b.n_tasks = (long long)b.res_task.size() / 8;
     b.built = 1;
     b.build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

@@ -27,6 +27,10 @@
 // owns one (ring, map); the maps of a ring are adjacent in the ring-major q
 // layout and their workgroups run back to back on the same XCD (dispatch is
 // round-robin over 8 XCDs), so lines read from HBM serve them all from L2.
+#include <mutex>
+#include <set>
+#include <utility>
+
 #include "internal.h"
 
 namespace sht {
@@ -442,14 +446,25 @@ __global__ __launch_bounds__(T) void k_ring_synth(RingArgs a) {
     }
 }
 
+// Raises a kernel's dynamic LDS limit to `bytes`, once per (kernel, device):
+// the attribute belongs to the device current at the call.
+hipError_t allow_dynamic_lds(const void *fn, int bytes) {
+    static std::mutex mu;
+    static std::set<std::pair<const void *, int>> done;
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(mu);
+    if (done.count({fn, dev})) return hipSuccess;
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess) done.insert({fn, dev});
+    return e;
+}
+
 template <int T>
 static hipError_t launch_classes(const sht_plan_s *p, RingArgs a, int nmaps, hipStream_t stream) {
-    static bool attr_set = false;
-    if (!attr_set) {
-        (void)hipFuncSetAttribute((const void *)k_ring_synth<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  160 * 1024);
-        attr_set = true;
-    }
+    hipError_t ea = allow_dynamic_lds((const void *)k_ring_synth<T>, 160 * 1024);
+    if (ea != hipSuccess) return ea;
     for (const auto &rc : p->classes) {
         a.rings = rc.d_rings;
         a.count = (int)rc.rings.size();
@@ -610,12 +625,8 @@ __global__ __launch_bounds__(T) void k_ring_analysis(RingArgs a) {
 
 template <int T>
 static hipError_t launch_analysis_classes(const sht_plan_s *p, RingArgs a, int nmaps, hipStream_t stream) {
-    static bool attr_set = false;
-    if (!attr_set) {
-        (void)hipFuncSetAttribute((const void *)k_ring_analysis<T>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        attr_set = true;
-    }
+    hipError_t ea = allow_dynamic_lds((const void *)k_ring_analysis<T>, 160 * 1024);
+    if (ea != hipSuccess) return ea;
     for (const auto &rc : p->classes) {
         a.rings = rc.d_rings;
         a.count = (int)rc.rings.size();

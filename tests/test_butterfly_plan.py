@@ -109,3 +109,12 @@ def test_plan_is_deterministic(lib):
     b = sht.Plan(200, 64, 1e-10, host_only=True, max_levels=2, nthreads=3).info()
     for key in ("bf_T_entries", "bf_res_elems", "bf_nodes", "bf_units", "bf_res_lanes"):
         assert a[key] == b[key]
+
+
+def test_plan_rejects_column_sets_beyond_the_level_lds():
+    # one 512-ring column block at level 1 would need 256 KiB of LDS in the
+    # fused level-1 kernel at 8 maps in FP64: refused when the plan is built
+    with pytest.raises(sht.ShtError, match="too wide"):
+        sht.Plan(511, 256, 1e-10, host_only=True, max_levels=1, chunk=512)
+    p = sht.Plan(511, 256, 1e-10, host_only=True, max_levels=1, chunk=128)
+    assert p.info()["bf_built"] == 1
