@@ -123,3 +123,21 @@ def test_plan_info_work_count(sht):
 def _odd_equator_steps(L, N):
     # odd chains vanish identically on the equator ring (z = 0)
     return sum((L - m - 1) // 2 + 1 for m in range(L + 1) if L - m - 1 >= 0)
+
+
+def test_workspace_sizes(sht):
+    # the analysis workspace is the synthesis workspace plus one residual map
+    # set (Npix B doubles) and one alm set (nalm B complex); on a butterfly
+    # plan the synthesis workspace also holds the level vectors
+    lib = sht.load()
+    for eps, path in ((0.0, sht.PATH_BRUTE), (1e-10, sht.PATH_BUTTERFLY)):
+        p = sht.Plan(63, 32, eps, host_only=True, max_levels=1 if eps else -1)
+        for B in (1, 3, 8, 9):
+            x = sht.ExecOpts()
+            lib.sht_exec_opts_default(x)
+            x.nmaps, x.path = B, path
+            ws = lib.sht_workspace_bytes(p._h, x)
+            wa = lib.sht_analysis_workspace_bytes(p._h, x)
+            q = (p.L + 1) * p.nrings * B * 16
+            assert ws >= q and (eps > 0 or ws == q)
+            assert wa == ws + 12 * 32 * 32 * B * 8 + p.nalm * B * 16
