@@ -49,14 +49,16 @@ typedef enum {
     SHT_EINVAL = -1,       /* bad argument (range, null, host pointer, layout) */
     SHT_ENOMEM = -2,       /* host or device allocation failed, or workspace too small */
     SHT_EDEVICE = -3,      /* HIP runtime error, or a host-only plan used for compute */
-    SHT_ECORRUPT = -4,     /* reserved: unreadable serialised plan */
-    SHT_EUNSUPPORTED = -5  /* valid request outside what the library supports */
+    SHT_ECORRUPT = -4,     /* plan file failed its integrity checks (truncated,
+                              altered, or not a plan file) */
+    SHT_EUNSUPPORTED = -5, /* valid request outside what the library supports */
+    SHT_EIO = -6           /* a plan file could not be opened, read or written */
 } sht_status;
 
 enum {
     SHT_PATH_AUTO = 0,      /* butterfly when the plan has it (eps > 0), else brute force */
     SHT_PATH_BRUTE = 1,     /* recurrence over every (l, ring) above the cutoff (App. A.2) */
-    SHT_PATH_BUTTERFLY = 2  /* compressed operator of Sec. 4.2; needs an eps > 0 plan */
+    SHT_PATH_BUTTERFLY = 2  /* compressed operator of Sec. 3.2; needs an eps > 0 plan */
 };
 
 /* Arithmetic of the butterfly level products (sht_exec_opts.precision).
@@ -103,7 +105,7 @@ typedef struct sht_plan_opts {
                           1024 (0 = default 512); a tuning knob */
     int host_only;     /* 1: build host tables only (no device memory); such a
                           plan can be inspected but not executed */
-    /* Butterfly compression (eps > 0 plans only; Sec. 4.2 and 4.4): */
+    /* Butterfly compression (eps > 0 plans only; Sec. 3.2 and 3.4): */
     double rho;        /* cost of one stored interpolation entry relative to one
                           residual recurrence element when choosing the depth per
                           (m, parity); <= 0 selects the default 2.5 (MI355X: HBM
@@ -184,9 +186,9 @@ void sht_exec_opts_default(sht_exec_opts *o);
  * geometry, the two-step recurrence coefficients of App. A.2 Eq. A2 and, per
  * (m, parity, ring), the first Legendre values above the cutoff (App. A.2):
  * everything the brute-force path needs.  eps > 0 additionally runs the FP64
- * butterfly precompute of Sec. 4.2 (interpolative decompositions at
- * tolerance eps, Eq. 17, depth per (m, parity) from the cost model of
- * Sec. 4.4) on the host's cores and uploads the compressed operator; this
+ * butterfly precompute of Sec. 3.2 (interpolative decompositions at
+ * tolerance eps, Eqs. 19-20, depth per (m, parity) from the cost model of
+ * Sec. 3.4) on the host's cores and uploads the compressed operator; this
  * takes minutes at L = 4095 and tens of GB of device memory.
  * Returns NULL on failure (see sht_last_error).  The plan is immutable and
  * may be shared by threads; free it with sht_plan_free. */
@@ -194,6 +196,51 @@ sht_plan_t *sht_plan(int L, int nside, double eps);
 sht_plan_t *sht_plan_ex(int L, int nside, double eps, const sht_plan_opts *opts);
 void sht_plan_free(sht_plan_t *plan);
 int sht_plan_info(const sht_plan_t *plan, sht_plan_info_t *out);
+
+/* ---- plan files ---------------------------------------------------------
+ * The precomputed data is built once and reused: the paper writes it to files
+ * that its core loads, and excludes that load from every timing (Sec. 4.1,
+ * Sec. 4.2; Table 1 lists the precompute cost that a file saves).
+ *
+ * sht_plan_save writes every host table of the plan (geometry, recurrence
+ * coefficients, chain starts, ring FFT tables and, for eps > 0, the whole
+ * compressed operator) to `path`: a versioned header holding L, nside, eps,
+ * the options that shape the operator (cutoff, dd_sin, rho, max_levels, chunk,
+ * id_safety, batch_mib, the tuning knobs and the store flags) and the
+ * library's record layout, then the tables, with checksums over both.  The
+ * file is written under a temporary name next to `path` and renamed into
+ * place.  A device plan whose host copy of the interpolation data was
+ * dropped after upload is read back from the device for the save (needs
+ * that much host memory).  Returns SHT_EIO when the file cannot be written.
+ *
+ * sht_plan_load reads a file written by sht_plan_save and builds the plan on
+ * the current HIP device, with the saved options; sht_plan_load_ex takes
+ * host_only, store_fp32, store_transpose and nthreads (threads for the
+ * checksum) from `opts` instead (NULL: as saved), so one file serves host-only
+ * inspection, FP64-only and FP32 execution.  Both return NULL on failure;
+ * sht_last_status() then gives SHT_ECORRUPT for a file that fails its
+ * integrity checks (wrong magic, header or payload checksum mismatch, size
+ * not matching the header, tables inconsistent with the geometry),
+ * SHT_EUNSUPPORTED for a file written by a library with another version or
+ * record layout, SHT_EIO when it cannot be opened, SHT_ENOMEM or SHT_EDEVICE
+ * for allocation and upload failures.  The loaded plan computes exactly what
+ * the saved one did. */
+int sht_plan_save(const sht_plan_t *plan, const char *path);
+sht_plan_t *sht_plan_load(const char *path);
+sht_plan_t *sht_plan_load_ex(const char *path, const sht_plan_opts *opts);
+
+/* Status of the last failed call on this thread (0 if none failed yet);
+ * sht_last_error() gives its message.  Calls that return a pointer (plan
+ * construction and loading) report their status here. */
+int sht_last_status(void);
+
+/* Device errors of asynchronous work: waits until the work queued on
+ * `stream` (hipStream_t, NULL = default stream) on the plan's device has
+ * finished, and returns SHT_EDEVICE with the HIP error text if the device
+ * or the runtime reported an error for it, else SHT_OK.  Every transform
+ * only enqueues work; this is the call that makes its failures visible
+ * without a transform of its own. */
+int sht_sync_status(const sht_plan_t *plan, void *stream);
 
 /* Device scratch needed by one synthesis or adjoint with these options: the
  * Legendre phase buffer, nmaps * (L+1) * nrings complex values, plus on the
@@ -215,7 +262,7 @@ int sht_synthesis_ex(const sht_plan_t *plan, const sht_exec_opts *x,
  * The Legendre functions are recomputed (nothing is kept from synthesis).
  * x->path picks the Legendre part as for synthesis: the brute-force
  * recurrence (deterministic), or on an eps > 0 plan the transposed butterfly
- * (Sec. 4.2 factorization applied backwards; x->precision FP32 runs its
+ * (Sec. 3.2 factorization applied backwards; x->precision FP32 runs its
  * interpolation products on FP32 matrix cores), which is the exact transpose
  * of that plan's compressed synthesis.  The butterfly adjoint adds the
  * residual rows into alm with device atomics, so its last bits may differ
@@ -244,7 +291,7 @@ int sht_analysis_ex(const sht_plan_t *plan, const sht_exec_opts *x, const double
 
 /* ---- batches of requests ---------------------------------------------
  * Many independent syntheses (possibly of different L, nside and map
- * counts) in one call: the many-transform regime of Sec. 4.4.  Requests run
+ * counts) in one call: the many-transform regime of Sec. 3.4.  Requests run
  * longest first on the least-loaded of nstreams internal default-priority
  * streams that fork from and join into o->stream through events; the call
  * allocates nothing (the workspace is required) and only enqueues, so a
@@ -307,7 +354,7 @@ int sht_debug_legendre_adjoint(const sht_plan_t *plan, const sht_exec_opts *x,
 
 int sht_debug_coef(const sht_plan_t *plan, int m, double *coef_out);
 
-/* Interpolative decomposition of Sec. 4.1 on the host, as the butterfly
+/* Interpolative decomposition of Sec. 3.1 on the host, as the butterfly
  * precompute takes it: A is r x c column-major (not modified), tol the
  * relative tolerance.  Writes the rank to *k, the column order to piv[c]
  * (piv[0..k) are the skeleton columns) and T (k x (c-k), row-major) with

@@ -61,8 +61,8 @@ def lib():
         L.oracle_synthesis_direct.argtypes = [_i, _l, _i, _pd, _l,
                                               ctypes.POINTER(_ll), _pd]
         L.oracle_adjoint.argtypes = [_i, _l, _i, _pd, _i, _pd]
-        L.oracle_adjoint_msel.argtypes = [_i, _l, _i, _pd, _i, _i,
-                                          ctypes.POINTER(_i), _pd]
+        for fn in (L.oracle_adjoint_msel, L.oracle_adjoint_msel_ld):
+            fn.argtypes = [_i, _l, _i, _pd, _i, _i, ctypes.POINTER(_i), _pd]
         L.oracle_num_threads.restype = _i
         _lib = L
     return _lib
@@ -174,13 +174,15 @@ def adjoint(L, nside, maps, conv: int = 0) -> np.ndarray:
     return out
 
 
-def adjoint_msel(L, nside, maps, ms, conv: int = 0) -> np.ndarray:
-    """Adjoint for selected m: (nm, L+1, B) complex, entry [k, l-m, b] = g_lm."""
+def adjoint_msel(L, nside, maps, ms, conv: int = 0, ld: bool = False) -> np.ndarray:
+    """Adjoint for selected m: (nm, L+1, B) complex, entry [k, l-m, b] = g_lm.
+    ld=True runs the same transpose in long double (rounded once)."""
     maps = np.ascontiguousarray(np.atleast_2d(maps), dtype=np.float64)
     B = maps.shape[0]
     ms = np.ascontiguousarray(ms, dtype=np.int32)
     out = np.zeros((len(ms), L + 1, B), dtype=np.complex128)
-    lib().oracle_adjoint_msel(L, nside, B, _ptr(maps), conv, len(ms),
+    fn = lib().oracle_adjoint_msel_ld if ld else lib().oracle_adjoint_msel
+    fn(L, nside, B, _ptr(maps), conv, len(ms),
                               ms.ctypes.data_as(ctypes.POINTER(_i)),
                               _ptr(out.view(np.float64)))
     return out

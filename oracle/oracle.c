@@ -46,6 +46,8 @@
 
 static long long nalm_of(int L) { return (long long)(L + 1) * (L + 2) / 2; }
 
+#define R_PI_LD 3.14159265358979323846264338327950288L
+
 /* ================================================================== */
 /* Geometry                                                            */
 /* ================================================================== */
@@ -428,6 +430,87 @@ void oracle_adjoint_msel(int L, long nside, int B, const double *map, int conv,
     }
     free(yb);
     free(col);
+}
+
+/* Long-double adjoint for selected m (spot-check mode at large L, where
+   the FP64 recurrence itself loses ~L eps / sin(theta) on polar rings):
+   the same plain transpose,
+     g_lm = w_m sum_k P~_l^m(z_k) sum_j y_kj e^{-i m phi_kj},
+   with geometry, phase tables, Legendre values and both sums in long
+   double, rounded once at the end.  Each ring's cos/sin table over the 2J
+   reduced phases is built once and serves every selected m.  The sum over
+   rings runs in ring order for every m, so the result does not depend on
+   the thread count.  g_out as for oracle_adjoint_msel. */
+void oracle_adjoint_msel_ld(int L, long nside, int B, const double *map, int conv,
+                            int nm, const int *ms, double *g_out)
+{
+    long nrings = 4 * nside - 1;
+    long long npix = 12LL * nside * nside;
+    /* ybar [nm][nrings][B] complex, long double */
+    long double *yb = malloc(sizeof(long double) * 2 * (size_t)nm * nrings * B);
+#pragma omp parallel
+    {
+        long double *cs = malloc(sizeof(long double) * 8 * nside);
+        long double *sn = malloc(sizeof(long double) * 8 * nside);
+#pragma omp for schedule(dynamic, 4)
+        for (long ring = 1; ring <= nrings; ring++) {
+            long double z, sth;
+            long J, s;
+            long long off;
+            ring_geom_ld(nside, ring, &z, &sth, &J, &s, &off);
+            for (long r = 0; r < 2 * J; r++) {
+                cs[r] = cosl(R_PI_LD * (long double)r / (long double)J);
+                sn[r] = sinl(R_PI_LD * (long double)r / (long double)J);
+            }
+            for (int k = 0; k < nm; k++) {
+                long long m = ms[k];
+                for (int b = 0; b < B; b++) {
+                    long double re = 0, im = 0;
+                    for (long j = 0; j < J; j++) {
+                        long r = (long)((m * (2 * j + s)) % (2 * J));
+                        long double y = map[b * npix + off + j];
+                        re += y * cs[r];
+                        im -= y * sn[r];
+                    }
+                    size_t o = 2 * (((size_t)k * nrings + (ring - 1)) * B + b);
+                    yb[o] = re;
+                    yb[o + 1] = im;
+                }
+            }
+        }
+        free(cs);
+        free(sn);
+    }
+    memset(g_out, 0, sizeof(double) * 2 * (size_t)nm * (L + 1) * B);
+#pragma omp parallel
+    {
+        long double *col = malloc(sizeof(long double) * (L + 1));
+        long double *acc = malloc(sizeof(long double) * 2 * (size_t)(L + 1) * B);
+#pragma omp for schedule(dynamic, 1)
+        for (int k = 0; k < nm; k++) {
+            int m = ms[k];
+            long double w = (long double)weight_of(m, conv);
+            memset(acc, 0, sizeof(long double) * 2 * (size_t)(L + 1) * B);
+            for (long ring = 1; ring <= nrings; ring++) {
+                long double z, sth;
+                long J, s;
+                long long off;
+                ring_geom_ld(nside, ring, &z, &sth, &J, &s, &off);
+                plm_column_ld(L, m, z, sth, col);
+                const long double *y = yb + 2 * (((size_t)k * nrings + (ring - 1)) * B);
+                for (int l = m; l <= L; l++)
+                    for (int b = 0; b < B; b++) {
+                        acc[2 * ((l - m) * B + b)] += col[l - m] * y[2 * b];
+                        if (m > 0) acc[2 * ((l - m) * B + b) + 1] += col[l - m] * y[2 * b + 1];
+                    }
+            }
+            double *gk = g_out + (size_t)k * 2 * (L + 1) * B;
+            for (long e = 0; e < 2L * (L - m + 1) * B; e++) gk[e] = (double)(w * acc[e]);
+        }
+        free(col);
+        free(acc);
+    }
+    free(yb);
 }
 
 /* Threads the OpenMP runtime will use (reported by the CPU baseline). */

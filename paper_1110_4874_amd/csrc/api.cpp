@@ -8,6 +8,7 @@
 
 namespace sht {
 const char *last_error();
+int last_status();
 size_t synth_ws_bytes_impl(const sht_plan_s *p, int nmaps, int path, int precision);
 }
 
@@ -207,6 +208,18 @@ void sht_exec_opts_default(sht_exec_opts *o) {
 }
 
 const char *sht_last_error(void) { return sht::last_error(); }
+
+int sht_last_status(void) { return sht::last_status(); }
+
+int sht_sync_status(const sht_plan_t *p, void *stream) {
+    int rc = check_plan(p);
+    if (rc) return rc;
+    DeviceGuard g(p->device);
+    if (!g.ok) return fail(SHT_EDEVICE, "cannot select the plan's device");
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e == hipSuccess) e = hipGetLastError();
+    return hip_status(e, "device work on the stream");
+}
 
 sht_plan_t *sht_plan(int L, int nside, double eps) { return sht_plan_ex(L, nside, eps, nullptr); }
 

@@ -1,5 +1,5 @@
 // Batched synthesis of many independent requests (the many-transform
-// regime of Sec. 4.4): requests are ordered by estimated work, longest
+// regime of Sec. 3.4): requests are ordered by estimated work, longest
 // first, and dealt to the least-loaded of a few internal streams that fork
 // from and join back into the caller's stream through events, so that small
 // transforms run concurrently with large ones.  Every launch is stream

@@ -1,4 +1,4 @@
-// Butterfly-compressed Legendre phase for gfx950 (Sec. 4.2 and App. A.1 of
+// Butterfly-compressed Legendre phase for gfx950 (Sec. 3.2 and App. A.1 of
 // the Wavemoth paper): q^t_m = Lambda^T a^t applied as
 //   a^T Lambda = (a^T R) S_d P_{d-1} ... P_1 S_1,
 // followed by the even/odd fold of Sec. 2.4 (Eqs. 13-14).

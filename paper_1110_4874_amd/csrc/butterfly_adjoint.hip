@@ -1,4 +1,4 @@
-// Adjoint of the butterfly-compressed Legendre phase (Sec. 4.2 and App. A.1
+// Adjoint of the butterfly-compressed Legendre phase (Sec. 3.2 and App. A.1
 // of the Wavemoth paper): g^t = Lambda ybar^t (Sec. 2.4 Eq. 12 transposed)
 // runs the factorization backwards, per batch of orders:
 //  1. level 1 takes ybar^even = ybar(z) + ybar(-z) and ybar^odd =

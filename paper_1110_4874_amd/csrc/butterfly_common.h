@@ -1,4 +1,4 @@
-// Shared pieces of the butterfly kernels (Sec. 4.2, App. A.1): the argument
+// Shared pieces of the butterfly kernels (Sec. 3.2, App. A.1): the argument
 // block every butterfly kernel receives, the wave shapes of the level
 // launches, and the 16x16x4 matrix-core product with its lane layout.
 #pragma once

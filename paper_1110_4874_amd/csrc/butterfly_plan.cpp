@@ -1,23 +1,23 @@
-// Host precompute of the butterfly-compressed Legendre operator (Sec. 4 of
+// Host precompute of the butterfly-compressed Legendre operator (Sec. 3 of
 // the Wavemoth paper), and its flattening into the records the GPU kernel
 // walks.
 //
 // For each order m and parity t the matrix Lambda (rows: l = m + t + 2i,
-// i = 0..n-1; columns: the north rings z_k) is factored as in Sec. 4.2,
-// Eq. 15: Lambda = R S_d P_{d-1} ... P_1 S_1.  Level 1 splits the rows in
-// two and takes the interpolative decomposition (Sec. 4.1, Eq. 16) of every
+// i = 0..n-1; columns: the north rings z_k) is factored as in Sec. 3.2,
+// Eq. 21: Lambda = R S_d P_{d-1} ... P_1 S_1.  Level 1 splits the rows in
+// two and takes the interpolative decomposition (Sec. 3.1, Eq. 19) of every
 // (row half, column block of about `chunk` rings); level i > 1 joins the
 // skeleton columns that two neighbouring level-(i-1) column groups kept in
 // the same parent row block, splits the rows again and takes the ID of each
 // half (Eq. 18).  After d levels the residual R consists of, per leaf (row
 // block, column group), the Legendre values at the leaf's rows and its
 // skeleton rings; the kernel regenerates those with the recurrence from two
-// stored values per column (Sec. 4.4), so only the interpolation matrices
+// stored values per column (Sec. 3.4), so only the interpolation matrices
 // (their dense, non-identity part, App. A.1) are streamed from memory.
 //
 // The depth d of each (m, t) minimises rho * (stored interpolation entries)
 // + (residual recurrence elements), the paper's CPU/memory trade-off of
-// Sec. 4.4 with rho set for MI355X instead of a CPU.
+// Sec. 3.4 with rho set for MI355X instead of a CPU.
 //
 // Interpolative decomposition: Householder QR with column pivoting
 // (Businger-Golub), stopped when the largest remaining column norm falls
@@ -98,7 +98,9 @@ int interp_decomp(double *A, int r, int c, double tol, double abs_floor, std::ve
                 for (int i = j + 1; i < r; i++) cq[i] -= w * v[i];
             }
         }
-        // downdate the remaining column norms (recompute on cancellation)
+        // downdate the remaining column norms, recomputing a norm once the
+        // downdated ratio falls below sqrt(eps) (the cancellation safeguard of
+        // Drmac and Bujanovic, 2008)
         for (int q = j + 1; q < c; q++) {
             if (vn1[q] == 0.0) continue;
             double *cq = A + (size_t)q * r;

@@ -22,12 +22,15 @@ typedef long double ld;
 static const ld kPi = 3.14159265358979323846264338327950288L;
 
 static thread_local std::string g_err;
+static thread_local int g_status = 0;
 void set_error(const std::string &msg) { g_err = msg; }
 int fail(int code, const std::string &msg) {
     g_err = msg;
+    g_status = code;
     return code;
 }
 const char *last_error() { return g_err.c_str(); }
+int last_status() { return g_status; }
 
 void parallel_for(long n, int nthreads, void (*fn)(long, void *), void *ctx) {
     if (n <= 0) return;

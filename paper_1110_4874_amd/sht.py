@@ -7,6 +7,7 @@ anything else.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import os
 
@@ -15,7 +16,7 @@ import torch  # imported first so that the library shares torch's HIP runtime
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsht.so")
 
-SHT_OK, SHT_EINVAL, SHT_ENOMEM, SHT_EDEVICE, SHT_ECORRUPT, SHT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+SHT_OK, SHT_EINVAL, SHT_ENOMEM, SHT_EDEVICE, SHT_ECORRUPT, SHT_EUNSUPPORTED, SHT_EIO = 0, -1, -2, -3, -4, -5, -6
 PATH_AUTO, PATH_BRUTE, PATH_BUTTERFLY = 0, 1, 2
 PREC_FP64, PREC_FP32 = 0, 1
 STAGE_LEGENDRE, STAGE_RING, STAGE_RING_ADJ, STAGE_LEGENDRE_ADJ = 0, 1, 2, 3
@@ -82,6 +83,11 @@ EXPORTS = {
     "sht_debug_ring_analysis": (_c.c_int, [_c.c_void_p, _c.POINTER(ExecOpts), _c.c_void_p, _c.c_void_p]),
     "sht_debug_legendre_adjoint": (_c.c_int, [_c.c_void_p, _c.POINTER(ExecOpts), _c.c_void_p, _c.c_void_p]),
     "sht_last_error": (_c.c_char_p, []),
+    "sht_last_status": (_c.c_int, []),
+    "sht_sync_status": (_c.c_int, [_c.c_void_p, _c.c_void_p]),
+    "sht_plan_save": (_c.c_int, [_c.c_void_p, _c.c_char_p]),
+    "sht_plan_load": (_c.c_void_p, [_c.c_char_p]),
+    "sht_plan_load_ex": (_c.c_void_p, [_c.c_char_p, _c.POINTER(PlanOpts)]),
     "sht_debug_legendre_phase": (_c.c_int, [_c.c_void_p, _c.POINTER(ExecOpts), _c.c_void_p, _c.c_void_p]),
     "sht_debug_ring_synthesis": (_c.c_int, [_c.c_void_p, _c.POINTER(ExecOpts), _c.c_void_p, _c.c_void_p]),
     "sht_debug_coef": (_c.c_int, [_c.c_void_p, _c.c_int, _c.POINTER(_c.c_double)]),
@@ -145,6 +151,14 @@ def _stream_handle(stream):
     return _c.c_void_p(s.cuda_stream)
 
 
+def _on(stream):
+    """Context in which a call's temporaries (outputs, workspace, contiguous
+    copies) are allocated and copied on the stream its kernels run on, so the
+    caching allocator never hands their memory to other work while the
+    kernels may still use it."""
+    return torch.cuda.stream(stream) if stream is not None else contextlib.nullcontext()
+
+
 class Plan:
     """A transform plan for band limit L on a HEALPix grid of resolution nside."""
 
@@ -173,13 +187,46 @@ class Plan:
             torch.cuda.init()
         h = lib.sht_plan_ex(int(L), int(nside), float(eps), _c.byref(o))
         if not h:
-            raise ShtError(-1, lib.sht_last_error().decode())
+            raise ShtError(lib.sht_last_status(), lib.sht_last_error().decode())
+        self._adopt(h, host_only)
+
+    def _adopt(self, h, host_only):
         self._h = _c.c_void_p(h)
-        self.L, self.nside, self.eps = int(L), int(nside), float(eps)
+        inf = self.info()
+        self.L, self.nside, self.eps = int(inf["L"]), int(inf["nside"]), float(inf["eps"])
         self.nrings = 4 * self.nside - 1
         self.npix = 12 * self.nside * self.nside
         self.nalm = nalm(self.L)
-        self.host_only = host_only
+        self.host_only = bool(host_only)
+
+    @classmethod
+    def load(cls, path, *, host_only=False, store_fp32=False, store_transpose=False, nthreads=0):
+        """A plan from a file written by save() (sht_plan_load_ex): the saved
+        operator, on cuda's current device unless host_only."""
+        lib = load()
+        o = PlanOpts()
+        lib.sht_plan_opts_default(_c.byref(o))
+        o.host_only = 1 if host_only else 0
+        o.store_fp32 = 1 if store_fp32 else 0
+        o.store_transpose = 1 if store_transpose else 0
+        o.nthreads = int(nthreads)
+        if not host_only:
+            torch.cuda.init()
+        h = lib.sht_plan_load_ex(os.fsencode(path), _c.byref(o))
+        if not h:
+            raise ShtError(lib.sht_last_status(), lib.sht_last_error().decode())
+        self = cls.__new__(cls)
+        self._adopt(h, host_only)
+        return self
+
+    def save(self, path):
+        """Write the plan to `path` (sht_plan_save)."""
+        _check(load().sht_plan_save(self._h, os.fsencode(path)))
+
+    def sync(self, stream=None):
+        """Wait for the work queued on `stream` and raise ShtError if the
+        device reported an error for it (sht_sync_status)."""
+        _check(load().sht_sync_status(self._h, _stream_handle(stream)))
 
     def close(self):
         if getattr(self, "_h", None):
@@ -254,16 +301,17 @@ class Plan:
     def synthesis(self, alm, out=None, *, path=PATH_AUTO, stream=None, workspace=None, events=None,
                   precision=PREC_FP64):
         """maps (B, Npix) float64 from alm (nalm, B) or (nalm,) complex128."""
-        a = self._alm_arg(alm)
-        B = a.shape[1]
-        if out is None:
-            out = torch.empty((B, self.npix), dtype=torch.float64, device=a.device)
-        if workspace is None:
-            workspace = self.workspace(B, a.device, path, precision)
-        x = self._exec(B, path, stream, workspace, events, precision=precision)
-        _check(load().sht_synthesis_ex(self._h, _c.byref(x), _c.c_void_p(a.data_ptr()),
-                                       _c.c_void_p(out.data_ptr())))
-        return out
+        with _on(stream):
+            a = self._alm_arg(alm)
+            B = a.shape[1]
+            if out is None:
+                out = torch.empty((B, self.npix), dtype=torch.float64, device=a.device)
+            if workspace is None:
+                workspace = self.workspace(B, a.device, path, precision)
+            x = self._exec(B, path, stream, workspace, events, precision=precision)
+            _check(load().sht_synthesis_ex(self._h, _c.byref(x), _c.c_void_p(a.data_ptr()),
+                                           _c.c_void_p(out.data_ptr())))
+            return out
 
     def _map_arg(self, maps):
         if maps.dtype != torch.float64 or not maps.is_cuda:
@@ -280,16 +328,17 @@ class Plan:
         path and precision select the Legendre part as for synthesis (the
         butterfly adjoint is the exact transpose of that plan's compressed
         synthesis)."""
-        m = self._map_arg(maps)
-        B = m.shape[0]
-        if out is None:
-            out = torch.empty((self.nalm, B), dtype=torch.complex128, device=m.device)
-        if workspace is None:
-            workspace = self.workspace(B, m.device, path, precision)
-        x = self._exec(B, path, stream, workspace, events, convention, precision)
-        _check(load().sht_adjoint_ex(self._h, _c.byref(x), _c.c_void_p(m.data_ptr()),
-                                     _c.c_void_p(out.data_ptr())))
-        return out
+        with _on(stream):
+            m = self._map_arg(maps)
+            B = m.shape[0]
+            if out is None:
+                out = torch.empty((self.nalm, B), dtype=torch.complex128, device=m.device)
+            if workspace is None:
+                workspace = self.workspace(B, m.device, path, precision)
+            x = self._exec(B, path, stream, workspace, events, convention, precision)
+            _check(load().sht_adjoint_ex(self._h, _c.byref(x), _c.c_void_p(m.data_ptr()),
+                                         _c.c_void_p(out.data_ptr())))
+            return out
 
     def analysis_workspace(self, nmaps=1, device="cuda", path=PATH_AUTO, precision=PREC_FP64):
         x = self._exec(nmaps, path=path, precision=precision)
@@ -301,57 +350,62 @@ class Plan:
         """alm (nalm, B) complex128 from maps (B, Npix) or (Npix,) float64: the
         quadrature rule with weight 4 pi / Npix, then `iterations` Jacobi steps
         a <- a + w Y^dagger (maps - Y a)."""
-        m = self._map_arg(maps)
-        B = m.shape[0]
-        if out is None:
-            out = torch.empty((self.nalm, B), dtype=torch.complex128, device=m.device)
-        if workspace is None:
-            workspace = self.analysis_workspace(B, m.device, path, precision)
-        x = self._exec(B, path, stream, workspace, None, ADJ_DAGGER, precision)
-        _check(load().sht_analysis_ex(self._h, _c.byref(x), _c.c_void_p(m.data_ptr()),
-                                      _c.c_void_p(out.data_ptr()), int(iterations)))
-        return out
+        with _on(stream):
+            m = self._map_arg(maps)
+            B = m.shape[0]
+            if out is None:
+                out = torch.empty((self.nalm, B), dtype=torch.complex128, device=m.device)
+            if workspace is None:
+                workspace = self.analysis_workspace(B, m.device, path, precision)
+            x = self._exec(B, path, stream, workspace, None, ADJ_DAGGER, precision)
+            _check(load().sht_analysis_ex(self._h, _c.byref(x), _c.c_void_p(m.data_ptr()),
+                                          _c.c_void_p(out.data_ptr()), int(iterations)))
+            return out
 
     def ring_analysis(self, maps, *, stream=None, convention=ADJ_TRANSPOSE):
         """ybar (nrings, L+1, B) complex128 (private test entry point)."""
-        m = self._map_arg(maps)
-        B = m.shape[0]
-        yb = torch.empty((self.nrings, self.L + 1, B), dtype=torch.complex128, device=m.device)
-        x = self._exec(B, stream=stream, convention=convention)
-        _check(load().sht_debug_ring_analysis(self._h, _c.byref(x), _c.c_void_p(m.data_ptr()),
-                                              _c.c_void_p(yb.data_ptr())))
-        return yb
+        with _on(stream):
+            m = self._map_arg(maps)
+            B = m.shape[0]
+            yb = torch.empty((self.nrings, self.L + 1, B), dtype=torch.complex128, device=m.device)
+            x = self._exec(B, stream=stream, convention=convention)
+            _check(load().sht_debug_ring_analysis(self._h, _c.byref(x), _c.c_void_p(m.data_ptr()),
+                                                  _c.c_void_p(yb.data_ptr())))
+            return yb
 
     def legendre_adjoint(self, ybar, *, stream=None):
         """alm (nalm, B) from ybar (nrings, L+1, B) (private test entry point)."""
-        yb = ybar.contiguous()
-        B = yb.shape[2]
-        out = torch.empty((self.nalm, B), dtype=torch.complex128, device=yb.device)
-        x = self._exec(B, stream=stream)
-        _check(load().sht_debug_legendre_adjoint(self._h, _c.byref(x), _c.c_void_p(yb.data_ptr()),
-                                                 _c.c_void_p(out.data_ptr())))
-        return out
+        with _on(stream):
+            yb = ybar.contiguous()
+            B = yb.shape[2]
+            out = torch.empty((self.nalm, B), dtype=torch.complex128, device=yb.device)
+            x = self._exec(B, stream=stream)
+            _check(load().sht_debug_legendre_adjoint(self._h, _c.byref(x), _c.c_void_p(yb.data_ptr()),
+                                                     _c.c_void_p(out.data_ptr())))
+            return out
 
     def legendre_phase(self, alm, *, stream=None):
         """q (nrings, L+1, B) complex128 (private test entry point)."""
-        a = self._alm_arg(alm)
-        B = a.shape[1]
-        q = torch.empty((self.nrings, self.L + 1, B), dtype=torch.complex128, device=a.device)
-        x = self._exec(B, stream=stream)
-        _check(load().sht_debug_legendre_phase(self._h, _c.byref(x), _c.c_void_p(a.data_ptr()),
-                                               _c.c_void_p(q.data_ptr())))
-        return q
+        with _on(stream):
+            a = self._alm_arg(alm)
+            B = a.shape[1]
+            q = torch.empty((self.nrings, self.L + 1, B), dtype=torch.complex128, device=a.device)
+            x = self._exec(B, stream=stream)
+            _check(load().sht_debug_legendre_phase(self._h, _c.byref(x), _c.c_void_p(a.data_ptr()),
+                                                   _c.c_void_p(q.data_ptr())))
+            return q
 
     def ring_synthesis(self, q, out=None, *, stream=None):
         """maps (B, Npix) from q (nrings, L+1, B) complex128 (private test entry point)."""
-        q = q.contiguous()
-        B = q.shape[2]
-        if out is None:
-            out = torch.empty((B, self.npix), dtype=torch.float64, device=q.device)
-        x = self._exec(B, stream=stream)
-        _check(load().sht_debug_ring_synthesis(self._h, _c.byref(x), _c.c_void_p(q.data_ptr()),
-                                               _c.c_void_p(out.data_ptr())))
-        return out
+        with _on(stream):
+            q = q.contiguous()
+            B = q.shape[2]
+            if out is None:
+                out = torch.empty((B, self.npix), dtype=torch.float64, device=q.device)
+            x = self._exec(B, stream=stream)
+            _check(load().sht_debug_ring_synthesis(self._h, _c.byref(x), _c.c_void_p(q.data_ptr()),
+                                                   _c.c_void_p(out.data_ptr())))
+            return out
 
     # ---- host tables ----------------------------------------------------
     def coef(self, m):

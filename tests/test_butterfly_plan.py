@@ -1,9 +1,9 @@
-"""Host-side checks of the butterfly precompute (Sec. 4.1-4.2): the
+"""Host-side checks of the butterfly precompute (Sec. 3.1-3.2): the
 interpolative decomposition and the compressed operator, evaluated on the
 host from the plan's records, against the oracle's Legendre values.
 
 These run without a GPU (host-only plans).  Pins:
-* the ID satisfies the bound of Sec. 4.1 (Eq. 17) with the singular values
+* the ID satisfies the bound of Sec. 3.1 (Eq. 20) with the singular values
   numpy's SVD gives, reproduces an exactly low-rank matrix, and keeps the
   rank scipy's ID library finds at the same tolerance (within one);
 * the compressed Lambda^T x equals the dense one (long-double oracle

@@ -1,5 +1,5 @@
 """Batched synthesis (many requests in one call; many-transform regime of
-Sec. 4.4): results equal the per-request calls exactly, and a captured HIP
+Sec. 3.4): results equal the per-request calls exactly, and a captured HIP
 graph of one batch replays correctly several times with eager work between
 the replays."""
 import numpy as np

@@ -1,4 +1,4 @@
-"""GPU parity of the butterfly-compressed synthesis (Sec. 4.2) against the
+"""GPU parity of the butterfly-compressed synthesis (Sec. 3.2) against the
 CPU oracle's plain definition.
 
 FP64 bar: max_p |y_p - x_p| / max_p |x_p| <= eps + 1e-12 per map (the

@@ -1,4 +1,4 @@
-"""GPU parity of the transposed butterfly (the adjoint through the Sec. 4.2
+"""GPU parity of the transposed butterfly (the adjoint through the Sec. 3.2
 factorization applied backwards) against the CPU oracle's plain transpose.
 
 FP64 bar: max |g - g_ref| / max |g_ref| per map <= eps + 1e-12, the same bar

@@ -13,7 +13,8 @@ index, a transposed operand, a wrong phase origin) fails at least one:
                        recurrence in long double
   DFT phase/wrap    -> O(L^2)-per-pixel direct sum, rotation by pi/2
   even/odd symmetry -> reflection a_lm -> (-1)^(l+m) a_lm
-  adjoint           -> dot-product test against synthesis
+  adjoint           -> dot-product test against synthesis (FP64 and the
+                       long-double spot mode)
   analysis          -> constant map (exact quadrature of Y_00), recovery of
                        a band-limited a_lm by the Jacobi steps
 """
@@ -406,6 +407,49 @@ def test_long_double_spot_mode():
         sth = oracle.ring_info(N, ring)[1]
         tol = 2e-14 + 0.1 * L * 1.1e-16 / sth
         assert np.max(np.abs(q[k] - qld[k])) <= tol * np.max(np.abs(qld)), ring
+
+
+def test_long_double_adjoint_dot_product():
+    # the long-double transpose, pinned by the transpose identity against the
+    # long-double synthesis over every ring: for a with nonzero orders only in
+    # the selection, <Y a, y> = sum_{m in sel} <a_m, g_m>_R
+    N, L = 16, 40
+    sel = [0, 1, 7, 23, 40]
+    a = alm_gaussian(L, [41, 42], spectrum="white")
+    _, ms = lm_index(L)
+    a[~np.isin(ms, sel)] = 0.0
+    a[: L + 1] = a[: L + 1].real
+    y = np.random.default_rng(43).standard_normal((2, 12 * N * N))
+    rings = list(range(1, 4 * N))
+    f = np.concatenate(oracle.synthesis_rings(L, N, a, rings, ld=True), axis=1)
+    g = oracle.adjoint_msel(L, N, y, sel, ld=True)
+    for b in range(2):
+        lhs = float(np.sum(f[b] * y[b]))  # rings in order = RING pixel order
+        rhs = 0.0
+        for k, m in enumerate(sel):
+            o = m * (2 * L + 3 - m) // 2
+            rhs += _real_dot(a[o:o + L + 1 - m, b], g[k, : L + 1 - m, b])
+        assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+    assert np.all(g[0].imag == 0)
+    # the dagger convention differs by w_m only
+    g1 = oracle.adjoint_msel(L, N, y, sel, conv=1, ld=True)
+    w = np.where(np.array(sel) == 0, 1.0, 2.0)[:, None, None]
+    assert np.max(np.abs(g1 * w - g)) <= 1e-15 * np.max(np.abs(g))
+
+
+def test_long_double_adjoint_matches_fp64():
+    # at L = 511 the FP64 transpose loses at most ~L eps / sin(theta) on the
+    # polar rings; the two modes agree to that level, and the thread count
+    # does not change the long-double result (rings are summed in order)
+    N, L = 256, 511
+    y = np.random.default_rng(44).standard_normal((1, 12 * N * N))
+    sel = [0, 2, 100, 300, 511]
+    gd = oracle.adjoint_msel(L, N, y, sel)
+    gl = oracle.adjoint_msel(L, N, y, sel, ld=True)
+    scale = np.max(np.abs(gl))
+    assert np.max(np.abs(gd - gl)) <= 2e-13 * scale
+    assert np.max(np.abs(gd - gl)) > 0.0  # the modes are distinct computations
+    assert np.array_equal(gl, oracle.adjoint_msel(L, N, y, sel, ld=True))
 
 
 def test_synthetic_inputs():
