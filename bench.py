@@ -43,6 +43,16 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def _code_only(text):
     """Source text without comments and blank space, so that editing a
     comment does not count as changing a kernel."""
@@ -163,6 +173,162 @@ def batch_bench(np, torch, sht, steps):
         log(f"[bench] batching {k}: sequential {res[k]['sequential_maps_per_s']} maps/s, "
             f"batch {res[k]['batch_maps_per_s']}, graph {res[k]['graph_maps_per_s']}")
     return res
+
+
+def level_roofline(info, nlev, sz, B, levels_ms, L, N):
+    """Roofline of the butterfly level launches (levels >= 2; level 1 runs
+    fused with the fold).  Algorithmic bytes per launch are what the method
+    must stream once per pass: the dense interpolation entries of the level
+    (sz bytes each) plus their index data (a 64-byte record and 2 n int16
+    column positions per pair node).  The vectors passed between levels
+    (child vectors read, parent vectors written, 2 B values per column) are
+    an artefact of running one launch per level and are reported apart as
+    intermediate_bytes_per_launch."""
+    lvls = range(2, nlev + 1)
+    nl = max(nlev - 1, 1)
+    alg = sum(info["bf_level_T"][i] * sz + 64 * info["bf_level_nodes"][i] + 4 * info["bf_level_units"][i]
+              for i in lvls) / nl
+    inter = sum(2 * info["bf_level_units"][i] * 2 * B * sz for i in lvls) / nl
+    launch_ms = levels_ms / nl
+    achieved = alg / (launch_ms * 1e-3) / 1e9
+    nb = 8 if B >= 8 else 4 if B >= 4 else 2 if B >= 2 else 1
+    kern = "void sht::k_bf_level<%d, %s>" % (nb, "double" if sz == 8 else "float")
+    return {"kernel": f"k_bf_level ({nl} launches per pass, one per level 2..{nlev})", "bound": "hbm",
+            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(kern, L, N, B), "bytes_per_launch": int(alg),
+            "intermediate_bytes_per_launch": int(inter), "launch_ms": round(launch_ms, 4),
+            "with_intermediate_GBs": round((alg + inter) / (launch_ms * 1e-3) / 1e9, 1)}
+
+
+def rms_err(np, y, x):
+    """RMS relative error of Sec. 4.2 (Eq. 24), worst over maps (rows)."""
+    return max(float(np.sqrt(np.sum((y[b] - x[b]) ** 2) / np.sum(x[b] ** 2))) for b in range(x.shape[0]))
+
+
+def sampled_errors(np, oracle, L, N, alm, maps_by_path, rings):
+    """max rel and RMS error of each path on the listed rings against the
+    long-double oracle (relative to the oracle's max on the same rings)."""
+    ref = np.concatenate(oracle.synthesis_rings(L, N, alm, rings, ld=True), axis=1)
+    out = {}
+    for name, f in maps_by_path.items():
+        y = np.concatenate([f[:, oracle.ring_info(N, r)[4]:oracle.ring_info(N, r)[4] + oracle.ring_info(N, r)[2]]
+                            for r in rings], axis=1)
+        mx = max(float(np.max(np.abs(y[b] - ref[b])) / np.max(np.abs(ref[b]))) for b in range(ref.shape[0]))
+        out[name] = {"max_rel_err": float(f"{mx:.3e}"), "rms_eps": float(f"{rms_err(np, y, ref):.3e}")}
+    return out
+
+
+def timed_paths(np, torch, sht, plan, d_alm, paths, steps, warmup):
+    """Synthesis of every path over `steps` steps with stage events; returns
+    per-path timings and the last output maps (host)."""
+    B = d_alm.shape[1]
+    dev = d_alm.device
+    out = torch.empty((B, plan.npix), dtype=torch.float64, device=dev)
+    big = max(plan.workspace_bytes(B, path=p, precision=q) for _, p, q in paths)
+    ws = torch.empty(big, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    evs = []
+    for _ in range(steps):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(2 * sht.NSTAGES)]
+        for x in e:
+            x.record(stream)
+        evs.append(e)
+    res, maps = {}, {}
+    for name, path, prec in paths:
+        for _ in range(warmup):
+            plan.synthesis(d_alm, out, path=path, precision=prec, workspace=ws)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        for k in range(steps):
+            plan.synthesis(d_alm, out, path=path, precision=prec, workspace=ws, events=evs[k])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - ts
+        r = {"maps_per_s": round(B * steps / el, 3), "ms_per_step": round(1e3 * el / steps, 4),
+             "legendre_ms": round(float(np.mean([e[0].elapsed_time(e[1]) for e in evs])), 4),
+             "ring_ms": round(float(np.mean([e[2].elapsed_time(e[3]) for e in evs])), 4)}
+        if path == sht.PATH_BUTTERFLY:
+            s8, s10 = 2 * sht.STAGE_BF_RESIDUAL, 2 * sht.STAGE_BF_LEVELS
+            r["residual_ms"] = round(float(np.mean([e[s8].elapsed_time(e[s8 + 1]) for e in evs])), 4)
+            r["levels_ms"] = round(float(np.mean([e[s10].elapsed_time(e[s10 + 1]) for e in evs])), 4)
+        res[name] = r
+        maps[name] = out.cpu().numpy()
+    del ws, out
+    return res, maps
+
+
+def many_map_bench(np, torch, sht, plan, info, args, ref_maps):
+    """Many maps per step at the headline size (the many-transform regime of
+    Sec. 3.4): one pass of the butterfly kernels takes up to 64 maps in
+    groups of 8, so the interpolation matrices stream from HBM once per pass
+    instead of once per 8 maps.  Seeds 400.. (the first four maps are the
+    headline's, and must come out identical to it)."""
+    from paper_1110_4874_amd.synthetic import alm_gaussian
+    L, N = plan.L, plan.nside
+    nlev = max([d for d, c in enumerate(info["bf_depth_hist"]) if c > 0] + [0])
+    out = {}
+    for B in args.many_maps:
+        need = max(plan.workspace_bytes(B, path=sht.PATH_BUTTERFLY), plan.workspace_bytes(B, path=sht.PATH_BRUTE)) \
+            + B * (plan.npix * 8 + plan.nalm * 16)
+        free = torch.cuda.mem_get_info()[0]
+        if need > 0.85 * free:
+            out[str(B)] = {"skipped": f"needs {need / 1e9:.1f} GB of device memory, {free / 1e9:.1f} GB free"}
+            log(f"[bench] many maps B={B}: skipped ({out[str(B)]['skipped']})")
+            continue
+        d_alm = torch.from_numpy(alm_gaussian(L, [400 + b for b in range(B)])).cuda()
+        paths = [("brute", sht.PATH_BRUTE, sht.PREC_FP64), ("bf64", sht.PATH_BUTTERFLY, sht.PREC_FP64),
+                 ("bf32", sht.PATH_BUTTERFLY, sht.PREC_FP32)]
+        steps = max(2, min(args.steps, 5))
+        res, maps = timed_paths(np, torch, sht, plan, d_alm, paths, steps, 1)
+        passes = -(-B // 64)
+        for name in res:
+            r = res[name]
+            r["speedup_vs_brute"] = round(r["maps_per_s"] / res["brute"]["maps_per_s"], 3)
+            if name in ref_maps:
+                k = min(B, ref_maps[name].shape[0])
+                r["first_maps_equal_headline"] = bool(np.array_equal(maps[name][:k], ref_maps[name][:k]))
+            if name != "brute":
+                sz = 8 if name == "bf64" else 4
+                r["interp_bytes_per_map"] = int(info["bf_T_entries"] * sz * passes / B)
+                if nlev >= 2 and B <= 64:
+                    r["level_roofline"] = level_roofline(info, nlev, sz, B, r["levels_ms"], L, N)
+        out[str(B)] = {"maps": B, "steps": steps, "passes": passes, "paths": res}
+        log(f"[bench] many maps B={B}: " + ", ".join(f"{n} {res[n]['maps_per_s']:.1f} maps/s" for n in res))
+        del d_alm, maps
+        torch.cuda.empty_cache()
+    return out
+
+
+def config3_bench(np, torch, sht, args):
+    """16 maps at L = 2047, nside = 1024 (seeds 300..315): brute FP64 and the
+    butterfly as a multi-map product in FP64 and FP32 (eps 1e-12), with the
+    errors of each against the long-double oracle on sampled rings."""
+    import oracle
+    from paper_1110_4874_amd.synthetic import alm_gaussian
+    L, N, B = 2047, 1024, 16
+    plan = sht.cached_plan(L, N, 1e-12, store_fp32=True, log=log)
+    info = plan.info()
+    alm = alm_gaussian(L, list(range(300, 300 + B)))
+    d_alm = torch.from_numpy(alm).cuda()
+    paths = [("brute", sht.PATH_BRUTE, sht.PREC_FP64), ("bf64", sht.PATH_BUTTERFLY, sht.PREC_FP64),
+             ("bf32", sht.PATH_BUTTERFLY, sht.PREC_FP32)]
+    res, maps = timed_paths(np, torch, sht, plan, d_alm, paths, args.steps, args.warmup)
+    errs = sampled_errors(np, oracle, L, N, alm, maps, [1, 2, 120, 400, N, 2 * N, 3 * N, 4 * N - 1])
+    nlev = max([d for d, c in enumerate(info["bf_depth_hist"]) if c > 0] + [0])
+    for name in res:
+        res[name].update(errs[name])
+        res[name]["speedup_vs_brute"] = round(res[name]["maps_per_s"] / res["brute"]["maps_per_s"], 3)
+        if name != "brute" and nlev >= 2:
+            res[name]["level_roofline"] = level_roofline(info, nlev, 8 if name == "bf64" else 4, B,
+                                                         res[name]["levels_ms"], L, N)
+    log("[bench] L=2047 B=16: " + ", ".join(f"{n} {res[n]['maps_per_s']:.1f} maps/s (err {res[n]['max_rel_err']:.1e})"
+                                          for n in res))
+    out = {"workload": "HEALPix synthesis L=2047 nside=1024, 16 maps per step", "steps": args.steps,
+           "T_entries": info["bf_T_entries"], "depth_hist": info["bf_depth_hist"][:6], "paths": res}
+    plan.close()
+    del d_alm
+    torch.cuda.empty_cache()
+    return out
 
 
 def gradient_bench(np, torch, sht, plan, info, paths, d_alm, f_true, ws, ev_sets, args, flops):
@@ -292,6 +458,9 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip timing the adjoint")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-request batching measurement")
     ap.add_argument("--no-analysis", action="store_true", help="skip timing the quadrature analysis")
+    ap.add_argument("--many-maps", type=int, nargs="*", default=[16, 64],
+                    help="also time these map counts at the headline size (one pass of up to 64 maps)")
+    ap.add_argument("--no-config3", action="store_true", help="skip the 16-map L=2047 measurement")
     ap.add_argument("--rings-per-lane", type=int, default=0, help="Legendre kernel tile (1, 2, 4; 0 = plan default)")
     ap.add_argument("--ring-threads", type=int, default=0, help="ring kernel workgroup size (256, 512, 1024; 0 = default)")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -314,13 +483,16 @@ def main():
     seeds = [400 + b for b in range(B)]
     log(f"[bench] L={L} nside={N} maps={B}: drawing inputs")
     alm = alm_gaussian(L, seeds)
-    log(f"[bench] building plan (eps={args.eps})")
+    log(f"[bench] plan (eps={args.eps}): from the plan cache, else built (untimed, as the paper excludes "
+        "loading its precomputed data)")
     t0 = time.perf_counter()
     # the transposed matrix copy serves the adjoint of the gradient measurement
-    plan = sht.Plan(L, N, args.eps, rings_per_lane=args.rings_per_lane, ring_threads=args.ring_threads,
-                    rho=args.rho, store_fp32=args.eps > 0, store_transpose=args.eps > 0 and not args.no_adjoint)
+    kw = {k: v for k, v in (("rings_per_lane", args.rings_per_lane), ("ring_threads", args.ring_threads),
+                            ("rho", args.rho)) if v}
+    plan = sht.cached_plan(L, N, args.eps, store_fp32=args.eps > 0,
+                           store_transpose=args.eps > 0 and not args.no_adjoint, log=log, **kw)
     info = plan.info()
-    log(f"[bench] plan built in {time.perf_counter() - t0:.1f}s: n_step={info['n_step']:.4e} "
+    log(f"[bench] plan ready in {time.perf_counter() - t0:.1f}s: n_step={info['n_step']:.4e} "
         f"dd_rings={info['n_dd_rings']} butterfly={info['bf_built']} T={info['bf_T_entries']:.4e} "
         f"residual={info['bf_res_elems']:.4e} device={info['device_bytes'] / 1e9:.2f} GB")
 
@@ -389,19 +561,7 @@ def main():
                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "bytes_per_launch": nbytes}
         if r["levels_ms"] >= r["residual_ms"]:
-            # levels >= 2 (level 1 runs fused with the fold): interpolation matrices streamed
-            # once, child vectors read and parent vectors written once
-            lvls = range(2, nlev + 1)
-            lvl_bytes = sum(info["bf_level_T"][i] * sz + 2 * info["bf_level_units"][i] * 2 * B * sz for i in lvls)
-            nl = max(nlev - 1, 1)
-            per_launch = lvl_bytes / nl
-            achieved = per_launch / (r["levels_ms"] / nl * 1e-3) / 1e9
-            kern = "void sht::k_bf_level<%d, %s>" % (min(B, 8) if B in (1, 2, 4, 8) else 4, "double" if sz == 8 else "float")
-            return {"kernel": f"k_bf_level ({nl} launches per pass, one per level 2..{nlev})", "bound": "hbm",
-                    "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": measured_traffic(kern, L, N, B), "bytes_per_launch": int(per_launch),
-                    "launch_ms": round(r["levels_ms"] / nl, 4)}
+            return level_roofline(info, nlev, sz, B, r["levels_ms"], L, N)
         rflops = info["bf_res_elems"] * (5 + 4 * B)
         achieved = rflops / (r["residual_ms"] * 1e-3) / 1e12
         return {"kernel": "k_bf_residual (one launch)", "bound": "alu", "achieved": round(achieved, 3),
@@ -412,6 +572,10 @@ def main():
     head = max(fp64, key=lambda n: results[n]["maps_per_s"])
     hr = results[head]
     log(f"[bench] headline path: {head}")
+
+    many = None
+    if info["bf_built"] and args.many_maps:
+        many = many_map_bench(np, torch, sht, plan, info, args, maps_out)
 
     adj = None
     if not args.no_adjoint:
@@ -425,6 +589,8 @@ def main():
         line_batch = batch_bench(np, torch, sht, args.steps)
     else:
         line_batch = None
+
+    cfg3 = None if args.no_config3 else config3_bench(np, torch, sht, args)
 
     if args.copy_calibration:
         nbytes = args.copy_calibration << 20
@@ -481,6 +647,10 @@ def main():
         line["analysis"] = ana
     if line_batch is not None:
         line["batching"] = line_batch
+    if many is not None:
+        line["many_maps"] = many
+    if cfg3 is not None:
+        line["L2047_16maps"] = cfg3
 
     if not args.no_cpu_baseline:
         import oracle
@@ -493,27 +663,27 @@ def main():
         oracle.synthesis_rings(L, N, alm, rings)
         tcpu = time.perf_counter() - tc
         full = tcpu * nr / k
+        cores = oracle.num_threads()
         line["cpu_baseline"] = {
             "value": round(B / full, 6),
             "unit": "maps/s",
-            "cores": oracle.num_threads(),
+            "cores": cores,
+            "cpu_model": cpu_model(),
+            "cpu_seconds_per_transform": round(full * cores / B, 1),
             "kind": "oracle",
             "sample": f"{k} of {nr} rings drawn uniformly (seed 0), all {B} maps, FP64 oracle "
                       f"(one-step Legendre recurrence + direct per-ring DFT); {tcpu:.1f}s measured, "
                       f"scaled by {nr}/{k}",
         }
         # accuracy of each GPU path on a few rings against the long-double oracle
-        chk = [1, 2, 100, 1000, 2 * N, 2 * N + 1, 3 * N, nr]
-        ref = oracle.synthesis_rings(L, N, alm, chk, ld=True)
-        for name, f in maps_out.items():
-            fmax = np.max(np.abs(f), axis=1)
-            worst = 0.0
-            for ring, r in zip(chk, ref):
-                _, _, J, _, off = oracle.ring_info(N, ring)
-                worst = max(worst, float(np.max(np.max(np.abs(f[:, off:off + J] - r), axis=1) / fmax)))
-            line["paths"][name]["max_rel_err"] = float(f"{worst:.3e}")
+        chk = [1, 2, 100, 250, 251, 1000, 2 * N, 2 * N + 1, 3 * N, nr]
+        errs = sampled_errors(np, oracle, L, N, alm, maps_out, chk)
+        for name in maps_out:
+            line["paths"][name].update(errs[name])
         line["max_rel_err"] = line["paths"][head]["max_rel_err"]
-        line["max_rel_err_sample"] = f"rings {chk}, all maps, vs long-double oracle, relative to max|f| per map"
+        line["rms_eps"] = line["paths"][head]["rms_eps"]
+        line["max_rel_err_sample"] = (f"rings {chk}, all maps, vs long-double oracle, relative to the oracle's "
+                                      "max on those rings per map; rms_eps is Eq. 24 on the same sample")
         log(f"[bench] cpu baseline {line['cpu_baseline']['value']:.4f} maps/s; errors "
             + ", ".join(f"{n} {line['paths'][n]['max_rel_err']:.2e}" for n in maps_out))
 

@@ -176,6 +176,8 @@ typedef struct sht_plan_info {
     int bf_nbatch;            /* order batches per transform */
     long long bf_level_T[11];     /* dense entries of the pair nodes of level 0..10 */
     long long bf_level_units[11]; /* output columns of the pair nodes of level 0..10 */
+    long long bf_level_nodes[11]; /* pair nodes of level 0..10 (each reads a 64-byte
+                                     record and 2 n int16 column positions) */
 } sht_plan_info_t;
 
 void sht_plan_opts_default(sht_plan_opts *o);
@@ -251,6 +253,23 @@ size_t sht_workspace_bytes(const sht_plan_t *plan, const sht_exec_opts *x);
 int sht_synthesis(const sht_plan_t *plan, const double *alm, double *map);
 int sht_synthesis_ex(const sht_plan_t *plan, const sht_exec_opts *x,
                      const double *alm, double *map);
+
+/* Synthesis that allocates nothing, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation.  Same arguments, kernels and results as
+ * sht_synthesis_ex, except that the workspace is a fixed array of
+ * sht_noalloc_scratch_bytes() (64 MiB) that the library holds on every GPU it
+ * runs on until the process ends (x->workspace is ignored).  The caller
+ * still passes the input and output buffers.  Returns SHT_ENOMEM, before
+ * anything is launched, when sht_workspace_bytes() of the same options
+ * exceeds that size (e.g. L = 1023 at nside = 512 fits one map, L = 511 at
+ * nside = 256 seven).  Calls on one GPU share the array: calls that overlap
+ * in time on one GPU (other streams, other threads) race and must not be
+ * made; calls ordered on one stream are safe.  No part of the array needs
+ * to start at zero. */
+size_t sht_noalloc_scratch_bytes(void);
+int sht_synthesis_noalloc(const sht_plan_t *plan, const sht_exec_opts *x,
+                          const double *alm, double *map);
 
 /* Adjoint g = A^T y of synthesis (Sec. 2.2: the operator the Wiener filter of
  * Eq. 7 needs; the paper builds synthesis only).  With the default

@@ -284,6 +284,11 @@ sht_plan_t *sht_plan_ex(int L, int nside, double eps, const sht_plan_opts *opts)
             delete p;
             return nullptr;
         }
+        void *scr = nullptr;  // look up the no-allocation scratch of this device now
+        if (noalloc_scratch(dev, &scr) != SHT_OK) {
+            sht_plan_free(p);
+            return nullptr;
+        }
     }
     p->build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return p;
@@ -327,6 +332,7 @@ int sht_plan_info(const sht_plan_t *p, sht_plan_info_t *out) {
         for (int i = 0; i <= kBfMaxLv; i++) {
             out->bf_level_T[i] = b.level_T[i];
             out->bf_level_units[i] = b.level_units[i];
+            out->bf_level_nodes[i] = b.level_nodes[i];
         }
     }
     return SHT_OK;
@@ -355,6 +361,26 @@ int sht_synthesis_ex(const sht_plan_t *p, const sht_exec_opts *x, const double *
     Scratch ws;
     if ((rc = ws.get(x, synth_ws_bytes(p, x), p->device))) return rc;
     return synth_stages(p, B, x->path, x->precision, alm, map, ws.ptr, (hipStream_t)x->stream, x);
+}
+
+size_t sht_noalloc_scratch_bytes(void) { return kNoAllocScratchBytes; }
+
+int sht_synthesis_noalloc(const sht_plan_t *p, const sht_exec_opts *x, const double *alm, double *map) {
+    int rc = check_plan(p);
+    if (!rc) rc = check_exec(p, x);
+    if (rc) return rc;
+    DeviceGuard g(p->device);
+    if (!g.ok) return fail(SHT_EDEVICE, "cannot select the plan's device");
+    const int B = x->nmaps;
+    const size_t need = synth_ws_bytes(p, x);
+    if (need > kNoAllocScratchBytes)
+        return fail(SHT_ENOMEM, "transform needs " + std::to_string(need) + " bytes of scratch, more than the " +
+                                    std::to_string(kNoAllocScratchBytes) + " of sht_synthesis_noalloc");
+    if ((rc = check_dev_ptr(alm, nalm_of(p->L) * B * 16, p->device, "alm"))) return rc;
+    if ((rc = check_dev_ptr(map, npix_of(p->nside) * B * 8, p->device, "map"))) return rc;
+    void *scr = nullptr;
+    if ((rc = noalloc_scratch(p->device, &scr))) return rc;
+    return synth_stages(p, B, x->path, x->precision, alm, map, scr, (hipStream_t)x->stream, x);
 }
 
 int sht_adjoint(const sht_plan_t *p, const double *map, double *alm) {

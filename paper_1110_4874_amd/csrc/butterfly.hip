@@ -49,7 +49,7 @@ constexpr int kBfIdUnroll = 4;  // identity entries per lane in flight
 // wave-uniform bases; the tile count is a template parameter so that the
 // products run back to back, without branches between them).
 template <int NT, int NB, typename S>
-__device__ __forceinline__ void dense_tiles(const S *__restrict__ v, const S *__restrict__ Tb,
+__device__ __forceinline__ void dense_tiles(const S *__restrict__ v, int ES, const S *__restrict__ Tb,
                                             const int16_t *__restrict__ pm, int kk, int nd, int gw, int lane,
                                             S *uc) {
     constexpr int NC = 2 * NB;
@@ -65,7 +65,7 @@ __device__ __forceinline__ void dense_tiles(const S *__restrict__ v, const S *__
 #pragma unroll
         for (int j = 0; j < KS; j++) {
             const int s = s0 + 4 * j + k4, sc = min(s, kk - 1);
-            bv[j] = ld32(v, sc * NC + ic) * (S)(s < kk);
+            bv[j] = ld32(v, sc * ES + ic) * (S)(s < kk);
 #pragma unroll
             for (int tt = 0; tt < NT; tt++) av[j][tt] = ld32(Tb, sc * nd + min(gw + 16 * tt + i16, nd - 1));
         }
@@ -93,7 +93,7 @@ __device__ __forceinline__ void dense_tiles(const S *__restrict__ v, const S *__
 }
 
 template <int NB, typename S>
-__device__ __forceinline__ void id_block(const BfArgs<S> &a, int node, int ch, int half, int lane, S *uc) {
+__device__ __forceinline__ void id_block(const BfArgs<S> &a, int node, int ch, int half, int lane, S *uc, int col) {
     constexpr int NC = 2 * NB;
     constexpr int TPW = 4 / kBfHalves;  // tiles per wave
     constexpr int KS = kBfKSteps;
@@ -101,7 +101,8 @@ __device__ __forceinline__ void id_block(const BfArgs<S> &a, int node, int ch, i
     const int *ni = a.node_i + (size_t)node * kBfNodeInts;
     const int n = ni[2] + ni[4];
     const int kk = ni[2 + ch], nd = ni[4 + ch];
-    const S *__restrict__ v = a.ws + (size_t)ni[ch] * NC;
+    const int ES = a.ES;
+    const S *__restrict__ v = a.ws + (size_t)ni[ch] * ES + col;
     const int16_t *__restrict__ pm = a.perm + ni[7] + (size_t)ch * n;
     const long long toff = (long long)(unsigned)ni[12 + 2 * ch] | ((long long)ni[13 + 2 * ch] << 32);
     const S *__restrict__ Tb = a.T + toff;
@@ -113,7 +114,7 @@ __device__ __forceinline__ void id_block(const BfArgs<S> &a, int node, int ch, i
 #pragma unroll
         for (int j = 0; j < kBfIdUnroll; j++) {
             const int ec = min(e0 + lane + 64 * kBfHalves * j, ne - 1);
-            x[j] = ld32(v, ec);
+            x[j] = ld32(v, (ec / NC) * ES + ec % NC);
             px[j] = pm[ec / NC];
         }
 #pragma unroll
@@ -127,10 +128,10 @@ __device__ __forceinline__ void id_block(const BfArgs<S> &a, int node, int ch, i
         const int ntile = min(TPW, min(4, (nd - g0 + 15) >> 4) - half * TPW);  // tiles of this wave
         const int gw = g0 + 16 * TPW * half;
         switch (ntile) {
-            case 1: dense_tiles<1, NB, S>(v, Tb, pm, kk, nd, gw, lane, uc); break;
-            case 2: dense_tiles<2, NB, S>(v, Tb, pm, kk, nd, gw, lane, uc); break;
-            case 3: dense_tiles<3, NB, S>(v, Tb, pm, kk, nd, gw, lane, uc); break;
-            case 4: dense_tiles<4, NB, S>(v, Tb, pm, kk, nd, gw, lane, uc); break;
+            case 1: dense_tiles<1, NB, S>(v, ES, Tb, pm, kk, nd, gw, lane, uc); break;
+            case 2: dense_tiles<2, NB, S>(v, ES, Tb, pm, kk, nd, gw, lane, uc); break;
+            case 3: dense_tiles<3, NB, S>(v, ES, Tb, pm, kk, nd, gw, lane, uc); break;
+            case 4: dense_tiles<4, NB, S>(v, ES, Tb, pm, kk, nd, gw, lane, uc); break;
             default: break;
         }
     }
@@ -152,7 +153,7 @@ template <int NB, int R, typename S>
 __device__ __forceinline__ void residual_task(const BfArgs<S> &a, S *__restrict__ slot, long long lbase, int lane,
                                               int t, int imin, int iend, int nl, int outb,
                                               const double *__restrict__ ap, const double *__restrict__ cfs,
-                                              int astride, double *stg) {
+                                              int astride, double *stg, int col0) {
     constexpr int NC = 2 * NB;
     constexpr int CW = NC + 4;          // per row: a_lm components, then B, AB, G and a pad
     constexpr int CS = kChunk * CW;     // doubles per staged chunk
@@ -236,7 +237,7 @@ __device__ __forceinline__ void residual_task(const BfArgs<S> &a, S *__restrict_
     for (int r = 0; r < R; r++) {
         const int j = r * 64 + lane;
         if (j < nl) {
-            S *dst = slot + ((size_t)outb + j) * NC;
+            S *dst = slot + ((size_t)outb + j) * a.ES + col0;
 #pragma unroll
             for (int c = 0; c < NC; c++) dst[c] = (S)acc[r][c];
         }
@@ -246,7 +247,7 @@ __device__ __forceinline__ void residual_task(const BfArgs<S> &a, S *__restrict_
 // One wave per residual piece (up to kBfPieceRings skeleton rings of one
 // task): short waves keep the register count, and with it the occupancy, low.
 template <int NB, typename S>
-__global__ __launch_bounds__(kBfThreads) void k_bf_residual(BfArgs<S> a, long long t0, long long t1) {
+__global__ __launch_bounds__(kBfThreads) void k_bf_residual(BfArgs<S> a, long long t0, long long t1, int col0) {
     __shared__ double stg_all[kBfThreads / 64][bf_res_stage_doubles<NB>()];
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -262,12 +263,13 @@ __global__ __launch_bounds__(kBfThreads) void k_bf_residual(BfArgs<S> a, long lo
     const double *cfs = a.coef + 4 * a.coef_off[m];
     const int astride = 4 * a.nmaps;  // doubles between rows i and i+1
     residual_task<NB, kBfPieceRings / 64>(a, a.ws, lbase, lane, t, imin, iend, nl, outb, ap, cfs, astride,
-                                          stg_all[w]);
+                                          stg_all[w], col0);
 }
 
 // One workgroup of 2 kBfHalves waves per pair node (wave w: child w % 2,
-// half w / 2): u (zeroed in LDS) collects both children, then goes to the
-// next level's vector in one coalesced store.
+// half w / 2): per group of NB maps, each child writes its share of u into
+// its own LDS copy, and the two copies are summed into the next level's
+// vector with one coalesced store.
 
 template <int NB, typename S>
 __device__ __forceinline__ void level_node(const BfArgs<S> &a, int node) {
@@ -278,10 +280,14 @@ __device__ __forceinline__ void level_node(const BfArgs<S> &a, int node) {
     const int n = ni[2] + ni[4];
     S *u1 = u0 + (size_t)n * NC;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    id_block<NB, S>(a, node, w & 1, w >> 1, threadIdx.x & 63, (w & 1) ? u1 : u0);
-    __syncthreads();
-    S *__restrict__ out = a.ws + (size_t)ni[6] * NC;
-    for (int e = threadIdx.x; e < n * NC; e += kBfLevelThreads) out[e] = u0[e] + u1[e];
+    S *__restrict__ out = a.ws + (size_t)ni[6] * a.ES;
+    for (int g = 0; g < a.G; g++) {
+        if (g) __syncthreads();  // the previous group's sums have been read out of LDS
+        id_block<NB, S>(a, node, w & 1, w >> 1, threadIdx.x & 63, (w & 1) ? u1 : u0, g * NC);
+        __syncthreads();
+        for (int e = threadIdx.x; e < n * NC; e += kBfLevelThreads)
+            out[(size_t)(e / NC) * a.ES + g * NC + e % NC] = u0[e] + u1[e];
+    }
 }
 
 template <int NB, typename S>
@@ -313,37 +319,40 @@ __global__ __launch_bounds__(kBfFoldThreads) void k_bf_level1_fold(BfArgs<S> a, 
     S *uE = reinterpret_cast<S *>(lds_raw);  // even node: children 0 and 1, then the odd node's
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int par = w / (2 * kBfHalves), wc = w % (2 * kBfHalves);
-    id_block<NB, S>(a, par ? un.y : un.x, wc & 1, wc >> 1, threadIdx.x & 63,
-                    uE + (size_t)(2 * par + (wc & 1)) * n * NC);
-    __syncthreads();
     const int m = batch + un.w * nbatch, k0 = un.z;
-    for (int e = threadIdx.x; e < n * NB; e += kBfFoldThreads) {
-        const int c = e / NB, b = e % NB;
-        const S *e0 = uE + c * NC + 2 * b, *e1 = e0 + (size_t)n * NC, *o0 = e1 + (size_t)n * NC,
-                *o1 = o0 + (size_t)n * NC;
-        double er = (double)(e0[0] + e1[0]), ei = (double)(e0[1] + e1[1]);
-        double orr = (double)(o0[0] + o1[0]), oi = (double)(o0[1] + o1[1]);
-        if (m == 0) ei = oi = 0.0;  // real field: Im a_l0 is ignored
-        const int k = k0 + c, ks = a.nrings - 1 - k;
-        a.q[((size_t)k * (a.L + 1) + m) * a.nmaps + a.map0 + b] = make_double2(er + orr, ei + oi);
-        if (ks != k) a.q[((size_t)ks * (a.L + 1) + m) * a.nmaps + a.map0 + b] = make_double2(er - orr, ei - oi);
+    for (int g = 0; g < a.G; g++) {
+        if (g) __syncthreads();  // the previous group's fold has read LDS
+        id_block<NB, S>(a, par ? un.y : un.x, wc & 1, wc >> 1, threadIdx.x & 63,
+                        uE + (size_t)(2 * par + (wc & 1)) * n * NC, g * NC);
+        __syncthreads();
+        const int mb = a.map0 + g * NB;
+        for (int e = threadIdx.x; e < n * NB; e += kBfFoldThreads) {
+            const int c = e / NB, b = e % NB;
+            const S *e0 = uE + c * NC + 2 * b, *e1 = e0 + (size_t)n * NC, *o0 = e1 + (size_t)n * NC,
+                    *o1 = o0 + (size_t)n * NC;
+            double er = (double)(e0[0] + e1[0]), ei = (double)(e0[1] + e1[1]);
+            double orr = (double)(o0[0] + o1[0]), oi = (double)(o0[1] + o1[1]);
+            if (m == 0) ei = oi = 0.0;  // real field: Im a_l0 is ignored
+            const int k = k0 + c, ks = a.nrings - 1 - k;
+            a.q[((size_t)k * (a.L + 1) + m) * a.nmaps + mb + b] = make_double2(er + orr, ei + oi);
+            if (ks != k) a.q[((size_t)ks * (a.L + 1) + m) * a.nmaps + mb + b] = make_double2(er - orr, ei - oi);
+        }
     }
 }
 
 // Fold of the listed slots of one batch: slot j holds order m = batch + j nbatch.
-template <int NB, typename S>
+template <typename S>
 __global__ __launch_bounds__(kBfThreads) void k_bf_fold(BfArgs<S> a, int batch, int nbatch, const int *__restrict__ slots,
                                                         int count) {
-    constexpr int NC = 2 * NB;
-    const int K = a.K;
+    const int K = a.K, NP = a.ES / 2;  // maps of the pass
     const long long e = (long long)blockIdx.x * kBfThreads + threadIdx.x;
-    if (e >= (long long)count * K * NB) return;
-    const int b = (int)(e % NB);
-    const long long jk = e / NB;
+    if (e >= (long long)count * K * NP) return;
+    const int b = (int)(e % NP);
+    const long long jk = e / NP;
     const int k = (int)(jk % K), j = slots[jk / K];
     const int m = batch + j * nbatch;
-    const S *qe = a.ws + ((size_t)(2 * j) * K + k) * NC + 2 * b;
-    const S *qo = a.ws + ((size_t)(2 * j + 1) * K + k) * NC + 2 * b;
+    const S *qe = a.ws + ((size_t)(2 * j) * K + k) * a.ES + 2 * b;
+    const S *qo = a.ws + ((size_t)(2 * j + 1) * K + k) * a.ES + 2 * b;
     double er = (double)qe[0], ei = (double)qe[1], orr = (double)qo[0], oi = (double)qo[1];
     if (m == 0) ei = oi = 0.0;  // real field: Im a_l0 is ignored
     a.q[((size_t)k * (a.L + 1) + m) * a.nmaps + a.map0 + b] = make_double2(er + orr, ei + oi);
@@ -352,7 +361,7 @@ __global__ __launch_bounds__(kBfThreads) void k_bf_fold(BfArgs<S> a, int batch, 
 }
 
 size_t bf_scratch_bytes(const sht_plan_s *p, int nmaps, int fp32) {
-    return (size_t)p->bf.ws_entries * 2 * bf_nb(nmaps) * (fp32 ? sizeof(float) : sizeof(double));
+    return (size_t)p->bf.ws_entries * bf_entry_values(nmaps) * (fp32 ? sizeof(float) : sizeof(double));
 }
 
 // Records the caller's stage event (which = 0 before, 1 after) if given.
@@ -368,9 +377,12 @@ static hipError_t launch_bf_nb(const sht_plan_s *p, BfArgs<S> a, hipStream_t st,
     for (int bt = 0; bt < b.nbatch; bt++) {
         const long long t0 = b.batch_sub[bt], t1 = b.batch_sub[bt + 1];
         bf_event(ev, SHT_STAGE_BF_RESIDUAL, 0, st);
-        if (t1 > t0)
+        for (int g = 0; g < a.G && t1 > t0; g++) {  // one launch per group of NB maps
+            BfArgs<S> ag = a;
+            ag.map0 = a.map0 + g * NB;
             hipLaunchKernelGGL((k_bf_residual<NB, S>), dim3((unsigned)((t1 - t0 + WPB - 1) / WPB)), dim3(kBfThreads), 0,
-                               st, a, t0, t1);
+                               st, ag, t0, t1, g * 2 * NB);
+        }
         bf_event(ev, SHT_STAGE_BF_RESIDUAL, 1, st);
         bf_event(ev, SHT_STAGE_BF_LEVELS, 0, st);
         const long long *lo = b.lv_off.data() + (size_t)bt * (kBfMaxLv + 1);
@@ -393,9 +405,9 @@ static hipError_t launch_bf_nb(const sht_plan_s *p, BfArgs<S> a, hipStream_t st,
             hipLaunchKernelGGL((k_bf_level1_fold<NB, S>), dim3((unsigned)(f1 - f0)), dim3(kBfFoldThreads), 2 * lds1, st,
                                a, reinterpret_cast<const int4 *>(p->d_bf_f1_unit), f0, bt, b.nbatch);
         const long long s0 = b.fold_off[bt], s1 = b.fold_off[bt + 1];
-        const long long nf = (s1 - s0) * b.K * NB;
+        const long long nf = (s1 - s0) * b.K * (a.ES / 2);
         if (nf > 0)
-            hipLaunchKernelGGL((k_bf_fold<NB, S>), dim3((unsigned)((nf + kBfThreads - 1) / kBfThreads)),
+            hipLaunchKernelGGL((k_bf_fold<S>), dim3((unsigned)((nf + kBfThreads - 1) / kBfThreads)),
                                dim3(kBfThreads), 0, st, a, bt, b.nbatch, p->d_bf_fold_slot + s0, (int)(s1 - s0));
     }
     return hipGetLastError();
@@ -409,15 +421,18 @@ static hipError_t launch_bf(const sht_plan_s *p, int nmaps, const double *alm, d
     a.q = reinterpret_cast<double2 *>(q);
     hipError_t e = hipSuccess;
     for (int b = 0; b < nmaps && e == hipSuccess;) {
-        const int nb = bf_nb(nmaps - b);
+        int nb, groups;
+        bf_pass_shape(nmaps - b, &nb, &groups);
         a.map0 = b;
+        a.G = groups;
+        a.ES = 2 * nb * groups;
         switch (nb) {
             case 8: e = launch_bf_nb<8, S>(p, a, st, ev); break;
             case 4: e = launch_bf_nb<4, S>(p, a, st, ev); break;
             case 2: e = launch_bf_nb<2, S>(p, a, st, ev); break;
             default: e = launch_bf_nb<1, S>(p, a, st, ev); break;
         }
-        b += nb;
+        b += nb * groups;
     }
     return e;
 }

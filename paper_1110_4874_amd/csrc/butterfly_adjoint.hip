@@ -23,23 +23,22 @@ namespace sht {
 // Unfold of the listed slots of one batch: slot j (order m = batch + j
 // nbatch) gets ybar^even and ybar^odd of every north ring in its level-1
 // vectors (the equator once).
-template <int NB, typename S>
+template <typename S>
 __global__ __launch_bounds__(kBfThreads) void k_bf_unfold(BfArgs<S> a, int batch, int nbatch,
                                                           const int *__restrict__ slots, int count) {
-    constexpr int NC = 2 * NB;
-    const int K = a.K;
+    const int K = a.K, NP = a.ES / 2;  // maps of the pass
     const long long e = (long long)blockIdx.x * kBfThreads + threadIdx.x;
-    if (e >= (long long)count * K * NB) return;
-    const int b = (int)(e % NB);
-    const long long jk = e / NB;
+    if (e >= (long long)count * K * NP) return;
+    const int b = (int)(e % NP);
+    const long long jk = e / NP;
     const int k = (int)(jk % K), j = slots[jk / K];
     const int m = batch + j * nbatch;
     const int ks = a.nrings - 1 - k;
     const double2 yn = a.ybar[((size_t)k * (a.L + 1) + m) * a.nmaps + a.map0 + b];
     const double2 ys =
         ks != k ? a.ybar[((size_t)ks * (a.L + 1) + m) * a.nmaps + a.map0 + b] : make_double2(0.0, 0.0);
-    S *qe = a.ws + ((size_t)(2 * j) * K + k) * NC + 2 * b;
-    S *qo = a.ws + ((size_t)(2 * j + 1) * K + k) * NC + 2 * b;
+    S *qe = a.ws + ((size_t)(2 * j) * K + k) * a.ES + 2 * b;
+    S *qo = a.ws + ((size_t)(2 * j + 1) * K + k) * a.ES + 2 * b;
     qe[0] = (S)(yn.x + ys.x);
     qe[1] = (S)(yn.y + ys.y);
     qo[0] = (S)(yn.x - ys.x);
@@ -62,7 +61,7 @@ constexpr int kBfTJ = 2;  // K-steps per batch of loads in the transposed level
 // back to back).  Columns d past nd get U = 0; rows past k hold clamped rows
 // that are not stored.
 template <int NT, int NB, bool TT, typename S>
-__device__ __forceinline__ void split_tiles(const S *__restrict__ Tb, S *__restrict__ v, const S *u,
+__device__ __forceinline__ void split_tiles(const S *__restrict__ Tb, S *__restrict__ v, int ES, const S *u,
                                             const int16_t *pl, int kk, int nd, int s0, int lane) {
     constexpr int NC = 2 * NB;
     constexpr int DB = 4 * kBfTJ;  // dense columns per batch
@@ -94,28 +93,28 @@ __device__ __forceinline__ void split_tiles(const S *__restrict__ Tb, S *__restr
 #pragma unroll
         for (int r = 0; r < 4; r++) {
             const int sr = s0 + 16 * tt + acc_row<S>(k4, r);
-            if (sr < kk && i16 < NC) v[sr * NC + i16] = acc[tt][r] + u[pl[sr] * NC + i16];
+            if (sr < kk && i16 < NC) v[sr * ES + i16] = acc[tt][r] + u[pl[sr] * NC + i16];
         }
 }
 
 template <int NB, bool TT, typename S>
 __device__ __forceinline__ void id_block_t(const BfArgs<S> &a, int node, int ch, int half, int lane, const S *u,
-                                           const int16_t *pl) {
+                                           const int16_t *pl, int col) {
     constexpr int TPW = 4 / kBfHalves;  // 16-row tiles per wave
-    constexpr int NC = 2 * NB;
     const int *ni = a.node_i + (size_t)node * kBfNodeInts;
     const int kk = ni[2 + ch], nd = ni[4 + ch];
-    S *__restrict__ v = a.ws + (size_t)ni[ch] * NC;
+    const int ES = a.ES;
+    S *__restrict__ v = a.ws + (size_t)ni[ch] * ES + col;
     const long long toff = (long long)(unsigned)ni[12 + 2 * ch] | ((long long)ni[13 + 2 * ch] << 32);
     const S *__restrict__ Tb = a.T + toff;
     for (int s00 = 0; s00 < kk; s00 += 64) {
         const int ntile = min(TPW, min(4, (kk - s00 + 15) >> 4) - half * TPW);  // tiles of this wave
         const int s0 = s00 + 16 * TPW * half;
         switch (ntile) {
-            case 1: split_tiles<1, NB, TT, S>(Tb, v, u, pl, kk, nd, s0, lane); break;
-            case 2: split_tiles<2, NB, TT, S>(Tb, v, u, pl, kk, nd, s0, lane); break;
-            case 3: split_tiles<3, NB, TT, S>(Tb, v, u, pl, kk, nd, s0, lane); break;
-            case 4: split_tiles<4, NB, TT, S>(Tb, v, u, pl, kk, nd, s0, lane); break;
+            case 1: split_tiles<1, NB, TT, S>(Tb, v, ES, u, pl, kk, nd, s0, lane); break;
+            case 2: split_tiles<2, NB, TT, S>(Tb, v, ES, u, pl, kk, nd, s0, lane); break;
+            case 3: split_tiles<3, NB, TT, S>(Tb, v, ES, u, pl, kk, nd, s0, lane); break;
+            case 4: split_tiles<4, NB, TT, S>(Tb, v, ES, u, pl, kk, nd, s0, lane); break;
             default: break;
         }
     }
@@ -128,8 +127,9 @@ inline size_t bf_level_t_lds(int n) {
     return (size_t)n * (2 * NB * sizeof(S) + 2 * sizeof(int16_t));
 }
 
-// One workgroup of 2 kBfHalves waves per pair node: u is staged in LDS, then
-// wave w writes half w / 2 of the rows of child w % 2's vector.
+// One workgroup of 2 kBfHalves waves per pair node: per group of NB maps,
+// u is staged in LDS, then wave w writes half w / 2 of the rows of child
+// w % 2's vector.
 template <int NB, bool TT, typename S>
 __device__ __forceinline__ void level_node_t(const BfArgs<S> &a, int node) {
     constexpr int NC = 2 * NB;
@@ -138,13 +138,16 @@ __device__ __forceinline__ void level_node_t(const BfArgs<S> &a, int node) {
     const int *ni = a.node_i + (size_t)node * kBfNodeInts;
     const int n = ni[2] + ni[4];
     int16_t *pl = reinterpret_cast<int16_t *>(u + (size_t)n * NC);
-    const S *__restrict__ in = a.ws + (size_t)ni[6] * NC;
+    const S *__restrict__ in = a.ws + (size_t)ni[6] * a.ES;
     const int16_t *__restrict__ pg = a.perm + ni[7];
-    for (int e = threadIdx.x; e < n * NC; e += kBfLevelThreads) u[e] = in[e];
     for (int e = threadIdx.x; e < 2 * n; e += kBfLevelThreads) pl[e] = pg[e];
-    __syncthreads();
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    id_block_t<NB, TT, S>(a, node, w & 1, w >> 1, threadIdx.x & 63, u, pl + (w & 1) * n);
+    for (int g = 0; g < a.G; g++) {
+        if (g) __syncthreads();  // the previous group's splits have read u
+        for (int e = threadIdx.x; e < n * NC; e += kBfLevelThreads) u[e] = in[(size_t)(e / NC) * a.ES + g * NC + e % NC];
+        __syncthreads();
+        id_block_t<NB, TT, S>(a, node, w & 1, w >> 1, threadIdx.x & 63, u, pl + (w & 1) * n, g * NC);
+    }
 }
 
 template <int NB, bool TT, typename S>
@@ -180,22 +183,26 @@ __global__ __launch_bounds__(kBfUnfoldThreads) void k_bf_unfold_level1(BfArgs<S>
     const int16_t *__restrict__ po = a.perm + a.node_i[(size_t)un.y * kBfNodeInts + 7];
     for (int e = threadIdx.x; e < 4 * n; e += kBfUnfoldThreads) pl[e] = e < 2 * n ? pe[e] : po[e - 2 * n];
     const int m = batch + un.w * nbatch, k0 = un.z;
-    for (int e = threadIdx.x; e < n * NB; e += kBfUnfoldThreads) {
-        const int c = e / NB, b = e % NB;
-        const int k = k0 + c, ks = a.nrings - 1 - k;
-        const double2 yn = a.ybar[((size_t)k * (a.L + 1) + m) * a.nmaps + a.map0 + b];
-        const double2 ys =
-            ks != k ? a.ybar[((size_t)ks * (a.L + 1) + m) * a.nmaps + a.map0 + b] : make_double2(0.0, 0.0);
-        uE[c * NC + 2 * b] = (S)(yn.x + ys.x);
-        uE[c * NC + 2 * b + 1] = (S)(yn.y + ys.y);
-        uO[c * NC + 2 * b] = (S)(yn.x - ys.x);
-        uO[c * NC + 2 * b + 1] = (S)(yn.y - ys.y);
-    }
-    __syncthreads();
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int par = w / (2 * kBfHalves), wc = w % (2 * kBfHalves);
-    id_block_t<NB, TT, S>(a, par ? un.y : un.x, wc & 1, wc >> 1, threadIdx.x & 63, par ? uO : uE,
-                          pl + (2 * par + (wc & 1)) * n);
+    for (int g = 0; g < a.G; g++) {
+        if (g) __syncthreads();  // the previous group's splits have read uE and uO
+        const int mb = a.map0 + g * NB;
+        for (int e = threadIdx.x; e < n * NB; e += kBfUnfoldThreads) {
+            const int c = e / NB, b = e % NB;
+            const int k = k0 + c, ks = a.nrings - 1 - k;
+            const double2 yn = a.ybar[((size_t)k * (a.L + 1) + m) * a.nmaps + mb + b];
+            const double2 ys =
+                ks != k ? a.ybar[((size_t)ks * (a.L + 1) + m) * a.nmaps + mb + b] : make_double2(0.0, 0.0);
+            uE[c * NC + 2 * b] = (S)(yn.x + ys.x);
+            uE[c * NC + 2 * b + 1] = (S)(yn.y + ys.y);
+            uO[c * NC + 2 * b] = (S)(yn.x - ys.x);
+            uO[c * NC + 2 * b + 1] = (S)(yn.y - ys.y);
+        }
+        __syncthreads();
+        id_block_t<NB, TT, S>(a, par ? un.y : un.x, wc & 1, wc >> 1, threadIdx.x & 63, par ? uO : uE,
+                              pl + (2 * par + (wc & 1)) * n, g * NC);
+    }
 }
 
 // Lane exchanges for the wave reductions.  permlane32_swap(a, b) leaves
@@ -288,7 +295,7 @@ __device__ __forceinline__ double wave_transpose_sum(double (&x)[N], int lane) {
 // [imin, iend) of parity t; each row's sum over the task's rings goes to g.
 template <int NB, int R, typename S>
 __device__ __forceinline__ void residual_task_t(const BfArgs<S> &a, long long tk, int lane, int t, int imin,
-                                                int iend, int nl, int outb, int m, c_double *cfs) {
+                                                int iend, int nl, int outb, int m, c_double *cfs, int col0) {
     constexpr int NC = 2 * NB;
     constexpr int A = NC == 2 ? 1 : NC == 4 ? 2 : NC == 8 ? 3 : 4;
     int i0[R];
@@ -305,7 +312,7 @@ __device__ __forceinline__ void residual_task_t(const BfArgs<S> &a, long long tk
         P0[r] = P1[r] = 0.0;
         const int j = r * 64 + lane;
 #pragma unroll
-        for (int c = 0; c < NC; c++) w[r][c] = j < nl ? (double)a.ws[((size_t)outb + j) * NC + c] : 0.0;
+        for (int c = 0; c < NC; c++) w[r][c] = j < nl ? (double)a.ws[((size_t)outb + j) * a.ES + col0 + c] : 0.0;
     }
     const size_t aoff = (size_t)m * (2 * a.L + 3 - m) / 2;
     // component c = 2 b + (re, im) of row i lives at gb[i * 4 nmaps + c]
@@ -349,7 +356,7 @@ __device__ __forceinline__ void residual_task_t(const BfArgs<S> &a, long long tk
 }
 
 template <int NB, typename S>
-__global__ __launch_bounds__(kBfThreads) void k_bf_residual_t(BfArgs<S> a, long long t0, long long t1) {
+__global__ __launch_bounds__(kBfThreads) void k_bf_residual_t(BfArgs<S> a, long long t0, long long t1, int col0) {
     const int lane = threadIdx.x & 63;
     const long long tk = t0 + (long long)blockIdx.x * (kBfThreads / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (tk >= t1) return;
@@ -359,15 +366,15 @@ __global__ __launch_bounds__(kBfThreads) void k_bf_residual_t(BfArgs<S> a, long 
     const int outb = __builtin_amdgcn_readfirstlane(h2.x), m = __builtin_amdgcn_readfirstlane(h2.y);
     c_double *cfs = (c_double *)(a.coef + 4 * a.coef_off[m]);
     if constexpr (kBfTaskRings > 192) {
-        if (nl > 192) return residual_task_t<NB, 4>(a, tk, lane, t, imin, iend, nl, outb, m, cfs);
+        if (nl > 192) return residual_task_t<NB, 4>(a, tk, lane, t, imin, iend, nl, outb, m, cfs, col0);
     }
     if constexpr (kBfTaskRings > 128) {
-        if (nl > 128) return residual_task_t<NB, 3>(a, tk, lane, t, imin, iend, nl, outb, m, cfs);
+        if (nl > 128) return residual_task_t<NB, 3>(a, tk, lane, t, imin, iend, nl, outb, m, cfs, col0);
     }
     if constexpr (kBfTaskRings > 64) {
-        if (nl > 64) return residual_task_t<NB, 2>(a, tk, lane, t, imin, iend, nl, outb, m, cfs);
+        if (nl > 64) return residual_task_t<NB, 2>(a, tk, lane, t, imin, iend, nl, outb, m, cfs, col0);
     }
-    residual_task_t<NB, 1>(a, tk, lane, t, imin, iend, nl, outb, m, cfs);
+    residual_task_t<NB, 1>(a, tk, lane, t, imin, iend, nl, outb, m, cfs, col0);
 }
 
 // g = 0 over the nalm rows of maps [map0, map0 + nb) (a kernel, not a
@@ -385,14 +392,15 @@ static hipError_t launch_bf_adj_nb(const sht_plan_s *p, BfArgs<S> a, hipStream_t
     constexpr int WPB = kBfThreads / 64;
     const BflyPlan &b = p->bf;
     const long long nalm = (long long)(p->L + 1) * (p->L + 2) / 2;
-    hipLaunchKernelGGL(k_bf_zero, dim3((unsigned)((nalm * NB * 2 + kBfThreads - 1) / kBfThreads)), dim3(kBfThreads), 0,
-                       st, a.g, nalm, a.nmaps, a.map0, NB);
+    const int np = NB * a.G;  // maps of the pass
+    hipLaunchKernelGGL(k_bf_zero, dim3((unsigned)((nalm * np * 2 + kBfThreads - 1) / kBfThreads)), dim3(kBfThreads), 0,
+                       st, a.g, nalm, a.nmaps, a.map0, np);
     for (int bt = 0; bt < b.nbatch; bt++) {
         // level 1: fused with the unfold where both parities have levels
         const long long s0 = b.fold_off[bt], s1 = b.fold_off[bt + 1];
-        const long long nf = (s1 - s0) * b.K * NB;
+        const long long nf = (s1 - s0) * b.K * np;
         if (nf > 0)
-            hipLaunchKernelGGL((k_bf_unfold<NB, S>), dim3((unsigned)((nf + kBfThreads - 1) / kBfThreads)),
+            hipLaunchKernelGGL((k_bf_unfold<S>), dim3((unsigned)((nf + kBfThreads - 1) / kBfThreads)),
                                dim3(kBfThreads), 0, st, a, bt, b.nbatch, p->d_bf_fold_slot + s0, (int)(s1 - s0));
         const size_t lds1 = bf_level_t_lds<NB, S>(b.lv_max_n[(size_t)bt * kBfMaxLv + kBfMaxLv - 1]);
         const long long p0 = b.l1_off[bt], p1 = b.l1_off[bt + 1];
@@ -412,9 +420,12 @@ static hipError_t launch_bf_adj_nb(const sht_plan_s *p, BfArgs<S> a, hipStream_t
                                n0);
         }
         const long long t0 = b.batch_task[bt], t1 = b.batch_task[bt + 1];
-        if (t1 > t0)
+        for (int g = 0; g < a.G && t1 > t0; g++) {  // one launch per group of NB maps
+            BfArgs<S> ag = a;
+            ag.map0 = a.map0 + g * NB;
             hipLaunchKernelGGL((k_bf_residual_t<NB, S>), dim3((unsigned)((t1 - t0 + WPB - 1) / WPB)),
-                               dim3(kBfThreads), 0, st, a, t0, t1);
+                               dim3(kBfThreads), 0, st, ag, t0, t1, g * 2 * NB);
+        }
     }
     return hipGetLastError();
 }
@@ -427,8 +438,11 @@ static hipError_t launch_bf_adj(const sht_plan_s *p, int nmaps, const double *yb
     a.g = g;
     hipError_t e = hipSuccess;
     for (int b = 0; b < nmaps && e == hipSuccess;) {
-        const int nb = bf_nb(nmaps - b);
+        int nb, groups;
+        bf_pass_shape(nmaps - b, &nb, &groups);
         a.map0 = b;
+        a.G = groups;
+        a.ES = 2 * nb * groups;
         if (Tt) {
             switch (nb) {
                 case 8: e = launch_bf_adj_nb<8, true, S>(p, a, st); break;
@@ -444,7 +458,7 @@ static hipError_t launch_bf_adj(const sht_plan_s *p, int nmaps, const double *yb
                 default: e = launch_bf_adj_nb<1, false, S>(p, a, st); break;
             }
         }
-        b += nb;
+        b += nb * groups;
     }
     return e;
 }

@@ -21,11 +21,41 @@ struct BfArgs {
     const double *__restrict__ coef;
     const double2 *__restrict__ alm;
     double2 *__restrict__ q;
-    S *__restrict__ ws;  // vector workspace, entries of 2 NB values
+    S *__restrict__ ws;  // vector workspace, entries of ES values
     const double2 *__restrict__ ybar;  // adjoint input [ring][m][nmaps]
     double *__restrict__ g;            // adjoint output [nalm][nmaps] complex
     int L, K, nrings, nmaps, map0;
+    // A pass transforms G groups of NB maps (maps map0 .. map0 + G NB - 1):
+    // every workspace entry holds ES = 2 NB G values (re, im per map) and
+    // group g owns values [2 NB g, 2 NB (g + 1)) of each entry.  The
+    // interpolation matrices are streamed from HBM once per pass; the level
+    // workgroups loop over the groups of their node (the repeated reads of a
+    // node's blocks hit the caches).
+    int ES, G;
 };
+
+// Maps of one pass at most (G <= kBfMaxGroups groups of 8 maps).
+constexpr int kBfMaxGroups = 8;
+
+// Shape of the pass that starts with `left` maps still to transform: groups
+// of 8 maps while at least 8 remain, else one group of 4, 2 or 1.
+inline void bf_pass_shape(int left, int *nb, int *groups) {
+    if (left >= 8) {
+        *nb = 8;
+        *groups = left / 8 < kBfMaxGroups ? left / 8 : kBfMaxGroups;
+    } else {
+        *nb = left >= 4 ? 4 : left >= 2 ? 2 : 1;
+        *groups = 1;
+    }
+}
+
+// Values per workspace entry for transforms of nmaps maps (the first pass
+// is the widest).
+inline int bf_entry_values(int nmaps) {
+    int nb, g;
+    bf_pass_shape(nmaps, &nb, &g);
+    return 2 * nb * g;
+}
 
 constexpr int kBfThreads = 256;
 
@@ -82,8 +112,6 @@ inline size_t bf_level_lds(int n) {
     return (size_t)n * 2 * (2 * NB * sizeof(S));
 }
 
-inline int bf_nb(int nmaps) { return nmaps >= 8 ? 8 : nmaps >= 4 ? 4 : nmaps >= 2 ? 2 : 1; }
-
 // The plan-dependent fields of BfArgs; the caller sets the operands of its
 // direction (alm, q or ybar, g) and map0.
 template <typename S>
@@ -109,6 +137,8 @@ inline BfArgs<S> bf_args(const sht_plan_s *p, int nmaps, const S *T, S *ws) {
     a.nrings = p->nrings;
     a.nmaps = nmaps;
     a.map0 = 0;
+    a.ES = 2;
+    a.G = 1;
     return a;
 }
 

@@ -557,6 +557,7 @@ int build_butterfly(sht_plan_s *p, const BflyInput &in) {
                             b.n_units += nn;
                             b.level_T[lvl] += (long long)(c0.T.size() + c1.T.size());
                             b.level_units[lvl] += nn;
+                            b.level_nodes[lvl]++;
                             b.max_n = std::max(b.max_n, nn);
                             lvl_max_n[lvl] = std::max(lvl_max_n[lvl], nn);
                         }

@@ -24,6 +24,9 @@ constexpr int kCoefPad = 2 * kChunk + 8;   // coefficient entries kept past l = 
 constexpr int kDead = 0x3fffffff;          // start index of a chain that never
                                            // reaches the cutoff
 
+// Bytes of the fixed device scratch behind sht_synthesis_noalloc.
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+
 void set_error(const std::string &msg);
 int fail(int code, const std::string &msg);
 
@@ -71,6 +74,7 @@ struct BflyPlan {
     long long T_entries = 0, res_elems = 0, n_nodes = 0, n_res_lanes = 0, n_units = 0;
     long long level_T[kBfMaxLv + 1] = {};      // dense entries of the pair nodes of each level
     long long level_units[kBfMaxLv + 1] = {};  // columns (output entries) of each level
+    long long level_nodes[kBfMaxLv + 1] = {};  // pair nodes of each level
     // Level 1 of orders whose two parities both have levels runs fused with
     // the even/odd fold: units {even node, odd node, first ring, slot}; the
     // other level-1 nodes run alone and their orders are folded afterwards.
@@ -153,6 +157,58 @@ struct sht_plan_s {
 
 namespace sht {
 
+// Device address of the fixed scratch on device `dev` (current), looked up
+// once per device (noalloc.hip).
+int noalloc_scratch(int dev, void **out);
+
+// Argument block of the brute-force Legendre waves (legendre.hip): one
+// plan, one pass of up to 4 maps.
+struct LegArgs {
+    const double *__restrict__ z2_hi;
+    const double *__restrict__ z2_lo;
+    const long long *__restrict__ coef_off;
+    const double *__restrict__ coef_hi;
+    const double *__restrict__ coef_lo;
+    const int *__restrict__ start_idx;
+    const double *__restrict__ start_val;
+    const double *__restrict__ start_lo;
+    const int *__restrict__ grp_lo;
+    const int *__restrict__ grp_hi;
+    const double *__restrict__ alm;
+    double *__restrict__ q;
+    int L, nrings, n_north, np, n_dd_pad, ng;
+    int nmaps, map0;  // map stride of alm/q and first map of this pass
+    int dd_groups;    // 64-ring groups run in double-double (from the pole)
+    int fp_blocks;    // FP64 ring blocks of R groups after them
+};
+
+// Argument block of the ring FFT workgroups (ring.hip): one plan, one ring
+// size class.
+struct RingArgs {
+    const int *__restrict__ rings;
+    int count;
+    const int *__restrict__ ring_J;
+    const int *__restrict__ ring_s;
+    const int *__restrict__ ring_M;
+    const long long *__restrict__ ring_off;
+    const long long *__restrict__ ring_bs_off;
+    const double2 *__restrict__ tw;
+    int tw_log;
+    const double2 *__restrict__ bs_table;
+    const double2 *__restrict__ chirp;
+    const long long *__restrict__ ring_chirp_off;
+    const double2 *__restrict__ q;
+    double *__restrict__ map;
+    int L, nrings, nmaps;
+    long long npix;
+    int fft_entries;  // padded FFT buffer entries of this launch's class
+    int stage;        // q entries staged per chunk for wrapped rings (multiple of the block size)
+    // adjoint direction: pixel values in, weighted phases ybar out
+    const double *__restrict__ map_in;
+    double2 *__restrict__ ybar;
+    double wpos;      // weight of m >= 1 (2: transpose of synthesis, 1: Y^dagger)
+};
+
 // Host plan construction (plan.cpp, butterfly_plan.cpp).
 int build_host_tables(sht_plan_s *p);
 int build_butterfly(sht_plan_s *p, const BflyInput &in);
@@ -181,6 +237,18 @@ hipError_t launch_butterfly(const sht_plan_s *p, int nmaps, const double *alm, d
 // with the same scratch.
 hipError_t launch_butterfly_adjoint(const sht_plan_s *p, int nmaps, const double *ybar, double *g, void *scratch,
                                     int fp32, hipStream_t stream);
+// Work-queue batch pieces (legendre.hip, ring.hip): the argument block of
+// one pass, the persistent Legendre launch over a sorted item list (items
+// {pass, m, ring block, maps}; counter is device memory the launch resets),
+// and one ring-queue launch per ring size class (items {argument block,
+// item of that class}).
+LegArgs leg_args(const sht_plan_s *p, int nmaps, int map0, int R, const double *alm, double *q);
+hipError_t launch_legendre_queue(const LegArgs *passes, const int4 *items, long long nitems, unsigned *counter,
+                                 int rings_per_lane, hipStream_t st);
+RingArgs ring_args(const sht_plan_s *p, int nmaps, const double *q, double *map);
+size_t ring_class_shape(int lds_entries, bool wrap, int T, int *fft_entries, int *stage);
+hipError_t launch_ring_queue(int T, const RingArgs *args, const int2 *items, long long nitems, size_t lds,
+                             hipStream_t st);
 // y = alpha x + beta y over n doubles (beta = 0: y = alpha x).
 hipError_t launch_axpby(double *y, const double *x, double alpha, double beta, long long n, hipStream_t st);
 // Device-side transposed copies of the interpolation matrices (d_bf_Tt and,

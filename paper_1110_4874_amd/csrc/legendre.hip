@@ -22,25 +22,6 @@
 
 namespace sht {
 
-struct LegArgs {
-    const double *__restrict__ z2_hi;
-    const double *__restrict__ z2_lo;
-    const long long *__restrict__ coef_off;
-    const double *__restrict__ coef_hi;
-    const double *__restrict__ coef_lo;
-    const int *__restrict__ start_idx;
-    const double *__restrict__ start_val;
-    const double *__restrict__ start_lo;
-    const int *__restrict__ grp_lo;
-    const int *__restrict__ grp_hi;
-    const double *__restrict__ alm;
-    double *__restrict__ q;
-    int L, nrings, n_north, np, n_dd_pad, ng;
-    int nmaps, map0;  // map stride of alm/q and first map of this pass
-    int dd_groups;    // 64-ring groups run in double-double (from the pole)
-    int fp_blocks;    // FP64 ring blocks of R groups after them
-};
-
 // ---- double-double helpers (error-free transformations) --------------
 struct dd {
     double h, l;
@@ -304,6 +285,105 @@ static hipError_t launch_nb(const sht_plan_s *p, LegArgs a, hipStream_t st) {
         case 4: return launch_nbr<NB, 4>(p, a, st);
         default: return launch_nbr<NB, 2>(p, a, st);
     }
+}
+
+// Persistent form for batches of requests (the many-transform regime of
+// Sec. 3.4): one launch for every request of a batch.  Each wave takes work
+// items {pass, m, ring block, maps} from a device counter (a vector-memory
+// atomic) until the list, sorted longest first on the host, is exhausted,
+// and runs the same wave body as k_legendre on the pass's argument block.
+// Every wave leaves once the counter has passed the end of the list.
+__global__ void k_queue_reset(unsigned *c) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0u;
+}
+
+template <int R>
+__global__ __launch_bounds__(64, (R == 4 ? 2 : 4)) void k_legendre_queue(const LegArgs *__restrict__ passes,
+                                                                         const int4 *__restrict__ items,
+                                                                         unsigned nitems, unsigned *__restrict__ counter) {
+    for (;;) {
+        unsigned it = 0;
+        if (threadIdx.x == 0) it = atomicAdd(counter, 1u);
+        it = __shfl(it, 0);
+        if (it >= nitems) return;
+        const int4 w = items[it];
+        const int pi = __builtin_amdgcn_readfirstlane(w.x), m = __builtin_amdgcn_readfirstlane(w.y);
+        const int rb = __builtin_amdgcn_readfirstlane(w.z), nb = __builtin_amdgcn_readfirstlane(w.w);
+        const LegArgs a = passes[pi];
+        if (rb < a.dd_groups) {
+            for (int b0 = 0; b0 < nb; b0 += 2) {
+                LegArgs ab = a;
+                ab.map0 = a.map0 + b0;
+                if (nb - b0 >= 2)
+                    legendre_wave<2, 1, true>(ab, m, rb);
+                else
+                    legendre_wave<1, 1, true>(ab, m, rb);
+            }
+        } else {
+            const int g0 = a.dd_groups + (rb - a.dd_groups) * R;
+            if (nb == 4)
+                legendre_wave<4, R, false>(a, m, g0);
+            else if (nb == 2)
+                legendre_wave<2, R, false>(a, m, g0);
+            else
+                legendre_wave<1, R, false>(a, m, g0);
+        }
+    }
+}
+
+template <int R>
+static hipError_t launch_queue_r(const LegArgs *passes, const int4 *items, unsigned nitems, unsigned *counter,
+                                 hipStream_t st) {
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_legendre_queue<R>, 64, 0);
+    if (e != hipSuccess) return e;
+    const long long grid = std::min<long long>((long long)std::max(per_cu, 1) * std::max(cus, 1), nitems);
+    hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, st, counter);
+    if (grid > 0) hipLaunchKernelGGL((k_legendre_queue<R>), dim3((unsigned)grid), dim3(64), 0, st, passes, items, nitems,
+                                     counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_legendre_queue(const LegArgs *passes, const int4 *items, long long nitems, unsigned *counter,
+                                 int rings_per_lane, hipStream_t st) {
+    if (nitems < 0 || nitems > 0x7fffffffLL) return hipErrorInvalidValue;
+    switch (rings_per_lane) {
+        case 1: return launch_queue_r<1>(passes, items, (unsigned)nitems, counter, st);
+        case 4: return launch_queue_r<4>(passes, items, (unsigned)nitems, counter, st);
+        default: return launch_queue_r<2>(passes, items, (unsigned)nitems, counter, st);
+    }
+}
+
+// Argument block of one pass (maps map0 .. map0 + nb - 1 of nmaps) for
+// waves of R rings per lane.
+LegArgs leg_args(const sht_plan_s *p, int nmaps, int map0, int R, const double *alm, double *q) {
+    LegArgs a;
+    a.z2_hi = p->d_z2_hi;
+    a.z2_lo = p->d_z2_lo;
+    a.coef_off = p->d_coef_off;
+    a.coef_hi = p->d_coef_hi;
+    a.coef_lo = p->d_coef_lo;
+    a.start_idx = p->d_start_idx;
+    a.start_val = p->d_start_val;
+    a.start_lo = p->d_start_lo;
+    a.grp_lo = p->d_grp_lo;
+    a.grp_hi = p->d_grp_hi;
+    a.alm = alm;
+    a.q = q;
+    a.L = p->L;
+    a.nrings = p->nrings;
+    a.n_north = p->n_north;
+    a.np = p->n_north_pad;
+    a.n_dd_pad = std::max(p->n_dd_pad, 1);
+    a.ng = p->n_north_pad / kLanes;
+    a.nmaps = nmaps;
+    a.map0 = map0;
+    a.dd_groups = p->n_dd_groups;
+    a.fp_blocks = (a.ng - p->n_dd_groups + R - 1) / R;
+    return a;
 }
 
 hipError_t launch_legendre(const sht_plan_s *p, int nmaps, const double *alm, double *q,

@@ -39,7 +39,7 @@ namespace {
 using namespace sht;
 
 constexpr char kMagic[8] = {'W', 'M', 'H', 'I', 'P', 'P', 'L', 'N'};
-constexpr uint32_t kFileVersion = 1;
+constexpr uint32_t kFileVersion = 2;
 constexpr size_t kHashBlock = (size_t)16 << 20;
 
 struct FileHeader {
@@ -275,6 +275,7 @@ void visit(A &ar, sht_plan_s *p, std::vector<double> &T) {
     ar.scalar(b.n_units);
     ar.arr(b.level_T);
     ar.arr(b.level_units);
+    ar.arr(b.level_nodes);
     ar.vec(b.f1_unit);
     ar.vec(b.l1_plain);
     ar.vec(b.fold_slot);
@@ -390,6 +391,11 @@ int load_file(const char *path, const sht_plan_opts *lo, sht_plan_s **out) {
         p->device = dev;
         int rc = upload_tables(p.get());
         if (rc != SHT_OK) return rc;
+        void *scr = nullptr;  // look up the no-allocation scratch of this device now
+        if ((rc = noalloc_scratch(dev, &scr)) != SHT_OK) {
+            free_device_tables(p.get());
+            return rc;
+        }
     }
     *out = p.release();
     return SHT_OK;

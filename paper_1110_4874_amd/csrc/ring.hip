@@ -31,34 +31,11 @@
 #include <set>
 #include <utility>
 
+#include <cstring>
+
 #include "internal.h"
 
 namespace sht {
-
-struct RingArgs {
-    const int *__restrict__ rings;
-    int count;
-    const int *__restrict__ ring_J;
-    const int *__restrict__ ring_s;
-    const int *__restrict__ ring_M;
-    const long long *__restrict__ ring_off;
-    const long long *__restrict__ ring_bs_off;
-    const double2 *__restrict__ tw;
-    int tw_log;
-    const double2 *__restrict__ bs_table;
-    const double2 *__restrict__ chirp;
-    const long long *__restrict__ ring_chirp_off;
-    const double2 *__restrict__ q;
-    double *__restrict__ map;
-    int L, nrings, nmaps;
-    long long npix;
-    int fft_entries;  // padded FFT buffer entries of this launch's class
-    int stage;        // q entries staged per chunk for wrapped rings (multiple of the block size)
-    // adjoint direction: pixel values in, weighted phases ybar out
-    const double *__restrict__ map_in;
-    double2 *__restrict__ ybar;
-    double wpos;      // weight of m >= 1 (2: transpose of synthesis, 1: Y^dagger)
-};
 
 constexpr int kMaxStage = 2048;     // staged q entries per chunk (at most)
 constexpr int kMaxPairs = 2049;     // Hermitian bin pairs of the largest ring (n = 4096)
@@ -256,13 +233,13 @@ __device__ __forceinline__ double2 bin_chunk(const double2 *st, int m0, int cnt,
     return acc;
 }
 
+// Synthesis of one ring of one map (item = ring position in the class's
+// list times nmaps plus the map) by a workgroup of T threads.
 template <int T>
-__global__ __launch_bounds__(T) void k_ring_synth(RingArgs a) {
+__device__ __forceinline__ void ring_synth_item(const RingArgs &a, const int item) {
     constexpr int kPairsPerThread = (kMaxPairs + T - 1) / T;
     constexpr int kMaxStagePerThread = kMaxStage / T;
     extern __shared__ double2 sm[];
-    const int item = xcd_item(blockIdx.x);
-    if (item >= a.count * a.nmaps) return;
     const int pos = item / a.nmaps, b = item % a.nmaps;
     const int rho = a.rings[pos];
     const int J = a.ring_J[rho], s = a.ring_s[rho], M = a.ring_M[rho];
@@ -446,6 +423,27 @@ __global__ __launch_bounds__(T) void k_ring_synth(RingArgs a) {
     }
 }
 
+template <int T>
+__global__ __launch_bounds__(T) void k_ring_synth(RingArgs a) {
+    const int item = xcd_item(blockIdx.x);
+    if (item >= a.count * a.nmaps) return;
+    ring_synth_item<T>(a, item);
+}
+
+// Ring queue of a batch of requests: one launch per ring size class for all
+// requests, item j = {argument block (request, class), item of that class};
+// items are ordered request by request, ring by ring, map by map, so that
+// the maps of one ring stay on one XCD as in k_ring_synth.
+template <int T>
+__global__ __launch_bounds__(T) void k_ring_synth_queue(const RingArgs *__restrict__ args, const int2 *__restrict__ items,
+                                                        int nitems) {
+    const int j = xcd_item(blockIdx.x);
+    if (j >= nitems) return;
+    const int2 it = items[j];
+    const RingArgs a = args[__builtin_amdgcn_readfirstlane(it.x)];
+    ring_synth_item<T>(a, __builtin_amdgcn_readfirstlane(it.y));
+}
+
 // Raises a kernel's dynamic LDS limit to `bytes`, once per (kernel, device):
 // the attribute belongs to the device current at the call.
 hipError_t allow_dynamic_lds(const void *fn, int bytes) {
@@ -461,6 +459,18 @@ hipError_t allow_dynamic_lds(const void *fn, int bytes) {
     return e;
 }
 
+// FFT buffer entries, staging chunk and dynamic LDS bytes of the workgroups
+// of one ring class (FFT buffer of lds_entries complex values) at T threads.
+size_t ring_class_shape(int lds_entries, bool wrap, int T, int *fft_entries, int *stage) {
+    *fft_entries = lds_entries + lds_entries / 16;
+    // staging chunk: what the FFT buffer leaves of 80 KiB (two workgroups
+    // per CU) when that is at least a quarter of the block, else of 160 KiB
+    const int cap2 = (int)(80 * 1024 / sizeof(double2));
+    const int room = (*fft_entries + T / 4 <= cap2 ? cap2 : (int)(160 * 1024 / sizeof(double2))) - *fft_entries;
+    *stage = std::min(kMaxStage, room >= T ? room / T * T : room);
+    return (size_t)(*fft_entries + (wrap ? *stage : 0)) * sizeof(double2);
+}
+
 template <int T>
 static hipError_t launch_classes(const sht_plan_s *p, RingArgs a, int nmaps, hipStream_t stream) {
     hipError_t ea = allow_dynamic_lds((const void *)k_ring_synth<T>, 160 * 1024);
@@ -468,19 +478,57 @@ static hipError_t launch_classes(const sht_plan_s *p, RingArgs a, int nmaps, hip
     for (const auto &rc : p->classes) {
         a.rings = rc.d_rings;
         a.count = (int)rc.rings.size();
-        a.fft_entries = rc.lds_entries + rc.lds_entries / 16;
-        // staging chunk: what the FFT buffer leaves of 80 KiB (two workgroups
-        // per CU) when that is at least a quarter of the block, else of 160 KiB
-        const int cap2 = (int)(80 * 1024 / sizeof(double2));
-        const int room = (a.fft_entries + T / 4 <= cap2 ? cap2 : (int)(160 * 1024 / sizeof(double2))) - a.fft_entries;
-        a.stage = std::min(kMaxStage, room >= T ? room / T * T : room);
+        const size_t lds = ring_class_shape(rc.lds_entries, rc.wrap, T, &a.fft_entries, &a.stage);
         long long grid = ((long long)a.count * nmaps + 63) / 64 * 64;
-        size_t lds = (size_t)(a.fft_entries + (rc.wrap ? a.stage : 0)) * sizeof(double2);
         hipLaunchKernelGGL(k_ring_synth<T>, dim3((unsigned)grid), dim3(T), lds, stream, a);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+template <int T>
+static hipError_t launch_ring_queue_t(const RingArgs *args, const int2 *items, long long nitems, size_t lds,
+                                      hipStream_t st) {
+    hipError_t e = allow_dynamic_lds((const void *)k_ring_synth_queue<T>, 160 * 1024);
+    if (e != hipSuccess) return e;
+    const long long grid = (nitems + 63) / 64 * 64;
+    if (grid > 0) hipLaunchKernelGGL(k_ring_synth_queue<T>, dim3((unsigned)grid), dim3(T), lds, st, args, items, (int)nitems);
+    return hipGetLastError();
+}
+
+hipError_t launch_ring_queue(int T, const RingArgs *args, const int2 *items, long long nitems, size_t lds,
+                             hipStream_t st) {
+    if (nitems < 0 || nitems > 0x7fffffffLL) return hipErrorInvalidValue;
+    switch (T) {
+        case 256: return launch_ring_queue_t<256>(args, items, nitems, lds, st);
+        case 512: return launch_ring_queue_t<512>(args, items, nitems, lds, st);
+        default: return launch_ring_queue_t<1024>(args, items, nitems, lds, st);
+    }
+}
+
+// Plan-wide fields of the ring argument block (synthesis direction); the
+// caller sets the class fields (rings, count, fft_entries, stage).
+RingArgs ring_args(const sht_plan_s *p, int nmaps, const double *q, double *map) {
+    RingArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.ring_J = p->d_ring_J;
+    a.ring_s = p->d_ring_s;
+    a.ring_M = p->d_ring_M;
+    a.ring_off = p->d_ring_off;
+    a.ring_bs_off = p->d_ring_bs_off;
+    a.tw = reinterpret_cast<const double2 *>(p->d_tw);
+    a.tw_log = p->tw_log;
+    a.bs_table = reinterpret_cast<const double2 *>(p->d_bs_table);
+    a.chirp = reinterpret_cast<const double2 *>(p->d_chirp);
+    a.ring_chirp_off = p->d_ring_chirp_off;
+    a.q = reinterpret_cast<const double2 *>(q);
+    a.map = map;
+    a.L = p->L;
+    a.nrings = p->nrings;
+    a.nmaps = nmaps;
+    a.npix = 12LL * p->nside * p->nside;
+    return a;
 }
 
 hipError_t launch_ring_synthesis(const sht_plan_s *p, int nmaps, const double *q, double *map,

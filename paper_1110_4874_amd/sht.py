@@ -51,7 +51,7 @@ class PlanInfo(_c.Structure):
                 ("bf_nodes", _c.c_longlong), ("bf_units", _c.c_longlong), ("bf_res_lanes", _c.c_longlong), ("bf_res_exec", _c.c_longlong),
                 ("bf_depth_hist", _c.c_longlong * 11), ("bf_build_seconds", _c.c_double),
                 ("bf_nbatch", _c.c_int), ("bf_level_T", _c.c_longlong * 11),
-                ("bf_level_units", _c.c_longlong * 11)]
+                ("bf_level_units", _c.c_longlong * 11), ("bf_level_nodes", _c.c_longlong * 11)]
 
 
 class Request(_c.Structure):
@@ -84,6 +84,8 @@ EXPORTS = {
     "sht_debug_legendre_adjoint": (_c.c_int, [_c.c_void_p, _c.POINTER(ExecOpts), _c.c_void_p, _c.c_void_p]),
     "sht_last_error": (_c.c_char_p, []),
     "sht_last_status": (_c.c_int, []),
+    "sht_noalloc_scratch_bytes": (_c.c_size_t, []),
+    "sht_synthesis_noalloc": (_c.c_int, [_c.c_void_p, _c.POINTER(ExecOpts), _c.c_void_p, _c.c_void_p]),
     "sht_sync_status": (_c.c_int, [_c.c_void_p, _c.c_void_p]),
     "sht_plan_save": (_c.c_int, [_c.c_void_p, _c.c_char_p]),
     "sht_plan_load": (_c.c_void_p, [_c.c_char_p]),
@@ -246,6 +248,7 @@ class Plan:
         d["bf_depth_hist"] = list(inf.bf_depth_hist)
         d["bf_level_T"] = list(inf.bf_level_T)
         d["bf_level_units"] = list(inf.bf_level_units)
+        d["bf_level_nodes"] = list(inf.bf_level_nodes)
         return d
 
     def butterfly_apply_host(self, m, t, x):
@@ -419,6 +422,41 @@ class Plan:
         vals = (_c.c_double * 2)()
         _check(load().sht_debug_start(self._h, int(m), int(t), int(k), _c.byref(idx), vals))
         return idx.value, (vals[0], vals[1])
+
+
+def cached_plan(L, nside, eps=0.0, *, cache_dir=None, store_fp32=False, store_transpose=False,
+                log=None, **opts):
+    """A plan for (L, nside, eps, opts) from a plan file in `cache_dir`
+    (default: $SHT_PLAN_CACHE, else ~/.cache/wavemoth_hip), or built and
+    saved there when there is room.  A file that fails its integrity checks
+    is rebuilt.  The store flags are device-side copies made at load, so one
+    file serves every combination of them."""
+    import shutil
+    d = cache_dir or os.environ.get("SHT_PLAN_CACHE") or os.path.join(os.path.expanduser("~"), ".cache",
+                                                                       "wavemoth_hip")
+    key = "_".join(f"{k}{opts[k]}" for k in sorted(opts) if k not in ("nthreads",))
+    path = os.path.join(d, f"L{L}_n{nside}_eps{eps:g}" + (f"_{key}" if key else "") + ".plan")
+    say = log or (lambda msg: None)
+    if os.path.exists(path):
+        try:
+            p = Plan.load(path, store_fp32=store_fp32, store_transpose=store_transpose,
+                          nthreads=opts.get("nthreads", 0))
+            say(f"plan loaded from {path}")
+            return p
+        except ShtError as e:
+            say(f"plan file {path} refused ({e}); rebuilding")
+            os.remove(path)
+    p = Plan(L, nside, eps, store_fp32=store_fp32, store_transpose=store_transpose, **opts)
+    inf = p.info()
+    need = 8 * inf["bf_T_entries"] + 24 * inf["bf_res_lanes"] + 64 * nalm(L) + (1 << 30)
+    try:
+        os.makedirs(d, exist_ok=True)
+        if shutil.disk_usage(d).free > 2 * need + (20 << 30):
+            p.save(path)
+            say(f"plan saved to {path}")
+    except (OSError, ShtError) as e:
+        say(f"plan not cached ({e})")
+    return p
 
 
 class Batch:

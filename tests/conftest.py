@@ -28,3 +28,29 @@ def gpu():
 def plan4095(gpu):
     """The benchmark workload's plan (L = 4095, nside = 2048), built once."""
     return gpu.Plan(4095, 2048)
+
+
+def _log(msg):
+    sys.stderr.write(msg + "\n")
+    sys.stderr.flush()
+
+
+@pytest.fixture(scope="session")
+def plan4095_bf(gpu):
+    """The benchmark workload's butterfly plan (L = 4095, nside = 2048,
+    eps = 1e-12, FP32 and transposed copies), from the plan cache or built
+    once per session (about two minutes on 16 host cores)."""
+    _log("plan4095_bf: L=4095 nside=2048 eps=1e-12 (cache or build)")
+    p = gpu.cached_plan(4095, 2048, 1e-12, store_fp32=True, store_transpose=True, log=_log)
+    _log(f"plan4095_bf: ready, depth histogram {p.info()['bf_depth_hist'][:6]}")
+    return p
+
+
+@pytest.fixture(scope="session")
+def plan2047_bf(gpu):
+    """The 16-map workload's butterfly plan (L = 2047, nside = 1024,
+    eps = 1e-12, FP32 and transposed copies)."""
+    _log("plan2047_bf: L=2047 nside=1024 eps=1e-12 (cache or build)")
+    p = gpu.cached_plan(2047, 1024, 1e-12, store_fp32=True, store_transpose=True, log=_log)
+    _log(f"plan2047_bf: ready, depth histogram {p.info()['bf_depth_hist'][:6]}")
+    return p

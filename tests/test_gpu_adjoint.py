@@ -3,8 +3,8 @@
 The adjoint is g_lm = w_m sum_k P~_l^m(z_k) sum_j y_kj e^{-i m phi_kj}
 (w_0 = 1 with Im g_l0 = 0, w_m = 2 otherwise, or w_m = 1 for the Y^dagger
 convention of Sec. 2.2 Eq. 7).  Tolerance: max |g - g_ref| / max |g_ref| per
-map <= 1e-12 (FP64 path); 1e-11 at L = 4095, where the FP64 oracle's own
-polar-ring Legendre values carry ~1e-11 relative error.
+map <= 1e-12 (FP64 path); at L = 4095 against the long-double oracle, since
+the FP64 oracle's own polar-ring Legendre values carry ~3e-12 there.
 """
 import numpy as np
 import pytest
@@ -125,20 +125,22 @@ def test_adjoint_deterministic_and_every_entry_written(gpu):
     assert torch.equal(outs[0], outs[1])
 
 
+@pytest.mark.timeout(600)
 def test_l4095_sampled_orders(gpu, plan4095):
     L, N, B = 4095, 2048, 2
     maps = _maps(N, B, 1100)
     g = plan4095.adjoint(_dev(maps)).cpu().numpy()
     ms = [0, 1, 2, 7, 64, 511, 1024, 2047, 3000, 4000, 4094, 4095]
-    ref = oracle.adjoint_msel(L, N, maps, ms)
-    gmax = np.max(np.abs(g), axis=0)
+    ref = oracle.adjoint_msel(L, N, maps, ms, ld=True)
+    # scale: the largest |g_lm| of the reference over the sampled orders
+    gmax = np.max(np.abs(ref), axis=(0, 1))
     worst = 0.0
     for k, m in enumerate(ms):
         o = m * (2 * L + 3 - m) // 2
         e = np.max(np.abs(g[o:o + L + 1 - m] - ref[k, :L + 1 - m]), axis=0) / gmax
         worst = max(worst, float(np.max(e)))
-    print(f"L=4095 sampled-order adjoint maxrel={worst:.3e}")
-    assert worst <= 1e-11
+    print(f"L=4095 sampled-order adjoint maxrel={worst:.3e} (long-double oracle)")
+    assert worst <= TOL
 
 
 def test_autograd_gradcheck(gpu):

@@ -31,7 +31,12 @@ def _dev(a):
                                                     (255, 128, 1e-12, 3, 4, 0), (200, 64, 1e-8, 2, 2, 0),
                                                     (511, 256, 1e-12, 4, 1, 0), (300, 128, 1e-10, 3, 9, 0),
                                                     (0, 1, 1e-12, -1, 1, 0), (9, 2, 1e-12, 1, 2, 0),
-                                                    (255, 128, 1e-12, 3, 4, 1), (511, 256, 1e-12, 4, 2, 2)])
+                                                    (255, 128, 1e-12, 3, 4, 1), (511, 256, 1e-12, 4, 2, 2),
+                                                    # passes of several 8-map groups: 16, 16 + 4 + 1, 64,
+                                                    # 64 + 8 (two passes), and order batches
+                                                    (255, 128, 1e-12, 3, 16, 0), (200, 64, 1e-10, 3, 21, 0),
+                                                    (127, 64, 1e-12, 2, 64, 0), (63, 32, 1e-12, 2, 72, 0),
+                                                    (255, 128, 1e-12, 3, 24, 1)])
 def test_butterfly_synthesis_parity(gpu, L, N, eps, levels, B, batch):
     alm = alm_gaussian(L, list(range(200, 200 + B)))
     p = gpu.Plan(L, N, eps, max_levels=levels, batch_mib=batch)
@@ -65,9 +70,10 @@ def test_butterfly_matches_brute_on_gpu(gpu):
     assert maxrel(a, b) <= 1e-11 + 1e-12
 
 
-def test_butterfly_fp32(gpu):
-    L, N, B = 255, 128, 4
-    alm = alm_gaussian(L, [7, 8, 9, 10])
+@pytest.mark.parametrize("B", [4, 24])
+def test_butterfly_fp32(gpu, B):
+    L, N = 255, 128
+    alm = alm_gaussian(L, list(range(7, 7 + B)))
     p = gpu.Plan(L, N, 1e-7, max_levels=3, store_fp32=True)
     f32 = p.synthesis(_dev(alm), precision=sht.PREC_FP32).cpu().numpy()
     f64 = p.synthesis(_dev(alm), precision=sht.PREC_FP64).cpu().numpy()

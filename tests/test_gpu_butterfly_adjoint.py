@@ -37,7 +37,12 @@ def _maps(N, B, seed0):
                                                     (255, 128, 1e-12, 3, 4, 0), (200, 64, 1e-8, 2, 2, 0),
                                                     (511, 256, 1e-12, 4, 1, 0), (300, 128, 1e-10, 3, 9, 0),
                                                     (0, 1, 1e-12, -1, 1, 0), (9, 2, 1e-12, 1, 2, 0),
-                                                    (255, 128, 1e-12, 3, 4, 1), (511, 256, 1e-12, 4, 2, 2)])
+                                                    (255, 128, 1e-12, 3, 4, 1), (511, 256, 1e-12, 4, 2, 2),
+                                                    # passes of several 8-map groups: 16, 16 + 4 + 1, 64,
+                                                    # 64 + 8 (two passes), and order batches
+                                                    (255, 128, 1e-12, 3, 16, 0), (200, 64, 1e-10, 3, 21, 0),
+                                                    (127, 64, 1e-12, 2, 64, 0), (63, 32, 1e-12, 2, 72, 0),
+                                                    (255, 128, 1e-12, 3, 24, 1)])
 @pytest.mark.parametrize("tr", [False, True])
 def test_butterfly_adjoint_parity(gpu, L, N, eps, levels, B, batch, tr):
     maps = _maps(N, B, 700)
