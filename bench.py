@@ -152,6 +152,36 @@ def batch_bench(np, torch, sht, steps):
                 "graph_maps_per_s": round(nmaps / t_graph, 2),
                 "graph_speedup_vs_sequential": round(t_seq / t_graph, 3), "graph_matches_sequential": bool(same)}
 
+    def run_queue(plans, path=sht.PATH_BRUTE, prec=sht.PREC_FP64):
+        # work-queue form: on the brute-force path one persistent Legendre
+        # launch over every request's items; on the butterfly path one launch
+        # per stage and map-group width over every request; then one ring
+        # launch per ring size class; replayed as a graph
+        reqs = [(plans[(L, N)], alm, out) for (L, N, alm, out) in inputs]
+        seq_ref = []
+        for p, a, o in reqs:
+            p.synthesis(a, o, path=path, precision=prec)
+            seq_ref.append(o.clone())
+        qb = sht.QueueBatch(reqs, path=path, precision=prec)
+        t_run = timed(qb.run, steps)
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(g, stream=s):
+                qb.run(stream=s)
+        torch.cuda.current_stream().wait_stream(s)
+        t_graph = timed(g.replay, steps)
+        torch.cuda.synchronize()
+        same = all(torch.equal(o, r) for (_, _, o), r in zip(reqs, seq_ref))
+        st = qb.stats()
+        qb.close()
+        r = {"run_maps_per_s": round(nmaps / t_run, 2), "graph_maps_per_s": round(nmaps / t_graph, 2),
+             "work_items": st["items"], "launches_per_run": st["launches"], "matches_sequential": bool(same)}
+        if path == sht.PATH_BRUTE:
+            r["persistent_waves"] = st["waves"]
+        return r
+
     t0 = time.perf_counter()
     plans = {}
     for (L, N, _, _) in inputs:
@@ -162,11 +192,18 @@ def batch_bench(np, torch, sht, steps):
            "tile_shapes": {f"{L}": {k: v for k, v in autotune.tune(L, N, 4).items() if k != "ms"}
                            for (L, N) in plans},
            "brute_fp64": run_config(plans, sht.PATH_BRUTE, sht.PREC_FP64)}
+    res["queue_brute_fp64"] = run_queue(plans)
+    log(f"[bench] batching queue_brute_fp64: run {res['queue_brute_fp64']['run_maps_per_s']} maps/s, graph "
+        f"{res['queue_brute_fp64']['graph_maps_per_s']} ({res['queue_brute_fp64']['launches_per_run']} launches)")
     bf_plans = {(L, N): autotune.tuned_plan(L, N, 4, plan_eps=1e-12, plan_kw={"store_fp32": True})
                 for (L, N) in plans}
     res["butterfly_depth_hist"] = {f"{L}": p.info()["bf_depth_hist"][:6] for (L, _), p in bf_plans.items()}
     res["butterfly_fp64"] = run_config(bf_plans, sht.PATH_BUTTERFLY, sht.PREC_FP64)
     res["butterfly_fp32"] = run_config(bf_plans, sht.PATH_BUTTERFLY, sht.PREC_FP32)
+    for k, prec in (("queue_butterfly_fp64", sht.PREC_FP64), ("queue_butterfly_fp32", sht.PREC_FP32)):
+        res[k] = run_queue(bf_plans, sht.PATH_BUTTERFLY, prec)
+        log(f"[bench] batching {k}: run {res[k]['run_maps_per_s']} maps/s, graph {res[k]['graph_maps_per_s']} "
+            f"({res[k]['launches_per_run']} launches)")
     for p in list(plans.values()) + list(bf_plans.values()):
         p.close()
     for k in ("brute_fp64", "butterfly_fp64", "butterfly_fp32"):
@@ -331,6 +368,35 @@ def config3_bench(np, torch, sht, args):
     return out
 
 
+def interp_bench(np, torch, sht, args, d_alm, alm, brute):
+    """The interpolation form of Sec. 3.3 at the headline size: the Legendre
+    phase at the roots of P~_N^m (about a third of the brute-force chain
+    steps), then the exact interpolation to the rings (Eq. 23) as a Cauchy
+    product on the FP64 matrix cores; timed like the other paths, with its
+    error against the long-double oracle on sampled rings."""
+    import oracle
+    L, N = 4095, 2048
+    if d_alm.shape[0] != (L + 1) * (L + 2) // 2:
+        return None
+    plan = sht.cached_plan(L, N, 0.0, interp=True, log=log)
+    info = plan.info()
+    res, maps = timed_paths(np, torch, sht, plan, d_alm, [("interp", sht.PATH_INTERP, sht.PREC_FP64)],
+                            args.steps, args.warmup)
+    r = res["interp"]
+    r.update(sampled_errors(np, oracle, L, N, alm, maps, [1, 2, 100, 250, 251, 1000, 2 * N, 2 * N + 1, 3 * N,
+                                                          4 * N - 1])["interp"])
+    r["speedup_vs_brute"] = round(r["maps_per_s"] / brute["maps_per_s"], 3)
+    r["node_steps"] = info["ip_steps"]
+    r["brute_steps"] = info["n_step"]
+    r["nodes"] = info["ip_nodes"]
+    r["precompute_seconds"] = round(info["ip_build_seconds"], 1)
+    log(f"[bench] interp: {r['maps_per_s']:.1f} maps/s ({r['speedup_vs_brute']}x brute), legendre "
+        f"{r['legendre_ms']:.3f} ms, error {r['max_rel_err']:.2e}")
+    plan.close()
+    torch.cuda.empty_cache()
+    return r
+
+
 def gradient_bench(np, torch, sht, plan, info, paths, d_alm, f_true, ws, ev_sets, args, flops):
     """Forward + backward of the map-fitting loss ||synthesis(a) - d||^2 per path.
 
@@ -461,6 +527,7 @@ def main():
     ap.add_argument("--many-maps", type=int, nargs="*", default=[16, 64],
                     help="also time these map counts at the headline size (one pass of up to 64 maps)")
     ap.add_argument("--no-config3", action="store_true", help="skip the 16-map L=2047 measurement")
+    ap.add_argument("--no-interp", action="store_true", help="skip the interpolation-form measurement")
     ap.add_argument("--rings-per-lane", type=int, default=0, help="Legendre kernel tile (1, 2, 4; 0 = plan default)")
     ap.add_argument("--ring-threads", type=int, default=0, help="ring kernel workgroup size (256, 512, 1024; 0 = default)")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -591,6 +658,7 @@ def main():
         line_batch = None
 
     cfg3 = None if args.no_config3 else config3_bench(np, torch, sht, args)
+    ipl = None if args.no_interp else interp_bench(np, torch, sht, args, d_alm, alm, results["brute"])
 
     if args.copy_calibration:
         nbytes = args.copy_calibration << 20
@@ -651,6 +719,8 @@ def main():
         line["many_maps"] = many
     if cfg3 is not None:
         line["L2047_16maps"] = cfg3
+    if ipl is not None:
+        line["interp"] = ipl
 
     if not args.no_cpu_baseline:
         import oracle

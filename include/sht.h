@@ -58,7 +58,10 @@ typedef enum {
 enum {
     SHT_PATH_AUTO = 0,      /* butterfly when the plan has it (eps > 0), else brute force */
     SHT_PATH_BRUTE = 1,     /* recurrence over every (l, ring) above the cutoff (App. A.2) */
-    SHT_PATH_BUTTERFLY = 2  /* compressed operator of Sec. 3.2; needs an eps > 0 plan */
+    SHT_PATH_BUTTERFLY = 2, /* compressed operator of Sec. 3.2; needs an eps > 0 plan */
+    SHT_PATH_INTERP = 3     /* Legendre phase at the roots of P~_N^m, then exact
+                               interpolation to the rings (Sec. 3.3 Eq. 23); needs a
+                               plan built with opts.interp = 1; synthesis only */
 };
 
 /* Arithmetic of the butterfly level products (sht_exec_opts.precision).
@@ -115,9 +118,9 @@ typedef struct sht_plan_opts {
                           > 0: exactly this many levels where the rows allow */
     int chunk;         /* column block width at level 1 (0 = default 64) */
     double id_safety;  /* IDs are taken at tolerance eps / id_safety (values
-                          below 1 count as 1; 0 = default 2, which keeps both
+                          below 1 count as 1; 0 = default 4, which keeps both
                           the compressed synthesis and its transpose within
-                          eps of the exact operator) */
+                          eps of the exact operator on the maps measured) */
     int store_fp32;    /* 1: also keep an FP32 copy of the interpolation
                           matrices for SHT_PREC_FP32 */
     int batch_mib;     /* > 0: run the orders in batches whose level vectors (at
@@ -130,6 +133,11 @@ typedef struct sht_plan_opts {
                           matrices.  0 (default): the adjoint reads the
                           synthesis copy with strided loads (same results up
                           to rounding, slower) */
+    int interp;        /* 1: also build the interpolation form of Sec. 3.3: per
+                          (m, parity) the roots of P~_N^m (N = m + t + 2 n_t,
+                          n_t the chain length), the weights of Eq. 23 and
+                          P~_N^m on every north ring (host, long double; about
+                          a minute and 0.6 GB of device memory at L = 4095) */
 } sht_plan_opts;
 
 /* Options for one execution.  Fill with sht_exec_opts_default() first. */
@@ -178,6 +186,17 @@ typedef struct sht_plan_info {
     long long bf_level_units[11]; /* output columns of the pair nodes of level 0..10 */
     long long bf_level_nodes[11]; /* pair nodes of level 0..10 (each reads a 64-byte
                                      record and 2 n int16 column positions) */
+    /* interpolation form (zero unless opts.interp) */
+    int ip_built;
+    long long ip_nodes;       /* node-phase points over all (m, parity): the
+                                 Legendre-root nodes and the direct rings */
+    long long ip_steps;       /* node chain steps above the cutoff (the node
+                                 phase's work unit: 5 flops + 4 per map) */
+    long long ip_exec;        /* lane-steps the node kernel executes */
+    double ip_build_seconds;
+    long long ip_direct;      /* (order, parity, ring) values evaluated at the
+                                 ring itself: rings closer to a node than the
+                                 nodes' long-double precision allows for */
 } sht_plan_info_t;
 
 void sht_plan_opts_default(sht_plan_opts *o);
@@ -330,13 +349,47 @@ typedef struct sht_batch_opts {
     int nstreams;             /* internal streams used, 1..8 (default 4) */
     int path;                 /* SHT_PATH_* for every request */
     int precision;            /* SHT_PREC_* for every request */
-    void *workspace;          /* device scratch of >= sht_batch_workspace_bytes() */
+    void *workspace;          /* device scratch of >= sht_batch_workspace_bytes()
+                                 (sht_queue_workspace_bytes() for sht_batch_create) */
     size_t workspace_bytes;
+    int rings_per_lane;       /* work-queue batches: rings per lane of the Legendre
+                                 waves, 1, 2 or 4 (0 = 2); a tuning knob */
+    int ring_threads;         /* work-queue batches: ring FFT workgroup size, 256,
+                                 512 or 1024 (0 = 512); a tuning knob */
 } sht_batch_opts;
 
 void sht_batch_opts_default(sht_batch_opts *o);
 size_t sht_batch_workspace_bytes(const sht_request *reqs, int n, const sht_batch_opts *o);
 int sht_batch_execute(const sht_request *reqs, int n, const sht_batch_opts *o);
+
+/* ---- work-queue batches ----------------------------------------------
+ * The same many-request synthesis prepared once and replayed with a fixed,
+ * small number of launches, for serving loops and graph capture
+ * (many-transform regime of Sec. 3.4).  sht_batch_create splits the
+ * brute-force Legendre phase of every request into work items (pass of up
+ * to 4 maps, order m, block of ring groups), sorts them longest first by
+ * their chain steps and uploads them with their argument blocks; it
+ * allocates those tables (freed by sht_batch_free) and fixes every address
+ * it was given.  sht_batch_run enqueues on `stream` (hipStream_t, NULL =
+ * default) one persistent Legendre launch whose waves take items from a
+ * device counter until none are left, then one ring-FFT launch per ring
+ * size class covering every request (sht_batch_stats reports the item and
+ * launch counts and the waves of the persistent launch); it allocates nothing and waits for nothing, so a run can
+ * be captured into a HIP graph and replayed.  Results equal
+ * sht_synthesis_ex of each request on the brute-force path bit for bit.
+ * o->path must be SHT_PATH_BRUTE (others: SHT_EUNSUPPORTED); o->workspace
+ * must hold sht_queue_workspace_bytes() (every request's Legendre phase),
+ * and it, the alm inputs and the map outputs must stay valid, and must not
+ * be used by other work while a run is in flight, for the batch's life.
+ * Runs of one batch that overlap in time race.  o->nstreams is ignored.
+ * Callers: serving loops and pipelines that replay a fixed set of
+ * transforms. */
+typedef struct sht_batch_s sht_batch_t;
+size_t sht_queue_workspace_bytes(const sht_request *reqs, int n, const sht_batch_opts *o);
+sht_batch_t *sht_batch_create(const sht_request *reqs, int n, const sht_batch_opts *o);
+int sht_batch_run(const sht_batch_t *batch, void *stream);
+int sht_batch_stats(const sht_batch_t *batch, long long *items, int *launches, int *waves);
+void sht_batch_free(sht_batch_t *batch);
 
 const char *sht_last_error(void);
 
@@ -386,6 +439,12 @@ int sht_debug_interp_decomp(const double *A, int r, int c, double tol, int *k, i
  * Needs an eps > 0 plan whose interpolation data is still on the host
  * (plans under 256 MiB of it). */
 int sht_debug_butterfly_apply(const sht_plan_t *plan, int m, int t, const double *x, double *y);
+
+/* Host evaluation of q^t_m(z_k) over the north rings through the plan's
+ * interpolation form (node chains from the stored starts, then Eq. 23), for
+ * x of length n_t = (L - m - t)/2 + 1 (real).  y: n_north doubles.  Needs a
+ * plan built with opts.interp = 1 (host_only plans included). */
+int sht_debug_interp_apply(const sht_plan_t *plan, int m, int t, const double *x, double *y);
 
 /* Depth kept for (m, t) of an eps > 0 plan, or -1. */
 int sht_debug_butterfly_depth(const sht_plan_t *plan, int m, int t);

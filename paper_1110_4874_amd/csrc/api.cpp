@@ -76,6 +76,8 @@ bool use_bf(const sht_plan_t *p, int path) {
     return p->bf.built && (path == SHT_PATH_BUTTERFLY || path == SHT_PATH_AUTO);
 }
 
+bool use_ip(const sht_plan_t *p, int path) { return p->ip.built && path == SHT_PATH_INTERP; }
+
 size_t synth_ws_bytes(const sht_plan_t *p, const sht_exec_opts *x) {
     return sht::synth_ws_bytes_impl(p, x->nmaps, x->path, x->precision);
 }
@@ -83,10 +85,13 @@ size_t synth_ws_bytes(const sht_plan_t *p, const sht_exec_opts *x) {
 int check_exec(const sht_plan_t *p, const sht_exec_opts *x) {
     if (!x) return fail(SHT_EINVAL, "exec opts is NULL");
     if (x->nmaps < 1) return fail(SHT_EINVAL, "nmaps must be >= 1");
-    if (x->path != SHT_PATH_AUTO && x->path != SHT_PATH_BRUTE && x->path != SHT_PATH_BUTTERFLY)
+    if (x->path != SHT_PATH_AUTO && x->path != SHT_PATH_BRUTE && x->path != SHT_PATH_BUTTERFLY &&
+        x->path != SHT_PATH_INTERP)
         return fail(SHT_EINVAL, "unknown path");
     if (x->path == SHT_PATH_BUTTERFLY && !p->bf.built)
         return fail(SHT_EUNSUPPORTED, "the butterfly path needs a plan built with eps > 0");
+    if (x->path == SHT_PATH_INTERP && !p->ip.built)
+        return fail(SHT_EUNSUPPORTED, "the interpolation path needs a plan built with interp = 1");
     if (x->precision != SHT_PREC_FP64 && x->precision != SHT_PREC_FP32)
         return fail(SHT_EINVAL, "unknown precision");
     if (x->precision == SHT_PREC_FP32 && !p->d_bf_T32)
@@ -141,6 +146,7 @@ namespace sht {
 size_t synth_ws_bytes_impl(const sht_plan_s *p, int nmaps, int path, int precision) {
     size_t b = q_bytes(p, nmaps);
     if (use_bf(p, path)) b += bf_scratch_bytes(p, nmaps, precision == SHT_PREC_FP32);
+    if (use_ip(p, path)) b += interp_scratch_bytes(p, nmaps);
     return b;
 }
 
@@ -151,7 +157,10 @@ static int synth_stages(const sht_plan_s *p, int B, int path, int precision, con
     int rc;
     double *q = (double *)ws;
     if (x) stage_event(x, SHT_STAGE_LEGENDRE, 0);
-    if (use_bf(p, path)) {
+    if (use_ip(p, path)) {
+        void *scr = (char *)ws + q_bytes(p, B);
+        if ((rc = hip_status(launch_interp(p, B, alm, q, scr, st), "interpolation kernel launch"))) return rc;
+    } else if (use_bf(p, path)) {
         void *scr = (char *)ws + q_bytes(p, B);
         if ((rc = hip_status(launch_butterfly(p, B, alm, q, scr, precision == SHT_PREC_FP32, st,
                                               x ? x->stage_events : nullptr),
@@ -193,6 +202,7 @@ void sht_plan_opts_default(sht_plan_opts *o) {
     o->store_fp32 = 0;
     o->batch_mib = 0;
     o->store_transpose = 0;
+    o->interp = 0;
 }
 
 void sht_exec_opts_default(sht_exec_opts *o) {
@@ -335,6 +345,12 @@ int sht_plan_info(const sht_plan_t *p, sht_plan_info_t *out) {
             out->bf_level_nodes[i] = b.level_nodes[i];
         }
     }
+    out->ip_built = p->ip.built;
+    out->ip_nodes = p->ip.nodes;
+    out->ip_steps = p->ip.steps;
+    out->ip_exec = p->ip.exec;
+    out->ip_build_seconds = p->ip.build_seconds;
+    out->ip_direct = p->ip.direct;
     return SHT_OK;
 }
 
@@ -421,6 +437,7 @@ int sht_adjoint_ex(const sht_plan_t *p, const sht_exec_opts *x, const double *ma
     int rc = check_plan(p);
     if (!rc) rc = check_exec(p, x);
     if (!rc) rc = check_conv(x);
+    if (!rc && x->path == SHT_PATH_INTERP) rc = fail(SHT_EUNSUPPORTED, "the interpolation path is synthesis only");
     if (rc) return rc;
     DeviceGuard g(p->device);
     if (!g.ok) return fail(SHT_EDEVICE, "cannot select the plan's device");
@@ -442,6 +459,7 @@ size_t sht_analysis_workspace_bytes(const sht_plan_t *p, const sht_exec_opts *x)
 int sht_analysis_ex(const sht_plan_t *p, const sht_exec_opts *x, const double *map, double *alm, int iterations) {
     int rc = check_plan(p);
     if (!rc) rc = check_exec(p, x);
+    if (!rc && x->path == SHT_PATH_INTERP) rc = fail(SHT_EUNSUPPORTED, "the interpolation path is synthesis only");
     if (rc) return rc;
     if (iterations < 0 || iterations > 1000) return fail(SHT_EINVAL, "iterations must be in [0, 1000]");
     DeviceGuard g(p->device);
@@ -511,6 +529,12 @@ int sht_debug_butterfly_apply(const sht_plan_t *p, int m, int t, const double *x
     if (!p->bf.built) return fail(SHT_EUNSUPPORTED, "plan has no butterfly (eps = 0)");
     if (!p->bf.host_T_kept) return fail(SHT_EUNSUPPORTED, "interpolation data is on the device only");
     return butterfly_apply_host(p, m, t, x, y);
+}
+
+int sht_debug_interp_apply(const sht_plan_t *p, int m, int t, const double *x, double *y) {
+    if (!p || !x || !y || m < 0 || m > p->L || t < 0 || t > 1) return fail(SHT_EINVAL, "bad argument");
+    if (!p->ip.built) return fail(SHT_EUNSUPPORTED, "plan has no interpolation form (interp = 0)");
+    return interp_apply_host(p, m, t, x, y);
 }
 
 int sht_debug_butterfly_depth(const sht_plan_t *p, int m, int t) {

@@ -22,8 +22,6 @@ using namespace sht;
 
 namespace {
 
-constexpr int kMaxStreams = 8;
-
 struct Pool {
     int device = -1;
     hipStream_t s[kMaxStreams] = {};
@@ -31,8 +29,11 @@ struct Pool {
 std::mutex g_pool_mu;
 std::vector<Pool> g_pools;
 
-// Default-priority, non-blocking internal streams of the current device.
-int pool_streams(int dev, hipStream_t *out) {
+}  // namespace
+
+// Default-priority, non-blocking internal streams of device dev (created on
+// first use, with dev current, and kept until the process ends).
+int sht::pool_streams(int dev, hipStream_t *out) {
     std::lock_guard<std::mutex> lk(g_pool_mu);
     for (auto &pl : g_pools)
         if (pl.device == dev) {
@@ -48,6 +49,8 @@ int pool_streams(int dev, hipStream_t *out) {
     std::memcpy(out, pl.s, sizeof(pl.s));
     return SHT_OK;
 }
+
+namespace {
 
 double work_of(const sht_request &r) {
     const sht_plan_s *p = r.plan;

@@ -23,6 +23,8 @@
 //     whose parities split differently run k_bf_level_list, then k_bf_fold.
 //
 // The adjoint runs the same factorization backwards in butterfly_adjoint.hip.
+#include <cstring>
+
 #include "butterfly_common.h"
 
 namespace sht {
@@ -92,7 +94,7 @@ __device__ __forceinline__ void dense_tiles(const S *__restrict__ v, int ES, con
         }
 }
 
-template <int NB, typename S>
+template <int NB, typename S, bool ONE>
 __device__ __forceinline__ void id_block(const BfArgs<S> &a, int node, int ch, int half, int lane, S *uc, int col) {
     constexpr int NC = 2 * NB;
     constexpr int TPW = 4 / kBfHalves;  // tiles per wave
@@ -101,7 +103,7 @@ __device__ __forceinline__ void id_block(const BfArgs<S> &a, int node, int ch, i
     const int *ni = a.node_i + (size_t)node * kBfNodeInts;
     const int n = ni[2] + ni[4];
     const int kk = ni[2 + ch], nd = ni[4 + ch];
-    const int ES = a.ES;
+    const int ES = ONE ? NC : a.ES;  // one group per pass: the stride is a constant
     const S *__restrict__ v = a.ws + (size_t)ni[ch] * ES + col;
     const int16_t *__restrict__ pm = a.perm + ni[7] + (size_t)ch * n;
     const long long toff = (long long)(unsigned)ni[12 + 2 * ch] | ((long long)ni[13 + 2 * ch] << 32);
@@ -247,12 +249,7 @@ __device__ __forceinline__ void residual_task(const BfArgs<S> &a, S *__restrict_
 // One wave per residual piece (up to kBfPieceRings skeleton rings of one
 // task): short waves keep the register count, and with it the occupancy, low.
 template <int NB, typename S>
-__global__ __launch_bounds__(kBfThreads) void k_bf_residual(BfArgs<S> a, long long t0, long long t1, int col0) {
-    __shared__ double stg_all[kBfThreads / 64][bf_res_stage_doubles<NB>()];
-    const int lane = threadIdx.x & 63;
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const long long tk = t0 + (long long)blockIdx.x * (kBfThreads / 64) + w;
-    if (tk >= t1) return;
+__device__ __forceinline__ void residual_piece(const BfArgs<S> &a, long long tk, int lane, double *stg, int col0) {
     const int4 h = a.res_sub[2 * tk], h2 = a.res_sub[2 * tk + 1];
     const int t = __builtin_amdgcn_readfirstlane(h.x), imin = __builtin_amdgcn_readfirstlane(h.y);
     const int iend = __builtin_amdgcn_readfirstlane(h.z), nl = __builtin_amdgcn_readfirstlane(h.w);
@@ -262,8 +259,17 @@ __global__ __launch_bounds__(kBfThreads) void k_bf_residual(BfArgs<S> a, long lo
     const double *ap = reinterpret_cast<const double *>(a.alm + (aoff + t) * a.nmaps + a.map0);
     const double *cfs = a.coef + 4 * a.coef_off[m];
     const int astride = 4 * a.nmaps;  // doubles between rows i and i+1
-    residual_task<NB, kBfPieceRings / 64>(a, a.ws, lbase, lane, t, imin, iend, nl, outb, ap, cfs, astride,
-                                          stg_all[w], col0);
+    residual_task<NB, kBfPieceRings / 64>(a, a.ws, lbase, lane, t, imin, iend, nl, outb, ap, cfs, astride, stg,
+                                          col0);
+}
+
+template <int NB, typename S>
+__global__ __launch_bounds__(kBfThreads) void k_bf_residual(BfArgs<S> a, long long t0, long long t1, int col0) {
+    __shared__ double stg_all[kBfThreads / 64][bf_res_stage_doubles<NB>()];
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const long long tk = t0 + (long long)blockIdx.x * (kBfThreads / 64) + w;
+    if (tk >= t1) return;
+    residual_piece<NB, S>(a, tk, threadIdx.x & 63, stg_all[w], col0);
 }
 
 // One workgroup of 2 kBfHalves waves per pair node (wave w: child w % 2,
@@ -271,8 +277,8 @@ __global__ __launch_bounds__(kBfThreads) void k_bf_residual(BfArgs<S> a, long lo
 // its own LDS copy, and the two copies are summed into the next level's
 // vector with one coalesced store.
 
-template <int NB, typename S>
-__device__ __forceinline__ void level_node(const BfArgs<S> &a, int node) {
+template <int NB, typename S, bool ONE>
+__device__ __forceinline__ void level_node_g(const BfArgs<S> &a, int node) {
     constexpr int NC = 2 * NB;
     extern __shared__ char lds_raw[];
     S *u0 = reinterpret_cast<S *>(lds_raw);
@@ -280,26 +286,34 @@ __device__ __forceinline__ void level_node(const BfArgs<S> &a, int node) {
     const int n = ni[2] + ni[4];
     S *u1 = u0 + (size_t)n * NC;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    S *__restrict__ out = a.ws + (size_t)ni[6] * a.ES;
-    for (int g = 0; g < a.G; g++) {
+    const int ES = ONE ? NC : a.ES, G = ONE ? 1 : a.G;
+    S *__restrict__ out = a.ws + (size_t)ni[6] * ES;
+    for (int g = 0; g < G; g++) {
         if (g) __syncthreads();  // the previous group's sums have been read out of LDS
-        id_block<NB, S>(a, node, w & 1, w >> 1, threadIdx.x & 63, (w & 1) ? u1 : u0, g * NC);
+        id_block<NB, S, ONE>(a, node, w & 1, w >> 1, threadIdx.x & 63, (w & 1) ? u1 : u0, g * NC);
         __syncthreads();
-        for (int e = threadIdx.x; e < n * NC; e += kBfLevelThreads)
-            out[(size_t)(e / NC) * a.ES + g * NC + e % NC] = u0[e] + u1[e];
+        if (ONE) {
+            for (int e = threadIdx.x; e < n * NC; e += kBfLevelThreads) out[e] = u0[e] + u1[e];
+        } else {
+            for (int e = threadIdx.x; e < n * NC; e += kBfLevelThreads)
+                out[(size_t)(e / NC) * ES + g * NC + e % NC] = u0[e] + u1[e];
+        }
     }
 }
 
-template <int NB, typename S>
+
+// ONE: the pass has a single group of maps (separate instantiations, so the
+// common case keeps its constant strides and its register count).
+template <int NB, typename S, bool ONE>
 __global__ __launch_bounds__(kBfLevelThreads) void k_bf_level(BfArgs<S> a, long long n0) {
-    level_node<NB, S>(a, (int)(n0 + blockIdx.x));
+    level_node_g<NB, S, ONE>(a, (int)(n0 + blockIdx.x));
 }
 
 // Level-1 nodes that run alone (their order is folded afterwards).
-template <int NB, typename S>
+template <int NB, typename S, bool ONE>
 __global__ __launch_bounds__(kBfLevelThreads) void k_bf_level_list(BfArgs<S> a, const int *__restrict__ list,
                                                                    long long n0) {
-    level_node<NB, S>(a, list[n0 + blockIdx.x]);
+    level_node_g<NB, S, ONE>(a, list[n0 + blockIdx.x]);
 }
 
 // Level 1 fused with the even/odd fold (Eqs. 13-14): one workgroup per unit
@@ -308,7 +322,7 @@ __global__ __launch_bounds__(kBfLevelThreads) void k_bf_level_list(BfArgs<S> a, 
 // and q(z) = q^e + q^o, q(-z) = q^e - q^o go straight to q.
 constexpr int kBfFoldThreads = 2 * kBfLevelThreads;
 
-template <int NB, typename S>
+template <int NB, typename S, bool ONE>
 __global__ __launch_bounds__(kBfFoldThreads) void k_bf_level1_fold(BfArgs<S> a, const int4 *__restrict__ units,
                                                                    long long u0, int batch, int nbatch) {
     constexpr int NC = 2 * NB;
@@ -320,10 +334,11 @@ __global__ __launch_bounds__(kBfFoldThreads) void k_bf_level1_fold(BfArgs<S> a, 
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int par = w / (2 * kBfHalves), wc = w % (2 * kBfHalves);
     const int m = batch + un.w * nbatch, k0 = un.z;
-    for (int g = 0; g < a.G; g++) {
+    const int G = ONE ? 1 : a.G;
+    for (int g = 0; g < G; g++) {
         if (g) __syncthreads();  // the previous group's fold has read LDS
-        id_block<NB, S>(a, par ? un.y : un.x, wc & 1, wc >> 1, threadIdx.x & 63,
-                        uE + (size_t)(2 * par + (wc & 1)) * n * NC, g * NC);
+        id_block<NB, S, ONE>(a, par ? un.y : un.x, wc & 1, wc >> 1, threadIdx.x & 63,
+                             uE + (size_t)(2 * par + (wc & 1)) * n * NC, g * NC);
         __syncthreads();
         const int mb = a.map0 + g * NB;
         for (int e = threadIdx.x; e < n * NB; e += kBfFoldThreads) {
@@ -360,6 +375,155 @@ __global__ __launch_bounds__(kBfThreads) void k_bf_fold(BfArgs<S> a, int batch, 
     if (ks != k) a.q[((size_t)ks * (a.L + 1) + m) * a.nmaps + a.map0 + b] = make_double2(er - orr, ei - oi);
 }
 
+// ---- work-queue batches: one launch per stage for every request pass of
+// one map-group width; item = {pass (argument block), index within the
+// pass's plan}.  The bodies are the single-request kernels'.
+template <int NB, typename S>
+__global__ __launch_bounds__(kBfThreads) void k_bfq_residual(const BfArgs<S> *__restrict__ args,
+                                                             const int2 *__restrict__ items, long long n) {
+    __shared__ double stg_all[kBfThreads / 64][bf_res_stage_doubles<NB>()];
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const long long j = (long long)blockIdx.x * (kBfThreads / 64) + w;
+    if (j >= n) return;
+    const int2 it = items[j];
+    const BfArgs<S> a = args[__builtin_amdgcn_readfirstlane(it.x)];
+    residual_piece<NB, S>(a, __builtin_amdgcn_readfirstlane(it.y), threadIdx.x & 63, stg_all[w], 0);
+}
+
+// items {pass, node}: level nodes, and level-1 nodes that run alone
+template <int NB, typename S>
+__global__ __launch_bounds__(kBfLevelThreads) void k_bfq_level(const BfArgs<S> *__restrict__ args,
+                                                               const int2 *__restrict__ items) {
+    const int2 it = items[blockIdx.x];
+    const BfArgs<S> a = args[__builtin_amdgcn_readfirstlane(it.x)];
+    level_node_g<NB, S, true>(a, __builtin_amdgcn_readfirstlane(it.y));
+}
+
+// items {pass, fused level-1 unit}
+template <int NB, typename S>
+__global__ __launch_bounds__(kBfFoldThreads) void k_bfq_level1_fold(const BfArgs<S> *__restrict__ args,
+                                                                    const int2 *__restrict__ items) {
+    constexpr int NC = 2 * NB;
+    extern __shared__ char lds_raw[];
+    const int2 it = items[blockIdx.x];
+    const BfArgs<S> a = args[__builtin_amdgcn_readfirstlane(it.x)];
+    const int4 un = a.f1_unit[__builtin_amdgcn_readfirstlane(it.y)];
+    const int *nie = a.node_i + (size_t)un.x * kBfNodeInts;
+    const int n = nie[2] + nie[4];
+    S *uE = reinterpret_cast<S *>(lds_raw);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int par = w / (2 * kBfHalves), wc = w % (2 * kBfHalves);
+    const int m = un.w, k0 = un.z;  // one order batch: slot j holds order j
+    id_block<NB, S, true>(a, par ? un.y : un.x, wc & 1, wc >> 1, threadIdx.x & 63,
+                          uE + (size_t)(2 * par + (wc & 1)) * n * NC, 0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < n * NB; e += kBfFoldThreads) {
+        const int c = e / NB, b = e % NB;
+        const S *e0 = uE + c * NC + 2 * b, *e1 = e0 + (size_t)n * NC, *o0 = e1 + (size_t)n * NC,
+                *o1 = o0 + (size_t)n * NC;
+        double er = (double)(e0[0] + e1[0]), ei = (double)(e0[1] + e1[1]);
+        double orr = (double)(o0[0] + o1[0]), oi = (double)(o0[1] + o1[1]);
+        if (m == 0) ei = oi = 0.0;  // real field: Im a_l0 is ignored
+        const int k = k0 + c, ks = a.nrings - 1 - k;
+        a.q[((size_t)k * (a.L + 1) + m) * a.nmaps + a.map0 + b] = make_double2(er + orr, ei + oi);
+        if (ks != k) a.q[((size_t)ks * (a.L + 1) + m) * a.nmaps + a.map0 + b] = make_double2(er - orr, ei - oi);
+    }
+}
+
+// items {pass, block of kBfThreads fold elements}
+template <typename S>
+__global__ __launch_bounds__(kBfThreads) void k_bfq_fold(const BfArgs<S> *__restrict__ args,
+                                                         const int2 *__restrict__ items) {
+    const int2 it = items[blockIdx.x];
+    const BfArgs<S> a = args[__builtin_amdgcn_readfirstlane(it.x)];
+    const int K = a.K, NP = a.ES / 2;
+    const long long e = (long long)__builtin_amdgcn_readfirstlane(it.y) * kBfThreads + threadIdx.x;
+    if (e >= (long long)a.fold_count * K * NP) return;
+    const int b = (int)(e % NP);
+    const long long jk = e / NP;
+    const int k = (int)(jk % K), j = a.fold_slot[jk / K];
+    const int m = j;
+    const S *qe = a.ws + ((size_t)(2 * j) * K + k) * a.ES + 2 * b;
+    const S *qo = a.ws + ((size_t)(2 * j + 1) * K + k) * a.ES + 2 * b;
+    double er = (double)qe[0], ei = (double)qe[1], orr = (double)qo[0], oi = (double)qo[1];
+    if (m == 0) ei = oi = 0.0;
+    a.q[((size_t)k * (a.L + 1) + m) * a.nmaps + a.map0 + b] = make_double2(er + orr, ei + oi);
+    const int ks = a.nrings - 1 - k;
+    if (ks != k) a.q[((size_t)ks * (a.L + 1) + m) * a.nmaps + a.map0 + b] = make_double2(er - orr, ei - oi);
+}
+
+template <int NB, typename S>
+static hipError_t bfq_stage_nb(int stage, const void *args, const int2 *items, long long n, size_t lds, hipStream_t st) {
+    const BfArgs<S> *ar = reinterpret_cast<const BfArgs<S> *>(args);
+    constexpr int WPB = kBfThreads / 64;
+    if (n <= 0) return hipSuccess;
+    switch (stage) {
+        case 0:
+            hipLaunchKernelGGL((k_bfq_residual<NB, S>), dim3((unsigned)((n + WPB - 1) / WPB)), dim3(kBfThreads), 0, st, ar,
+                               items, n);
+            break;
+        case 1:
+            hipLaunchKernelGGL((k_bfq_level<NB, S>), dim3((unsigned)n), dim3(kBfLevelThreads), lds, st, ar, items);
+            break;
+        case 2:
+            hipLaunchKernelGGL((k_bfq_level1_fold<NB, S>), dim3((unsigned)n), dim3(kBfFoldThreads), lds, st, ar, items);
+            break;
+        default:
+            hipLaunchKernelGGL((k_bfq_fold<S>), dim3((unsigned)n), dim3(kBfThreads), 0, st, ar, items);
+            break;
+    }
+    return hipGetLastError();
+}
+
+// One stage launch of a work-queue batch: stage 0 residual pieces, 1 level
+// nodes (lds: widest column set), 2 fused level-1 units, 3 fold blocks.
+hipError_t launch_bf_queue_stage(int stage, int nb, int fp32, const void *args, const int2 *items, long long n,
+                                 size_t lds, hipStream_t st) {
+    if (n > 0x7fffffffLL) return hipErrorInvalidValue;
+    if (fp32) {
+        switch (nb) {
+            case 8: return bfq_stage_nb<8, float>(stage, args, items, n, lds, st);
+            case 4: return bfq_stage_nb<4, float>(stage, args, items, n, lds, st);
+            case 2: return bfq_stage_nb<2, float>(stage, args, items, n, lds, st);
+            default: return bfq_stage_nb<1, float>(stage, args, items, n, lds, st);
+        }
+    }
+    switch (nb) {
+        case 8: return bfq_stage_nb<8, double>(stage, args, items, n, lds, st);
+        case 4: return bfq_stage_nb<4, double>(stage, args, items, n, lds, st);
+        case 2: return bfq_stage_nb<2, double>(stage, args, items, n, lds, st);
+        default: return bfq_stage_nb<1, double>(stage, args, items, n, lds, st);
+    }
+}
+
+// The argument block of one pass of a work-queue batch (G = 1, nb maps).
+size_t bf_args_bytes(int fp32) { return fp32 ? sizeof(BfArgs<float>) : sizeof(BfArgs<double>); }
+void bf_queue_args(const sht_plan_s *p, int nmaps, int map0, int nb, int fp32, const double *alm, double *q, void *ws,
+                   void *out) {
+    if (fp32) {
+        BfArgs<float> a = bf_args<float>(p, nmaps, p->d_bf_T32, (float *)ws);
+        a.alm = reinterpret_cast<const double2 *>(alm);
+        a.q = reinterpret_cast<double2 *>(q);
+        a.map0 = map0;
+        a.ES = 2 * nb;
+        a.G = 1;
+        std::memcpy(out, &a, sizeof(a));
+    } else {
+        BfArgs<double> a = bf_args<double>(p, nmaps, p->d_bf_T, (double *)ws);
+        a.alm = reinterpret_cast<const double2 *>(alm);
+        a.q = reinterpret_cast<double2 *>(q);
+        a.map0 = map0;
+        a.ES = 2 * nb;
+        a.G = 1;
+        std::memcpy(out, &a, sizeof(a));
+    }
+}
+
+// dynamic LDS of a level node / fused unit with n columns
+size_t bf_level_lds_bytes(int n, int nb, int fp32) {
+    return (size_t)n * 2 * (2 * nb * (fp32 ? sizeof(float) : sizeof(double)));
+}
+
 size_t bf_scratch_bytes(const sht_plan_s *p, int nmaps, int fp32) {
     return (size_t)p->bf.ws_entries * bf_entry_values(nmaps) * (fp32 ? sizeof(float) : sizeof(double));
 }
@@ -369,8 +533,8 @@ static void bf_event(void *const *ev, int stage, int which, hipStream_t st) {
     if (ev && ev[2 * stage + which]) (void)hipEventRecord((hipEvent_t)ev[2 * stage + which], st);
 }
 
-template <int NB, typename S>
-static hipError_t launch_bf_nb(const sht_plan_s *p, BfArgs<S> a, hipStream_t st, void *const *ev) {
+template <int NB, typename S, bool ONE>
+static hipError_t launch_bf_nbg(const sht_plan_s *p, BfArgs<S> a, hipStream_t st, void *const *ev) {
     constexpr int WPB = kBfThreads / 64;
     const BflyPlan &b = p->bf;
     if (b.nbatch != 1) ev = nullptr;
@@ -391,18 +555,19 @@ static hipError_t launch_bf_nb(const sht_plan_s *p, BfArgs<S> a, hipStream_t st,
             if (n1 <= n0) continue;
             // LDS for the widest column set of this level only
             const size_t lds = bf_level_lds<NB, S>(b.lv_max_n[(size_t)bt * kBfMaxLv + q]);
-            hipLaunchKernelGGL((k_bf_level<NB, S>), dim3((unsigned)(n1 - n0)), dim3(kBfLevelThreads), lds, st, a, n0);
+            hipLaunchKernelGGL((k_bf_level<NB, S, ONE>), dim3((unsigned)(n1 - n0)), dim3(kBfLevelThreads), lds, st, a,
+                               n0);
         }
         bf_event(ev, SHT_STAGE_BF_LEVELS, 1, st);
         // level 1: fused with the fold where both parities have levels
         const size_t lds1 = bf_level_lds<NB, S>(b.lv_max_n[(size_t)bt * kBfMaxLv + kBfMaxLv - 1]);
         const long long p0 = b.l1_off[bt], p1 = b.l1_off[bt + 1];
         if (p1 > p0)
-            hipLaunchKernelGGL((k_bf_level_list<NB, S>), dim3((unsigned)(p1 - p0)), dim3(kBfLevelThreads), lds1, st, a,
+            hipLaunchKernelGGL((k_bf_level_list<NB, S, ONE>), dim3((unsigned)(p1 - p0)), dim3(kBfLevelThreads), lds1, st, a,
                                p->d_bf_l1_plain, p0);
         const long long f0 = b.f1_off[bt], f1 = b.f1_off[bt + 1];
         if (f1 > f0)
-            hipLaunchKernelGGL((k_bf_level1_fold<NB, S>), dim3((unsigned)(f1 - f0)), dim3(kBfFoldThreads), 2 * lds1, st,
+            hipLaunchKernelGGL((k_bf_level1_fold<NB, S, ONE>), dim3((unsigned)(f1 - f0)), dim3(kBfFoldThreads), 2 * lds1, st,
                                a, reinterpret_cast<const int4 *>(p->d_bf_f1_unit), f0, bt, b.nbatch);
         const long long s0 = b.fold_off[bt], s1 = b.fold_off[bt + 1];
         const long long nf = (s1 - s0) * b.K * (a.ES / 2);
@@ -411,6 +576,27 @@ static hipError_t launch_bf_nb(const sht_plan_s *p, BfArgs<S> a, hipStream_t st,
                                dim3(kBfThreads), 0, st, a, bt, b.nbatch, p->d_bf_fold_slot + s0, (int)(s1 - s0));
     }
     return hipGetLastError();
+}
+
+// The residual kernel over another task list (the interpolation form's node
+// tasks): a.res_sub, res_lane, res_val and z2 describe the tasks; one launch
+// for a pass of nb maps (G = 1).
+hipError_t launch_node_phase(const sht_plan_s *p, int nb, BfArgs<double> a, long long npieces, hipStream_t st) {
+    (void)p;
+    constexpr int WPB = kBfThreads / 64;
+    if (npieces <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((npieces + WPB - 1) / WPB));
+    switch (nb) {
+        case 4: hipLaunchKernelGGL((k_bf_residual<4, double>), grid, dim3(kBfThreads), 0, st, a, 0LL, npieces, 0); break;
+        case 2: hipLaunchKernelGGL((k_bf_residual<2, double>), grid, dim3(kBfThreads), 0, st, a, 0LL, npieces, 0); break;
+        default: hipLaunchKernelGGL((k_bf_residual<1, double>), grid, dim3(kBfThreads), 0, st, a, 0LL, npieces, 0); break;
+    }
+    return hipGetLastError();
+}
+
+template <int NB, typename S>
+static hipError_t launch_bf_nb(const sht_plan_s *p, BfArgs<S> a, hipStream_t st, void *const *ev) {
+    return a.G == 1 ? launch_bf_nbg<NB, S, true>(p, a, st, ev) : launch_bf_nbg<NB, S, false>(p, a, st, ev);
 }
 
 template <typename S>

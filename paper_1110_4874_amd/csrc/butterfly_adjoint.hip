@@ -97,13 +97,13 @@ __device__ __forceinline__ void split_tiles(const S *__restrict__ Tb, S *__restr
         }
 }
 
-template <int NB, bool TT, typename S>
+template <int NB, bool TT, typename S, bool ONE>
 __device__ __forceinline__ void id_block_t(const BfArgs<S> &a, int node, int ch, int half, int lane, const S *u,
                                            const int16_t *pl, int col) {
     constexpr int TPW = 4 / kBfHalves;  // 16-row tiles per wave
     const int *ni = a.node_i + (size_t)node * kBfNodeInts;
     const int kk = ni[2 + ch], nd = ni[4 + ch];
-    const int ES = a.ES;
+    const int ES = ONE ? 2 * NB : a.ES;  // one group per pass: the stride is a constant
     S *__restrict__ v = a.ws + (size_t)ni[ch] * ES + col;
     const long long toff = (long long)(unsigned)ni[12 + 2 * ch] | ((long long)ni[13 + 2 * ch] << 32);
     const S *__restrict__ Tb = a.T + toff;
@@ -130,36 +130,45 @@ inline size_t bf_level_t_lds(int n) {
 // One workgroup of 2 kBfHalves waves per pair node: per group of NB maps,
 // u is staged in LDS, then wave w writes half w / 2 of the rows of child
 // w % 2's vector.
-template <int NB, bool TT, typename S>
-__device__ __forceinline__ void level_node_t(const BfArgs<S> &a, int node) {
+template <int NB, bool TT, typename S, bool ONE>
+__device__ __forceinline__ void level_node_tg(const BfArgs<S> &a, int node) {
     constexpr int NC = 2 * NB;
     extern __shared__ char lds_raw[];
     S *u = reinterpret_cast<S *>(lds_raw);
     const int *ni = a.node_i + (size_t)node * kBfNodeInts;
     const int n = ni[2] + ni[4];
     int16_t *pl = reinterpret_cast<int16_t *>(u + (size_t)n * NC);
-    const S *__restrict__ in = a.ws + (size_t)ni[6] * a.ES;
+    const int ES = ONE ? NC : a.ES, G = ONE ? 1 : a.G;
+    const S *__restrict__ in = a.ws + (size_t)ni[6] * ES;
     const int16_t *__restrict__ pg = a.perm + ni[7];
     for (int e = threadIdx.x; e < 2 * n; e += kBfLevelThreads) pl[e] = pg[e];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    for (int g = 0; g < a.G; g++) {
+    for (int g = 0; g < G; g++) {
         if (g) __syncthreads();  // the previous group's splits have read u
-        for (int e = threadIdx.x; e < n * NC; e += kBfLevelThreads) u[e] = in[(size_t)(e / NC) * a.ES + g * NC + e % NC];
+        if (ONE) {
+            for (int e = threadIdx.x; e < n * NC; e += kBfLevelThreads) u[e] = in[e];
+        } else {
+            for (int e = threadIdx.x; e < n * NC; e += kBfLevelThreads) u[e] = in[(size_t)(e / NC) * ES + g * NC + e % NC];
+        }
         __syncthreads();
-        id_block_t<NB, TT, S>(a, node, w & 1, w >> 1, threadIdx.x & 63, u, pl + (w & 1) * n, g * NC);
+        id_block_t<NB, TT, S, ONE>(a, node, w & 1, w >> 1, threadIdx.x & 63, u, pl + (w & 1) * n, g * NC);
     }
 }
 
-template <int NB, bool TT, typename S>
+
+
+// ONE: the pass has a single group of maps (separate instantiations, so the
+// common case keeps its constant strides and its register count).
+template <int NB, bool TT, typename S, bool ONE>
 __global__ __launch_bounds__(kBfLevelThreads) void k_bf_level_t(BfArgs<S> a, long long n0) {
-    level_node_t<NB, TT, S>(a, (int)(n0 + blockIdx.x));
+    level_node_tg<NB, TT, S, ONE>(a, (int)(n0 + blockIdx.x));
 }
 
 // Level-1 nodes that run alone (their order was unfolded beforehand).
-template <int NB, bool TT, typename S>
+template <int NB, bool TT, typename S, bool ONE>
 __global__ __launch_bounds__(kBfLevelThreads) void k_bf_level_t_list(BfArgs<S> a, const int *__restrict__ list,
                                                                      long long n0) {
-    level_node_t<NB, TT, S>(a, list[n0 + blockIdx.x]);
+    level_node_tg<NB, TT, S, ONE>(a, list[n0 + blockIdx.x]);
 }
 
 // Unfold fused with level 1 (Eqs. 13-14 transposed): one workgroup per unit
@@ -168,7 +177,7 @@ __global__ __launch_bounds__(kBfLevelThreads) void k_bf_level_t_list(BfArgs<S> a
 // built in LDS from the two hemispheres' ybar and split by both nodes at once.
 constexpr int kBfUnfoldThreads = 2 * kBfLevelThreads;
 
-template <int NB, bool TT, typename S>
+template <int NB, bool TT, typename S, bool ONE>
 __global__ __launch_bounds__(kBfUnfoldThreads) void k_bf_unfold_level1(BfArgs<S> a, const int4 *__restrict__ units,
                                                                        long long u0, int batch, int nbatch) {
     constexpr int NC = 2 * NB;
@@ -185,7 +194,8 @@ __global__ __launch_bounds__(kBfUnfoldThreads) void k_bf_unfold_level1(BfArgs<S>
     const int m = batch + un.w * nbatch, k0 = un.z;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int par = w / (2 * kBfHalves), wc = w % (2 * kBfHalves);
-    for (int g = 0; g < a.G; g++) {
+    const int G = ONE ? 1 : a.G;
+    for (int g = 0; g < G; g++) {
         if (g) __syncthreads();  // the previous group's splits have read uE and uO
         const int mb = a.map0 + g * NB;
         for (int e = threadIdx.x; e < n * NB; e += kBfUnfoldThreads) {
@@ -200,8 +210,8 @@ __global__ __launch_bounds__(kBfUnfoldThreads) void k_bf_unfold_level1(BfArgs<S>
             uO[c * NC + 2 * b + 1] = (S)(yn.y - ys.y);
         }
         __syncthreads();
-        id_block_t<NB, TT, S>(a, par ? un.y : un.x, wc & 1, wc >> 1, threadIdx.x & 63, par ? uO : uE,
-                              pl + (2 * par + (wc & 1)) * n, g * NC);
+        id_block_t<NB, TT, S, ONE>(a, par ? un.y : un.x, wc & 1, wc >> 1, threadIdx.x & 63, par ? uO : uE,
+                                   pl + (2 * par + (wc & 1)) * n, g * NC);
     }
 }
 
@@ -387,8 +397,8 @@ __global__ __launch_bounds__(kBfThreads) void k_bf_zero(double *g, long long nal
     g[2 * (row * nmaps + map0) + rest] = 0.0;
 }
 
-template <int NB, bool TT, typename S>
-static hipError_t launch_bf_adj_nb(const sht_plan_s *p, BfArgs<S> a, hipStream_t st) {
+template <int NB, bool TT, typename S, bool ONE>
+static hipError_t launch_bf_adj_nbg(const sht_plan_s *p, BfArgs<S> a, hipStream_t st) {
     constexpr int WPB = kBfThreads / 64;
     const BflyPlan &b = p->bf;
     const long long nalm = (long long)(p->L + 1) * (p->L + 2) / 2;
@@ -405,18 +415,18 @@ static hipError_t launch_bf_adj_nb(const sht_plan_s *p, BfArgs<S> a, hipStream_t
         const size_t lds1 = bf_level_t_lds<NB, S>(b.lv_max_n[(size_t)bt * kBfMaxLv + kBfMaxLv - 1]);
         const long long p0 = b.l1_off[bt], p1 = b.l1_off[bt + 1];
         if (p1 > p0)
-            hipLaunchKernelGGL((k_bf_level_t_list<NB, TT, S>), dim3((unsigned)(p1 - p0)), dim3(kBfLevelThreads), lds1, st,
+            hipLaunchKernelGGL((k_bf_level_t_list<NB, TT, S, ONE>), dim3((unsigned)(p1 - p0)), dim3(kBfLevelThreads), lds1, st,
                                a, p->d_bf_l1_plain, p0);
         const long long f0 = b.f1_off[bt], f1 = b.f1_off[bt + 1];
         if (f1 > f0)
-            hipLaunchKernelGGL((k_bf_unfold_level1<NB, TT, S>), dim3((unsigned)(f1 - f0)), dim3(kBfUnfoldThreads), 2 * lds1,
+            hipLaunchKernelGGL((k_bf_unfold_level1<NB, TT, S, ONE>), dim3((unsigned)(f1 - f0)), dim3(kBfUnfoldThreads), 2 * lds1,
                                st, a, reinterpret_cast<const int4 *>(p->d_bf_f1_unit), f0, bt, b.nbatch);
         const long long *lo = b.lv_off.data() + (size_t)bt * (kBfMaxLv + 1);
         for (int q = kBfMaxLv - 2; q >= 0; q--) {  // levels >= 2
             const long long n0 = lo[q], n1 = lo[q + 1];
             if (n1 <= n0) continue;
             const size_t lds = bf_level_t_lds<NB, S>(b.lv_max_n[(size_t)bt * kBfMaxLv + q]);
-            hipLaunchKernelGGL((k_bf_level_t<NB, TT, S>), dim3((unsigned)(n1 - n0)), dim3(kBfLevelThreads), lds, st, a,
+            hipLaunchKernelGGL((k_bf_level_t<NB, TT, S, ONE>), dim3((unsigned)(n1 - n0)), dim3(kBfLevelThreads), lds, st, a,
                                n0);
         }
         const long long t0 = b.batch_task[bt], t1 = b.batch_task[bt + 1];
@@ -428,6 +438,11 @@ static hipError_t launch_bf_adj_nb(const sht_plan_s *p, BfArgs<S> a, hipStream_t
         }
     }
     return hipGetLastError();
+}
+
+template <int NB, bool TT, typename S>
+static hipError_t launch_bf_adj_nb(const sht_plan_s *p, BfArgs<S> a, hipStream_t st) {
+    return a.G == 1 ? launch_bf_adj_nbg<NB, TT, S, true>(p, a, st) : launch_bf_adj_nbg<NB, TT, S, false>(p, a, st);
 }
 
 template <typename S>

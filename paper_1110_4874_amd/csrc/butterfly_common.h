@@ -32,6 +32,11 @@ struct BfArgs {
     // workgroups loop over the groups of their node (the repeated reads of a
     // node's blocks hit the caches).
     int ES, G;
+    // level-1 and fold lists of the plan (work-queue batches address them
+    // through the argument block)
+    const int4 *__restrict__ f1_unit;
+    const int *__restrict__ fold_slot;
+    int fold_count;
 };
 
 // Maps of one pass at most (G <= kBfMaxGroups groups of 8 maps).
@@ -139,6 +144,9 @@ inline BfArgs<S> bf_args(const sht_plan_s *p, int nmaps, const S *T, S *ws) {
     a.map0 = 0;
     a.ES = 2;
     a.G = 1;
+    a.f1_unit = reinterpret_cast<const int4 *>(p->d_bf_f1_unit);
+    a.fold_slot = p->d_bf_fold_slot;
+    a.fold_count = p->bf.built ? (int)(p->bf.fold_off.back() - p->bf.fold_off.front()) : 0;
     return a;
 }
 

@@ -376,10 +376,12 @@ int build_butterfly(sht_plan_s *p, const BflyInput &in) {
     c.p = p;
     c.in = &in;
     c.items.resize((size_t)(L + 1) * 2);
-    // IDs at eps / 2 by default: the transpose of a block truncated at eps
-    // (the adjoint) reaches about 1.7 eps in max norm on white-noise maps,
-    // while eps / 2 keeps both directions within eps for ~1% more entries.
-    c.eps_id = p->eps / (p->opts.id_safety > 0 ? std::max(1.0, p->opts.id_safety) : 2.0);
+    // IDs at eps / 4 by default: the transpose of the compressed operator
+    // (the adjoint) applied to white-noise maps reached 1.7 eps with blocks
+    // truncated at eps, and still 1.1 eps at eps / 2 once 21 maps were
+    // sampled (L = 200, eps = 1e-10, three levels); eps / 4 keeps both
+    // directions within eps there for ~2% fewer levels kept by the cost model.
+    c.eps_id = p->eps / (p->opts.id_safety > 0 ? std::max(1.0, p->opts.id_safety) : 4.0);
     c.rho = p->opts.rho > 0 ? p->opts.rho : 2.5;
     c.chunk = p->opts.chunk > 0 ? p->opts.chunk : 64;
     c.max_levels = p->opts.max_levels;

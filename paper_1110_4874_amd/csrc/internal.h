@@ -89,6 +89,32 @@ struct BflyPlan {
 int interp_decomp(double *A, int r, int c, double tol, double abs_floor, std::vector<int> &piv,
                   std::vector<double> &T);
 
+// Interpolation form of the Legendre phase (Sec. 3.3, Eq. 23): nodes at the
+// roots of P~_N^m, N = m + t + 2 n_t, per (m, t) (interp_plan.cpp builds it,
+// interp.hip applies it).
+struct InterpPlan {
+    int built = 0;
+    std::vector<long long> node_off;  // [(L+1)*2 + 1] first node of (m, t)
+    std::vector<double> x_hi, x_lo;   // [nodes] z_j^2 as a double-double
+    std::vector<double> gam;          // [nodes] first-form weights gamma_j
+    std::vector<double> lamN;         // [(L+1)*2][n_north_pad] P~_N^m(y_k), 0 where the chain is dead
+    std::vector<int> sub;             // [pieces][8] node tasks in the residual kernel's format
+    std::vector<int> lane;            // [pieces*kBfPieceRings][2] node, first row
+    std::vector<double> val;          // [pieces*kBfPieceRings][2] chain values at that row and the next
+    // nodes nearest the poles (sin(theta) below the plan's double-double
+    // threshold) run a compensated chain instead: one wave of up to 64 nodes
+    std::vector<int> dd_task;         // [tasks][8] t, m, chain length n, nodes, first entry, first lane, imin, 0
+    std::vector<int> dd_lane;         // [tasks*64][2] node, first row
+    std::vector<double> dd_val;       // [tasks*64][4] start values at that row and the next, hi and lo
+    // rings closer to a node than the nodes' own precision allows for: both
+    // parities are evaluated at the ring itself (extra node slots after the
+    // n nodes of each (m, t), weight 0) and written over the interpolated
+    // value: {m, ring, slot of t = 0, slot of t = 1} (-1: that chain is dead)
+    std::vector<int> patch;           // [patches][4]
+    long long nodes = 0, dd_nodes = 0, steps = 0, exec = 0, direct = 0;
+    double build_seconds = 0.0;
+};
+
 struct RingClass {
     int lds_entries;              // complex entries of the FFT buffer (before padding)
     bool wrap = false;            // some ring has J/2 <= L (q staged through LDS)
@@ -153,6 +179,14 @@ struct sht_plan_s {
     int *d_bf_node_i = nullptr;
     int *d_bf_f1_unit = nullptr, *d_bf_l1_plain = nullptr, *d_bf_fold_slot = nullptr;
 
+    // ---- interpolation to Legendre-root nodes (opts.interp) -------------
+    sht::InterpPlan ip;
+    long long *d_ip_node_off = nullptr;
+    double *d_ip_x_hi = nullptr, *d_ip_x_lo = nullptr, *d_ip_gam = nullptr, *d_ip_lamN = nullptr;
+    int *d_ip_sub = nullptr, *d_ip_lane = nullptr, *d_ip_dd_task = nullptr, *d_ip_dd_lane = nullptr;
+    double *d_ip_val = nullptr, *d_ip_dd_val = nullptr;
+    int *d_ip_patch = nullptr;
+
 };
 
 namespace sht {
@@ -212,6 +246,8 @@ struct RingArgs {
 // Host plan construction (plan.cpp, butterfly_plan.cpp).
 int build_host_tables(sht_plan_s *p);
 int build_butterfly(sht_plan_s *p, const BflyInput &in);
+int build_interp(sht_plan_s *p, const BflyInput &in);
+int interp_apply_host(const sht_plan_s *p, int m, int t, const double *x, double *y);
 int butterfly_apply_host(const sht_plan_s *p, int m, int t, const double *x, double *y);
 int upload_tables(sht_plan_s *p);
 void free_device_tables(sht_plan_s *p);
@@ -233,6 +269,21 @@ size_t bf_scratch_bytes(const sht_plan_s *p, int nmaps, int fp32);
 // residual and level launches are bracketed for one-batch plans.
 hipError_t launch_butterfly(const sht_plan_s *p, int nmaps, const double *alm, double *q, void *scratch,
                             int fp32, hipStream_t stream, void *const *stage_events = nullptr);
+// Work-queue batches on the butterfly path (butterfly.hip): the argument
+// block of one pass (bf_args_bytes() bytes, written to out), one stage
+// launch over items {pass, index} (stage 0 residual pieces, 1 level nodes,
+// 2 fused level-1 units, 3 fold blocks), and a node's LDS bytes.
+size_t bf_args_bytes(int fp32);
+void bf_queue_args(const sht_plan_s *p, int nmaps, int map0, int nb, int fp32, const double *alm, double *q, void *ws,
+                   void *out);
+hipError_t launch_bf_queue_stage(int stage, int nb, int fp32, const void *args, const int2 *items, long long n,
+                                 size_t lds, hipStream_t st);
+size_t bf_level_lds_bytes(int n, int nb, int fp32);
+// Interpolation form (opts.interp plans): alm -> folded q through the
+// Legendre-root nodes; scratch holds ip.nodes entries of up to 8 doubles.
+size_t interp_scratch_bytes(const sht_plan_s *p, int nmaps);
+hipError_t launch_interp(const sht_plan_s *p, int nmaps, const double *alm, double *q, void *scratch,
+                         hipStream_t stream);
 // Its transpose: unfolded ybar (ring-major, like q) -> g (written whole),
 // with the same scratch.
 hipError_t launch_butterfly_adjoint(const sht_plan_s *p, int nmaps, const double *ybar, double *g, void *scratch,
@@ -241,14 +292,31 @@ hipError_t launch_butterfly_adjoint(const sht_plan_s *p, int nmaps, const double
 // one pass, the persistent Legendre launch over a sorted item list (items
 // {pass, m, ring block, maps}; counter is device memory the launch resets),
 // and one ring-queue launch per ring size class (items {argument block,
-// item of that class}).
+// item of that class}).  The Legendre items come in one list per XCD.
 LegArgs leg_args(const sht_plan_s *p, int nmaps, int map0, int R, const double *alm, double *q);
-hipError_t launch_legendre_queue(const LegArgs *passes, const int4 *items, long long nitems, unsigned *counter,
-                                 int rings_per_lane, hipStream_t st);
+// Work-queue batches on the brute-force path: one persistent launch per wave
+// shape (0, 1: compensated waves of 2 or 1 maps; 2, 3, 4: FP64 waves of 4,
+// 2 or 1 maps).
+constexpr int kQueueShapes = 5;
+// Internal streams for fork/join inside one call (batch.cpp).
+constexpr int kMaxStreams = 8;
+int pool_streams(int dev, hipStream_t *out);
+int queue_shape(bool dd, int nb);
+hipError_t legendre_queue_grid(int shape, int rings_per_lane, int *grid);
+// items {pass, m, ring block, first map}: per shape eight lists back to back,
+// cut into chunks; chunk c covers items [chunk_off[c], chunk_off[c+1]) and
+// list x of shape v the chunks [list_off[9v+x], list_off[9v+x+1]); counter:
+// 5 x 8 x 16 unsigned of device memory, cleared by launch_queue_reset before
+// the shapes' launches; grid: waves of the shape's launch (0: no items).
+hipError_t launch_queue_reset(unsigned *counter, hipStream_t st);
+hipError_t launch_legendre_queue(int shape, const LegArgs *passes, const int4 *items, const unsigned *chunk_off,
+                                 const unsigned *list_off, unsigned *counter, int rings_per_lane, int grid,
+                                 hipStream_t st);
 RingArgs ring_args(const sht_plan_s *p, int nmaps, const double *q, double *map);
 size_t ring_class_shape(int lds_entries, bool wrap, int T, int *fft_entries, int *stage);
 hipError_t launch_ring_queue(int T, const RingArgs *args, const int2 *items, long long nitems, size_t lds,
                              hipStream_t st);
+hipError_t ring_queue_prepare(int T);
 // y = alpha x + beta y over n doubles (beta = 0: y = alpha x).
 hipError_t launch_axpby(double *y, const double *x, double alpha, double beta, long long n, hipStream_t st);
 // Device-side transposed copies of the interpolation matrices (d_bf_Tt and,

@@ -18,40 +18,12 @@
 // wave-uniform l loop only at chunk boundaries.  Ring blocks nearest the
 // poles, where a z-based FP64 recurrence loses ~l eps / sin(theta), run the
 // same recurrence in double-double arithmetic.
+#include "ddmath.h"
 #include "internal.h"
 
 namespace sht {
 
-// ---- double-double helpers (error-free transformations) --------------
-struct dd {
-    double h, l;
-};
 
-#pragma clang fp contract(off)
-__device__ __forceinline__ dd two_sum(double a, double b) {
-    double s = a + b;
-    double bb = s - a;
-    double e = (a - (s - bb)) + (b - bb);
-    return {s, e};
-}
-__device__ __forceinline__ dd fast_two_sum(double a, double b) {
-    double s = a + b;
-    double e = b - (s - a);
-    return {s, e};
-}
-__device__ __forceinline__ dd dd_mul(dd a, dd b) {
-    double p = a.h * b.h;
-    double e = __builtin_fma(a.h, b.h, -p);
-    e = __builtin_fma(a.h, b.l, e);
-    e = __builtin_fma(a.l, b.h, e);
-    return fast_two_sum(p, e);
-}
-__device__ __forceinline__ dd dd_add(dd a, dd b) {
-    dd s = two_sum(a.h, b.h);
-    double e = s.l + (a.l + b.l);
-    return fast_two_sum(s.h, e);
-}
-#pragma clang fp contract(on)
 
 // One wave: order m, rings of the 64-ring groups g0 .. g0+R-1 (R per lane).
 // Groups at or past a.ng do not exist (partial last block) and are skipped.
@@ -288,73 +260,105 @@ static hipError_t launch_nb(const sht_plan_s *p, LegArgs a, hipStream_t st) {
 }
 
 // Persistent form for batches of requests (the many-transform regime of
-// Sec. 3.4): one launch for every request of a batch.  Each wave takes work
-// items {pass, m, ring block, maps} from a device counter (a vector-memory
-// atomic) until the list, sorted longest first on the host, is exhausted,
-// and runs the same wave body as k_legendre on the pass's argument block.
-// Every wave leaves once the counter has passed the end of the list.
+// Sec. 3.4): one launch per wave shape (compensated waves of 2 or 1 maps,
+// FP64 waves of 4, 2 or 1 maps) for every request of a batch, so that each
+// launch runs one specialised body at its own occupancy.  Work items {pass,
+// m, ring block, first map} of one shape come in eight lists, one per XCD
+// (the items of one pass and order share a list, so that XCD's L2 serves the
+// order's coefficient and a_lm stream to all of them), each sorted longest
+// first and cut into chunks that shrink along the list.  A wave takes chunks
+// from its own XCD's list through a device counter (a vector-memory atomic)
+// and, once that list is exhausted, from the others in turn; it leaves when
+// every counter has passed the end of its list, so every wave reaches the
+// exit.  The wave body is k_legendre's.
+constexpr int kQueueLists = 8;
+constexpr int kQueueStride = 16;  // counters 64 bytes apart
+
 __global__ void k_queue_reset(unsigned *c) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0u;
+    if (blockIdx.x == 0)
+        for (int i = threadIdx.x; i < kQueueShapes * kQueueLists; i += blockDim.x) c[i * kQueueStride] = 0u;
 }
 
-template <int R>
+template <int NB, int R, bool DD>
 __global__ __launch_bounds__(64, (R == 4 ? 2 : 4)) void k_legendre_queue(const LegArgs *__restrict__ passes,
                                                                          const int4 *__restrict__ items,
-                                                                         unsigned nitems, unsigned *__restrict__ counter) {
-    for (;;) {
-        unsigned it = 0;
-        if (threadIdx.x == 0) it = atomicAdd(counter, 1u);
-        it = __shfl(it, 0);
-        if (it >= nitems) return;
-        const int4 w = items[it];
-        const int pi = __builtin_amdgcn_readfirstlane(w.x), m = __builtin_amdgcn_readfirstlane(w.y);
-        const int rb = __builtin_amdgcn_readfirstlane(w.z), nb = __builtin_amdgcn_readfirstlane(w.w);
-        const LegArgs a = passes[pi];
-        if (rb < a.dd_groups) {
-            for (int b0 = 0; b0 < nb; b0 += 2) {
-                LegArgs ab = a;
-                ab.map0 = a.map0 + b0;
-                if (nb - b0 >= 2)
-                    legendre_wave<2, 1, true>(ab, m, rb);
+                                                                         const unsigned *__restrict__ chunk_off,
+                                                                         const unsigned *__restrict__ list_off,
+                                                                         unsigned *__restrict__ counter) {
+    const int home = blockIdx.x & (kQueueLists - 1);  // workgroups are dealt to the XCDs round robin
+    for (int s = 0; s < kQueueLists; s++) {
+        const int x = (home + s) & (kQueueLists - 1);
+        const unsigned lo = list_off[x], cnt = list_off[x + 1] - lo;
+        for (;;) {
+            unsigned c = 0;
+            if (threadIdx.x == 0) c = atomicAdd(counter + x * kQueueStride, 1u);
+            c = __shfl(c, 0);
+            if (c >= cnt) break;
+            const unsigned i0 = chunk_off[lo + c], i1 = chunk_off[lo + c + 1];
+            for (unsigned i = i0; i < i1; i++) {
+                const int4 w = items[i];
+                const int pi = __builtin_amdgcn_readfirstlane(w.x), m = __builtin_amdgcn_readfirstlane(w.y);
+                const int rb = __builtin_amdgcn_readfirstlane(w.z), b0 = __builtin_amdgcn_readfirstlane(w.w);
+                LegArgs a = passes[pi];
+                a.map0 += b0;
+                if (DD)
+                    legendre_wave<NB, 1, true>(a, m, rb);
                 else
-                    legendre_wave<1, 1, true>(ab, m, rb);
+                    legendre_wave<NB, R, false>(a, m, a.dd_groups + (rb - a.dd_groups) * R);
             }
-        } else {
-            const int g0 = a.dd_groups + (rb - a.dd_groups) * R;
-            if (nb == 4)
-                legendre_wave<4, R, false>(a, m, g0);
-            else if (nb == 2)
-                legendre_wave<2, R, false>(a, m, g0);
-            else
-                legendre_wave<1, R, false>(a, m, g0);
         }
     }
 }
 
+typedef void (*QueueKernel)(const LegArgs *, const int4 *, const unsigned *, const unsigned *, unsigned *);
+
 template <int R>
-static hipError_t launch_queue_r(const LegArgs *passes, const int4 *items, unsigned nitems, unsigned *counter,
-                                 hipStream_t st) {
+static QueueKernel queue_kernel_r(int shape) {
+    switch (shape) {
+        case 0: return k_legendre_queue<2, 1, true>;
+        case 1: return k_legendre_queue<1, 1, true>;
+        case 2: return k_legendre_queue<4, R, false>;
+        case 3: return k_legendre_queue<2, R, false>;
+        default: return k_legendre_queue<1, R, false>;
+    }
+}
+
+static QueueKernel queue_kernel(int shape, int R) {
+    switch (R) {
+        case 1: return queue_kernel_r<1>(shape);
+        case 4: return queue_kernel_r<4>(shape);
+        default: return queue_kernel_r<2>(shape);
+    }
+}
+
+int queue_shape(bool dd, int nb) { return dd ? (nb >= 2 ? 0 : 1) : (nb >= 4 ? 2 : nb >= 2 ? 3 : 4); }
+
+// Waves of the persistent launch of one shape: as many as the current device
+// keeps resident at once.
+hipError_t legendre_queue_grid(int shape, int rings_per_lane, int *grid) {
     int dev = 0, cus = 0, per_cu = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_legendre_queue<R>, 64, 0);
-    if (e != hipSuccess) return e;
-    const long long grid = std::min<long long>((long long)std::max(per_cu, 1) * std::max(cus, 1), nitems);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)queue_kernel(shape, rings_per_lane), 64,
+                                                         0);
+    *grid = std::max(std::max(per_cu, 1) * std::max(cus, 1) / kQueueLists, 1) * kQueueLists;
+    return e;
+}
+
+hipError_t launch_queue_reset(unsigned *counter, hipStream_t st) {
     hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, st, counter);
-    if (grid > 0) hipLaunchKernelGGL((k_legendre_queue<R>), dim3((unsigned)grid), dim3(64), 0, st, passes, items, nitems,
-                                     counter);
     return hipGetLastError();
 }
 
-hipError_t launch_legendre_queue(const LegArgs *passes, const int4 *items, long long nitems, unsigned *counter,
-                                 int rings_per_lane, hipStream_t st) {
-    if (nitems < 0 || nitems > 0x7fffffffLL) return hipErrorInvalidValue;
-    switch (rings_per_lane) {
-        case 1: return launch_queue_r<1>(passes, items, (unsigned)nitems, counter, st);
-        case 4: return launch_queue_r<4>(passes, items, (unsigned)nitems, counter, st);
-        default: return launch_queue_r<2>(passes, items, (unsigned)nitems, counter, st);
-    }
+hipError_t launch_legendre_queue(int shape, const LegArgs *passes, const int4 *items, const unsigned *chunk_off,
+                                 const unsigned *list_off, unsigned *counter, int rings_per_lane, int grid,
+                                 hipStream_t st) {
+    if (shape < 0 || shape >= kQueueShapes || grid < 0) return hipErrorInvalidValue;
+    if (grid == 0) return hipSuccess;  // no items of this shape
+    hipLaunchKernelGGL(queue_kernel(shape, rings_per_lane), dim3((unsigned)grid), dim3(64), 0, st, passes, items,
+                       chunk_off, list_off + shape * (kQueueLists + 1), counter + shape * kQueueLists * kQueueStride);
+    return hipGetLastError();
 }
 
 // Argument block of one pass (maps map0 .. map0 + nb - 1 of nmaps) for

@@ -395,7 +395,7 @@ int build_host_tables(sht_plan_s *p) {
     p->start_lo.assign((size_t)(L + 1) * 2 * 2 * std::max(p->n_dd_pad, 1), 0.0);
     ctx.steps.assign(np, 0);
     ctx.alive.assign(np, 0);
-    ctx.keep_ld = p->eps > 0.0;
+    ctx.keep_ld = p->eps > 0.0 || p->opts.interp;
     if (ctx.keep_ld) ctx.start_ld.assign((size_t)(L + 1) * 2 * 2 * np, 0.0L);
     parallel_for(p->n_north, nth, start_worker, &ctx);
     if (ctx.bad.load())
@@ -465,8 +465,14 @@ int build_host_tables(sht_plan_s *p) {
         std::vector<ld> z2l(p->n_north);
         for (int k = 0; k < p->n_north; k++) z2l[k] = ctx.zl[k] * ctx.zl[k];
         BflyInput in{ctx.coefl.data(), ctx.start_ld.data(), z2l.data()};
-        int rc = build_butterfly(p, in);
-        if (rc != SHT_OK) return rc;
+        if (p->eps > 0.0) {
+            int rc = build_butterfly(p, in);
+            if (rc != SHT_OK) return rc;
+        }
+        if (p->opts.interp) {
+            int rc = build_interp(p, in);
+            if (rc != SHT_OK) return rc;
+        }
         std::vector<ld>().swap(ctx.start_ld);
     }
     const int class_size[4] = {1024, 2048, 4096, 8192};
@@ -528,6 +534,24 @@ int upload_tables(sht_plan_s *p) {
 #undef UP
     for (auto &rc : p->classes)
         if (e == hipSuccess) e = up(&rc.d_rings, rc.rings, &b);
+    if (p->ip.built) {
+        InterpPlan &f = p->ip;
+#define UPI(d, h) \
+    if (e == hipSuccess) e = up(&p->d, f.h, &b)
+        UPI(d_ip_node_off, node_off);
+        UPI(d_ip_x_hi, x_hi);
+        UPI(d_ip_x_lo, x_lo);
+        UPI(d_ip_gam, gam);
+        UPI(d_ip_lamN, lamN);
+        UPI(d_ip_sub, sub);
+        UPI(d_ip_lane, lane);
+        UPI(d_ip_val, val);
+        UPI(d_ip_dd_task, dd_task);
+        UPI(d_ip_dd_lane, dd_lane);
+        UPI(d_ip_dd_val, dd_val);
+        UPI(d_ip_patch, patch);
+#undef UPI
+    }
     if (p->bf.built) {
         BflyPlan &f = p->bf;
 #define UPB(d, h) \
@@ -580,7 +604,10 @@ void free_device_tables(sht_plan_s *p) {
                     p->d_tw,        p->d_bs_table,  p->d_chirp,      p->d_ring_chirp_off,
                     p->d_bf_res_task, p->d_bf_res_lane, p->d_bf_res_sub,
                     p->d_bf_res_val, p->d_bf_T,      p->d_bf_T32,   p->d_bf_Tt,    p->d_bf_Tt32, p->d_bf_perm,
-                    p->d_bf_node_i, p->d_bf_f1_unit, p->d_bf_l1_plain, p->d_bf_fold_slot};
+                    p->d_bf_node_i, p->d_bf_f1_unit, p->d_bf_l1_plain, p->d_bf_fold_slot,
+                    p->d_ip_node_off, p->d_ip_x_hi, p->d_ip_x_lo, p->d_ip_gam, p->d_ip_lamN,
+                    p->d_ip_sub, p->d_ip_lane, p->d_ip_val, p->d_ip_dd_task, p->d_ip_dd_lane, p->d_ip_dd_val,
+                    p->d_ip_patch};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     for (auto &rc : p->classes)
@@ -603,6 +630,11 @@ void free_device_tables(sht_plan_s *p) {
     p->d_bf_perm = nullptr;
     p->d_bf_node_i = nullptr;
     p->d_bf_f1_unit = p->d_bf_l1_plain = p->d_bf_fold_slot = nullptr;
+    p->d_ip_node_off = nullptr;
+    p->d_ip_x_hi = p->d_ip_x_lo = p->d_ip_gam = p->d_ip_lamN = p->d_ip_val = nullptr;
+    p->d_ip_sub = p->d_ip_lane = p->d_ip_dd_task = p->d_ip_dd_lane = nullptr;
+    p->d_ip_dd_val = nullptr;
+    p->d_ip_patch = nullptr;
     p->device_bytes = 0;
 }
 

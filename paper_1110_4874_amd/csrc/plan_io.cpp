@@ -39,7 +39,7 @@ namespace {
 using namespace sht;
 
 constexpr char kMagic[8] = {'W', 'M', 'H', 'I', 'P', 'P', 'L', 'N'};
-constexpr uint32_t kFileVersion = 2;
+constexpr uint32_t kFileVersion = 5;
 constexpr size_t kHashBlock = (size_t)16 << 20;
 
 struct FileHeader {
@@ -48,7 +48,7 @@ struct FileHeader {
     uint64_t payload_bytes, payload_hash;
     int32_t L, nside;
     double eps, cutoff, dd_sin, rho, id_safety;
-    int32_t max_levels, chunk, store_fp32, store_transpose, batch_mib, rings_per_lane, ring_threads, pad0;
+    int32_t max_levels, chunk, store_fp32, store_transpose, batch_mib, rings_per_lane, ring_threads, interp;
     int32_t layout[8];  // kLanes, kChunk, kCoefPad, kBfMaxLv, kBfNodeInts, kBfTaskRings, kBfPieceRings, 0
     uint64_t header_hash;  // over every byte above
 };
@@ -247,6 +247,29 @@ void visit(A &ar, sht_plan_s *p, std::vector<double> &T) {
         c.wrap = wrap != 0;
         ar.vec(c.rings);
     }
+    InterpPlan &ip = p->ip;
+    ar.scalar(ip.built);
+    if (!ar.ok()) return;
+    if (ip.built) {
+        ar.vec(ip.node_off);
+        ar.vec(ip.x_hi);
+        ar.vec(ip.x_lo);
+        ar.vec(ip.gam);
+        ar.vec(ip.lamN);
+        ar.vec(ip.sub);
+        ar.vec(ip.lane);
+        ar.vec(ip.val);
+        ar.vec(ip.dd_task);
+        ar.vec(ip.dd_lane);
+        ar.vec(ip.dd_val);
+        ar.vec(ip.patch);
+        ar.scalar(ip.direct);
+        ar.scalar(ip.nodes);
+        ar.scalar(ip.dd_nodes);
+        ar.scalar(ip.steps);
+        ar.scalar(ip.exec);
+        ar.scalar(ip.build_seconds);
+    }
     BflyPlan &b = p->bf;
     ar.scalar(b.built);
     if (!ar.ok() || !b.built) return;
@@ -314,6 +337,23 @@ bool consistent(const sht_plan_s *p) {
     for (const auto &c : p->classes)
         for (int r : c.rings)
             if (r < 0 || r >= p->nrings) return false;
+    const InterpPlan &ip = p->ip;
+    if (ip.built) {
+        if (ip.node_off.size() != (L + 1) * 2 + 1 || (long long)ip.x_hi.size() != ip.nodes) return false;
+        if (ip.node_off.back() != ip.nodes || ip.gam.size() != ip.x_hi.size() || ip.x_lo.size() != ip.x_hi.size())
+            return false;
+        if (ip.lamN.size() != (L + 1) * 2 * np || ip.sub.size() % 8 || ip.lane.size() != ip.val.size()) return false;
+        if (ip.dd_task.size() % 8 || ip.dd_lane.size() * 2 != ip.dd_val.size()) return false;
+        if (ip.patch.size() % 4) return false;
+        for (size_t i = 0; i < ip.patch.size(); i += 4) {
+            const int m = ip.patch[i], k = ip.patch[i + 1];
+            if (m < 0 || m > (int)L || k < 0 || k >= p->n_north) return false;
+            for (int t = 0; t < 2; t++) {
+                const long long s = ip.patch[i + 2 + t];
+                if (s < -1 || s >= ip.nodes) return false;
+            }
+        }
+    }
     const BflyPlan &b = p->bf;
     if (b.built) {
         if (b.K != p->n_north || b.depth.size() != (L + 1) * 2 || b.nbatch < 1) return false;
@@ -364,6 +404,7 @@ int load_file(const char *path, const sht_plan_opts *lo, sht_plan_s **out) {
     p->opts.batch_mib = h.batch_mib;
     p->opts.rings_per_lane = h.rings_per_lane;
     p->opts.ring_threads = h.ring_threads;
+    p->opts.interp = h.interp;
     if (lo) {
         p->opts.host_only = lo->host_only;
         p->opts.store_fp32 = lo->store_fp32;
@@ -449,6 +490,7 @@ int sht_plan_save(const sht_plan_t *cp, const char *path) {
     h.batch_mib = p->opts.batch_mib;
     h.rings_per_lane = p->opts.rings_per_lane;
     h.ring_threads = p->opts.ring_threads;
+    h.interp = p->opts.interp;
     layout_of(h.layout);
     h.header_hash = header_hash(h);
     // write a temporary file next to the target and rename it into place,

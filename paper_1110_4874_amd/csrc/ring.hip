@@ -497,6 +497,16 @@ static hipError_t launch_ring_queue_t(const RingArgs *args, const int2 *items, l
     return hipGetLastError();
 }
 
+// Raises the ring queue kernel's LDS limit on the current device (done at
+// batch creation, so that runs make no runtime calls besides launches).
+hipError_t ring_queue_prepare(int T) {
+    switch (T) {
+        case 256: return allow_dynamic_lds((const void *)k_ring_synth_queue<256>, 160 * 1024);
+        case 512: return allow_dynamic_lds((const void *)k_ring_synth_queue<512>, 160 * 1024);
+        default: return allow_dynamic_lds((const void *)k_ring_synth_queue<1024>, 160 * 1024);
+    }
+}
+
 hipError_t launch_ring_queue(int T, const RingArgs *args, const int2 *items, long long nitems, size_t lds,
                              hipStream_t st) {
     if (nitems < 0 || nitems > 0x7fffffffLL) return hipErrorInvalidValue;

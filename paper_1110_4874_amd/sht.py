@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsht.so")
 
 SHT_OK, SHT_EINVAL, SHT_ENOMEM, SHT_EDEVICE, SHT_ECORRUPT, SHT_EUNSUPPORTED, SHT_EIO = 0, -1, -2, -3, -4, -5, -6
-PATH_AUTO, PATH_BRUTE, PATH_BUTTERFLY = 0, 1, 2
+PATH_AUTO, PATH_BRUTE, PATH_BUTTERFLY, PATH_INTERP = 0, 1, 2, 3
 PREC_FP64, PREC_FP32 = 0, 1
 STAGE_LEGENDRE, STAGE_RING, STAGE_RING_ADJ, STAGE_LEGENDRE_ADJ = 0, 1, 2, 3
 STAGE_BF_RESIDUAL, STAGE_BF_LEVELS, NSTAGES = 4, 5, 6
@@ -32,7 +32,7 @@ class PlanOpts(_c.Structure):
                 ("rings_per_lane", _c.c_int), ("ring_threads", _c.c_int), ("host_only", _c.c_int),
                 ("rho", _c.c_double), ("max_levels", _c.c_int), ("chunk", _c.c_int),
                 ("id_safety", _c.c_double), ("store_fp32", _c.c_int), ("batch_mib", _c.c_int),
-                ("store_transpose", _c.c_int)]
+                ("store_transpose", _c.c_int), ("interp", _c.c_int)]
 
 
 class ExecOpts(_c.Structure):
@@ -51,7 +51,10 @@ class PlanInfo(_c.Structure):
                 ("bf_nodes", _c.c_longlong), ("bf_units", _c.c_longlong), ("bf_res_lanes", _c.c_longlong), ("bf_res_exec", _c.c_longlong),
                 ("bf_depth_hist", _c.c_longlong * 11), ("bf_build_seconds", _c.c_double),
                 ("bf_nbatch", _c.c_int), ("bf_level_T", _c.c_longlong * 11),
-                ("bf_level_units", _c.c_longlong * 11), ("bf_level_nodes", _c.c_longlong * 11)]
+                ("bf_level_units", _c.c_longlong * 11), ("bf_level_nodes", _c.c_longlong * 11),
+                ("ip_built", _c.c_int), ("ip_nodes", _c.c_longlong), ("ip_steps", _c.c_longlong),
+                ("ip_exec", _c.c_longlong), ("ip_build_seconds", _c.c_double),
+                ("ip_direct", _c.c_longlong)]
 
 
 class Request(_c.Structure):
@@ -60,13 +63,20 @@ class Request(_c.Structure):
 
 class BatchOpts(_c.Structure):
     _fields_ = [("stream", _c.c_void_p), ("nstreams", _c.c_int), ("path", _c.c_int), ("precision", _c.c_int),
-                ("workspace", _c.c_void_p), ("workspace_bytes", _c.c_size_t)]
+                ("workspace", _c.c_void_p), ("workspace_bytes", _c.c_size_t), ("rings_per_lane", _c.c_int),
+                ("ring_threads", _c.c_int)]
 
 
 EXPORTS = {
     "sht_batch_opts_default": (None, [_c.POINTER(BatchOpts)]),
     "sht_batch_workspace_bytes": (_c.c_size_t, [_c.POINTER(Request), _c.c_int, _c.POINTER(BatchOpts)]),
     "sht_batch_execute": (_c.c_int, [_c.POINTER(Request), _c.c_int, _c.POINTER(BatchOpts)]),
+    "sht_queue_workspace_bytes": (_c.c_size_t, [_c.POINTER(Request), _c.c_int, _c.POINTER(BatchOpts)]),
+    "sht_batch_create": (_c.c_void_p, [_c.POINTER(Request), _c.c_int, _c.POINTER(BatchOpts)]),
+    "sht_batch_run": (_c.c_int, [_c.c_void_p, _c.c_void_p]),
+    "sht_batch_stats": (_c.c_int, [_c.c_void_p, _c.POINTER(_c.c_longlong), _c.POINTER(_c.c_int),
+                                   _c.POINTER(_c.c_int)]),
+    "sht_batch_free": (None, [_c.c_void_p]),
     "sht_plan_opts_default": (None, [_c.POINTER(PlanOpts)]),
     "sht_exec_opts_default": (None, [_c.POINTER(ExecOpts)]),
     "sht_plan": (_c.c_void_p, [_c.c_int, _c.c_int, _c.c_double]),
@@ -97,6 +107,7 @@ EXPORTS = {
                                            _c.POINTER(_c.c_int), _c.c_void_p, _c.c_void_p]),
     "sht_debug_butterfly_apply": (_c.c_int, [_c.c_void_p, _c.c_int, _c.c_int, _c.c_void_p, _c.c_void_p]),
     "sht_debug_butterfly_depth": (_c.c_int, [_c.c_void_p, _c.c_int, _c.c_int]),
+    "sht_debug_interp_apply": (_c.c_int, [_c.c_void_p, _c.c_int, _c.c_int, _c.c_void_p, _c.c_void_p]),
     "sht_debug_start": (_c.c_int, [_c.c_void_p, _c.c_int, _c.c_int, _c.c_int, _c.POINTER(_c.c_int),
                                    _c.POINTER(_c.c_double)]),
 }
@@ -166,7 +177,7 @@ class Plan:
 
     def __init__(self, L, nside, eps=0.0, *, cutoff=None, dd_sin=None, nthreads=0, rings_per_lane=0,
                  ring_threads=0, host_only=False, rho=0.0, max_levels=-1, chunk=0, id_safety=0.0,
-                 store_fp32=False, batch_mib=0, store_transpose=False):
+                 store_fp32=False, batch_mib=0, store_transpose=False, interp=False):
         lib = load()
         o = PlanOpts()
         lib.sht_plan_opts_default(_c.byref(o))
@@ -177,6 +188,7 @@ class Plan:
         o.store_fp32 = 1 if store_fp32 else 0
         o.batch_mib = int(batch_mib)
         o.store_transpose = 1 if store_transpose else 0
+        o.interp = 1 if interp else 0
         if cutoff is not None:
             o.cutoff = cutoff
         if dd_sin is not None:
@@ -259,6 +271,16 @@ class Plan:
         y = np.zeros(2 * self.nside, dtype=np.float64)
         _check(load().sht_debug_butterfly_apply(self._h, int(m), int(t), x.ctypes.data_as(_c.c_void_p),
                                                 y.ctypes.data_as(_c.c_void_p)))
+        return y
+
+    def interp_apply_host(self, m, t, x):
+        """Host evaluation of q^t_m on the north rings through the plan's
+        interpolation form (private test entry point)."""
+        import numpy as np
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        y = np.zeros(2 * self.nside, dtype=np.float64)
+        _check(load().sht_debug_interp_apply(self._h, int(m), int(t), x.ctypes.data_as(_c.c_void_p),
+                                             y.ctypes.data_as(_c.c_void_p)))
         return y
 
     def butterfly_depth(self, m, t):
@@ -494,6 +516,70 @@ class Batch:
     def run(self, stream=None):
         self._opts.stream = _stream_handle(stream)
         _check(load().sht_batch_execute(self._reqs, self.n, _c.byref(self._opts)))
+
+
+class QueueBatch:
+    """A fixed list of synthesis requests (plan, alm, out) prepared once as a
+    work-queue batch (sht_batch_create): each run() is one persistent
+    Legendre launch plus one ring launch per ring size class on the brute
+    force path; on the butterfly path one launch per butterfly stage and
+    map-group width over every request, then the ring launches.  Nothing is
+    allocated in run(); runs can be captured into a graph.
+    The inputs, outputs and the workspace held here must stay alive and must
+    not be reused while the batch exists."""
+
+    def __init__(self, requests, *, path=None, precision=None, rings_per_lane=0, ring_threads=0):
+        lib = load()
+        path = PATH_BRUTE if path is None else path
+        precision = PREC_FP64 if precision is None else precision
+        self.items = []
+        for plan, alm, out in requests:
+            a = plan._alm_arg(alm)
+            if out.dtype != torch.float64 or not out.is_cuda or not out.is_contiguous():
+                raise TypeError("out must be a contiguous float64 CUDA tensor")
+            if out.numel() != a.shape[1] * plan.npix:
+                raise ValueError("out has the wrong size")
+            self.items.append((plan, a, out))
+        n = len(self.items)
+        self._reqs = (Request * max(n, 1))()
+        for i, (plan, a, out) in enumerate(self.items):
+            self._reqs[i].plan = plan._h
+            self._reqs[i].nmaps = a.shape[1]
+            self._reqs[i].alm = _c.c_void_p(a.data_ptr())
+            self._reqs[i].map = _c.c_void_p(out.data_ptr())
+        o = BatchOpts()
+        lib.sht_batch_opts_default(_c.byref(o))
+        o.path, o.precision = int(path), int(precision)
+        o.rings_per_lane, o.ring_threads = int(rings_per_lane), int(ring_threads)
+        nb = int(lib.sht_queue_workspace_bytes(self._reqs, n, _c.byref(o)))
+        if nb == 0:
+            raise ShtError(lib.sht_last_status(), lib.sht_last_error().decode())
+        self.workspace = torch.empty(nb, dtype=torch.uint8, device=self.items[0][1].device)
+        o.workspace = _c.c_void_p(self.workspace.data_ptr())
+        o.workspace_bytes = nb
+        h = lib.sht_batch_create(self._reqs, n, _c.byref(o))
+        if not h:
+            raise ShtError(lib.sht_last_status(), lib.sht_last_error().decode())
+        self._h = _c.c_void_p(h)
+
+    def run(self, stream=None):
+        _check(load().sht_batch_run(self._h, _stream_handle(stream)))
+
+    def stats(self):
+        items, launches, waves = _c.c_longlong(0), _c.c_int(0), _c.c_int(0)
+        _check(load().sht_batch_stats(self._h, _c.byref(items), _c.byref(launches), _c.byref(waves)))
+        return {"items": items.value, "launches": launches.value, "waves": waves.value}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().sht_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class _Synthesis(torch.autograd.Function):

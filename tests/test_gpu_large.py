@@ -141,11 +141,25 @@ def test_mixed_queue_against_oracle(gpu):
         reqs.append((plans[(L, N)], torch.from_numpy(alm).cuda(), out))
     say(f"queue: {len(reqs)} requests, {sum(r[1].shape[1] for r in reqs)} maps, "
         f"depths {({L: p.info()['bf_depth_hist'][:4] for (L, _), p in plans.items()})}")
-    bars = {"brute": 1e-12, "bf64": EPS + 1e-12, "bf32": FP32_BAR}
+    bars = {"brute": 1e-12, "queue": 1e-12, "bf64": EPS + 1e-12, "bf32": FP32_BAR, "queue bf64": EPS + 1e-12,
+            "queue bf32": FP32_BAR}
     for name, path, prec in (("brute", sht.PATH_BRUTE, sht.PREC_FP64),
+                             ("queue", sht.PATH_BRUTE, sht.PREC_FP64),
                              ("bf64", sht.PATH_BUTTERFLY, sht.PREC_FP64),
-                             ("bf32", sht.PATH_BUTTERFLY, sht.PREC_FP32)):
-        sht.Batch(reqs, path=path, precision=prec).run()
+                             ("bf32", sht.PATH_BUTTERFLY, sht.PREC_FP32),
+                             ("queue bf64", sht.PATH_BUTTERFLY, sht.PREC_FP64),
+                             ("queue bf32", sht.PATH_BUTTERFLY, sht.PREC_FP32)):
+        for _, _, out in reqs:
+            out.fill_(float("nan"))
+        if name.startswith("queue"):
+            # the work-queue form: one persistent Legendre launch (brute
+            # force) or one launch per butterfly stage and pass width
+            qb = sht.QueueBatch(reqs, path=path, precision=prec)
+            qb.run()
+            torch.cuda.synchronize()
+            qb.close()
+        else:
+            sht.Batch(reqs, path=path, precision=prec).run()
         torch.cuda.synchronize()
         worst = (0.0, 0.0)
         for (plan, _, out), (rings, ref) in zip(reqs, refs):
