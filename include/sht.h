@@ -197,6 +197,9 @@ typedef struct sht_plan_info {
     long long ip_direct;      /* (order, parity, ring) values evaluated at the
                                  ring itself: rings closer to a node than the
                                  nodes' long-double precision allows for */
+    int pol_rings;            /* north rings (each with its south mirror) where the
+                                 polarized synthesis evaluates the spin-2
+                                 functions directly */
 } sht_plan_info_t;
 
 void sht_plan_opts_default(sht_plan_opts *o);
@@ -272,6 +275,33 @@ size_t sht_workspace_bytes(const sht_plan_t *plan, const sht_exec_opts *x);
 int sht_synthesis(const sht_plan_t *plan, const double *alm, double *map);
 int sht_synthesis_ex(const sht_plan_t *plan, const sht_exec_opts *x,
                      const double *alm, double *map);
+
+/* Polarized (spin-2) synthesis: Q and U maps from E- and B-mode
+ * coefficients.  The Discussion of the paper notes that the transform of a
+ * polarized map reduces to three scalar transforms (per mode), which also
+ * amortises the streaming of the plan's data; here the three coefficient
+ * sets of E and of B (the spin-2 functions written through the scalar
+ * P~_l^m, P~_{l+-1}^m by two spin raisings) run as 6 x->nmaps maps through
+ * one scalar Legendre phase of the chosen path, are combined per ring and
+ * order into Q_m, U_m, and go through the scalar ring stage.  On the rings
+ * nearest the poles (sin(theta) < 0.1 sqrt((L+1)/4096)), where the
+ * combination would divide by sin^2(theta), the spin-2 functions are
+ * evaluated by their own recurrence in double-double arithmetic instead.
+ * Convention: a_{+-2,lm} = -(E_lm +- i B_lm), Q +- iU = sum a_{+-2,lm}
+ * _{+-2}Y_lm with the spin-weighted harmonics of Goldberg et al. (1967)
+ * (Condon-Shortley phase, as the scalar P~).
+ * E, B: x->nmaps maps each in the alm layout of band limit L - 1 (a plan for
+ * L serves polarized maps up to L - 1; Im of the m = 0 entries is ignored),
+ * device memory, not modified.  QU: 2 x->nmaps maps of Npix doubles, Q of
+ * map b at row b and U at row nmaps + b.  Workspace (x->workspace, or
+ * allocated stream-ordered when NULL): sht_pol_workspace_bytes() of the
+ * same options (0 for FP32 options).  FP64 only: SHT_EUNSUPPORTED for
+ * x->precision = SHT_PREC_FP32, since the combination's division by
+ * sin^2(theta) would magnify the FP32 products' error.  Returns SHT_EINVAL
+ * for L < 1 or bad pointers and the errors of sht_synthesis_ex. */
+size_t sht_pol_workspace_bytes(const sht_plan_t *plan, const sht_exec_opts *x);
+int sht_pol_synthesis(const sht_plan_t *plan, const sht_exec_opts *x, const double *E, const double *B,
+                      double *QU);
 
 /* Synthesis that allocates nothing, for callers that cannot allocate device
  * memory: code under HIP graph capture, tight serving loops, harnesses that
@@ -445,6 +475,10 @@ int sht_debug_butterfly_apply(const sht_plan_t *plan, int m, int t, const double
  * x of length n_t = (L - m - t)/2 + 1 (real).  y: n_north doubles.  Needs a
  * plan built with opts.interp = 1 (host_only plans included). */
 int sht_debug_interp_apply(const sht_plan_t *plan, int m, int t, const double *x, double *y);
+/* Test entry point: _s lambda_lm (s = +-2) at polar ring k (0 <= k <
+ * pol_rings, ring k+1 of the RING scheme) by the host form of the polarized
+ * synthesis' polar recurrence; out[l - m], l = m .. L - 1. */
+int sht_debug_pol_column(const sht_plan_t *plan, int m, int s, int k, double *out);
 
 /* Depth kept for (m, t) of an eps > 0 plan, or -1. */
 int sht_debug_butterfly_depth(const sht_plan_t *plan, int m, int t);

@@ -63,6 +63,11 @@ def lib():
         L.oracle_adjoint.argtypes = [_i, _l, _i, _pd, _i, _pd]
         for fn in (L.oracle_adjoint_msel, L.oracle_adjoint_msel_ld):
             fn.argtypes = [_i, _l, _i, _pd, _i, _i, ctypes.POINTER(_i), _pd]
+        L.oracle_spin_z.argtypes = [_i, _i, _i, _d, _d, _pd]
+        L.oracle_spin_z_ld.argtypes = [_i, _i, _i, _d, _d, _pd]
+        L.oracle_spin_ring_ld.argtypes = [_i, _i, _i, _l, _l, _pd]
+        for fn in (L.oracle_pol_synthesis_rings_d, L.oracle_pol_synthesis_rings_ld):
+            fn.argtypes = [_i, _l, _i, _pd, _pd, _i, _pl, _pd, _pd]
         L.oracle_num_threads.restype = _i
         _lib = L
     return _lib
@@ -186,6 +191,45 @@ def adjoint_msel(L, nside, maps, ms, conv: int = 0, ld: bool = False) -> np.ndar
                               ms.ctypes.data_as(ctypes.POINTER(_i)),
                               _ptr(out.view(np.float64)))
     return out
+
+
+def spin_z(L: int, m: int, s: int, z: float, sth: float, ld: bool = False) -> np.ndarray:
+    """Spin-weighted _s lambda_lm(theta), l = m..L (zero for l < max(m, |s|))."""
+    out = np.zeros(L - m + 1)
+    fn = lib().oracle_spin_z_ld if ld else lib().oracle_spin_z
+    fn(L, m, s, z, sth, _ptr(out))
+    return out
+
+
+def spin_ring(L: int, m: int, s: int, nside: int, ring: int) -> np.ndarray:
+    """Long-double _s lambda_lm at ring 1..4N-1 (exact ring geometry), l = m..L."""
+    out = np.zeros(L - m + 1)
+    lib().oracle_spin_ring_ld(L, m, s, nside, ring, _ptr(out))
+    return out
+
+
+def pol_synthesis_rings(L, nside, E, B, rings, ld=False):
+    """Polarized synthesis (Q, U) from E and B modes on the listed rings:
+    two lists (per ring) of (nmaps, J) arrays.  a_{+-2,lm} = -(E_lm +- i B_lm),
+    Q +- iU = sum a_{+-2,lm} _{+-2}Y_lm (spin-weighted harmonics of Goldberg
+    et al. 1967, Condon-Shortley phase)."""
+    E, B = _alm_in(E), _alm_in(B)
+    if E.shape != B.shape:
+        raise ValueError("E and B must have the same shape")
+    nm = E.shape[1]
+    rings = np.ascontiguousarray(rings, dtype=np.int64)
+    Js = [ring_info(nside, int(r))[2] for r in rings]
+    oq = np.zeros((nm, int(sum(Js))))
+    ou = np.zeros((nm, int(sum(Js))))
+    fn = lib().oracle_pol_synthesis_rings_ld if ld else lib().oracle_pol_synthesis_rings_d
+    fn(L, nside, nm, _ptr(E.view(np.float64)), _ptr(B.view(np.float64)), len(rings),
+       rings.ctypes.data_as(_pl), _ptr(oq), _ptr(ou))
+    rq, ru, o = [], [], 0
+    for J in Js:
+        rq.append(oq[:, o:o + J].copy())
+        ru.append(ou[:, o:o + J].copy())
+        o += J
+    return rq, ru
 
 
 def analysis(L, nside, maps, iterations: int = 0) -> np.ndarray:

@@ -515,3 +515,82 @@ void oracle_adjoint_msel_ld(int L, long nside, int B, const double *map, int con
 
 /* Threads the OpenMP runtime will use (reported by the CPU baseline). */
 int oracle_num_threads(void) { return omp_get_max_threads(); }
+
+/* ================================================================== */
+/* Polarization (spin 2)                                               */
+/* ================================================================== */
+
+/* _s lambda_lm at (z, sin theta): out[l-m], l = m..L (spin_column). */
+void oracle_spin_z(int L, int m, int s, double z, double sth, double *out)
+{
+    spin_column_d(L, m, s, z, sth, out);
+}
+
+void oracle_spin_z_ld(int L, int m, int s, double z, double sth, double *out)
+{
+    long double *col = malloc(sizeof(long double) * (L - m + 1));
+    spin_column_ld(L, m, s, (long double)z, (long double)sth, col);
+    for (int l = m; l <= L; l++) out[l - m] = (double)col[l - m];
+    free(col);
+}
+
+/* Long-double _s lambda_lm at a ring (exact ring geometry), rounded once. */
+void oracle_spin_ring_ld(int L, int m, int s, long nside, long ring, double *out)
+{
+    long double z, sth;
+    long J, sh;
+    long long off;
+    ring_geom_ld(nside, ring, &z, &sth, &J, &sh, &off);
+    long double *col = malloc(sizeof(long double) * (L - m + 1));
+    spin_column_ld(L, m, s, z, sth, col);
+    for (int l = m; l <= L; l++) out[l - m] = (double)col[l - m];
+    free(col);
+}
+
+/* Q and U on the listed rings from E and B (band limit L, [nalm][B]
+   complex each): outQ, outU [B][sum J], rings concatenated in order. */
+#define POL_RINGS(SUF, RT)                                                                  \
+    void oracle_pol_synthesis_rings##SUF(int L, long nside, int B, const double *E,         \
+                                         const double *Bm, int nr, const long *rings,       \
+                                         double *outQ, double *outU)                        \
+    {                                                                                       \
+        long long *base = malloc(sizeof(long long) * (nr + 1));                             \
+        base[0] = 0;                                                                        \
+        for (int r = 0; r < nr; r++) {                                                      \
+            double z, sth;                                                                  \
+            long J, s;                                                                      \
+            long long off;                                                                  \
+            ring_geom_d(nside, rings[r], &z, &sth, &J, &s, &off);                           \
+            base[r + 1] = base[r] + J;                                                      \
+        }                                                                                   \
+        long long tot = base[nr];                                                           \
+        _Pragma("omp parallel")                                                             \
+        {                                                                                   \
+            RT *cp = malloc(sizeof(RT) * (L + 1));                                          \
+            RT *cm = malloc(sizeof(RT) * (L + 1));                                          \
+            RT *qQ = malloc(sizeof(RT) * 2 * (L + 1) * B);                                  \
+            RT *qU = malloc(sizeof(RT) * 2 * (L + 1) * B);                                  \
+            RT *cs = malloc(sizeof(RT) * 8 * nside);                                        \
+            RT *sn = malloc(sizeof(RT) * 8 * nside);                                        \
+            RT *f = malloc(sizeof(RT) * 4 * nside * B);                                     \
+            _Pragma("omp for schedule(dynamic, 1)")                                         \
+            for (int r = 0; r < nr; r++) {                                                  \
+                RT z, sth;                                                                  \
+                long J, s;                                                                  \
+                long long off;                                                              \
+                ring_geom##SUF(nside, rings[r], &z, &sth, &J, &s, &off);                    \
+                ring_phase_pol##SUF(L, z, sth, B, E, Bm, qQ, qU, cp, cm);                   \
+                ring_dft##SUF(L, J, s, B, qQ, f, cs, sn);                                   \
+                for (int b = 0; b < B; b++)                                                 \
+                    for (long j = 0; j < J; j++) outQ[b * tot + base[r] + j] = (double)f[b * J + j]; \
+                ring_dft##SUF(L, J, s, B, qU, f, cs, sn);                                   \
+                for (int b = 0; b < B; b++)                                                 \
+                    for (long j = 0; j < J; j++) outU[b * tot + base[r] + j] = (double)f[b * J + j]; \
+            }                                                                               \
+            free(cp); free(cm); free(qQ); free(qU); free(cs); free(sn); free(f);            \
+        }                                                                                   \
+        free(base);                                                                         \
+    }
+POL_RINGS(_d, double)
+POL_RINGS(_ld, long double)
+#undef POL_RINGS

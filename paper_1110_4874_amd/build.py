@@ -21,8 +21,8 @@ LIB = os.path.join(HERE, "libsht.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 HIP_SOURCES = ["legendre.hip", "ring.hip", "adjoint.hip", "butterfly.hip", "butterfly_adjoint.hip",
-               "analysis.hip", "noalloc.hip", "interp.hip"]
-CXX_SOURCES = ["plan.cpp", "plan_io.cpp", "interp_plan.cpp", "api.cpp", "butterfly_plan.cpp", "batch.cpp", "queue.cpp"]
+               "analysis.hip", "noalloc.hip", "interp.hip", "pol.hip"]
+CXX_SOURCES = ["plan.cpp", "plan_io.cpp", "interp_plan.cpp", "api.cpp", "butterfly_plan.cpp", "batch.cpp", "queue.cpp", "pol_plan.cpp"]
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 HIP_FLAGS = ["-x", "hip", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
              "-packed-fp32-ops", "-munsafe-fp-atomics"]

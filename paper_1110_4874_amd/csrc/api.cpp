@@ -150,13 +150,12 @@ size_t synth_ws_bytes_impl(const sht_plan_s *p, int nmaps, int path, int precisi
     return b;
 }
 
-// Legendre phase and ring stage of one synthesis on stream st; ws holds
-// synth_ws_bytes_impl() bytes.  Events of x (if any) bracket the stages.
-static int synth_stages(const sht_plan_s *p, int B, int path, int precision, const double *alm, double *map,
-                        void *ws, hipStream_t st, const sht_exec_opts *x) {
+// Legendre phase of one synthesis on stream st into q = ws (the first
+// q_bytes of the synth_ws_bytes_impl() bytes of ws).
+static int legendre_stage(const sht_plan_s *p, int B, int path, int precision, const double *alm, void *ws,
+                          hipStream_t st, const sht_exec_opts *x) {
     int rc;
     double *q = (double *)ws;
-    if (x) stage_event(x, SHT_STAGE_LEGENDRE, 0);
     if (use_ip(p, path)) {
         void *scr = (char *)ws + q_bytes(p, B);
         if ((rc = hip_status(launch_interp(p, B, alm, q, scr, st), "interpolation kernel launch"))) return rc;
@@ -169,6 +168,17 @@ static int synth_stages(const sht_plan_s *p, int B, int path, int precision, con
     } else if ((rc = hip_status(launch_legendre(p, B, alm, q, st), "Legendre kernel launch"))) {
         return rc;
     }
+    return SHT_OK;
+}
+
+// Legendre phase and ring stage of one synthesis on stream st; ws holds
+// synth_ws_bytes_impl() bytes.  Events of x (if any) bracket the stages.
+static int synth_stages(const sht_plan_s *p, int B, int path, int precision, const double *alm, double *map,
+                        void *ws, hipStream_t st, const sht_exec_opts *x) {
+    int rc;
+    double *q = (double *)ws;
+    if (x) stage_event(x, SHT_STAGE_LEGENDRE, 0);
+    if ((rc = legendre_stage(p, B, path, precision, alm, ws, st, x))) return rc;
     if (x) stage_event(x, SHT_STAGE_LEGENDRE, 1);
     if (x) stage_event(x, SHT_STAGE_RING, 0);
     rc = hip_status(launch_ring_synthesis(p, B, q, map, st), "ring kernel launch");
@@ -179,6 +189,13 @@ static int synth_stages(const sht_plan_s *p, int B, int path, int precision, con
 int synth_launch(const sht_plan_s *p, int nmaps, int path, int precision, const double *alm, double *map,
                  void *ws, hipStream_t st) {
     return synth_stages(p, nmaps, path, precision, alm, map, ws, st, nullptr);
+}
+
+// Polarized synthesis workspace: the six coefficient sets per map, the
+// scalar synthesis workspace of 6 nmaps maps (its Legendre phase first), and
+// the Q/U Legendre phase of 2 nmaps maps.
+size_t pol_ws_bytes_impl(const sht_plan_s *p, int nmaps, int path, int precision) {
+    return pol_alm_bytes(p, nmaps) + synth_ws_bytes_impl(p, 6 * nmaps, path, precision) + q_bytes(p, 2 * nmaps);
 }
 }  // namespace sht
 
@@ -351,6 +368,7 @@ int sht_plan_info(const sht_plan_t *p, sht_plan_info_t *out) {
     out->ip_exec = p->ip.exec;
     out->ip_build_seconds = p->ip.build_seconds;
     out->ip_direct = p->ip.direct;
+    out->pol_rings = p->pol_n;
     return SHT_OK;
 }
 
@@ -377,6 +395,44 @@ int sht_synthesis_ex(const sht_plan_t *p, const sht_exec_opts *x, const double *
     Scratch ws;
     if ((rc = ws.get(x, synth_ws_bytes(p, x), p->device))) return rc;
     return synth_stages(p, B, x->path, x->precision, alm, map, ws.ptr, (hipStream_t)x->stream, x);
+}
+
+size_t sht_pol_workspace_bytes(const sht_plan_t *p, const sht_exec_opts *x) {
+    if (check_plan(p) || check_exec(p, x) || x->precision != SHT_PREC_FP64) return 0;
+    return pol_ws_bytes_impl(p, x->nmaps, x->path, x->precision);
+}
+
+int sht_pol_synthesis(const sht_plan_t *p, const sht_exec_opts *x, const double *E, const double *B, double *QU) {
+    int rc = check_plan(p);
+    if (!rc) rc = check_exec(p, x);
+    if (rc) return rc;
+    if (p->L < 1) return fail(SHT_EINVAL, "polarized synthesis needs a plan with L >= 1 (band limit L - 1)");
+    if (x->precision != SHT_PREC_FP64)
+        return fail(SHT_EUNSUPPORTED, "polarized synthesis runs in FP64 (its combination divides by sin^2(theta))");
+    DeviceGuard g(p->device);
+    if (!g.ok) return fail(SHT_EDEVICE, "cannot select the plan's device");
+    const int n = x->nmaps;
+    if ((rc = check_dev_ptr(E, nalm_of(p->L - 1) * n * 16, p->device, "E"))) return rc;
+    if ((rc = check_dev_ptr(B, nalm_of(p->L - 1) * n * 16, p->device, "B"))) return rc;
+    if ((rc = check_dev_ptr(QU, npix_of(p->nside) * 2 * n * 8, p->device, "QU"))) return rc;
+    Scratch ws;
+    if ((rc = ws.get(x, pol_ws_bytes_impl(p, n, x->path, x->precision), p->device))) return rc;
+    hipStream_t st = (hipStream_t)x->stream;
+    char *base = (char *)ws.ptr;
+    double *alm6 = (double *)base;
+    void *sws = base + pol_alm_bytes(p, n);
+    double *q6 = (double *)sws;
+    double *q2 = (double *)((char *)sws + synth_ws_bytes_impl(p, 6 * n, x->path, x->precision));
+    stage_event(x, SHT_STAGE_LEGENDRE, 0);
+    if ((rc = hip_status(launch_pol_prep(p, n, E, B, alm6, st), "polarization coefficient launch"))) return rc;
+    if ((rc = legendre_stage(p, 6 * n, x->path, x->precision, alm6, sws, st, nullptr))) return rc;
+    if ((rc = hip_status(launch_pol_combine(p, n, q6, q2, st), "spin-2 combination launch"))) return rc;
+    if ((rc = hip_status(launch_pol_polar(p, n, E, B, q2, st), "polar spin-2 launch"))) return rc;
+    stage_event(x, SHT_STAGE_LEGENDRE, 1);
+    stage_event(x, SHT_STAGE_RING, 0);
+    rc = hip_status(launch_ring_synthesis(p, 2 * n, q2, QU, st), "ring kernel launch");
+    stage_event(x, SHT_STAGE_RING, 1);
+    return rc;
 }
 
 size_t sht_noalloc_scratch_bytes(void) { return kNoAllocScratchBytes; }
@@ -535,6 +591,13 @@ int sht_debug_interp_apply(const sht_plan_t *p, int m, int t, const double *x, d
     if (!p || !x || !y || m < 0 || m > p->L || t < 0 || t > 1) return fail(SHT_EINVAL, "bad argument");
     if (!p->ip.built) return fail(SHT_EUNSUPPORTED, "plan has no interpolation form (interp = 0)");
     return interp_apply_host(p, m, t, x, y);
+}
+
+int sht_debug_pol_column(const sht_plan_t *p, int m, int s, int k, double *out) {
+    if (!p || !out) return fail(SHT_EINVAL, "bad argument");
+    if (pol_column_host(p, m, s, k, out) != SHT_OK)
+        return fail(SHT_EINVAL, "m must be in [0, L-1], s = +-2 and k a polar ring below sht_plan_info().pol_rings");
+    return SHT_OK;
 }
 
 int sht_debug_butterfly_depth(const sht_plan_t *p, int m, int t) {

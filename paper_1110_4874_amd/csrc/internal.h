@@ -156,6 +156,16 @@ struct sht_plan_s {
     std::vector<long long> ring_chirp_off;     // [nrings] offset (complex entries) into chirp
     std::vector<sht::RingClass> classes;
 
+    // polarized synthesis near the poles: north rings [0, pol_n) (and their
+    // mirrors) whose sin(theta) is below the threshold where the reduction
+    // to scalar transforms loses accuracy; per ring z, sin(theta/2),
+    // cos(theta/2) as double-double pairs; per (m, s = +2, -2) the value of
+    // _s lambda at l0 = max(m, 2) without its powers of sin and cos(theta/2),
+    // as a double-double mantissa times 2^exp (sign included)
+    int pol_n = 0;
+    std::vector<double> pol_ring;              // [pol_n][6]
+    std::vector<double> pol_K;                 // [(L+1)*2][4] hi, lo, exp, 0
+
     // ---- device copies ------------------------------------------------
     double *d_z2_hi = nullptr, *d_z2_lo = nullptr;
     int *d_ring_J = nullptr, *d_ring_s = nullptr, *d_ring_M = nullptr;
@@ -166,6 +176,7 @@ struct sht_plan_s {
     int *d_grp_lo = nullptr, *d_grp_hi = nullptr;
     double *d_tw = nullptr, *d_bs_table = nullptr, *d_chirp = nullptr;
     long long *d_ring_chirp_off = nullptr;
+    double *d_pol_ring = nullptr, *d_pol_K = nullptr;
     size_t device_bytes = 0;
 
     // ---- butterfly (eps > 0) ------------------------------------------
@@ -247,6 +258,15 @@ struct RingArgs {
 int build_host_tables(sht_plan_s *p);
 int build_butterfly(sht_plan_s *p, const BflyInput &in);
 int build_interp(sht_plan_s *p, const BflyInput &in);
+int build_pol_tables(sht_plan_s *p);
+int pol_column_host(const sht_plan_s *p, int m, int s, int k, double *out);
+// polarized synthesis (pol.hip)
+size_t pol_alm_bytes(const sht_plan_s *p, int nmaps);
+hipError_t launch_pol_prep(const sht_plan_s *p, int nmaps, const double *E, const double *B, double *alm6,
+                           hipStream_t st);
+hipError_t launch_pol_combine(const sht_plan_s *p, int nmaps, const double *q6, double *q2, hipStream_t st);
+hipError_t launch_pol_polar(const sht_plan_s *p, int nmaps, const double *E, const double *B, double *q2,
+                            hipStream_t st);
 int interp_apply_host(const sht_plan_s *p, int m, int t, const double *x, double *y);
 int butterfly_apply_host(const sht_plan_s *p, int m, int t, const double *x, double *y);
 int upload_tables(sht_plan_s *p);

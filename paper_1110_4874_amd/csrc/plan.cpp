@@ -373,6 +373,8 @@ int build_host_tables(sht_plan_s *p) {
     p->n_dd_rings = ndd;
     p->n_dd_groups = (ndd + kLanes - 1) / kLanes;
     p->n_dd_pad = p->n_dd_groups * kLanes;
+    // polarized synthesis near the poles
+    if (int rcp = build_pol_tables(p)) return rcp;
 
     // recurrence coefficients
     p->coef_off.resize(L + 2);
@@ -531,6 +533,8 @@ int upload_tables(sht_plan_s *p) {
     UP(d_bs_table, bs_table);
     UP(d_chirp, chirp);
     UP(d_ring_chirp_off, ring_chirp_off);
+    UP(d_pol_ring, pol_ring);
+    UP(d_pol_K, pol_K);
 #undef UP
     for (auto &rc : p->classes)
         if (e == hipSuccess) e = up(&rc.d_rings, rc.rings, &b);
@@ -602,6 +606,7 @@ void free_device_tables(sht_plan_s *p) {
                     p->d_ring_off,  p->d_ring_bs_off, p->d_coef_off, p->d_coef_hi,  p->d_coef_lo,
                     p->d_start_idx, p->d_start_val, p->d_start_lo,   p->d_grp_lo,   p->d_grp_hi,
                     p->d_tw,        p->d_bs_table,  p->d_chirp,      p->d_ring_chirp_off,
+                    p->d_pol_ring,  p->d_pol_K,
                     p->d_bf_res_task, p->d_bf_res_lane, p->d_bf_res_sub,
                     p->d_bf_res_val, p->d_bf_T,      p->d_bf_T32,   p->d_bf_Tt,    p->d_bf_Tt32, p->d_bf_perm,
                     p->d_bf_node_i, p->d_bf_f1_unit, p->d_bf_l1_plain, p->d_bf_fold_slot,
@@ -622,6 +627,7 @@ void free_device_tables(sht_plan_s *p) {
     p->d_grp_lo = p->d_grp_hi = nullptr;
     p->d_tw = p->d_bs_table = p->d_chirp = nullptr;
     p->d_ring_chirp_off = nullptr;
+    p->d_pol_ring = p->d_pol_K = nullptr;
     p->d_bf_res_task = p->d_bf_res_lane = p->d_bf_res_sub = nullptr;
     p->d_bf_res_val = p->d_bf_T = nullptr;
     p->d_bf_T32 = nullptr;

@@ -39,7 +39,7 @@ namespace {
 using namespace sht;
 
 constexpr char kMagic[8] = {'W', 'M', 'H', 'I', 'P', 'P', 'L', 'N'};
-constexpr uint32_t kFileVersion = 5;
+constexpr uint32_t kFileVersion = 6;
 constexpr size_t kHashBlock = (size_t)16 << 20;
 
 struct FileHeader {
@@ -236,6 +236,9 @@ void visit(A &ar, sht_plan_s *p, std::vector<double> &T) {
     ar.vec(p->bs_table);
     ar.vec(p->chirp);
     ar.vec(p->ring_chirp_off);
+    ar.scalar(p->pol_n);
+    ar.vec(p->pol_ring);
+    ar.vec(p->pol_K);
     uint64_t ncls = p->classes.size();
     ar.scalar(ncls);
     if (!ar.ok() || ncls > 64) return;
@@ -337,6 +340,9 @@ bool consistent(const sht_plan_s *p) {
     for (const auto &c : p->classes)
         for (int r : c.rings)
             if (r < 0 || r >= p->nrings) return false;
+    if (p->pol_n < 0 || p->pol_n > p->n_north || p->pol_ring.size() != (size_t)p->pol_n * 6 ||
+        p->pol_K.size() != (L + 1) * 8)
+        return false;
     const InterpPlan &ip = p->ip;
     if (ip.built) {
         if (ip.node_off.size() != (L + 1) * 2 + 1 || (long long)ip.x_hi.size() != ip.nodes) return false;

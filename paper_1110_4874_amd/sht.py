@@ -54,7 +54,7 @@ class PlanInfo(_c.Structure):
                 ("bf_level_units", _c.c_longlong * 11), ("bf_level_nodes", _c.c_longlong * 11),
                 ("ip_built", _c.c_int), ("ip_nodes", _c.c_longlong), ("ip_steps", _c.c_longlong),
                 ("ip_exec", _c.c_longlong), ("ip_build_seconds", _c.c_double),
-                ("ip_direct", _c.c_longlong)]
+                ("ip_direct", _c.c_longlong), ("pol_rings", _c.c_int)]
 
 
 class Request(_c.Structure):
@@ -108,6 +108,9 @@ EXPORTS = {
     "sht_debug_butterfly_apply": (_c.c_int, [_c.c_void_p, _c.c_int, _c.c_int, _c.c_void_p, _c.c_void_p]),
     "sht_debug_butterfly_depth": (_c.c_int, [_c.c_void_p, _c.c_int, _c.c_int]),
     "sht_debug_interp_apply": (_c.c_int, [_c.c_void_p, _c.c_int, _c.c_int, _c.c_void_p, _c.c_void_p]),
+    "sht_pol_workspace_bytes": (_c.c_size_t, [_c.c_void_p, _c.POINTER(ExecOpts)]),
+    "sht_pol_synthesis": (_c.c_int, [_c.c_void_p, _c.POINTER(ExecOpts), _c.c_void_p, _c.c_void_p, _c.c_void_p]),
+    "sht_debug_pol_column": (_c.c_int, [_c.c_void_p, _c.c_int, _c.c_int, _c.c_int, _c.c_void_p]),
     "sht_debug_start": (_c.c_int, [_c.c_void_p, _c.c_int, _c.c_int, _c.c_int, _c.POINTER(_c.c_int),
                                    _c.POINTER(_c.c_double)]),
 }
@@ -283,6 +286,14 @@ class Plan:
                                              y.ctypes.data_as(_c.c_void_p)))
         return y
 
+    def pol_column_host(self, m, s, k):
+        """_s lambda_lm, l = m .. L-1, at polar ring k by the host form of the
+        polarized synthesis' polar recurrence (private test entry point)."""
+        import numpy as np
+        y = np.zeros(self.L - m, dtype=np.float64)
+        _check(load().sht_debug_pol_column(self._h, int(m), int(s), int(k), y.ctypes.data_as(_c.c_void_p)))
+        return y
+
     def butterfly_depth(self, m, t):
         return int(load().sht_debug_butterfly_depth(self._h, int(m), int(t)))
 
@@ -336,6 +347,39 @@ class Plan:
             x = self._exec(B, path, stream, workspace, events, precision=precision)
             _check(load().sht_synthesis_ex(self._h, _c.byref(x), _c.c_void_p(a.data_ptr()),
                                            _c.c_void_p(out.data_ptr())))
+            return out
+
+    def pol_workspace_bytes(self, nmaps=1, path=PATH_AUTO, precision=PREC_FP64):
+        x = self._exec(nmaps, path=path, precision=precision)
+        return int(load().sht_pol_workspace_bytes(self._h, _c.byref(x)))
+
+    def pol_synthesis(self, E, B, out=None, *, path=PATH_AUTO, stream=None, workspace=None, events=None,
+                      precision=PREC_FP64):
+        """Polarized synthesis: (2, n, Npix) float64 Q and U maps from E and B
+        modes, each (nalm(L-1), n) or (nalm(L-1),) complex128 (band limit
+        L - 1 of this plan)."""
+        with _on(stream):
+            nal = self.L * (self.L + 1) // 2
+            ea, ba = [], []
+            for name, A, acc in (("E", E, ea), ("B", B, ba)):
+                if A.dtype != torch.complex128 or not A.is_cuda:
+                    raise TypeError(f"{name} must be a complex128 CUDA tensor")
+                a = A if A.dim() == 2 else A.reshape(-1, 1)
+                if a.shape[0] != nal:
+                    raise ValueError(f"{name} has {a.shape[0]} rows, expected nalm(L-1) = {nal}")
+                acc.append(a.contiguous())
+            e, b = ea[0], ba[0]
+            if e.shape != b.shape:
+                raise ValueError("E and B must have the same shape")
+            n = e.shape[1]
+            if out is None:
+                out = torch.empty((2, n, self.npix), dtype=torch.float64, device=e.device)
+            if workspace is None:
+                workspace = torch.empty(self.pol_workspace_bytes(n, path, precision), dtype=torch.uint8,
+                                        device=e.device)
+            x = self._exec(n, path, stream, workspace, events, precision=precision)
+            _check(load().sht_pol_synthesis(self._h, _c.byref(x), _c.c_void_p(e.data_ptr()),
+                                            _c.c_void_p(b.data_ptr()), _c.c_void_p(out.data_ptr())))
             return out
 
     def _map_arg(self, maps):
