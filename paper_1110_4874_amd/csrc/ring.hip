@@ -274,6 +274,37 @@ __device__ __forceinline__ void ring_synth_item(const RingArgs &a, const int ite
                 if (k != 0 && n - k <= L) xb[j] = qr[(size_t)(n - k) * qstride];
             }
         }
+    } else if (2 * n > L) {
+        // J > L: bin b <= n collects m = b and, when J - b <= L, m = J - b
+        // (conjugated, sign (-1)^s); direct loads as above, no staging
+        const double sg = (s & 1) ? -1.0 : 1.0;
+        const int J2 = 2 * n;
+#pragma unroll
+        for (int j = 0; j < kPairsPerThread; j++) {
+            const int k = tid + j * T;
+            if (k < npair) {
+                double2 v = qr[(size_t)k * qstride];  // k <= n <= L
+                if (k == 0) v.y = 0.0;
+                if (J2 - k <= L) {
+                    const double2 w = qr[(size_t)(J2 - k) * qstride];
+                    v = make_double2(v.x + sg * w.x, v.y - sg * w.y);
+                }
+                xa[j] = v;
+                if (k != 0) {
+                    const int b = n - k;  // 0 < b < n
+                    double2 u = qr[(size_t)b * qstride];
+                    if (J2 - b <= L) {
+                        const double2 w = qr[(size_t)(J2 - b) * qstride];
+                        u = make_double2(u.x + sg * w.x, u.y - sg * w.y);
+                    }
+                    xb[j] = u;
+                } else {
+                    // bin n: m = n (j = 0) and m = J - n = n (j = 1, conjugated)
+                    const double2 w = qr[(size_t)n * qstride];
+                    xb[j] = make_double2(w.x + sg * w.x, w.y - sg * w.y);
+                }
+            }
+        }
     } else {
         G = npair >= T ? 1 : T / npair;
         for (int m0 = 0; m0 <= L; m0 += a.stage) {
