@@ -414,6 +414,52 @@ def interp_bench(np, torch, sht, args, d_alm, alm, brute):
     return r
 
 
+def pol_bench(np, torch, sht, plan, args):
+    """Polarized synthesis (the Discussion's reduction to scalar transforms)
+    with the headline plan: E and B of band limit L - 1 (seeds 900, 901, the
+    headline spectrum), one polarized map per step = six scalar maps through
+    one Legendre phase plus Q and U through the ring stage; brute force and
+    FP64 butterfly, with the error against the long-double oracle on sampled
+    rings (the polar caps on both sides of the direct-recurrence threshold)."""
+    import oracle
+    from paper_1110_4874_amd.synthetic import alm_gaussian
+    L, N = plan.L, plan.nside
+    E = alm_gaussian(L - 1, [900])
+    B = alm_gaussian(L - 1, [901])
+    dE, dB = torch.from_numpy(E).cuda(), torch.from_numpy(B).cuda()
+    npol = plan.info()["pol_rings"]
+    rings = sorted(set(r for r in [1, 2, npol, npol + 1, N // 2, N, 2 * N, 3 * N, 4 * N - 1 - npol, 4 * N - 1]
+                       if 1 <= r <= 4 * N - 1))
+    t0 = time.perf_counter()
+    rq, ru = oracle.pol_synthesis_rings(L - 1, N, E, B, rings, ld=True)
+    log(f"[bench] polarization oracle (long double) on {len(rings)} rings: {time.perf_counter() - t0:.1f} s")
+    res = {"band_limit": L - 1, "polar_rings": npol, "rings_checked": rings}
+    paths = [("brute", sht.PATH_BRUTE)] + ([("bf64", sht.PATH_BUTTERFLY)] if plan.info()["bf_built"] else [])
+    for name, path in paths:
+        ws = torch.empty(plan.pol_workspace_bytes(1, path), dtype=torch.uint8, device="cuda")
+        out = torch.empty((2, 1, plan.npix), dtype=torch.float64, device="cuda")
+        for _ in range(args.warmup):
+            plan.pol_synthesis(dE, dB, out, path=path, workspace=ws)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        for _ in range(args.steps):
+            plan.pol_synthesis(dE, dB, out, path=path, workspace=ws)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - ts) / args.steps
+        f = out.cpu().numpy()
+        ys = np.concatenate([np.concatenate([f[c][:, oracle.ring_info(N, r)[4]:oracle.ring_info(N, r)[4] +
+                                                   oracle.ring_info(N, r)[2]] for r in rings], axis=1)
+                             for c in (0, 1)], axis=1)
+        xs = np.concatenate([np.concatenate(rq, axis=1), np.concatenate(ru, axis=1)], axis=1)
+        err = float(np.max(np.abs(ys - xs)) / np.max(np.abs(xs)))
+        res[name] = {"pol_maps_per_s": round(1.0 / el, 3), "ms_per_step": round(1e3 * el, 4),
+                     "max_rel_err": err}
+        log(f"[bench] polarization {name}: {1e3 * el:.3f} ms per Q/U map pair, error {err:.2e}")
+        del ws, out
+    torch.cuda.empty_cache()
+    return res
+
+
 def gradient_bench(np, torch, sht, plan, info, paths, d_alm, f_true, ws, ev_sets, args, flops):
     """Forward + backward of the map-fitting loss ||synthesis(a) - d||^2 per path.
 
@@ -545,6 +591,7 @@ def main():
                     help="also time these map counts at the headline size (one pass of up to 64 maps)")
     ap.add_argument("--no-config3", action="store_true", help="skip the 16-map L=2047 measurement")
     ap.add_argument("--no-interp", action="store_true", help="skip the interpolation-form measurement")
+    ap.add_argument("--no-pol", action="store_true", help="skip the polarized-synthesis measurement")
     ap.add_argument("--rings-per-lane", type=int, default=0, help="Legendre kernel tile (1, 2, 4; 0 = plan default)")
     ap.add_argument("--ring-threads", type=int, default=0, help="ring kernel workgroup size (256, 512, 1024; 0 = default)")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -675,6 +722,7 @@ def main():
         line_batch = None
 
     cfg3 = None if args.no_config3 else config3_bench(np, torch, sht, args)
+    pol = None if args.no_pol else pol_bench(np, torch, sht, plan, args)
     ipl = None if args.no_interp else interp_bench(np, torch, sht, args, d_alm, alm, results["brute"])
 
     if args.copy_calibration:
@@ -738,6 +786,8 @@ def main():
         line["L2047_16maps"] = cfg3
     if ipl is not None:
         line["interp"] = ipl
+    if pol is not None:
+        line["polarization"] = pol
 
     if not args.no_cpu_baseline:
         import oracle

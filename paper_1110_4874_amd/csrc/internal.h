@@ -247,7 +247,7 @@ struct RingArgs {
     int L, nrings, nmaps;
     long long npix;
     int fft_entries;  // padded FFT buffer entries of this launch's class
-    int stage;        // q entries staged per chunk for wrapped rings (multiple of the block size)
+    int stage;        // LDS entries past the FFT buffer (wrapped rings' reduction room)
     // adjoint direction: pixel values in, weighted phases ybar out
     const double *__restrict__ map_in;
     double2 *__restrict__ ybar;

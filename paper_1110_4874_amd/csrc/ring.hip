@@ -12,8 +12,11 @@
 // residue classes m = b + jJ and m = jJ - b; all of them share the phase
 // e^{i pi b s/J} up to the sign (-1)^{js}, so each bin needs one sincospi.
 // Rings with J/2 > L (no wrap) load their q values straight into registers,
-// all loads in flight at once; wrapped rings stage q through LDS in chunks
-// and reduce bin sums in a fixed order (deterministic, no atomics).  The
+// all loads in flight at once; so do rings with J > L, whose bins collect
+// at most two orders.  Shorter rings sum the orders of each bin straight
+// from q as well, several threads per bin when the ring has fewer bins than
+// the workgroup has threads, and reduce those partial sums through LDS in a
+// fixed order (deterministic, no atomics).  The
 // half-length DFT runs in LDS with in-place radix-8 passes (radix-4/2 for the
 // remainder): decimation in time on bit-reversed input when n is a power of
 // two.  Otherwise n = 2h (J is a multiple of 4) and the DFT is split into its
@@ -37,7 +40,6 @@
 
 namespace sht {
 
-constexpr int kMaxStage = 2048;     // staged q entries per chunk (at most)
 constexpr int kMaxPairs = 2049;     // Hermitian bin pairs of the largest ring (n = 4096)
 constexpr int kMaxHalf = 2048;      // half length h of the largest Bluestein ring (n = 2h <= 4096)
 
@@ -196,37 +198,26 @@ __device__ __forceinline__ void backward_dft(double2 *buf, int n, int M, const d
     __syncthreads();
 }
 
-// First j >= jlo with j = g (mod G) (32-bit: m < 2^15, J <= 8192).
-__device__ __forceinline__ int first_in_class(int jlo, int g, int G) {
-    if (G == 1) return jlo;
-    int d = (g - jlo) % G;
-    if (d < 0) d += G;
-    return jlo + d;
-}
-
-// Raw wrap sum of bin b (before the common phase) over the q values staged
-// for m in [m0, m0 + cnt), restricted to terms j = g (mod G).
-__device__ __forceinline__ double2 bin_chunk(const double2 *st, int m0, int cnt, int J, int s, int b, int g,
-                                             int G) {
+// Raw wrap sum of bin b (before the common phase) over every order,
+// restricted to terms j = g (mod G): class 1 m = b + jJ (j >= 0), class 2
+// m = jJ - b (j >= 1), read straight from the ring's q column (stride qs).
+__device__ __forceinline__ double2 bin_direct(const double2 *__restrict__ qr, size_t qs, int L, int J, int s, int b,
+                                              int g, int G) {
     double2 acc = make_double2(0.0, 0.0);
-    const int m1 = m0 + cnt;  // exclusive
-    // class 1: m = b + jJ, j >= 0
-    const int jlo = m0 - b <= 0 ? 0 : (m0 - b + J - 1) / J;
-    for (int j = first_in_class(jlo, g, G);; j += G) {
+#pragma unroll 4
+    for (int j = g;; j += G) {
         const int m = b + j * J;
-        if (m >= m1) break;
-        double2 v = st[m - m0];
-        if (m == 0) v = make_double2(v.x, 0.0);  // real part of q_0 only
+        if (m > L) break;
+        double2 v = qr[(size_t)m * qs];
+        if (m == 0) v.y = 0.0;  // real part of q_0 only
         if (s & j & 1) v = make_double2(-v.x, -v.y);
         acc = cadd(acc, v);
     }
-    // class 2: m = jJ - b, j >= 1
-    int jlo2 = (m0 + b + J - 1) / J;
-    if (jlo2 < 1) jlo2 = 1;
-    for (int j = first_in_class(jlo2, g, G);; j += G) {
+#pragma unroll 4
+    for (int j = g == 0 ? G : g;; j += G) {
         const int m = j * J - b;
-        if (m >= m1) break;
-        double2 v = cconj(st[m - m0]);
+        if (m > L) break;
+        double2 v = cconj(qr[(size_t)m * qs]);
         if (s & j & 1) v = make_double2(-v.x, -v.y);
         acc = cadd(acc, v);
     }
@@ -238,7 +229,6 @@ __device__ __forceinline__ double2 bin_chunk(const double2 *st, int m0, int cnt,
 template <int T>
 __device__ __forceinline__ void ring_synth_item(const RingArgs &a, const int item) {
     constexpr int kPairsPerThread = (kMaxPairs + T - 1) / T;
-    constexpr int kMaxStagePerThread = kMaxStage / T;
     extern __shared__ double2 sm[];
     const int pos = item / a.nmaps, b = item % a.nmaps;
     const int rho = a.rings[pos];
@@ -247,7 +237,6 @@ __device__ __forceinline__ void ring_synth_item(const RingArgs &a, const int ite
     const bool bs = M > 0;
     const double2 *__restrict__ W = a.chirp + (bs ? a.ring_chirp_off[rho] : 0);
     double2 *buf = sm;
-    double2 *stage = sm + a.fft_entries;  // a.stage entries (wrapped rings only)
     const int tid = threadIdx.x;
     const int L = a.L;
     const int npair = n / 2 + 1;
@@ -306,51 +295,41 @@ __device__ __forceinline__ void ring_synth_item(const RingArgs &a, const int ite
             }
         }
     } else {
+        // J <= L: every bin collects several orders; each thread sums the
+        // orders of its bins (terms j = g mod G) straight from q, in a fixed
+        // order, with its loads independent of each other
         G = npair >= T ? 1 : T / npair;
-        for (int m0 = 0; m0 <= L; m0 += a.stage) {
-            const int cnt = min(a.stage, L + 1 - m0);
-            double2 v[kMaxStagePerThread];
 #pragma unroll
-            for (int i = 0; i < kMaxStagePerThread; i++) {
-                const int mm = tid + i * T;
-                if (mm < cnt) v[i] = qr[(size_t)(m0 + mm) * qstride];
+        for (int j = 0; j < kPairsPerThread; j++) {
+            const int u = tid + j * T;
+            const int g = u / npair, k = u % npair;
+            if (g < G) {
+                xa[j] = bin_direct(qr, qstride, L, J, s, k, g, G);
+                if (k != 0 && 2 * k != n)
+                    xb[j] = bin_direct(qr, qstride, L, J, s, n - k, g, G);
+                else if (k == 0)
+                    xb[j] = bin_direct(qr, qstride, L, J, s, n, g, G);
             }
-#pragma unroll
-            for (int i = 0; i < kMaxStagePerThread; i++) {
-                const int mm = tid + i * T;
-                if (mm < cnt) stage[mm] = v[i];
-            }
-            __syncthreads();
-#pragma unroll
-            for (int j = 0; j < kPairsPerThread; j++) {
-                const int u = tid + j * T;
-                const int g = u / npair, k = u % npair;
-                if (g < G) {
-                    xa[j] = cadd(xa[j], bin_chunk(stage, m0, cnt, J, s, k, g, G));
-                    if (k != 0 && 2 * k != n)
-                        xb[j] = cadd(xb[j], bin_chunk(stage, m0, cnt, J, s, n - k, g, G));
-                    else if (k == 0)
-                        xb[j] = cadd(xb[j], bin_chunk(stage, m0, cnt, J, s, n, g, G));
-                }
-            }
-            __syncthreads();
         }
         if (G > 1) {
-            // reduce the group partials in a fixed order (stage region reused)
+            // reduce the group partials in a fixed order, through the start
+            // of the LDS block (at least 2 T entries), before the DFT uses it
+            double2 *red = sm;
             if (tid < G * npair) {
-                stage[2 * tid] = xa[0];
-                stage[2 * tid + 1] = xb[0];
+                red[2 * tid] = xa[0];
+                red[2 * tid + 1] = xb[0];
             }
             __syncthreads();
             if (tid < npair) {
                 double2 s0 = make_double2(0.0, 0.0), s1 = make_double2(0.0, 0.0);
                 for (int g = 0; g < G; g++) {
-                    s0 = cadd(s0, stage[2 * (g * npair + tid)]);
-                    s1 = cadd(s1, stage[2 * (g * npair + tid) + 1]);
+                    s0 = cadd(s0, red[2 * (g * npair + tid)]);
+                    s1 = cadd(s1, red[2 * (g * npair + tid) + 1]);
                 }
                 xa[0] = s0;
                 xb[0] = s1;
             }
+            __syncthreads();
         }
     }
 
@@ -490,16 +469,14 @@ hipError_t allow_dynamic_lds(const void *fn, int bytes) {
     return e;
 }
 
-// FFT buffer entries, staging chunk and dynamic LDS bytes of the workgroups
-// of one ring class (FFT buffer of lds_entries complex values) at T threads.
+// FFT buffer entries, extra entries and dynamic LDS bytes of the workgroups
+// of one ring class (FFT buffer of lds_entries complex values) at T threads:
+// wrapped rings reduce up to 2 T partial bin sums through the start of the
+// block, so the block holds at least 2 T entries.
 size_t ring_class_shape(int lds_entries, bool wrap, int T, int *fft_entries, int *stage) {
     *fft_entries = lds_entries + lds_entries / 16;
-    // staging chunk: what the FFT buffer leaves of 80 KiB (two workgroups
-    // per CU) when that is at least a quarter of the block, else of 160 KiB
-    const int cap2 = (int)(80 * 1024 / sizeof(double2));
-    const int room = (*fft_entries + T / 4 <= cap2 ? cap2 : (int)(160 * 1024 / sizeof(double2))) - *fft_entries;
-    *stage = std::min(kMaxStage, room >= T ? room / T * T : room);
-    return (size_t)(*fft_entries + (wrap ? *stage : 0)) * sizeof(double2);
+    *stage = wrap ? std::max(0, 2 * T - *fft_entries) : 0;
+    return (size_t)(*fft_entries + *stage) * sizeof(double2);
 }
 
 template <int T>
