@@ -36,6 +36,7 @@ METRIC = "L=4095 synthesis maps/s: butterfly vs brute-force, FP64 vs FP32-MFMA, 
 FP64_PEAK_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 flops x 2.4 GHz (vector FMA)
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters.json")
 CSRC = os.path.join(ROOT, "paper_1110_4874_amd", "csrc")
 
 
@@ -75,13 +76,13 @@ def source_sha(src):
     return h.hexdigest()
 
 
-def measured_traffic(kernel, L, nside, nmaps):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source and workload."""
-    if not os.path.exists(TRAFFIC_FILE):
+def _profile_record(path, kernel, L, nside, nmaps):
+    """The record of `kernel` in a committed rocprofv3 summary, if it was
+    taken on the current kernel source and workload."""
+    if not os.path.exists(path):
         return None
     try:
-        recs = json.load(open(TRAFFIC_FILE)).get("records", [])
+        recs = json.load(open(path)).get("records", [])
     except (ValueError, AttributeError):
         return None
     for rec in recs:
@@ -91,8 +92,25 @@ def measured_traffic(kernel, L, nside, nmaps):
             return None
         if (rec.get("L"), rec.get("nside"), rec.get("nmaps")) != (L, nside, nmaps):
             return None
-        return rec.get("bytes_per_launch")
+        return rec
     return None
+
+
+def measured_traffic(kernel, L, nside, nmaps):
+    """HBM bytes per launch of `kernel` (FETCH_SIZE and WRITE_SIZE, scaled by
+    the same counters' reading of a 1 GiB copy)."""
+    rec = _profile_record(TRAFFIC_FILE, kernel, L, nside, nmaps)
+    return rec.get("bytes_per_launch") if rec else None
+
+
+def measured_counters(kernel, L, nside, nmaps):
+    """FP64 rate and matrix-core use of `kernel` from the committed counter
+    pass (FP64 VALU and MFMA instruction counts, MFMA busy cycles)."""
+    rec = _profile_record(COUNTERS_FILE, kernel, L, nside, nmaps)
+    if not rec:
+        return None
+    return {k: rec.get(k) for k in ("mean_duration_ms", "fp64_tflops", "fp64_frac", "mfma_busy_frac",
+                                    "fp64_valu_flops", "fp64_mfma_flops", "fp32_mfma_flops")}
 
 
 def batch_bench(np, torch, sht, steps):
@@ -246,11 +264,12 @@ def level_roofline(info, nlev, sz, B, levels_ms, L, N):
     launch_ms = levels_ms / nl
     achieved = alg / (launch_ms * 1e-3) / 1e9
     nb = 8 if B >= 8 else 4 if B >= 4 else 2 if B >= 2 else 1
-    kern = "void sht::k_bf_level<%d, %s>" % (nb, "double" if sz == 8 else "float")
+    kern = "void sht::k_bf_level<%d, %s, true>(" % (nb, "double" if sz == 8 else "float")
     return {"kernel": f"k_bf_level ({nl} launches per pass, one per level 2..{nlev})", "bound": "hbm",
             "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(kern, L, N, B), "bytes_per_launch": int(alg),
+            "traffic": measured_traffic(kern, L, N, B), "counters": measured_counters(kern, L, N, B),
+            "bytes_per_launch": int(alg),
             "intermediate_bytes_per_launch": int(inter), "launch_ms": round(launch_ms, 4),
             "with_intermediate_GBs": round((alg + inter) / (launch_ms * 1e-3) / 1e9, 1)}
 
@@ -683,7 +702,8 @@ def main():
             return {"kernel": "k_legendre (brute-force Legendre phase, one launch)", "bound": "alu",
                     "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                     "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
-                    "traffic": measured_traffic("void sht::k_legendre<", L, N, B), "flops_per_launch": flops}
+                    "traffic": measured_traffic("void sht::k_legendre<", L, N, B),
+                    "counters": measured_counters("void sht::k_legendre<", L, N, B), "flops_per_launch": flops}
         sz = 8 if name == "bf64" else 4
         if "levels_ms" not in r or nlev == 0:
             nbytes = info["bf_T_entries"] * sz + alm_bytes + q_bytes
@@ -697,7 +717,9 @@ def main():
         achieved = rflops / (r["residual_ms"] * 1e-3) / 1e12
         return {"kernel": "k_bf_residual (one launch)", "bound": "alu", "achieved": round(achieved, 3),
                 "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
-                "traffic": None, "flops_per_launch": rflops, "launch_ms": round(r["residual_ms"], 4)}
+                "traffic": None, "counters": measured_counters("void sht::k_bf_residual<%d, %s>(" % (
+                    min(B, 8), "double" if sz == 8 else "float"), L, N, B),
+                "flops_per_launch": rflops, "launch_ms": round(r["residual_ms"], 4)}
 
     fp64 = [n for n in results if n != "bf32"]
     head = max(fp64, key=lambda n: results[n]["maps_per_s"])
