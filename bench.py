@@ -76,9 +76,10 @@ def source_sha(src):
     return h.hexdigest()
 
 
-def _profile_record(path, kernel, L, nside, nmaps):
+def _profile_record(path, kernel, L, nside, nmaps, t_entries=None):
     """The record of `kernel` in a committed rocprofv3 summary, if it was
-    taken on the current kernel source and workload."""
+    taken on the current kernel source and workload (and, for butterfly
+    kernels, on a plan with the same number of dense entries)."""
     if not os.path.exists(path):
         return None
     try:
@@ -92,21 +93,23 @@ def _profile_record(path, kernel, L, nside, nmaps):
             return None
         if (rec.get("L"), rec.get("nside"), rec.get("nmaps")) != (L, nside, nmaps):
             return None
+        if t_entries is not None and rec.get("plan_T_entries") not in (None, t_entries):
+            return None
         return rec
     return None
 
 
-def measured_traffic(kernel, L, nside, nmaps):
+def measured_traffic(kernel, L, nside, nmaps, t_entries=None):
     """HBM bytes per launch of `kernel` (FETCH_SIZE and WRITE_SIZE, scaled by
     the same counters' reading of a 1 GiB copy)."""
-    rec = _profile_record(TRAFFIC_FILE, kernel, L, nside, nmaps)
+    rec = _profile_record(TRAFFIC_FILE, kernel, L, nside, nmaps, t_entries)
     return rec.get("bytes_per_launch") if rec else None
 
 
-def measured_counters(kernel, L, nside, nmaps):
+def measured_counters(kernel, L, nside, nmaps, t_entries=None):
     """FP64 rate and matrix-core use of `kernel` from the committed counter
     pass (FP64 VALU and MFMA instruction counts, MFMA busy cycles)."""
-    rec = _profile_record(COUNTERS_FILE, kernel, L, nside, nmaps)
+    rec = _profile_record(COUNTERS_FILE, kernel, L, nside, nmaps, t_entries)
     if not rec:
         return None
     return {k: rec.get(k) for k in ("mean_duration_ms", "fp64_tflops", "fp64_frac", "mfma_busy_frac",
@@ -268,7 +271,8 @@ def level_roofline(info, nlev, sz, B, levels_ms, L, N):
     return {"kernel": f"k_bf_level ({nl} launches per pass, one per level 2..{nlev})", "bound": "hbm",
             "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(kern, L, N, B), "counters": measured_counters(kern, L, N, B),
+            "traffic": measured_traffic(kern, L, N, B, info["bf_T_entries"]),
+            "counters": measured_counters(kern, L, N, B, info["bf_T_entries"]),
             "bytes_per_launch": int(alg),
             "intermediate_bytes_per_launch": int(inter), "launch_ms": round(launch_ms, 4),
             "with_intermediate_GBs": round((alg + inter) / (launch_ms * 1e-3) / 1e9, 1)}
@@ -717,8 +721,10 @@ def main():
         achieved = rflops / (r["residual_ms"] * 1e-3) / 1e12
         return {"kernel": "k_bf_residual (one launch)", "bound": "alu", "achieved": round(achieved, 3),
                 "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
-                "traffic": None, "counters": measured_counters("void sht::k_bf_residual<%d, %s>(" % (
-                    min(B, 8), "double" if sz == 8 else "float"), L, N, B),
+                "traffic": measured_traffic("void sht::k_bf_residual<%d, %s>(" % (
+                    min(B, 8), "double" if sz == 8 else "float"), L, N, B, info["bf_T_entries"]),
+                "counters": measured_counters("void sht::k_bf_residual<%d, %s>(" % (
+                    min(B, 8), "double" if sz == 8 else "float"), L, N, B, info["bf_T_entries"]),
                 "flops_per_launch": rflops, "launch_ms": round(r["residual_ms"], 4)}
 
     fp64 = [n for n in results if n != "bf32"]

@@ -111,9 +111,9 @@ typedef struct sht_plan_opts {
     /* Butterfly compression (eps > 0 plans only; Sec. 3.2 and 3.4): */
     double rho;        /* cost of one stored interpolation entry relative to one
                           residual recurrence element when choosing the depth per
-                          (m, parity); <= 0 selects the default 2.5 (MI355X: HBM
-                          bytes of an FP64 entry vs the FP64 flops of an element
-                          at 4 maps) */
+                          (m, parity); <= 0 selects the default 4 (measured on
+                          MI355X for FP64 level products at 4 maps; FP32 level
+                          products favour lower values) */
     int max_levels;    /* -1: depth from the rho cost model; 0: no compression;
                           > 0: exactly this many levels where the rows allow */
     int chunk;         /* column block width at level 1 (0 = default 64) */
