@@ -148,7 +148,7 @@ __device__ __forceinline__ void id_block(const BfArgs<S> &a, int node, int ch, i
 // complete in order, so no barrier is needed.
 template <int NB>
 constexpr int bf_res_stage_doubles() {
-    return 2 * kChunk * (2 * NB + 4);
+    return 2 * 64 * ((kChunk * (2 * NB + 4) + 63) / 64);
 }
 
 template <int NB, int R, typename S>
@@ -157,9 +157,9 @@ __device__ __forceinline__ void residual_task(const BfArgs<S> &a, S *__restrict_
                                               const double *__restrict__ ap, const double *__restrict__ cfs,
                                               int astride, double *stg, int col0) {
     constexpr int NC = 2 * NB;
-    constexpr int CW = NC + 4;          // per row: a_lm components, then B, AB, G and a pad
-    constexpr int CS = kChunk * CW;     // doubles per staged chunk
-    constexpr int E = (CS + 63) / 64;   // staged doubles per lane
+    constexpr int CW = NC + 4;               // per row: a_lm components, then B, AB, G and a pad
+    constexpr int E = (kChunk * CW + 63) / 64;  // staged doubles per lane
+    constexpr int CS = 64 * E;               // doubles per staged chunk (a whole number per lane)
     int i0[R];
     double z2[R], v0[R], v1[R], P0[R], P1[R], acc[R][NC];
 #pragma unroll
@@ -175,27 +175,25 @@ __device__ __forceinline__ void residual_task(const BfArgs<S> &a, S *__restrict_
 #pragma unroll
         for (int c = 0; c < NC; c++) acc[r][c] = 0.0;
     }
+    // Chunk loads without branches: every lane loads from a row clamped into
+    // [imin, iend) and keeps zero where the row or the component lies outside,
+    // so that a chunk's whole update is one basic block the compiler cannot
+    // reorder around branches.
     double pre[E];
     auto fetch = [&](int c0) {
 #pragma unroll
         for (int e = 0; e < E; e++) {
-            const int idx = lane + 64 * e, i = c0 + idx / CW, comp = idx % CW;
-            double v = 0.0;
-            if (idx < CS && i < iend) {
-                if (comp < NC)
-                    v = ap[(size_t)i * astride + comp];
-                else if (comp < NC + 3)
-                    v = cfs[4 * (t + 2 * i + 2) + comp - NC];
-            }
-            pre[e] = v;
+            const int idx = lane + 64 * e, ir = c0 + idx / CW, comp = idx % CW;
+            const int i = min(ir, iend - 1);
+            const double *p = comp < NC ? ap + (size_t)i * astride + comp
+                                        : cfs + 4 * (t + 2 * i + 2) + min(comp - NC, 2);
+            const double v = *p;
+            pre[e] = (ir < iend && idx < kChunk * CW && comp < NC + 3) ? v : 0.0;
         }
     };
     auto stage = [&](int sl) {
 #pragma unroll
-        for (int e = 0; e < E; e++) {
-            const int idx = lane + 64 * e;
-            if (idx < CS) stg[sl * CS + idx] = pre[e];
-        }
+        for (int e = 0; e < E; e++) stg[sl * CS + lane + 64 * e] = pre[e];
     };
     auto step = [&](const double *row) {
         double av[NC];
@@ -211,28 +209,42 @@ __device__ __forceinline__ void residual_task(const BfArgs<S> &a, S *__restrict_
             P1[r] = P2;
         }
     };
-    int c0 = imin & ~(kChunk - 1), sl = 0;
-    fetch(c0);
-    stage(0);
-    if (c0 + kChunk < iend) fetch(c0 + kChunk);
-    for (; c0 < iend; c0 += kChunk, sl ^= 1) {
-        const int cs = max(c0, imin), ce = min(iend, c0 + kChunk);
+    // a piece without rows (a parity with no l <= L) writes zeros and loads
+    // nothing: its clamped row iend - 1 would lie outside the order's rows
+    if (imin < iend) {
+        int c0 = imin & ~(kChunk - 1), sl = 0;
+        fetch(c0);
+        stage(0);
+        fetch(c0 + kChunk);
+        // The rings that start at imin; a first chunk that begins before imin
+        // runs row by row, every later chunk as eight unrolled steps (rows past
+        // iend are staged as zeros, which leave the sums unchanged).
 #pragma unroll
         for (int r = 0; r < R; r++)
-            if (i0[r] == cs) {
+            if (i0[r] == imin) {
                 P0[r] = v0[r];
                 P1[r] = v1[r];
             }
-        const double *cur = stg + sl * CS;
-        if (cs == c0 && ce - c0 == kChunk) {
-#pragma unroll
-            for (int u = 0; u < kChunk; u++) step(cur + u * CW);
-        } else {
-            for (int i = cs; i < ce; i++) step(cur + (i - c0) * CW);
+        if (c0 != imin) {
+            const int ce = min(iend, c0 + kChunk);
+            for (int i = imin; i < ce; i++) step(stg + (i - c0) * CW);
+            stage(1);
+            fetch(c0 + 2 * kChunk);
+            c0 += kChunk;
+            sl = 1;
         }
-        if (c0 + kChunk < iend) {
+        for (; c0 < iend; c0 += kChunk, sl ^= 1) {
+#pragma unroll
+            for (int r = 0; r < R; r++) {
+                const bool st = i0[r] == c0;
+                P0[r] = st ? v0[r] : P0[r];
+                P1[r] = st ? v1[r] : P1[r];
+            }
+            const double *cur = stg + sl * CS;
+#pragma unroll 2
+            for (int u = 0; u < kChunk; u++) step(cur + u * CW);
             stage(sl ^ 1);
-            if (c0 + 2 * kChunk < iend) fetch(c0 + 2 * kChunk);
+            fetch(c0 + 2 * kChunk);
         }
     }
 #pragma unroll
