@@ -139,16 +139,66 @@ __device__ __forceinline__ void id_block(const BfArgs<S> &a, int node, int ch, i
     }
 }
 
+// acc[c] += x_c * p for c < N, where x_c is the value that lane c of the
+// lane's 16-lane row holds in rv: each FP64 FMA reads rv through the DPP
+// broadcast (row_newbcast), so the per-row operands need neither one LDS
+// broadcast read per value nor a register each.  One asm block per call:
+// its leading s_nop gives the two wait states that a DPP read needs after a
+// vector-ALU write of rv, and nothing can be scheduled inside it.
+#define SHT_FMAC_BC(c, o) "v_fmac_f64_dpp %" #o ", %[rv], %[p] row_newbcast:" #c " row_mask:0xf bank_mask:0xf\n"
+template <int N>
+__device__ __forceinline__ void fmac_row_bcast(double *acc, double rv, double p);
+template <>
+__device__ __forceinline__ void fmac_row_bcast<2>(double *acc, double rv, double p) {
+    asm("s_nop 1\n" SHT_FMAC_BC(0, 0) SHT_FMAC_BC(1, 1) : "+v"(acc[0]), "+v"(acc[1]) : [rv] "v"(rv), [p] "v"(p));
+}
+template <>
+__device__ __forceinline__ void fmac_row_bcast<4>(double *acc, double rv, double p) {
+    asm("s_nop 1\n" SHT_FMAC_BC(0, 0) SHT_FMAC_BC(1, 1) SHT_FMAC_BC(2, 2) SHT_FMAC_BC(3, 3)
+        : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3])
+        : [rv] "v"(rv), [p] "v"(p));
+}
+template <>
+__device__ __forceinline__ void fmac_row_bcast<8>(double *acc, double rv, double p) {
+    asm("s_nop 1\n" SHT_FMAC_BC(0, 0) SHT_FMAC_BC(1, 1) SHT_FMAC_BC(2, 2) SHT_FMAC_BC(3, 3) SHT_FMAC_BC(4, 4)
+            SHT_FMAC_BC(5, 5) SHT_FMAC_BC(6, 6) SHT_FMAC_BC(7, 7)
+        : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3]), "+v"(acc[4]), "+v"(acc[5]), "+v"(acc[6]),
+          "+v"(acc[7])
+        : [rv] "v"(rv), [p] "v"(p));
+}
+template <>
+__device__ __forceinline__ void fmac_row_bcast<16>(double *acc, double rv, double p) {
+    fmac_row_bcast<8>(acc, rv, p);
+    asm("s_nop 1\n" SHT_FMAC_BC(8, 0) SHT_FMAC_BC(9, 1) SHT_FMAC_BC(10, 2) SHT_FMAC_BC(11, 3) SHT_FMAC_BC(12, 4)
+            SHT_FMAC_BC(13, 5) SHT_FMAC_BC(14, 6) SHT_FMAC_BC(15, 7)
+        : "+v"(acc[8]), "+v"(acc[9]), "+v"(acc[10]), "+v"(acc[11]), "+v"(acc[12]), "+v"(acc[13]), "+v"(acc[14]),
+          "+v"(acc[15])
+        : [rv] "v"(rv), [p] "v"(p));
+}
+#undef SHT_FMAC_BC
+
+// The value of lane K of each 16-lane row, in every lane of that row.
+template <int K>
+__device__ __forceinline__ double row_bcast(double x) {
+    return __builtin_amdgcn_mov_dpp(x, 0x150 + K, 0xF, 0xF, false);
+}
+
 // One residual piece on one wave: R rings per lane (lane j: rings j + 64 r,
 // lane records from lbase), rows [imin, iend) of one parity, outputs at
 // entries outb + ring.  The a_lm rows and recurrence coefficients of each
 // aligned chunk of kChunk rows are fetched one chunk ahead with coalesced
-// vector loads and staged in the wave's own LDS slot (stg: two chunks), from
-// where every lane reads them as broadcasts; LDS operations of one wave
+// vector loads and staged in the wave's own LDS slot (stg: two chunks) as
+// rows of 16 (NC <= 13) or 32 values: a_lm components, then B, AB and G.
+// Lane k of every 16-lane row reads value k of a row, and the products take
+// the values from there by DPP broadcasts; LDS operations of one wave
 // complete in order, so no barrier is needed.
 template <int NB>
+constexpr int bf_res_row_doubles() {
+    return 2 * NB + 3 <= 16 ? 16 : 32;
+}
+template <int NB>
 constexpr int bf_res_stage_doubles() {
-    return 2 * 64 * ((kChunk * (2 * NB + 4) + 63) / 64);
+    return 2 * kChunk * bf_res_row_doubles<NB>();
 }
 
 template <int NB, int R, typename S>
@@ -157,9 +207,10 @@ __device__ __forceinline__ void residual_task(const BfArgs<S> &a, S *__restrict_
                                               const double *__restrict__ ap, const double *__restrict__ cfs,
                                               int astride, double *stg, int col0) {
     constexpr int NC = 2 * NB;
-    constexpr int CW = NC + 4;               // per row: a_lm components, then B, AB, G and a pad
-    constexpr int E = (kChunk * CW + 63) / 64;  // staged doubles per lane
-    constexpr int CS = 64 * E;               // doubles per staged chunk (a whole number per lane)
+    constexpr int CW = bf_res_row_doubles<NB>();  // staged values per row
+    constexpr int CS = kChunk * CW;                // doubles per staged chunk
+    constexpr int E = CS / 64;                     // staged doubles per lane
+    constexpr int CO = NC < 16 ? NC : 0;           // lane of B within its 16-lane group
     int i0[R];
     double z2[R], v0[R], v1[R], P0[R], P1[R], acc[R][NC];
 #pragma unroll
@@ -188,26 +239,26 @@ __device__ __forceinline__ void residual_task(const BfArgs<S> &a, S *__restrict_
             const double *p = comp < NC ? ap + (size_t)i * astride + comp
                                         : cfs + 4 * (t + 2 * i + 2) + min(comp - NC, 2);
             const double v = *p;
-            pre[e] = (ir < iend && idx < kChunk * CW && comp < NC + 3) ? v : 0.0;
+            pre[e] = (ir < iend && comp < NC + 3) ? v : 0.0;
         }
     };
     auto stage = [&](int sl) {
 #pragma unroll
         for (int e = 0; e < E; e++) stg[sl * CS + lane + 64 * e] = pre[e];
     };
-    auto step = [&](const double *row) {
-        double av[NC];
-#pragma unroll
-        for (int c = 0; c < NC; c++) av[c] = row[c];
-        const double eb = row[NC], eab = row[NC + 1], eg = row[NC + 2];
+    auto step_v = [&](double rv, double rc) {
+        const double eb = row_bcast<CO>(rc), eab = row_bcast<CO + 1>(rc), eg = row_bcast<CO + 2>(rc);
 #pragma unroll
         for (int r = 0; r < R; r++) {
-#pragma unroll
-            for (int c = 0; c < NC; c++) acc[r][c] = __builtin_fma(P0[r], av[c], acc[r][c]);
+            fmac_row_bcast<NC>(acc[r], rv, P0[r]);
             const double P2 = __builtin_fma(__builtin_fma(z2[r], eb, eab), P1[r], eg * P0[r]);
             P0[r] = P1[r];
             P1[r] = P2;
         }
+    };
+    auto step = [&](const double *row) {
+        const double rv = row[lane & 15];
+        step_v(rv, CW == 16 ? rv : row[16 + (lane & 15)]);
     };
     // a piece without rows (a parity with no l <= L) writes zeros and loads
     // nothing: its clamped row iend - 1 would lie outside the order's rows
@@ -240,9 +291,17 @@ __device__ __forceinline__ void residual_task(const BfArgs<S> &a, S *__restrict_
                 P0[r] = st ? v0[r] : P0[r];
                 P1[r] = st ? v1[r] : P1[r];
             }
-            const double *cur = stg + sl * CS;
-#pragma unroll 2
-            for (int u = 0; u < kChunk; u++) step(cur + u * CW);
+            // the chunk's rows are read at once (one or two values per lane
+            // and row), so that their LDS latency is paid once per chunk
+            const double *cur = stg + sl * CS + (lane & 15);
+            double rv[kChunk], rc[kChunk];
+#pragma unroll
+            for (int u = 0; u < kChunk; u++) {
+                rv[u] = cur[u * CW];
+                rc[u] = CW == 16 ? rv[u] : cur[u * CW + 16];
+            }
+#pragma unroll
+            for (int u = 0; u < kChunk; u++) step_v(rv[u], rc[u]);
             stage(sl ^ 1);
             fetch(c0 + 2 * kChunk);
         }
