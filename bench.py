@@ -798,7 +798,8 @@ def main():
         }
     if info["bf_built"]:
         line["butterfly_plan"] = {"eps": args.eps, "T_entries": info["bf_T_entries"],
-                                  "residual_elements": info["bf_res_elems"], "nodes": info["bf_nodes"],
+                                  "residual_elements": info["bf_res_elems"],
+                                  "residual_lane_steps": info["bf_res_exec"], "nodes": info["bf_nodes"],
                                   "depth_hist": info["bf_depth_hist"][:8],
                                   "build_seconds": round(info["bf_build_seconds"], 1),
                                   "device_gb": round(info["device_bytes"] / 1e9, 2)}

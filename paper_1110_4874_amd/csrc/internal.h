@@ -248,6 +248,7 @@ struct RingArgs {
     long long npix;
     int fft_entries;  // padded FFT buffer entries of this launch's class
     int stage;        // LDS entries past the FFT buffer (wrapped rings' reduction room)
+    int mpw;          // maps of one ring per workgroup (1, 2 or 4; divides nmaps)
     // adjoint direction: pixel values in, weighted phases ybar out
     const double *__restrict__ map_in;
     double2 *__restrict__ ybar;
@@ -334,6 +335,7 @@ hipError_t launch_legendre_queue(int shape, const LegArgs *passes, const int4 *i
                                  hipStream_t st);
 RingArgs ring_args(const sht_plan_s *p, int nmaps, const double *q, double *map);
 size_t ring_class_shape(int lds_entries, bool wrap, int T, int *fft_entries, int *stage);
+int ring_maps_per_wg(int lds_entries, int nmaps);
 hipError_t launch_ring_queue(int T, const RingArgs *args, const int2 *items, long long nitems, size_t lds,
                              hipStream_t st);
 hipError_t ring_queue_prepare(int T);

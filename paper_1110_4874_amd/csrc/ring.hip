@@ -84,10 +84,11 @@ __device__ __forceinline__ double2 rot8(double2 x, int j) {
 // e^{+2 pi i (pos + j h) / (2^(u+1) h)}, j = k mod 2^u.
 template <int r>
 __device__ __forceinline__ void dit_pass(double2 *a, int lg, int s, const double2 *__restrict__ tw,
-                                         int tw_log) {
+                                         int tw_log, int tid, int nt) {
     constexpr int R = 1 << r;
     const int n = 1 << lg, h = 1 << (s - 1);
-    for (int gi = threadIdx.x; gi < n / R; gi += blockDim.x) {
+#pragma unroll 1
+    for (int gi = tid; gi < n / R; gi += nt) {
         const int pos = gi & (h - 1);
         const int base = (gi >> (s - 1)) * (R * h) + pos;
         double2 x[R];
@@ -121,10 +122,11 @@ __device__ __forceinline__ void dit_pass(double2 *a, int lg, int s, const double
 // difference.
 template <int r>
 __device__ __forceinline__ void dif_pass(double2 *a, int lg, int s, const double2 *__restrict__ tw,
-                                         int tw_log) {
+                                         int tw_log, int tid, int nt) {
     constexpr int R = 1 << r;
     const int n = 1 << lg, h = 1 << (s - 1);
-    for (int gi = threadIdx.x; gi < n / R; gi += blockDim.x) {
+#pragma unroll 1
+    for (int gi = tid; gi < n / R; gi += nt) {
         const int pos = gi & (h - 1);
         const int base = (gi >> (s - 1)) * (R * h) + pos;
         double2 x[R];
@@ -153,48 +155,47 @@ __device__ __forceinline__ void dif_pass(double2 *a, int lg, int s, const double
     __syncthreads();
 }
 
-// Backward DFT of size 2^lg, bit-reversed input, natural output.
-__device__ void fft_dit_inv(double2 *a, int lg, const double2 *__restrict__ tw, int tw_log) {
+// Backward DFT of size 2^lg, bit-reversed input, natural output, by the nt
+// threads tid = 0..nt-1 of the caller's thread group.
+__device__ void fft_dit_inv(double2 *a, int lg, const double2 *__restrict__ tw, int tw_log, int tid, int nt) {
     int s = 1;
     while (lg - s + 1 >= 3) {
-        dit_pass<3>(a, lg, s, tw, tw_log);
+        dit_pass<3>(a, lg, s, tw, tw_log, tid, nt);
         s += 3;
     }
-    if (lg - s + 1 == 2) dit_pass<2>(a, lg, s, tw, tw_log);
-    else if (lg - s + 1 == 1) dit_pass<1>(a, lg, s, tw, tw_log);
+    if (lg - s + 1 == 2) dit_pass<2>(a, lg, s, tw, tw_log, tid, nt);
+    else if (lg - s + 1 == 1) dit_pass<1>(a, lg, s, tw, tw_log, tid, nt);
 }
 
 // Forward DFT of size 2^lg, natural input, bit-reversed output.
-__device__ void fft_dif_fwd(double2 *a, int lg, const double2 *__restrict__ tw, int tw_log) {
+__device__ void fft_dif_fwd(double2 *a, int lg, const double2 *__restrict__ tw, int tw_log, int tid, int nt) {
     const int rem = lg % 3;
     int s = lg - 2;
     while (s >= 1 + rem) {
-        dif_pass<3>(a, lg, s, tw, tw_log);
+        dif_pass<3>(a, lg, s, tw, tw_log, tid, nt);
         s -= 3;
     }
-    if (rem == 2) dif_pass<2>(a, lg, 1, tw, tw_log);
-    else if (rem == 1) dif_pass<1>(a, lg, 1, tw, tw_log);
+    if (rem == 2) dif_pass<2>(a, lg, 1, tw, tw_log, tid, nt);
+    else if (rem == 1) dif_pass<1>(a, lg, 1, tw, tw_log, tid, nt);
 }
 
 // Unnormalised backward DFT of size n in LDS: z_p = sum_k Z_k e^{+2 pi i k p/n}.
 // On entry the buffer holds Z_k at pidx(bitrev(k)) (n a power of two, M = 0)
 // or the chirp-weighted u_k = Z_k W_k, W_k = e^{i pi k^2/n}, at pidx(k) with
 // zeros up to M (Bluestein); on exit z_p is at pidx(p), p < n.
-template <int T>
 __device__ __forceinline__ void backward_dft(double2 *buf, int n, int M, const double2 *__restrict__ V,
                                              const double2 *__restrict__ W, const double2 *__restrict__ tw,
-                                             int tw_log) {
-    const int tid = threadIdx.x;
+                                             int tw_log, int tid, int nt) {
     if (M == 0) {
-        fft_dit_inv(buf, ilog2_dev(n), tw, tw_log);
+        fft_dit_inv(buf, ilog2_dev(n), tw, tw_log, tid, nt);
         return;
     }
     const int lgM = ilog2_dev(M);
-    fft_dif_fwd(buf, lgM, tw, tw_log);
-    for (int i = tid; i < M; i += T) buf[pidx(i)] = cmul(buf[pidx(i)], V[i]);
+    fft_dif_fwd(buf, lgM, tw, tw_log, tid, nt);
+    for (int i = tid; i < M; i += nt) buf[pidx(i)] = cmul(buf[pidx(i)], V[i]);
     __syncthreads();
-    fft_dit_inv(buf, lgM, tw, tw_log);
-    for (int p = tid; p < n; p += T) buf[pidx(p)] = cmul(buf[pidx(p)], W[p]);
+    fft_dit_inv(buf, lgM, tw, tw_log, tid, nt);
+    for (int p = tid; p < n; p += nt) buf[pidx(p)] = cmul(buf[pidx(p)], W[p]);
     __syncthreads();
 }
 
@@ -225,19 +226,20 @@ __device__ __forceinline__ double2 bin_direct(const double2 *__restrict__ qr, si
 }
 
 // Synthesis of one ring of one map (item = ring position in the class's
-// list times nmaps plus the map) by a workgroup of T threads.
-template <int T>
-__device__ __forceinline__ void ring_synth_item(const RingArgs &a, const int item) {
+// list times nmaps plus the map) by the nt threads tid = 0..nt-1 of a group
+// owning the LDS block buf.  A workgroup of T threads is one group, or T/nt
+// groups for maps of one ring (identical control flow, so the workgroup's
+// barriers match); a ring whose transform size is at most 4096 nt / T keeps
+// the per-thread counts within those sized for T.
+template <int T, int nt>
+__device__ __forceinline__ void ring_synth_item(const RingArgs &a, const int item, const int tid, double2 *buf) {
     constexpr int kPairsPerThread = (kMaxPairs + T - 1) / T;
-    extern __shared__ double2 sm[];
     const int pos = item / a.nmaps, b = item % a.nmaps;
     const int rho = a.rings[pos];
     const int J = a.ring_J[rho], s = a.ring_s[rho], M = a.ring_M[rho];
     const int n = J / 2, lgn = ilog2_dev(n);
     const bool bs = M > 0;
     const double2 *__restrict__ W = a.chirp + (bs ? a.ring_chirp_off[rho] : 0);
-    double2 *buf = sm;
-    const int tid = threadIdx.x;
     const int L = a.L;
     const int npair = n / 2 + 1;
     // ring-major q: the maps of one ring interleave in one contiguous block,
@@ -256,7 +258,7 @@ __device__ __forceinline__ void ring_synth_item(const RingArgs &a, const int ite
         // every bin b <= L holds exactly q_b; issue all loads first
 #pragma unroll
         for (int j = 0; j < kPairsPerThread; j++) {
-            const int k = tid + j * T;
+            const int k = tid + j * nt;
             if (k < npair) {
                 if (k <= L) xa[j] = qr[(size_t)k * qstride];
                 if (k == 0) xa[j].y = 0.0;
@@ -270,7 +272,7 @@ __device__ __forceinline__ void ring_synth_item(const RingArgs &a, const int ite
         const int J2 = 2 * n;
 #pragma unroll
         for (int j = 0; j < kPairsPerThread; j++) {
-            const int k = tid + j * T;
+            const int k = tid + j * nt;
             if (k < npair) {
                 double2 v = qr[(size_t)k * qstride];  // k <= n <= L
                 if (k == 0) v.y = 0.0;
@@ -298,10 +300,10 @@ __device__ __forceinline__ void ring_synth_item(const RingArgs &a, const int ite
         // J <= L: every bin collects several orders; each thread sums the
         // orders of its bins (terms j = g mod G) straight from q, in a fixed
         // order, with its loads independent of each other
-        G = npair >= T ? 1 : T / npair;
+        G = npair >= nt ? 1 : nt / npair;
 #pragma unroll
         for (int j = 0; j < kPairsPerThread; j++) {
-            const int u = tid + j * T;
+            const int u = tid + j * nt;
             const int g = u / npair, k = u % npair;
             if (g < G) {
                 xa[j] = bin_direct(qr, qstride, L, J, s, k, g, G);
@@ -313,8 +315,9 @@ __device__ __forceinline__ void ring_synth_item(const RingArgs &a, const int ite
         }
         if (G > 1) {
             // reduce the group partials in a fixed order, through the start
-            // of the LDS block (at least 2 T entries), before the DFT uses it
-            double2 *red = sm;
+            // of the group's LDS block (at least 2 nt entries), before the
+            // DFT uses it
+            double2 *red = buf;
             if (tid < G * npair) {
                 red[2 * tid] = xa[0];
                 red[2 * tid + 1] = xb[0];
@@ -337,19 +340,19 @@ __device__ __forceinline__ void ring_synth_item(const RingArgs &a, const int ite
     // bit-reversed order for power-of-two n; for split Bluestein rings even k
     // at k/2 and odd k at h + (k-1)/2 (n = 2h), weighted by the chirp
     const int h = n / 2;
-    // e^{i pi k/J} and e^{i pi k/n} for k = tid + j T by products with the
-    // step e^{i pi T/J} (resp. n): two sincospi per thread instead of three
+    // e^{i pi k/J} and e^{i pi k/n} for k = tid + j nt by products with the
+    // step e^{i pi nt/J} (resp. n): two sincospi per thread instead of three
     // per pair (the rounding grows by about an ulp per step)
     double2 pJ = make_double2(1.0, 0.0), sJ = pJ;
     if (s) {
         pJ = expipi((double)tid / J);
-        sJ = expipi((double)T / J);
+        sJ = expipi((double)nt / J);
     }
     double2 pn = expipi((double)tid / n);
-    const double2 sn = expipi((double)T / n);
+    const double2 sn = expipi((double)nt / n);
 #pragma unroll
     for (int j = 0; j < kPairsPerThread; j++) {
-        const int k = tid + j * T;
+        const int k = tid + j * nt;
         if (k < npair && !(G > 1 && j > 0)) {
         double2 Xk = xa[j], Xnk = xb[j];
         if (s) {
@@ -388,8 +391,8 @@ __device__ __forceinline__ void ring_synth_item(const RingArgs &a, const int ite
     // pixel 2p = Re z_p, pixel 2p+1 = Im z_p
     double2 *out = reinterpret_cast<double2 *>(a.map + (size_t)b * a.npix + a.ring_off[rho]);
     if (!bs) {
-        backward_dft<T>(buf, n, 0, nullptr, nullptr, a.tw, a.tw_log);
-        for (int p = tid; p < n; p += T) out[p] = buf[pidx(p)];
+        backward_dft(buf, n, 0, nullptr, nullptr, a.tw, a.tw_log, tid, nt);
+        for (int p = tid; p < n; p += nt) out[p] = buf[pidx(p)];
         return;
     }
 
@@ -400,30 +403,30 @@ __device__ __forceinline__ void ring_synth_item(const RingArgs &a, const int ite
     double2 R[kHalfPerThread];
 #pragma unroll
     for (int jj = 0; jj < kHalfPerThread; jj++) {
-        const int p = tid + jj * T;
+        const int p = tid + jj * nt;
         if (p < h) R[jj] = buf[pidx(h + p)];
     }
     __syncthreads();
-    for (int i = h + tid; i < M; i += T) buf[pidx(i)] = make_double2(0.0, 0.0);
+    for (int i = h + tid; i < M; i += nt) buf[pidx(i)] = make_double2(0.0, 0.0);
     __syncthreads();
-    backward_dft<T>(buf, h, M, V, W, a.tw, a.tw_log);
+    backward_dft(buf, h, M, V, W, a.tw, a.tw_log, tid, nt);
 #pragma unroll
     for (int jj = 0; jj < kHalfPerThread; jj++) {
-        const int p = tid + jj * T;
+        const int p = tid + jj * nt;
         if (p < h) {
             const double2 odd_in = R[jj];
             R[jj] = buf[pidx(p)];  // A_p
             buf[pidx(p)] = odd_in;
         }
     }
-    for (int i = h + tid; i < M; i += T) buf[pidx(i)] = make_double2(0.0, 0.0);
+    for (int i = h + tid; i < M; i += nt) buf[pidx(i)] = make_double2(0.0, 0.0);
     __syncthreads();
-    backward_dft<T>(buf, h, M, V, W, a.tw, a.tw_log);
+    backward_dft(buf, h, M, V, W, a.tw, a.tw_log, tid, nt);
     double2 wp = expipi(2.0 * tid / n);  // e^{2 pi i p/n}, stepped as above
-    const double2 ws = expipi(2.0 * T / n);
+    const double2 ws = expipi(2.0 * nt / n);
 #pragma unroll
     for (int jj = 0; jj < kHalfPerThread; jj++) {
-        const int p = tid + jj * T;
+        const int p = tid + jj * nt;
         if (p < h) {
             const double2 t = cmul(buf[pidx(p)], wp);
             out[p] = cadd(R[jj], t);
@@ -433,11 +436,18 @@ __device__ __forceinline__ void ring_synth_item(const RingArgs &a, const int ite
     }
 }
 
-template <int T>
-__global__ __launch_bounds__(T) void k_ring_synth(RingArgs a) {
-    const int item = xcd_item(blockIdx.x);
-    if (item >= a.count * a.nmaps) return;
-    ring_synth_item<T>(a, item);
+// Workgroup w runs the items w G .. w G + G - 1 (G = a.mpw maps of one
+// ring, G | nmaps), one group of T/G threads and one LDS block each.
+template <int T, int G>
+__global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(T == 512 ? 4 : 1))) void k_ring_synth(RingArgs a) {
+    extern __shared__ double2 sm[];
+    constexpr int nt = T / G;
+    const int sub = G == 1 ? 0 : (int)threadIdx.x / nt;
+    const int item0 = xcd_item(blockIdx.x) * G;
+    if (item0 >= a.count * a.nmaps) return;
+    // (one group: the plain thread index and LDS base keep 26 fewer VGPRs)
+    if (G == 1) ring_synth_item<T, nt>(a, item0, threadIdx.x, sm);
+    else ring_synth_item<T, nt>(a, item0 + sub, threadIdx.x - sub * nt, sm + (size_t)sub * (a.fft_entries + a.stage));
 }
 
 // Ring queue of a batch of requests: one launch per ring size class for all
@@ -450,8 +460,9 @@ __global__ __launch_bounds__(T) void k_ring_synth_queue(const RingArgs *__restri
     const int j = xcd_item(blockIdx.x);
     if (j >= nitems) return;
     const int2 it = items[j];
+    extern __shared__ double2 sm[];
     const RingArgs a = args[__builtin_amdgcn_readfirstlane(it.x)];
-    ring_synth_item<T>(a, __builtin_amdgcn_readfirstlane(it.y));
+    ring_synth_item<T, T>(a, __builtin_amdgcn_readfirstlane(it.y), threadIdx.x, sm);
 }
 
 // Raises a kernel's dynamic LDS limit to `bytes`, once per (kernel, device):
@@ -479,16 +490,34 @@ size_t ring_class_shape(int lds_entries, bool wrap, int T, int *fft_entries, int
     return (size_t)(*fft_entries + *stage) * sizeof(double2);
 }
 
+// Maps of one ring per workgroup for a class of transform size S: as many
+// as fill the workgroup's threads with the groups a 4096-entry transform
+// would use (at most 4), dividing nmaps.
+int ring_maps_per_wg(int lds_entries, int nmaps) {
+    int g = 1;
+    while (g < 4 && (g * 2) * lds_entries <= 4096 && nmaps % (g * 2) == 0) g *= 2;
+    return g;
+}
+
 template <int T>
 static hipError_t launch_classes(const sht_plan_s *p, RingArgs a, int nmaps, hipStream_t stream) {
-    hipError_t ea = allow_dynamic_lds((const void *)k_ring_synth<T>, 160 * 1024);
-    if (ea != hipSuccess) return ea;
+    const void *fn[3] = {(const void *)k_ring_synth<T, 1>, (const void *)k_ring_synth<T, 2>,
+                         (const void *)k_ring_synth<T, 4>};
+    for (const void *f : fn) {
+        hipError_t ea = allow_dynamic_lds(f, 160 * 1024);
+        if (ea != hipSuccess) return ea;
+    }
     for (const auto &rc : p->classes) {
         a.rings = rc.d_rings;
         a.count = (int)rc.rings.size();
-        const size_t lds = ring_class_shape(rc.lds_entries, rc.wrap, T, &a.fft_entries, &a.stage);
-        long long grid = ((long long)a.count * nmaps + 63) / 64 * 64;
-        hipLaunchKernelGGL(k_ring_synth<T>, dim3((unsigned)grid), dim3(T), lds, stream, a);
+        a.mpw = ring_maps_per_wg(rc.lds_entries, nmaps);
+        const size_t lds = a.mpw * ring_class_shape(rc.lds_entries, rc.wrap, T / a.mpw, &a.fft_entries, &a.stage);
+        long long grid = ((long long)a.count * nmaps / a.mpw + 63) / 64 * 64;
+        switch (a.mpw) {
+            case 1: hipLaunchKernelGGL((k_ring_synth<T, 1>), dim3((unsigned)grid), dim3(T), lds, stream, a); break;
+            case 2: hipLaunchKernelGGL((k_ring_synth<T, 2>), dim3((unsigned)grid), dim3(T), lds, stream, a); break;
+            default: hipLaunchKernelGGL((k_ring_synth<T, 4>), dim3((unsigned)grid), dim3(T), lds, stream, a); break;
+        }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -546,6 +575,7 @@ RingArgs ring_args(const sht_plan_s *p, int nmaps, const double *q, double *map)
     a.nrings = p->nrings;
     a.nmaps = nmaps;
     a.npix = 12LL * p->nside * p->nside;
+    a.mpw = 1;
     return a;
 }
 
@@ -588,28 +618,33 @@ hipError_t launch_ring_synthesis(const sht_plan_s *p, int nmaps, const double *q
 // every m of bin b's two residue classes is written from G_b =
 // e^{-i pi b s/J} F_b:  ybar_{b+jJ} = w (-1)^{js} G_b,
 // ybar_{jJ-b} = w (-1)^{js} conj(G_b).
-template <int T>
-__global__ __launch_bounds__(T) void k_ring_analysis(RingArgs a) {
+// Workgroups of a.mpw maps of one ring, one group of T/a.mpw threads and one
+// LDS block each, as in k_ring_synth.
+template <int T, int G>
+__global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(T == 512 ? 4 : 1))) void k_ring_analysis(RingArgs a) {
     extern __shared__ double2 sm[];
-    const int item = xcd_item(blockIdx.x);
-    if (item >= a.count * a.nmaps) return;
+    constexpr int nt = T / G;
+    const int sub = G == 1 ? 0 : (int)threadIdx.x / nt;
+    const int item0 = xcd_item(blockIdx.x) * G;
+    if (item0 >= a.count * a.nmaps) return;
+    const int item = item0 + sub;
     const int pos = item / a.nmaps, b = item % a.nmaps;
     const int rho = a.rings[pos];
     const int J = a.ring_J[rho], s = a.ring_s[rho], M = a.ring_M[rho];
     const int n = J / 2, lgn = ilog2_dev(n);
     const bool bs = M > 0;
     const double2 *__restrict__ W = a.chirp + (bs ? a.ring_chirp_off[rho] : 0);
-    double2 *buf = sm;
-    const int tid = threadIdx.x;
+    double2 *buf = G == 1 ? sm : sm + (size_t)sub * a.fft_entries;
+    const int tid = G == 1 ? (int)threadIdx.x : (int)threadIdx.x - sub * nt;
     const int L = a.L;
     const size_t qstride = (size_t)a.nmaps;
     double2 *yr = a.ybar + (size_t)rho * (L + 1) * a.nmaps + b;
 
     const double2 *pix = reinterpret_cast<const double2 *>(a.map_in + (size_t)b * a.npix + a.ring_off[rho]);
     if (!bs) {
-        for (int p = tid; p < n; p += T) buf[pidx(bitrev(p, lgn))] = cconj(pix[p]);
+        for (int p = tid; p < n; p += nt) buf[pidx(bitrev(p, lgn))] = cconj(pix[p]);
         __syncthreads();
-        backward_dft<T>(buf, n, 0, nullptr, nullptr, a.tw, a.tw_log);
+        backward_dft(buf, n, 0, nullptr, nullptr, a.tw, a.tw_log, tid, nt);
     } else {
         // split Bluestein: even inputs (hh = 0), then odd inputs (hh = 1)
         constexpr int kHalfPerThread = (kMaxHalf + T - 1) / T;
@@ -617,14 +652,14 @@ __global__ __launch_bounds__(T) void k_ring_analysis(RingArgs a) {
         const double2 *__restrict__ V = a.bs_table + a.ring_bs_off[rho];
         double2 A[kHalfPerThread];
         for (int hh = 0; hh < 2; hh++) {
-            for (int i = h + tid; i < M; i += T) buf[pidx(i)] = make_double2(0.0, 0.0);
-            for (int p = tid; p < h; p += T) buf[pidx(p)] = cmul(cconj(pix[2 * p + hh]), W[p]);
+            for (int i = h + tid; i < M; i += nt) buf[pidx(i)] = make_double2(0.0, 0.0);
+            for (int p = tid; p < h; p += nt) buf[pidx(p)] = cmul(cconj(pix[2 * p + hh]), W[p]);
             __syncthreads();
-            backward_dft<T>(buf, h, M, V, W, a.tw, a.tw_log);
+            backward_dft(buf, h, M, V, W, a.tw, a.tw_log, tid, nt);
             if (hh == 0) {
 #pragma unroll
                 for (int jj = 0; jj < kHalfPerThread; jj++) {
-                    const int p = tid + jj * T;
+                    const int p = tid + jj * nt;
                     if (p < h) A[jj] = buf[pidx(p)];
                 }
                 __syncthreads();
@@ -634,10 +669,10 @@ __global__ __launch_bounds__(T) void k_ring_analysis(RingArgs a) {
         // thread reads B_p before writing p and p + h, which no other thread
         // reads)
         double2 wp = expipi(2.0 * tid / n);  // e^{2 pi i p/n}, stepped by products
-        const double2 ws = expipi(2.0 * T / n);
+        const double2 ws = expipi(2.0 * nt / n);
 #pragma unroll
         for (int jj = 0; jj < kHalfPerThread; jj++) {
-            const int p = tid + jj * T;
+            const int p = tid + jj * nt;
             if (p < h) {
                 const double2 t = cmul(buf[pidx(p)], wp);
                 buf[pidx(p)] = cadd(A[jj], t);
@@ -648,15 +683,15 @@ __global__ __launch_bounds__(T) void k_ring_analysis(RingArgs a) {
         __syncthreads();
     }
 
-    // bins b = 0..n, split over G groups of the residue classes for small rings
+    // bins b = 0..n, split over NG groups of the residue classes for small rings
     const int nb = n + 1;
-    const int G = nb >= T ? 1 : T / nb;
-    // e^{-i pi bin/n} and e^{-i pi bin/J}: with G = 1 a thread's bins are
-    // tid + j T, stepped by products; with G > 1 each thread has one bin
+    const int NG = nb >= nt ? 1 : nt / nb;
+    // e^{-i pi bin/n} and e^{-i pi bin/J}: with NG = 1 a thread's bins are
+    // tid + j nt, stepped by products; with NG > 1 each thread has one bin
     const int bin0 = tid % nb;
     double2 qn = expipi(-(double)bin0 / n), qJ = s ? expipi(-(double)bin0 / J) : make_double2(1.0, 0.0);
-    const double2 sn = expipi(-(double)T / n), sJ = s ? expipi(-(double)T / J) : make_double2(1.0, 0.0);
-    for (int u = tid; u < G * nb; u += T) {
+    const double2 sn = expipi(-(double)nt / n), sJ = s ? expipi(-(double)nt / J) : make_double2(1.0, 0.0);
+    for (int u = tid; u < NG * nb; u += nt) {
         const int g = u / nb, bin = u % nb;
         const double2 Zb = cconj(buf[pidx(bin == n ? 0 : bin)]);
         const double2 Znb = cconj(buf[pidx(bin == 0 ? 0 : n - bin)]);
@@ -668,7 +703,7 @@ __global__ __launch_bounds__(T) void k_ring_analysis(RingArgs a) {
         qn = cmul(qn, sn);
         qJ = cmul(qJ, sJ);
         // class 1: m = bin + jJ (j >= 0)
-        for (long long j = g;; j += G) {
+        for (long long j = g;; j += NG) {
             const long long m = bin + j * J;
             if (m > L) break;
             double2 v = (s & j & 1) ? make_double2(-Gb.x, -Gb.y) : Gb;
@@ -678,7 +713,7 @@ __global__ __launch_bounds__(T) void k_ring_analysis(RingArgs a) {
         }
         // class 2: m = jJ - bin (j >= 1); bins 0 and n are covered by class 1
         if (bin != 0 && bin != n) {
-            for (long long j = (g == 0 ? G : g);; j += G) {
+            for (long long j = (g == 0 ? NG : g);; j += NG) {
                 const long long m = j * J - bin;
                 if (m > L) break;
                 double2 v = cconj(Gb);
@@ -691,15 +726,24 @@ __global__ __launch_bounds__(T) void k_ring_analysis(RingArgs a) {
 
 template <int T>
 static hipError_t launch_analysis_classes(const sht_plan_s *p, RingArgs a, int nmaps, hipStream_t stream) {
-    hipError_t ea = allow_dynamic_lds((const void *)k_ring_analysis<T>, 160 * 1024);
-    if (ea != hipSuccess) return ea;
+    const void *fn[3] = {(const void *)k_ring_analysis<T, 1>, (const void *)k_ring_analysis<T, 2>,
+                         (const void *)k_ring_analysis<T, 4>};
+    for (const void *f : fn) {
+        hipError_t ea = allow_dynamic_lds(f, 160 * 1024);
+        if (ea != hipSuccess) return ea;
+    }
     for (const auto &rc : p->classes) {
         a.rings = rc.d_rings;
         a.count = (int)rc.rings.size();
         a.fft_entries = rc.lds_entries + rc.lds_entries / 16;
-        long long grid = ((long long)a.count * nmaps + 63) / 64 * 64;
-        size_t lds = (size_t)a.fft_entries * sizeof(double2);
-        hipLaunchKernelGGL(k_ring_analysis<T>, dim3((unsigned)grid), dim3(T), lds, stream, a);
+        a.mpw = ring_maps_per_wg(rc.lds_entries, nmaps);
+        long long grid = ((long long)a.count * nmaps / a.mpw + 63) / 64 * 64;
+        size_t lds = (size_t)a.mpw * a.fft_entries * sizeof(double2);
+        switch (a.mpw) {
+            case 1: hipLaunchKernelGGL((k_ring_analysis<T, 1>), dim3((unsigned)grid), dim3(T), lds, stream, a); break;
+            case 2: hipLaunchKernelGGL((k_ring_analysis<T, 2>), dim3((unsigned)grid), dim3(T), lds, stream, a); break;
+            default: hipLaunchKernelGGL((k_ring_analysis<T, 4>), dim3((unsigned)grid), dim3(T), lds, stream, a); break;
+        }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
