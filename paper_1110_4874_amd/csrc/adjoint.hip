@@ -8,13 +8,15 @@
 //
 // (the equator ring counts once).  The recurrence runs along l for every
 // ring, but the outputs are indexed by l and summed over rings, so one
-// workgroup owns one order m and a block of rings: each thread runs the
-// two-step recurrence (App. A.2 Eq. A2) for R rings and forms per-step
-// partial sums over them, and the workgroup adds the partials of each step
-// through double-buffered LDS in a fixed order (deterministic, no atomics, no
-// partial-sum workspace).  Rings nearest the poles run the recurrence in
-// double-double arithmetic in their own launch (writing g); the FP64 ring
-// blocks then add their share to g in place, launch after launch.
+// workgroup owns one order m and a block of rings, each thread running the
+// two-step recurrence (App. A.2 Eq. A2) for its rings.  Rings nearest the
+// poles run the recurrence in double-double arithmetic in their own launch
+// (k_legendre_adj: per-step partial sums over a thread's rings, added
+// through double-buffered LDS), writing g; the FP64 ring blocks then add
+// their share to g in place, launch after launch (k_legendre_adj_mf: the sum
+// over rings as FP64 MFMA products of Legendre tiles with the ring phases).
+// Every sum runs in a fixed order: deterministic, no atomics, no partial-sum
+// workspace.
 #include "internal.h"
 
 namespace sht {
@@ -379,6 +381,192 @@ __global__ __launch_bounds__(T) void k_legendre_adj(AdjArgs a) {
     }
 }
 
+// FP64 rings on the matrix cores: the sum over rings of each output is a
+// product P Y of the Legendre values P (chain step and parity by ring) with
+// the unfolded ring phases Y (ring by parity, map and re/im), so it runs as
+// MFMA 16x16x4 tiles with the rings as the contraction dimension.
+// 512 threads, one ring per lane (8 waves, 512 rings; two workgroups share a
+// CU, so that one computes while the other reduces).  Per block of 8
+// chain steps every lane writes its ring's 16 values (8 steps x 2 parities)
+// to its wave's LDS tile; the wave then multiplies the tile (rows: 8 t + u,
+// columns: its 64 rings) by its Y operands (16 per lane, in registers,
+// columns 8 t' + c for parity t', map c / 2, re/im c % 2) in 16 MFMAs; rows
+// and columns of the same parity are the outputs.  The 8 waves' tiles are
+// added through LDS in a fixed order (deterministic).  Chain starts and the
+// coefficient blocks follow k_legendre_adj.
+typedef double adj_d4 __attribute__((ext_vector_type(4)));
+// The value of lane K of each 16-lane row, in every lane of that row.
+template <int K>
+__device__ __forceinline__ double row_bcast64(double x) {
+    return __builtin_amdgcn_mov_dpp(x, 0x150 + K, 0xF, 0xF, false);
+}
+constexpr int kAdjMfThreads = 512;
+constexpr int kAdjMfRow = 65;  // doubles per tile row (64 rings and a pad)
+
+template <int NB>
+__global__ __launch_bounds__(kAdjMfThreads) void k_legendre_adj_mf(AdjArgs a) {
+    constexpr int T = kAdjMfThreads, SB = 8, CW = 8;
+    constexpr int CE = (kAdjCB * CW + T - 1) / T;
+    static_assert(2 * NB <= 8 && kChunk == SB && kAdjCB % SB == 0, "tile shape");
+    extern __shared__ double tiles[];  // [wave][16 rows][kAdjMfRow]
+    __shared__ double cbuf[2][kAdjCB * CW];
+    const int m = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int L = a.L;
+    const int n0 = (L - m) / 2 + 1;
+    const int n1 = (L - m >= 1) ? (L - m - 1) / 2 + 1 : 0;
+    const size_t aoff = (size_t)m * (2 * L + 3 - m) / 2;
+
+    __shared__ int s_lo, s_hi;
+    if (tid == 0) {
+        int lo = kDead, hi = -1;
+        for (int gr = a.k0 / kLanes; gr < (a.k1 + kLanes - 1) / kLanes; gr++) {
+            lo = min(lo, a.grp_lo[(size_t)m * a.ng + gr]);
+            hi = max(hi, a.grp_hi[(size_t)m * a.ng + gr]);
+        }
+        s_lo = lo;
+        s_hi = hi;
+    }
+    __syncthreads();
+    const int lo = s_lo, hi = s_hi;
+    auto gaddr = [&](int l, int b, int ri) { return a.g + 2 * ((aoff + l - m) * a.nmaps + a.map0 + b) + ri; };
+    if (lo >= n0) {
+        if (!a.accumulate)
+            for (int e = tid; e < (L - m + 1) * NB * 2; e += T) *gaddr(m + e / (NB * 2), (e / 2) % NB, e % 2) = 0.0;
+        return;
+    }
+
+    // this lane's ring
+    const int k = a.k0 + tid;
+    const bool val = k < a.k1 && k < a.n_north;
+    const int kk = val ? k : a.k0;
+    const double z2 = a.z2_hi[kk];
+    int sid[2];
+    double p0[2] = {0.0, 0.0}, p1[2] = {0.0, 0.0};
+    int wlo = kDead;
+#pragma unroll
+    for (int t = 0; t < 2; t++) {
+        sid[t] = val ? a.start_idx[(size_t)(2 * m + t) * a.np + kk] : kDead;
+        wlo = min(wlo, sid[t]);
+    }
+    wlo = __builtin_amdgcn_readfirstlane(wave_min(wlo));
+    // Y operands: MFMA j takes B[l / 16][l % 16] = Y_t'[ring 4 j + l / 16][c]
+    double yb[16];
+    {
+        const int cc = lane & 15, tp = cc >> 3, c = cc & 7, b = c >> 1, ri = c & 1;
+#pragma unroll
+        for (int j = 0; j < 16; j++) {
+            const int kr = a.k0 + 64 * wv + 4 * j + (lane >> 4);
+            double v = 0.0;
+            if (c < 2 * NB && kr < a.k1 && kr < a.n_north) {
+                const int ks = a.nrings - 1 - kr;
+                const double *yn = reinterpret_cast<const double *>(a.ybar + ((size_t)kr * (L + 1) + m) * a.nmaps +
+                                                                    a.map0 + b);
+                const double *ys = reinterpret_cast<const double *>(a.ybar + ((size_t)ks * (L + 1) + m) * a.nmaps +
+                                                                    a.map0 + b);
+                const double vn = yn[ri], vs = ks != kr ? ys[ri] : 0.0;
+                v = tp == 0 ? vn + vs : vn - vs;
+            }
+            yb[j] = v;
+        }
+    }
+
+    const long long cbase = a.coef_off[m];
+    const double *__restrict__ chd = a.coef_hi + 4 * cbase;
+    double creg[CE];
+    auto fetch_block = [&](int j) {
+#pragma unroll
+        for (int e = 0; e < CE; e++) {
+            const int el = tid + e * T;
+            const int step = lo + j * kAdjCB + el / CW;
+            const size_t idx = (size_t)(2 * step + 2) * 4 + el % CW;
+            creg[e] = (el < kAdjCB * CW && step <= n0) ? chd[idx] : 0.0;
+        }
+    };
+    auto stage_block = [&](int slot) {
+#pragma unroll
+        for (int e = 0; e < CE; e++)
+            if (tid + e * T < kAdjCB * CW) cbuf[slot][tid + e * T] = creg[e];
+    };
+    fetch_block(0);
+    stage_block(0);
+    fetch_block(1);
+    __syncthreads();
+
+    double *tile = tiles + (size_t)wv * 16 * kAdjMfRow;
+    // reduction role (threads 0..127): output row q, column 8 t(q) + c
+    const int rq = (tid >> 3) & 15, rc = tid & 7, rt = rq >> 3, ru = rq & 7;
+    const int rlane = 16 * (rq & 3) + 8 * rt + rc, rreg = rq >> 2;
+    const int nt = rt == 0 ? n0 : n1;
+    for (int g0 = lo; g0 < n0; g0 += SB) {
+        const int j = (g0 - lo) / kAdjCB, s0 = (g0 - lo) % kAdjCB;
+        // the output this thread adds, fetched before the block's work
+        const int is = g0 + ru;
+        double gold = 0.0;
+        if (a.accumulate && tid < 128 && rc < 2 * NB && is < nt) gold = *gaddr(m + rt + 2 * is, rc >> 1, rc & 1);
+        adj_d4 acc = {0.0, 0.0, 0.0, 0.0};
+        if (g0 + SB > wlo) {
+            if ((g0 % kChunk) == 0 && g0 <= hi) {
+#pragma unroll
+                for (int t = 0; t < 2; t++)
+                    if (sid[t] == g0) {  // the chain's two start values, loaded once
+                        const size_t row = (size_t)(2 * m + t);
+                        p0[t] = a.start_val[(row * 2 + 0) * a.np + kk];
+                        p1[t] = a.start_val[(row * 2 + 1) * a.np + kk];
+                    }
+            }
+#pragma unroll
+            for (int u = 0; u < SB; u++) {
+                // the step's 8 coefficients, one per lane of each 8, reach
+                // every lane by DPP broadcasts (one LDS read instead of two
+                // 32-byte broadcast reads)
+                const double cv = cbuf[j & 1][(s0 + u) * CW + (lane & 7)];
+                const double eB = row_bcast64<0>(cv), eAB = row_bcast64<1>(cv), eG = row_bcast64<2>(cv);
+                const double oB = row_bcast64<4>(cv), oAB = row_bcast64<5>(cv), oG = row_bcast64<6>(cv);
+                tile[u * kAdjMfRow + lane] = p0[0];
+                tile[(8 + u) * kAdjMfRow + lane] = p0[1];
+                const double ne = __builtin_fma(__builtin_fma(z2, eB, eAB), p1[0], eG * p0[0]);
+                const double no = __builtin_fma(__builtin_fma(z2, oB, oAB), p1[1], oG * p0[1]);
+                p0[0] = p1[0];
+                p1[0] = ne;
+                p0[1] = p1[1];
+                p1[1] = no;
+            }
+            // the wave's own tile: its LDS writes and reads complete in order
+#pragma unroll
+            for (int jj = 0; jj < 16; jj++)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(tile[(lane & 15) * kAdjMfRow + 4 * jj + (lane >> 4)],
+                                                           yb[jj], acc, 0, 0, 0);
+        }
+        // the wave's 16 x 16 sums (element r of lane l: row l / 16 + 4 r,
+        // column l % 16) replace its tile, then the waves are added
+#pragma unroll
+        for (int r = 0; r < 4; r++) tile[r * 64 + lane] = acc[r];
+        __syncthreads();
+        if ((g0 - lo) % kAdjCB == 0) {  // next coefficient block to LDS, the one after fetched
+            stage_block((j + 1) & 1);
+            fetch_block(j + 2);
+        }
+        if (tid < 128 && rc < 2 * NB) {
+            double sum = 0.0;
+#pragma unroll
+            for (int w = 0; w < T / 64; w++) sum += tiles[(size_t)w * 16 * kAdjMfRow + rreg * 64 + rlane];
+            if (is < nt) {
+                sum += gold;
+                if (m == 0 && (rc & 1)) sum = 0.0;
+                *gaddr(m + rt + 2 * is, rc >> 1, rc & 1) = sum;
+            }
+        }
+        __syncthreads();
+    }
+    if (!a.accumulate) {
+        for (int e = tid; e < 2 * lo * NB * 2 && e < (L - m + 1) * NB * 2; e += T) {
+            const int l = m + e / (NB * 2);
+            if (l - m < 2 * lo) *gaddr(l, (e / 2) % NB, e % 2) = 0.0;
+        }
+    }
+}
+
 // Defined with the ring kernels: raises a kernel's dynamic LDS limit once
 // per (kernel, device).
 hipError_t allow_dynamic_lds(const void *fn, int bytes);
@@ -392,15 +580,13 @@ static hipError_t launch_adj_cfg(const sht_plan_s *p, AdjArgs a, hipStream_t st)
     return hipGetLastError();
 }
 
-// FP64 rings: 256 threads, R rings each (R = 1, 2, 4 by the ring count, at
-// most kAdjFpRings rings per launch).
-constexpr int kAdjFpRings = 1024;
 template <int NB>
-static hipError_t launch_adj_fp(const sht_plan_s *p, AdjArgs a, hipStream_t st) {
-    const int nr = a.k1 - a.k0;
-    if (nr <= 256) return launch_adj_cfg<256, 1, NB, false>(p, a, st);
-    if (nr <= 512) return launch_adj_cfg<256, 2, NB, false>(p, a, st);
-    return launch_adj_cfg<256, 4, NB, false>(p, a, st);
+static hipError_t launch_adj_mf(const sht_plan_s *p, AdjArgs a, hipStream_t st) {
+    const size_t lds = (size_t)(kAdjMfThreads / 64) * 16 * kAdjMfRow * sizeof(double);
+    hipError_t ea = allow_dynamic_lds((const void *)k_legendre_adj_mf<NB>, (int)lds);
+    if (ea != hipSuccess) return ea;
+    hipLaunchKernelGGL((k_legendre_adj_mf<NB>), dim3((unsigned)(p->L + 1)), dim3(kAdjMfThreads), lds, st, a);
+    return hipGetLastError();
 }
 
 // Double-double rings: 256 threads, one ring each (at most 256 per launch).
@@ -433,25 +619,30 @@ hipError_t launch_legendre_adjoint(const sht_plan_s *p, int nmaps, const double 
     a.nmaps = nmaps;
     hipError_t e = hipSuccess;
     const int kdd = std::min(p->n_dd_pad, p->n_north);
+    // polar rings (double-double) first, two maps per pass, in chunks of 256
+    // rings; the first chunk writes g
     for (int b = 0; b < nmaps && e == hipSuccess;) {
         const int nb = (nmaps - b) >= 2 ? 2 : 1;
         a.map0 = b;
-        bool wrote = false;
-        // polar rings (double-double), in chunks of 256 rings
         for (int k0 = 0; k0 < kdd && e == hipSuccess; k0 += 256) {
             a.k0 = k0;
             a.k1 = std::min(kdd, k0 + 256);
-            a.accumulate = wrote ? 1 : 0;
+            a.accumulate = k0 > 0 ? 1 : 0;
             e = nb == 2 ? launch_adj_dd<2>(p, a, stream) : launch_adj_dd<1>(p, a, stream);
-            wrote = true;
         }
-        // the remaining rings in FP64, in chunks of up to kAdjFpRings rings
-        for (int k0 = kdd; k0 < p->n_north && e == hipSuccess; k0 += kAdjFpRings) {
+        b += nb;
+    }
+    // the remaining rings in FP64 on the matrix cores, up to four maps per
+    // pass, in chunks of kAdjMfThreads rings, each adding to g
+    for (int b = 0; b < nmaps && e == hipSuccess;) {
+        const int nb = (nmaps - b) >= 4 ? 4 : (nmaps - b) >= 2 ? 2 : 1;
+        a.map0 = b;
+        for (int k0 = kdd; k0 < p->n_north && e == hipSuccess; k0 += kAdjMfThreads) {
             a.k0 = k0;
-            a.k1 = std::min(p->n_north, k0 + kAdjFpRings);
-            a.accumulate = wrote ? 1 : 0;
-            e = nb == 2 ? launch_adj_fp<2>(p, a, stream) : launch_adj_fp<1>(p, a, stream);
-            wrote = true;
+            a.k1 = std::min(p->n_north, k0 + kAdjMfThreads);
+            a.accumulate = (kdd > 0 || k0 > kdd) ? 1 : 0;
+            e = nb == 4 ? launch_adj_mf<4>(p, a, stream)
+                        : nb == 2 ? launch_adj_mf<2>(p, a, stream) : launch_adj_mf<1>(p, a, stream);
         }
         b += nb;
     }
