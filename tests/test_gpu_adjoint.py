@@ -49,7 +49,9 @@ def _ybar_numpy(L, N, maps, wpos):
 
 
 @pytest.mark.parametrize("L,N,B", [(0, 1, 1), (5, 1, 1), (31, 16, 2), (40, 16, 3), (70, 12, 1),
-                                   (100, 24, 5), (127, 64, 2)])
+                                   (100, 24, 5), (127, 64, 2),
+                                   # 600 north rings: two FP64 ring chunks, the second partial
+                                   (700, 300, 4)])
 def test_adjoint_parity(gpu, L, N, B):
     maps = _maps(N, B, 900)
     p = gpu.Plan(L, N)
