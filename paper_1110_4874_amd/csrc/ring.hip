@@ -25,8 +25,13 @@
 // M >= 2h-1 (forward decimation in frequency, pointwise product with the
 // plan's chirp spectrum, backward decimation in time), the first result
 // waiting in registers; z_p = A_p + w^p B_p, z_{p+h} = A_p - w^p B_p with
-// w = e^{2 pi i/n}.  This halves the LDS of the longest polar rings.  LDS indices are padded by one
-// entry per 16 to spread strided accesses over the banks.  One workgroup
+// w = e^{2 pi i/n}.  This halves the LDS of the longest polar rings.  The
+// zero padding of each convolution input is implied (the first forward pass
+// reads the entries past h as zeros), so it is never stored.  LDS indices
+// are padded by one entry per 16 to spread strided accesses over the banks.
+// Global loads (q columns, chirps, chirp spectra, pixels) are issued in
+// batches before their first use, so that a thread waits for memory once per
+// batch rather than once per value.  One workgroup
 // owns one (ring, map); the maps of a ring are adjacent in the ring-major q
 // layout and their workgroups run back to back on the same XCD (dispatch is
 // round-robin over 8 XCDs), so lines read from HBM serve them all from L2.
@@ -45,6 +50,14 @@ constexpr int kMaxHalf = 2048;      // half length h of the largest Bluestein ri
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// Complex product with a fixed rounding pattern (explicit fused multiply-adds)
+// for the chirp products, whose loops take different shapes in different
+// kernels (batched loads or one at a time): whichever way the compiler would
+// contract the plain expression there, the ring kernels of one plan (one map
+// per workgroup, several, or the batch queue) agree bit for bit.
+__device__ __forceinline__ double2 cmul_fixed(double2 a, double2 b) {
+    return make_double2(__builtin_fma(a.x, b.x, -(a.y * b.y)), __builtin_fma(a.x, b.y, a.y * b.x));
 }
 __device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
@@ -122,7 +135,7 @@ __device__ __forceinline__ void dit_pass(double2 *a, int lg, int s, const double
 // difference.
 template <int r>
 __device__ __forceinline__ void dif_pass(double2 *a, int lg, int s, const double2 *__restrict__ tw,
-                                         int tw_log, int tid, int nt) {
+                                         int tw_log, int tid, int nt, int nz) {
     constexpr int R = 1 << r;
     const int n = 1 << lg, h = 1 << (s - 1);
 #pragma unroll 1
@@ -131,7 +144,7 @@ __device__ __forceinline__ void dif_pass(double2 *a, int lg, int s, const double
         const int base = (gi >> (s - 1)) * (R * h) + pos;
         double2 x[R];
 #pragma unroll
-        for (int k = 0; k < R; k++) x[k] = a[pidx(base + k * h)];
+        for (int k = 0; k < R; k++) x[k] = base + k * h < nz ? a[pidx(base + k * h)] : make_double2(0.0, 0.0);
         double2 wp[r];
         wp[r - 1] = tw[pos << (tw_log - (s - 1) - r)];
 #pragma unroll
@@ -167,22 +180,51 @@ __device__ void fft_dit_inv(double2 *a, int lg, const double2 *__restrict__ tw, 
     else if (lg - s + 1 == 1) dit_pass<1>(a, lg, s, tw, tw_log, tid, nt);
 }
 
-// Forward DFT of size 2^lg, natural input, bit-reversed output.
-__device__ void fft_dif_fwd(double2 *a, int lg, const double2 *__restrict__ tw, int tw_log, int tid, int nt) {
-    const int rem = lg % 3;
+// Forward DFT of size 2^lg, natural input, bit-reversed output; the inputs
+// past the first nz are zero (the first pass reads them as such, so they
+// need not be stored).
+__device__ void fft_dif_fwd(double2 *a, int lg, const double2 *__restrict__ tw, int tw_log, int tid, int nt,
+                            int nz) {
+    const int n = 1 << lg, rem = lg % 3;
     int s = lg - 2;
     while (s >= 1 + rem) {
-        dif_pass<3>(a, lg, s, tw, tw_log, tid, nt);
+        dif_pass<3>(a, lg, s, tw, tw_log, tid, nt, s == lg - 2 ? nz : n);
         s -= 3;
     }
-    if (rem == 2) dif_pass<2>(a, lg, 1, tw, tw_log, tid, nt);
-    else if (rem == 1) dif_pass<1>(a, lg, 1, tw, tw_log, tid, nt);
+    if (rem == 2) dif_pass<2>(a, lg, 1, tw, tw_log, tid, nt, lg == 2 ? nz : n);
+    else if (rem == 1) dif_pass<1>(a, lg, 1, tw, tw_log, tid, nt, lg == 1 ? nz : n);
+}
+
+// buf[pidx(i)] *= X[i] for the entries i = tid + j nt < cnt (j < PT) of one
+// thread, up to NB loads of X in flight before the first product (loads
+// past cnt read X[cnt - 1] and are dropped).
+template <int PT, int NB>
+__device__ __forceinline__ void lds_cmul(double2 *buf, const double2 *__restrict__ X, int cnt, int tid, int nt) {
+    constexpr int B = PT < NB ? PT : NB;
+    if (B == 1) {  // one load at a time
+        for (int i = tid; i < cnt; i += nt) buf[pidx(i)] = cmul_fixed(buf[pidx(i)], X[i]);
+        return;
+    }
+#pragma unroll
+    for (int j0 = 0; j0 < PT; j0 += B) {
+        double2 x[B];
+#pragma unroll
+        for (int j = 0; j < B; j++) x[j] = X[min(tid + (j0 + j) * nt, cnt - 1)];
+#pragma unroll
+        for (int j = 0; j < B; j++) {
+            const int i = tid + (j0 + j) * nt;
+            if (i < cnt) buf[pidx(i)] = cmul_fixed(buf[pidx(i)], x[j]);
+        }
+    }
 }
 
 // Unnormalised backward DFT of size n in LDS: z_p = sum_k Z_k e^{+2 pi i k p/n}.
 // On entry the buffer holds Z_k at pidx(bitrev(k)) (n a power of two, M = 0)
-// or the chirp-weighted u_k = Z_k W_k, W_k = e^{i pi k^2/n}, at pidx(k) with
-// zeros up to M (Bluestein); on exit z_p is at pidx(p), p < n.
+// or the chirp-weighted u_k = Z_k W_k, W_k = e^{i pi k^2/n}, at pidx(k), k < n
+// (Bluestein: the zero padding up to M is implied, entries n..M-1 are not
+// read); on exit z_p is at pidx(p), p < n.  PT bounds M / nt (and so
+// 2n / nt); NB loads of V or W per thread are in flight at once.
+template <int PT, int NB>
 __device__ __forceinline__ void backward_dft(double2 *buf, int n, int M, const double2 *__restrict__ V,
                                              const double2 *__restrict__ W, const double2 *__restrict__ tw,
                                              int tw_log, int tid, int nt) {
@@ -191,38 +233,81 @@ __device__ __forceinline__ void backward_dft(double2 *buf, int n, int M, const d
         return;
     }
     const int lgM = ilog2_dev(M);
-    fft_dif_fwd(buf, lgM, tw, tw_log, tid, nt);
-    for (int i = tid; i < M; i += nt) buf[pidx(i)] = cmul(buf[pidx(i)], V[i]);
+    fft_dif_fwd(buf, lgM, tw, tw_log, tid, nt, n);
+    lds_cmul<PT, NB>(buf, V, M, tid, nt);
     __syncthreads();
     fft_dit_inv(buf, lgM, tw, tw_log, tid, nt);
-    for (int p = tid; p < n; p += nt) buf[pidx(p)] = cmul(buf[pidx(p)], W[p]);
+    lds_cmul<(PT > 1 ? PT / 2 : 1), NB>(buf, W, n, tid, nt);
     __syncthreads();
 }
 
-// Raw wrap sum of bin b (before the common phase) over every order,
-// restricted to terms j = g (mod G): class 1 m = b + jJ (j >= 0), class 2
-// m = jJ - b (j >= 1), read straight from the ring's q column (stride qs).
-__device__ __forceinline__ double2 bin_direct(const double2 *__restrict__ qr, size_t qs, int L, int J, int s, int b,
-                                              int g, int G) {
-    double2 acc = make_double2(0.0, 0.0);
-#pragma unroll 4
-    for (int j = g;; j += G) {
-        const int m = b + j * J;
-        if (m > L) break;
-        double2 v = qr[(size_t)m * qs];
-        if (m == 0) v.y = 0.0;  // real part of q_0 only
-        if (s & j & 1) v = make_double2(-v.x, -v.y);
-        acc = cadd(acc, v);
+// Raw wrap sums (before the common phase) of the NBIN bins bin[p] of one
+// thread (bins with on[p] false give 0) over every order, restricted to the
+// terms j = g (mod G): class 1 m = b + jJ (j >= 0), then class 2 m = jJ - b
+// (j >= 1), each in increasing j, read straight from the ring's q column
+// (stride qs).  Loads go in rounds of U terms of every bin: all of a round's
+// loads are issued before the first is added (loads past a bin's last term
+// take order 0 and are dropped), so a thread waits for memory once per
+// round rather than once per term.
+template <int NBIN, int U>
+__device__ __forceinline__ void bins_direct(const double2 *__restrict__ qr, size_t qs, int L, int J, int s,
+                                            const int (&bin)[NBIN], const bool (&on)[NBIN], int g, int G,
+                                            double2 (&acc)[NBIN]) {
+    const int g2 = g == 0 ? G : g;  // first j of class 2
+    int c1[NBIN], c2[NBIN];         // terms of each class (m <= L: j <= (L -+ b) / J)
+    int r1 = 0, r2 = 0;
+#pragma unroll
+    for (int p = 0; p < NBIN; p++) {
+        acc[p] = make_double2(0.0, 0.0);
+        const int j1 = (L - bin[p]) / J, j2 = (L + bin[p]) / J;
+        c1[p] = on[p] && j1 >= g ? (j1 - g) / G + 1 : 0;
+        c2[p] = on[p] && j2 >= g2 ? (j2 - g2) / G + 1 : 0;
+        r1 = max(r1, c1[p]);
+        r2 = max(r2, c2[p]);
     }
-#pragma unroll 4
-    for (int j = g == 0 ? G : g;; j += G) {
-        const int m = j * J - b;
-        if (m > L) break;
-        double2 v = cconj(qr[(size_t)m * qs]);
-        if (s & j & 1) v = make_double2(-v.x, -v.y);
-        acc = cadd(acc, v);
+    for (int i0 = 0; i0 < r1; i0 += U) {
+        double2 v[NBIN][U];
+#pragma unroll
+        for (int p = 0; p < NBIN; p++)
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const int i = min(i0 + u, c1[p] - 1);
+                v[p][u] = qr[(size_t)(i < 0 ? 0 : bin[p] + (g + i * G) * J) * qs];
+            }
+#pragma unroll
+        for (int p = 0; p < NBIN; p++)
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const int j = g + (i0 + u) * G;
+                if (i0 + u < c1[p]) {
+                    double2 x = v[p][u];
+                    if (bin[p] + j * J == 0) x.y = 0.0;  // real part of q_0 only
+                    if (s & j & 1) x = make_double2(-x.x, -x.y);
+                    acc[p] = cadd(acc[p], x);
+                }
+            }
     }
-    return acc;
+    for (int i0 = 0; i0 < r2; i0 += U) {
+        double2 v[NBIN][U];
+#pragma unroll
+        for (int p = 0; p < NBIN; p++)
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const int i = min(i0 + u, c2[p] - 1);
+                v[p][u] = qr[(size_t)(i < 0 ? 0 : (g2 + i * G) * J - bin[p]) * qs];
+            }
+#pragma unroll
+        for (int p = 0; p < NBIN; p++)
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const int j = g2 + (i0 + u) * G;
+                if (i0 + u < c2[p]) {
+                    double2 x = cconj(v[p][u]);
+                    if (s & j & 1) x = make_double2(-x.x, -x.y);
+                    acc[p] = cadd(acc[p], x);
+                }
+            }
+    }
 }
 
 // Synthesis of one ring of one map (item = ring position in the class's
@@ -231,9 +316,10 @@ __device__ __forceinline__ double2 bin_direct(const double2 *__restrict__ qr, si
 // groups for maps of one ring (identical control flow, so the workgroup's
 // barriers match); a ring whose transform size is at most 4096 nt / T keeps
 // the per-thread counts within those sized for T.
-template <int T, int nt>
+template <int T, int nt, int kNB>
 __device__ __forceinline__ void ring_synth_item(const RingArgs &a, const int item, const int tid, double2 *buf) {
     constexpr int kPairsPerThread = (kMaxPairs + T - 1) / T;
+    constexpr int kMPerThread = (2 * kMaxHalf + T - 1) / T;  // Bluestein size M <= 2 kMaxHalf
     const int pos = item / a.nmaps, b = item % a.nmaps;
     const int rho = a.rings[pos];
     const int J = a.ring_J[rho], s = a.ring_s[rho], M = a.ring_M[rho];
@@ -267,50 +353,83 @@ __device__ __forceinline__ void ring_synth_item(const RingArgs &a, const int ite
         }
     } else if (2 * n > L) {
         // J > L: bin b <= n collects m = b and, when J - b <= L, m = J - b
-        // (conjugated, sign (-1)^s); direct loads as above, no staging
+        // (conjugated, sign (-1)^s); bin n (pair k = 0) collects m = n
+        // (j = 0) and m = J - n = n (j = 1, conjugated).  Direct loads, no
+        // staging: the four loads of every pair of a chunk of kCH pairs are
+        // issued (at valid orders) before any is used, and the optional
+        // terms enter by selection
         const double sg = (s & 1) ? -1.0 : 1.0;
         const int J2 = 2 * n;
+        constexpr int kCH = kPairsPerThread < 3 ? kPairsPerThread : 3;
 #pragma unroll
-        for (int j = 0; j < kPairsPerThread; j++) {
-            const int k = tid + j * nt;
-            if (k < npair) {
-                double2 v = qr[(size_t)k * qstride];  // k <= n <= L
-                if (k == 0) v.y = 0.0;
-                if (J2 - k <= L) {
-                    const double2 w = qr[(size_t)(J2 - k) * qstride];
-                    v = make_double2(v.x + sg * w.x, v.y - sg * w.y);
-                }
-                xa[j] = v;
-                if (k != 0) {
-                    const int b = n - k;  // 0 < b < n
-                    double2 u = qr[(size_t)b * qstride];
-                    if (J2 - b <= L) {
-                        const double2 w = qr[(size_t)(J2 - b) * qstride];
-                        u = make_double2(u.x + sg * w.x, u.y - sg * w.y);
-                    }
-                    xb[j] = u;
-                } else {
-                    // bin n: m = n (j = 0) and m = J - n = n (j = 1, conjugated)
-                    const double2 w = qr[(size_t)n * qstride];
-                    xb[j] = make_double2(w.x + sg * w.x, w.y - sg * w.y);
+        for (int j0 = 0; j0 < kPairsPerThread; j0 += kCH) {
+            double2 v[kCH][4];
+#pragma unroll
+            for (int c = 0; c < kCH; c++) {
+                const int k = tid + (j0 + c) * nt;
+                const int kc = j0 + c < kPairsPerThread && k < npair ? k : 0;
+                const int b = kc == 0 ? n : n - kc;  // second bin, 0 < b <= n
+                v[c][0] = qr[(size_t)kc * qstride];  // kc <= n <= L
+                v[c][1] = qr[(size_t)(J2 - kc <= L ? J2 - kc : 0) * qstride];
+                v[c][2] = qr[(size_t)b * qstride];
+                v[c][3] = qr[(size_t)(kc == 0 ? n : (J2 - b <= L ? J2 - b : 0)) * qstride];
+            }
+#pragma unroll
+            for (int c = 0; c < kCH; c++) {
+                const int j = j0 + c, k = tid + j * nt;
+                if (j < kPairsPerThread && k < npair) {
+                    const int b = k == 0 ? n : n - k;
+                    double2 x = v[c][0];
+                    if (k == 0) x.y = 0.0;
+                    const double2 xw = make_double2(x.x + sg * v[c][1].x, x.y - sg * v[c][1].y);
+                    xa[j] = J2 - k <= L ? xw : x;
+                    const double2 u = v[c][2];
+                    const double2 uw = make_double2(u.x + sg * v[c][3].x, u.y - sg * v[c][3].y);
+                    xb[j] = k == 0 || J2 - b <= L ? uw : u;
                 }
             }
+            asm volatile("" ::: "memory");  // keep the next chunk's loads after this one's uses
         }
     } else {
         // J <= L: every bin collects several orders; each thread sums the
         // orders of its bins (terms j = g mod G) straight from q, in a fixed
-        // order, with its loads independent of each other
+        // order: pair k owns bins k and n - k (bin n for k = 0, none for
+        // 2k = n)
         G = npair >= nt ? 1 : nt / npair;
+        if (npair <= nt) {
+            // one pair per thread (G groups of npair threads), four terms
+            // of each bin per round of loads
+            const int g = tid / npair, k = tid % npair;
+            const int bn[2] = {k, k == 0 ? n : n - k};
+            const bool on[2] = {g < G, g < G && 2 * k != n};
+            double2 acc[2];
+            bins_direct<2, 4>(qr, qstride, L, J, s, bn, on, g, G, acc);
+            xa[0] = acc[0];
+            xb[0] = acc[1];
+        } else {
+            // several pairs per thread (G = 1): rounds of one term of each
+            // of up to 2 kCP bins
+            constexpr int kCP = kPairsPerThread < 3 ? kPairsPerThread : 3;
 #pragma unroll
-        for (int j = 0; j < kPairsPerThread; j++) {
-            const int u = tid + j * nt;
-            const int g = u / npair, k = u % npair;
-            if (g < G) {
-                xa[j] = bin_direct(qr, qstride, L, J, s, k, g, G);
-                if (k != 0 && 2 * k != n)
-                    xb[j] = bin_direct(qr, qstride, L, J, s, n - k, g, G);
-                else if (k == 0)
-                    xb[j] = bin_direct(qr, qstride, L, J, s, n, g, G);
+            for (int j0 = 0; j0 < kPairsPerThread; j0 += kCP) {
+                int bn[2 * kCP];
+                bool on[2 * kCP];
+#pragma unroll
+                for (int c = 0; c < kCP; c++) {
+                    const int k = tid + (j0 + c) * nt;
+                    bn[2 * c] = k;
+                    bn[2 * c + 1] = k == 0 ? n : n - k;
+                    on[2 * c] = j0 + c < kPairsPerThread && k < npair;
+                    on[2 * c + 1] = on[2 * c] && 2 * k != n;
+                }
+                double2 acc[2 * kCP];
+                bins_direct<2 * kCP, 1>(qr, qstride, L, J, s, bn, on, 0, 1, acc);
+#pragma unroll
+                for (int c = 0; c < kCP; c++)
+                    if (j0 + c < kPairsPerThread) {
+                        xa[j0 + c] = acc[2 * c];
+                        xb[j0 + c] = acc[2 * c + 1];
+                    }
             }
         }
         if (G > 1) {
@@ -350,8 +469,24 @@ __device__ __forceinline__ void ring_synth_item(const RingArgs &a, const int ite
     }
     double2 pn = expipi((double)tid / n);
     const double2 sn = expipi((double)nt / n);
+    // Bluestein chirp weights W[kp], W[kq] of a chunk of kCW pairs loaded
+    // (at clamped, valid indices) before the chunk's first use
+    constexpr int kCW = kPairsPerThread < 3 ? kPairsPerThread : 3;
 #pragma unroll
-    for (int j = 0; j < kPairsPerThread; j++) {
+    for (int j0 = 0; j0 < kPairsPerThread; j0 += kCW) {
+    double2 wv[kCW][2];
+    if (bs) {
+#pragma unroll
+        for (int c = 0; c < kCW; c++) {
+            const int k = tid + (j0 + c) * nt, odd = k & 1;
+            wv[c][0] = W[max(0, min((k - odd) / 2, h - 1))];
+            wv[c][1] = W[max(0, min((n - k - odd) / 2, h - 1))];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < kCW; c++) {
+        const int j = j0 + c;
+        if (j >= kPairsPerThread) break;
         const int k = tid + j * nt;
         if (k < npair && !(G > 1 && j > 0)) {
         double2 Xk = xa[j], Xnk = xb[j];
@@ -377,21 +512,22 @@ __device__ __forceinline__ void ring_synth_item(const RingArgs &a, const int ite
             if (two) buf[pidx(bitrev(n - k, lgn))] = Znk;
         } else {
             const int odd = k & 1, kp = (k - odd) / 2;
-            buf[pidx(kp + odd * h)] = cmul(Zk, W[kp]);
+            buf[pidx(kp + odd * h)] = cmul(Zk, wv[c][0]);
             if (two) {
                 const int kq = (n - k - odd) / 2;
-                buf[pidx(kq + odd * h)] = cmul(Znk, W[kq]);
+                buf[pidx(kq + odd * h)] = cmul(Znk, wv[c][1]);
             }
         }
         }
         pJ = cmul(pJ, sJ);
         pn = cmul(pn, sn);
     }
+    }
     __syncthreads();
     // pixel 2p = Re z_p, pixel 2p+1 = Im z_p
     double2 *out = reinterpret_cast<double2 *>(a.map + (size_t)b * a.npix + a.ring_off[rho]);
     if (!bs) {
-        backward_dft(buf, n, 0, nullptr, nullptr, a.tw, a.tw_log, tid, nt);
+        backward_dft<kMPerThread, kNB>(buf, n, 0, nullptr, nullptr, a.tw, a.tw_log, tid, nt);
         for (int p = tid; p < n; p += nt) out[p] = buf[pidx(p)];
         return;
     }
@@ -407,9 +543,7 @@ __device__ __forceinline__ void ring_synth_item(const RingArgs &a, const int ite
         if (p < h) R[jj] = buf[pidx(h + p)];
     }
     __syncthreads();
-    for (int i = h + tid; i < M; i += nt) buf[pidx(i)] = make_double2(0.0, 0.0);
-    __syncthreads();
-    backward_dft(buf, h, M, V, W, a.tw, a.tw_log, tid, nt);
+    backward_dft<kMPerThread, kNB>(buf, h, M, V, W, a.tw, a.tw_log, tid, nt);
 #pragma unroll
     for (int jj = 0; jj < kHalfPerThread; jj++) {
         const int p = tid + jj * nt;
@@ -419,9 +553,8 @@ __device__ __forceinline__ void ring_synth_item(const RingArgs &a, const int ite
             buf[pidx(p)] = odd_in;
         }
     }
-    for (int i = h + tid; i < M; i += nt) buf[pidx(i)] = make_double2(0.0, 0.0);
     __syncthreads();
-    backward_dft(buf, h, M, V, W, a.tw, a.tw_log, tid, nt);
+    backward_dft<kMPerThread, kNB>(buf, h, M, V, W, a.tw, a.tw_log, tid, nt);
     double2 wp = expipi(2.0 * tid / n);  // e^{2 pi i p/n}, stepped as above
     const double2 ws = expipi(2.0 * nt / n);
 #pragma unroll
@@ -446,8 +579,8 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(T == 512 ? 4 
     const int item0 = xcd_item(blockIdx.x) * G;
     if (item0 >= a.count * a.nmaps) return;
     // (one group: the plain thread index and LDS base keep 26 fewer VGPRs)
-    if (G == 1) ring_synth_item<T, nt>(a, item0, threadIdx.x, sm);
-    else ring_synth_item<T, nt>(a, item0 + sub, threadIdx.x - sub * nt, sm + (size_t)sub * (a.fft_entries + a.stage));
+    if (G == 1) ring_synth_item<T, nt, (T >= 512 ? 8 : 1)>(a, item0, threadIdx.x, sm);
+    else ring_synth_item<T, nt, 1>(a, item0 + sub, threadIdx.x - sub * nt, sm + (size_t)sub * (a.fft_entries + a.stage));
 }
 
 // Ring queue of a batch of requests: one launch per ring size class for all
@@ -462,7 +595,7 @@ __global__ __launch_bounds__(T) void k_ring_synth_queue(const RingArgs *__restri
     const int2 it = items[j];
     extern __shared__ double2 sm[];
     const RingArgs a = args[__builtin_amdgcn_readfirstlane(it.x)];
-    ring_synth_item<T, T>(a, __builtin_amdgcn_readfirstlane(it.y), threadIdx.x, sm);
+    ring_synth_item<T, T, 1>(a, __builtin_amdgcn_readfirstlane(it.y), threadIdx.x, sm);
 }
 
 // Raises a kernel's dynamic LDS limit to `bytes`, once per (kernel, device):
@@ -641,21 +774,57 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(T == 512 ? 4 
     double2 *yr = a.ybar + (size_t)rho * (L + 1) * a.nmaps + b;
 
     const double2 *pix = reinterpret_cast<const double2 *>(a.map_in + (size_t)b * a.npix + a.ring_off[rho]);
+    constexpr int kMPerThread = (2 * kMaxHalf + T - 1) / T;  // n / nt, or M / nt for Bluestein rings
+    constexpr int kLdMax = G == 1 && T >= 512 ? 8 : 1;  // input loads in flight per thread (registers permitting)
+    constexpr int kLd = kMPerThread < kLdMax ? kMPerThread : kLdMax;
+    constexpr int kNB = G == 1 && T >= 512 ? 8 : 1;  // chirp loads in flight (registers permitting)
     if (!bs) {
-        for (int p = tid; p < n; p += nt) buf[pidx(bitrev(p, lgn))] = cconj(pix[p]);
+        if (kLd == 1) {
+            for (int p = tid; p < n; p += nt) buf[pidx(bitrev(p, lgn))] = cconj(pix[p]);
+        } else {
+#pragma unroll
+            for (int j0 = 0; j0 < kMPerThread; j0 += kLd) {
+                double2 x[kLd];
+#pragma unroll
+                for (int j = 0; j < kLd; j++) x[j] = pix[min(tid + (j0 + j) * nt, n - 1)];
+#pragma unroll
+                for (int j = 0; j < kLd; j++) {
+                    const int p = tid + (j0 + j) * nt;
+                    if (p < n) buf[pidx(bitrev(p, lgn))] = cconj(x[j]);
+                }
+            }
+        }
         __syncthreads();
-        backward_dft(buf, n, 0, nullptr, nullptr, a.tw, a.tw_log, tid, nt);
+        backward_dft<kMPerThread, kNB>(buf, n, 0, nullptr, nullptr, a.tw, a.tw_log, tid, nt);
     } else {
         // split Bluestein: even inputs (hh = 0), then odd inputs (hh = 1)
         constexpr int kHalfPerThread = (kMaxHalf + T - 1) / T;
+        constexpr int kLdH = kHalfPerThread < kLdMax ? kHalfPerThread : kLdMax;
         const int h = n / 2;
         const double2 *__restrict__ V = a.bs_table + a.ring_bs_off[rho];
         double2 A[kHalfPerThread];
         for (int hh = 0; hh < 2; hh++) {
-            for (int i = h + tid; i < M; i += nt) buf[pidx(i)] = make_double2(0.0, 0.0);
-            for (int p = tid; p < h; p += nt) buf[pidx(p)] = cmul(cconj(pix[2 * p + hh]), W[p]);
+            if (kLdH == 1) {
+                for (int p = tid; p < h; p += nt) buf[pidx(p)] = cmul(cconj(pix[2 * p + hh]), W[p]);
+            } else {
+#pragma unroll
+                for (int j0 = 0; j0 < kHalfPerThread; j0 += kLdH) {
+                    double2 x[kLdH], w[kLdH];
+#pragma unroll
+                    for (int j = 0; j < kLdH; j++) {
+                        const int pc = min(tid + (j0 + j) * nt, h - 1);
+                        x[j] = pix[2 * pc + hh];
+                        w[j] = W[pc];
+                    }
+#pragma unroll
+                    for (int j = 0; j < kLdH; j++) {
+                        const int p = tid + (j0 + j) * nt;
+                        if (p < h) buf[pidx(p)] = cmul(cconj(x[j]), w[j]);
+                    }
+                }
+            }
             __syncthreads();
-            backward_dft(buf, h, M, V, W, a.tw, a.tw_log, tid, nt);
+            backward_dft<kMPerThread, kNB>(buf, h, M, V, W, a.tw, a.tw_log, tid, nt);
             if (hh == 0) {
 #pragma unroll
                 for (int jj = 0; jj < kHalfPerThread; jj++) {
