@@ -89,7 +89,29 @@ int interp_decomp(double *A, int r, int c, double tol, double abs_floor, std::ve
             for (int i = j + 1; i < r; i++) cj[i] = 0.0;
         }
         if (tau != 0.0) {
-            for (int q = j + 1; q < c; q++) {
+            // apply the reflector to the remaining columns, NW at a time: each
+            // column's product with v is summed in row order as for a single
+            // column, the NW sums interleaved (independent chains)
+            constexpr int NW = 8;
+            int q = j + 1;
+            for (; q + NW <= c; q += NW) {
+                double *cc[NW], w[NW];
+                for (int u = 0; u < NW; u++) {
+                    cc[u] = A + (size_t)(q + u) * r;
+                    w[u] = cc[u][j];
+                }
+                for (int i = j + 1; i < r; i++) {
+                    const double vi = v[i];
+                    for (int u = 0; u < NW; u++) w[u] += vi * cc[u][i];
+                }
+                for (int u = 0; u < NW; u++) {
+                    const double wu = w[u] * tau;
+                    double *cq = cc[u];
+                    cq[j] -= wu;
+                    for (int i = j + 1; i < r; i++) cq[i] -= wu * v[i];
+                }
+            }
+            for (; q < c; q++) {
                 double *cq = A + (size_t)q * r;
                 double w = cq[j];
                 for (int i = j + 1; i < r; i++) w += v[i] * cq[i];
@@ -117,16 +139,24 @@ int interp_decomp(double *A, int r, int c, double tol, double abs_floor, std::ve
         }
         k = j + 1;
     }
-    // T = R11^{-1} R12
+    // T = R11^{-1} R12 by back substitution along contiguous rows of T (R11
+    // copied row-major); every entry is reduced over s2 = s+1 .. k-1 in
+    // increasing order, as a column-by-column solve would
     const int nd = c - k;
     T.assign((size_t)k * nd, 0.0);
-    for (int d = 0; d < nd; d++) {
-        const double *cq = A + (size_t)(k + d) * r;
-        for (int s = k - 1; s >= 0; s--) {
-            double acc = cq[s];
-            for (int s2 = s + 1; s2 < k; s2++) acc -= A[(size_t)s2 * r + s] * T[(size_t)s2 * nd + d];
-            T[(size_t)s * nd + d] = acc / A[(size_t)s * r + s];
+    std::vector<double> R((size_t)k * k);
+    for (int s = 0; s < k; s++)
+        for (int s2 = s; s2 < k; s2++) R[(size_t)s * k + s2] = A[(size_t)s2 * r + s];
+    for (int s = k - 1; s >= 0; s--) {
+        double *ts = T.data() + (size_t)s * nd;
+        for (int d = 0; d < nd; d++) ts[d] = A[(size_t)(k + d) * r + s];
+        for (int s2 = s + 1; s2 < k; s2++) {
+            const double a = R[(size_t)s * k + s2];
+            const double *t2 = T.data() + (size_t)s2 * nd;
+            for (int d = 0; d < nd; d++) ts[d] -= a * t2[d];
         }
+        const double diag = R[(size_t)s * k + s];
+        for (int d = 0; d < nd; d++) ts[d] /= diag;
     }
     return k;
 }
