@@ -119,9 +119,10 @@ def measured_counters(kernel, L, nside, nmaps, t_entries=None):
 def batch_bench(np, torch, sht, steps):
     """64 queued syntheses of mixed L in {127, 255, 511, 1023}, nside =
     (L+1)/2, 1-8 maps each (seed 500): one batch call (and its captured HIP
-    graph) against 64 sequential calls, with plans of tuned tile shapes: FP64
-    brute force, then butterfly plans (eps 1e-12, depth from the cost model)
-    with FP64 and FP32 matrix-core level products."""
+    graph) against 64 sequential calls, with tuned plans: FP64 brute force
+    (tuned tile shapes), then butterfly plans (eps 1e-12, depth from the cost
+    model with rho tuned per precision) with FP64 and FP32 matrix-core level
+    products."""
     from paper_1110_4874_amd import autotune
     from paper_1110_4874_amd.synthetic import alm_gaussian, mixed_requests
 
@@ -220,29 +221,38 @@ def batch_bench(np, torch, sht, steps):
         best["sweep_graph_maps_per_s"] = sweep
         return best
 
+    # tile shapes and cost model tuned per path and precision at 4 maps per
+    # request (the ring shape on the brute-force path, rho on the butterfly
+    # path for FP64 and FP32 level products separately)
     t0 = time.perf_counter()
-    plans = {}
-    for (L, N, _, _) in inputs:
-        if (L, N) not in plans:
-            plans[(L, N)] = autotune.tuned_plan(L, N, 4)
+    shapes = sorted({(L, N) for (L, N, _, _) in inputs})
+    plans = {(L, N): autotune.tuned_plan(L, N, 4) for (L, N) in shapes}
+    bf_plans = {prec: {(L, N): autotune.tuned_plan(L, N, 4, 1e-12, path=sht.PATH_BUTTERFLY, precision=prec,
+                                                   plan_kw={"store_fp32": True}) for (L, N) in shapes}
+                for prec in (sht.PREC_FP64, sht.PREC_FP32)}
     tune_s = time.perf_counter() - t0
-    res = {"requests": len(inputs), "maps": nmaps, "tuning_seconds": round(tune_s, 1),
-           "tile_shapes": {f"{L}": {k: v for k, v in autotune.tune(L, N, 4).items() if k != "ms"}
-                           for (L, N) in plans},
+
+    def shape(L, N, eps=0.0, path=sht.PATH_BRUTE, prec=sht.PREC_FP64):
+        return {k: v for k, v in autotune.tune(L, N, 4, eps, path=path, precision=prec).items() if k != "ms"}
+
+    res = {"requests": len(inputs), "maps": nmaps, "tuning_seconds": round(tune_s, 1), "arch": autotune.arch(),
+           "tile_shapes": {f"{L}": {"brute_fp64": shape(L, N),
+                                    "butterfly_fp64": shape(L, N, 1e-12, sht.PATH_BUTTERFLY, sht.PREC_FP64),
+                                    "butterfly_fp32": shape(L, N, 1e-12, sht.PATH_BUTTERFLY, sht.PREC_FP32)}
+                           for (L, N) in shapes},
            "brute_fp64": run_config(plans, sht.PATH_BRUTE, sht.PREC_FP64)}
     res["queue_brute_fp64"] = run_queue(plans)
     log(f"[bench] batching queue_brute_fp64: run {res['queue_brute_fp64']['run_maps_per_s']} maps/s, graph "
         f"{res['queue_brute_fp64']['graph_maps_per_s']} ({res['queue_brute_fp64']['launches_per_run']} launches)")
-    bf_plans = {(L, N): autotune.tuned_plan(L, N, 4, plan_eps=1e-12, plan_kw={"store_fp32": True})
-                for (L, N) in plans}
-    res["butterfly_depth_hist"] = {f"{L}": p.info()["bf_depth_hist"][:6] for (L, _), p in bf_plans.items()}
-    res["butterfly_fp64"] = run_config(bf_plans, sht.PATH_BUTTERFLY, sht.PREC_FP64)
-    res["butterfly_fp32"] = run_config(bf_plans, sht.PATH_BUTTERFLY, sht.PREC_FP32)
+    res["butterfly_depth_hist"] = {f"{L}": p.info()["bf_depth_hist"][:6]
+                                   for (L, _), p in bf_plans[sht.PREC_FP64].items()}
+    res["butterfly_fp64"] = run_config(bf_plans[sht.PREC_FP64], sht.PATH_BUTTERFLY, sht.PREC_FP64)
+    res["butterfly_fp32"] = run_config(bf_plans[sht.PREC_FP32], sht.PATH_BUTTERFLY, sht.PREC_FP32)
     for k, prec in (("queue_butterfly_fp64", sht.PREC_FP64), ("queue_butterfly_fp32", sht.PREC_FP32)):
-        res[k] = run_queue(bf_plans, sht.PATH_BUTTERFLY, prec)
+        res[k] = run_queue(bf_plans[prec], sht.PATH_BUTTERFLY, prec)
         log(f"[bench] batching {k}: run {res[k]['run_maps_per_s']} maps/s, graph {res[k]['graph_maps_per_s']} "
             f"({res[k]['launches_per_run']} launches)")
-    for p in list(plans.values()) + list(bf_plans.values()):
+    for p in list(plans.values()) + [q for d in bf_plans.values() for q in d.values()]:
         p.close()
     for k in ("brute_fp64", "butterfly_fp64", "butterfly_fp32"):
         log(f"[bench] batching {k}: sequential {res[k]['sequential_maps_per_s']} maps/s, "
