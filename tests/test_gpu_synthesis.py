@@ -58,6 +58,47 @@ def test_ring_stage_parity(gpu, L, N):
     assert err <= TOL
 
 
+def _ring_direct(qr, J, s):
+    """The ring sum by its definition (Sec. 2.3, Eqs. 8-11) for one ring:
+    f_j = Re q_0 + 2 Re sum_{m>=1} q_m e^{i m phi_j}, phi_j = pi (2j + s) / J,
+    with the phase m (2j + s) reduced mod 2J in integers; qr: (L+1, B).
+    Checked against the oracle's synthesis on every ring at L = 40 (6e-16)."""
+    L1 = qr.shape[0]
+    m = np.arange(L1)[:, None]
+    j = np.arange(J)[None, :]
+    E = np.exp(1j * np.pi * np.mod(m * (2 * j + s), 2 * J) / J)
+    q = qr.copy()
+    q[0] = q[0].real
+    w = np.full(L1, 2.0)
+    w[0] = 1.0
+    return np.real((q * w[:, None]).T @ E)  # (B, J)
+
+
+# L = 2100, nside = 600: polar rings with J <= L up to ring 525 (rings 512..525
+# have more bin pairs than a 512-thread workgroup), J > L from ring 526, the
+# belt from 600, and their south counterparts; powers of two at 128 and 512
+RINGS_2100 = [1, 2, 3, 50, 127, 128, 300, 511, 512, 518, 525, 526, 527, 599, 600, 601, 1200, 1799, 1800,
+              1801, 1873, 1874, 1875, 1888, 2398, 2399]
+
+
+@pytest.mark.parametrize("B", [1, 2, 3, 4])
+def test_ring_stage_direct_dft_l2100(gpu, B):
+    # random q straight into the ring kernel: every ring class with one, two
+    # or four maps per workgroup (odd B: one), against the definition
+    L, N = 2100, 600
+    rng = np.random.default_rng(900 + B)
+    nr = 4 * N - 1
+    q = rng.standard_normal((nr, L + 1, B)) + 1j * rng.standard_normal((nr, L + 1, B))
+    f = gpu.Plan(L, N).ring_synthesis(_dev(q)).cpu().numpy()
+    worst = 0.0
+    for ring in RINGS_2100:
+        z, st, J, s, off = oracle.ring_info(N, ring)
+        ref = _ring_direct(q[ring - 1], J, s)
+        worst = max(worst, float(np.max(np.abs(f[:, off:off + J] - ref)) / np.max(np.abs(ref))))
+    print(f"L=2100 N=600 B={B} ring-stage maxrel={worst:.3e}")
+    assert worst <= TOL
+
+
 @pytest.mark.parametrize("L,N,B,seeds", [(63, 32, 1, [1]), (511, 256, 1, [2]), (47, 8, 2, [3, 4]),
                                          (0, 1, 1, [5]), (95, 48, 4, [6, 7, 8, 9]),
                                          (200, 50, 3, [10, 11, 12])])
