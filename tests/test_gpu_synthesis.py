@@ -11,6 +11,7 @@ import torch
 
 import oracle
 from paper_1110_4874_amd.synthetic import alm_gaussian
+from ring_defs import ring_direct
 
 pytestmark = pytest.mark.gpu
 
@@ -58,22 +59,6 @@ def test_ring_stage_parity(gpu, L, N):
     assert err <= TOL
 
 
-def _ring_direct(qr, J, s):
-    """The ring sum by its definition (Sec. 2.3, Eqs. 8-11) for one ring:
-    f_j = Re q_0 + 2 Re sum_{m>=1} q_m e^{i m phi_j}, phi_j = pi (2j + s) / J,
-    with the phase m (2j + s) reduced mod 2J in integers; qr: (L+1, B).
-    Checked against the oracle's synthesis on every ring at L = 40 (6e-16)."""
-    L1 = qr.shape[0]
-    m = np.arange(L1)[:, None]
-    j = np.arange(J)[None, :]
-    E = np.exp(1j * np.pi * np.mod(m * (2 * j + s), 2 * J) / J)
-    q = qr.copy()
-    q[0] = q[0].real
-    w = np.full(L1, 2.0)
-    w[0] = 1.0
-    return np.real((q * w[:, None]).T @ E)  # (B, J)
-
-
 # L = 2100, nside = 600: polar rings with J <= L up to ring 525 (rings 512..525
 # have more bin pairs than a 512-thread workgroup), J > L from ring 526, the
 # belt from 600, and their south counterparts; powers of two at 128 and 512
@@ -84,7 +69,8 @@ RINGS_2100 = [1, 2, 3, 50, 127, 128, 300, 511, 512, 518, 525, 526, 527, 599, 600
 @pytest.mark.parametrize("B", [1, 2, 3, 4])
 def test_ring_stage_direct_dft_l2100(gpu, B):
     # random q straight into the ring kernel: every ring class with one, two
-    # or four maps per workgroup (odd B: one), against the definition
+    # or four maps per workgroup (odd B: one), against the ring sum by its
+    # definition (pinned to the oracle in test_ring_definitions.py)
     L, N = 2100, 600
     rng = np.random.default_rng(900 + B)
     nr = 4 * N - 1
@@ -93,7 +79,7 @@ def test_ring_stage_direct_dft_l2100(gpu, B):
     worst = 0.0
     for ring in RINGS_2100:
         z, st, J, s, off = oracle.ring_info(N, ring)
-        ref = _ring_direct(q[ring - 1], J, s)
+        ref = ring_direct(q[ring - 1], J, s)
         worst = max(worst, float(np.max(np.abs(f[:, off:off + J] - ref)) / np.max(np.abs(ref))))
     print(f"L=2100 N=600 B={B} ring-stage maxrel={worst:.3e}")
     assert worst <= TOL
